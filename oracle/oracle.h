@@ -1,0 +1,118 @@
+/*
+ * oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, single-threaded CPU reference for semisort, histogram and
+ * collect-reduce as defined in Dong, Wu, Wang, Dhulipala, Gu and Sun,
+ * "High-Performance and Flexible Parallel Algorithms for Semisort and Related
+ * Problems" (SPAA 2023).  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may call this library.  It shares no code,
+ * header, helper or constant table with the GPU library; everything here is
+ * written from the paper's definitions and from the published definitions of
+ * the two mixing functions it uses.
+ *
+ * All pointers are host pointers owned by the caller.  Functions that can fail
+ * (only on allocation) return a negative value; nothing else is checked.
+ */
+#ifndef SEMISORT_ORACLE_H
+#define SEMISORT_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- hashing ---------------------------------------------------------- */
+
+/* User hash h (Section 2.1 asks the user for a hash family on keys).
+ * mode 0: the 64-bit finalizer published with MurmurHash3 (a bijection).
+ * mode 1: identity, the paper's "-i" variants (Section 4.1, Flexible Interface). */
+uint64_t orc_hash(uint64_t k, int hash_mode);
+
+/* SplitMix64 output function (Steele, Lea and Flood, OOPSLA 2014), used as the
+ * counter-based generator that picks sample positions. */
+uint64_t orc_splitmix_mix(uint64_t z);
+
+/* ---- plain definitions (Section 2.1) ---------------------------------- */
+
+/* semisort by equality: equal keys contiguous, input order kept among equal
+ * keys (stability, Section 2.2).  Canonical group order: ascending (h(k), k).
+ * val_bytes is 4 or 8.  Returns 0, or -1 when out of memory. */
+int orc_semisort_equal(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                       uint64_t n, int hash_mode, uint64_t* keys_out, void* vals_out);
+
+/* semisort by comparison with groups in ascending key order, stable:
+ * exactly a stable sort by key. */
+int orc_semisort_less(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                      uint64_t n, uint64_t* keys_out, void* vals_out);
+
+/* histogram: (unique key, occurrences), ascending keys.  Returns m or -1. */
+int64_t orc_histogram(const uint64_t* keys, uint64_t n, uint64_t* out_keys,
+                      uint64_t* out_counts);
+
+/* collect-reduce with map = value and monoid (+ mod 2^64, 0): (unique key,
+ * wrapping sum of its values), ascending keys.  Returns m or -1. */
+int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                           uint64_t* out_keys, uint64_t* out_sums);
+
+/* Canonical form of a candidate semisort_= output: split it into maximal runs
+ * of equal keys and order the runs by ascending (h(k), k).  Because a stable
+ * semisort is unique up to the order of its groups, a correct output has the
+ * same canonical form as orc_semisort_equal's result.  Returns -1 when equal
+ * keys are contiguous, otherwise the position of the first run whose key
+ * already had an earlier run (canonical buffers are then unspecified), or -2
+ * when out of memory. */
+int64_t orc_canonicalize_equal(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                               uint64_t n, int hash_mode, uint64_t* canon_keys,
+                               void* canon_vals);
+
+/* Table 3 statistics: distinct keys, maximum frequency, and the number of
+ * records whose key occurs more than heavy_threshold times (the "Heavy Freq."
+ * column uses 500 log n).  Returns 0 or -1. */
+int orc_stats(const uint64_t* keys, uint64_t n, double heavy_threshold,
+              uint64_t* distinct, uint64_t* max_freq, uint64_t* heavy_records);
+
+/* ---- one level of Algorithm 1, step by step ---------------------------- */
+
+/* Step 1 sample size |S| = ceil(c * ln n') and heavy threshold ceil(ln n')
+ * (Algorithm 1 and Section 3.6, natural logarithm). */
+uint32_t orc_sample_size(uint64_t len, uint32_t c);
+uint32_t orc_heavy_threshold(uint64_t len);
+
+/* Position in [0, len) of the i-th sample of the subproblem that starts at
+ * `start` on recursion level `level`, drawn with replacement. */
+uint64_t orc_sample_index(uint64_t seed, uint32_t level, uint64_t start, uint64_t len,
+                          uint64_t i);
+
+/* Heavy keys: the distinct sampled keys seen at least tau times, in ascending
+ * (h(k), k) order; their bucket ids are n_L, n_L+1, ... in that order.
+ * Returns n_H (at most max_heavy; -1 if more keys qualify, -2 on OOM). */
+int64_t orc_select_heavy(const uint64_t* sample_keys, uint32_t s, uint32_t tau,
+                         int hash_mode, uint32_t max_heavy, uint64_t* heavy_keys);
+
+/* GetBucketId of Algorithm 1: the heavy id when k is a heavy key, otherwise
+ * the light id taken from nl_bits bits of h(k) starting at bit `shift`. */
+void orc_bucket_ids(const uint64_t* keys, uint64_t n, const uint64_t* heavy_keys,
+                    uint32_t n_heavy, uint32_t nl_bits, uint32_t shift, int hash_mode,
+                    uint32_t* bids);
+
+/* Counting matrix C[i][j]: records of subarray i (size l, last one short)
+ * whose bucket is j.  C is row-major ceil(n/l) x nb. */
+void orc_count_matrix(const uint32_t* bids, uint64_t n, uint64_t l, uint32_t nb,
+                      uint32_t* C);
+
+/* Column-major prefix X[i][j] = sum of C over buckets j' < j, plus bucket j in
+ * subarrays i' < i; offsets[j] = X[0][j], offsets[nb] = n. */
+void orc_column_prefix(const uint32_t* C, uint64_t tiles, uint32_t nb, uint64_t n,
+                       uint32_t* X, uint64_t* offsets);
+
+/* Distribution into T: each subarray in order, T[X[i][id]++] = A[j]. */
+void orc_distribute(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                    const uint32_t* bids, uint64_t n, uint64_t l, uint32_t nb,
+                    const uint32_t* X, uint64_t* t_keys, void* t_vals);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,279 @@
+"""Pins for the CPU oracle: it is checked here against the problem definitions
+(Section 2.1), stability (Section 2.2), brute force on tiny inputs, library
+routines and closed forms -- never against itself."""
+import itertools
+import math
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+ALPHABET = [0, 1, 1 << 63, (1 << 64) - 1]
+MOD = 1 << 64
+
+
+def _all_sequences(max_len):
+    for n in range(max_len + 1):
+        for seq in itertools.product(ALPHABET, repeat=n):
+            yield list(seq)
+
+
+# ---------------------------------------------------------------- hash pins
+
+
+def _inv_xorshift(y, s):
+    x = y
+    for _ in range(64 // s + 1):
+        x = y ^ (x >> s)
+    return x
+
+
+def test_hash_is_a_bijection_with_the_published_inverse():
+    # Invert the finalizer step by step with modular inverses of its two
+    # multipliers; a wrong constant or shift anywhere breaks the round trip.
+    c1 = 0xFF51AFD7ED558CCD
+    c2 = 0xC4CEB9FE1A85EC53
+    i1, i2 = pow(c1, -1, MOD), pow(c2, -1, MOD)
+    rng = np.random.default_rng(1)
+    xs = [0, 1, 2, (1 << 64) - 1, 1 << 63] + [int(v) for v in rng.integers(0, 2 ** 63, 200, dtype=np.int64)]
+    for x in xs:
+        y = O.hash64(x)
+        z = _inv_xorshift(y, 33)
+        z = (z * i2) % MOD
+        z = _inv_xorshift(z, 33)
+        z = (z * i1) % MOD
+        z = _inv_xorshift(z, 33)
+        assert z == x
+    assert O.hash64(0) == 0
+    assert O.hash64(12345, O.HASH_IDENTITY) == 12345
+
+
+def test_hash_low_bits_spread_consecutive_keys():
+    # The light bucket id uses low hash bits; consecutive integers must land
+    # in all 1024 buckets about evenly (chi-square, 1023 dof).
+    h = np.array([O.hash64(i) for i in range(1 << 16)], dtype=np.uint64)
+    counts = np.bincount((h & np.uint64(1023)).astype(np.int64), minlength=1024)
+    exp = (1 << 16) / 1024
+    chi2 = float(((counts - exp) ** 2 / exp).sum())
+    assert chi2 < 1023 + 6 * math.sqrt(2 * 1023)
+
+
+# ------------------------------------------------ definitions, exhaustively
+
+
+def _check_semisort_equal(keys, ko, vo):
+    n = len(keys)
+    vo = [int(v) for v in vo]
+    ko = [int(k) for k in ko]
+    assert sorted(vo) == list(range(n))  # a permutation of the records
+    assert all(ko[p] == keys[vo[p]] for p in range(n))  # records moved whole
+    seen = set()
+    for p in range(n):  # equal keys contiguous
+        if p == 0 or ko[p] != ko[p - 1]:
+            assert ko[p] not in seen
+            seen.add(ko[p])
+    for p in range(1, n):  # stable: input order kept inside a group
+        if ko[p] == ko[p - 1]:
+            assert vo[p] > vo[p - 1]
+
+
+def test_semisort_equal_exhaustive_tiny():
+    count = 0
+    for keys in _all_sequences(7):
+        n = len(keys)
+        k = np.array(keys, dtype=np.uint64)
+        v = np.arange(n, dtype=np.uint64)
+        ko, vo = O.semisort_equal(k, v)
+        _check_semisort_equal(keys, ko, vo)
+        # canonical group order: ascending hash of the group's key
+        firsts = [int(ko[p]) for p in range(n) if p == 0 or ko[p] != ko[p - 1]]
+        hs = [O.hash64(x) for x in firsts]
+        assert hs == sorted(hs)
+        count += 1
+    assert count == sum(4 ** i for i in range(8))
+
+
+def test_semisort_less_is_pythons_stable_sort():
+    for keys in _all_sequences(6):
+        n = len(keys)
+        k = np.array(keys, dtype=np.uint64)
+        v = np.arange(n, dtype=np.uint32)
+        ko, vo = O.semisort_less(k, v)
+        order = sorted(range(n), key=lambda i: keys[i])  # Python's sort is stable
+        assert [int(x) for x in vo] == order
+        assert [int(x) for x in ko] == [keys[i] for i in order]
+
+
+def test_histogram_and_collect_reduce_brute_force():
+    rng = np.random.default_rng(7)
+    for keys in _all_sequences(5):
+        n = len(keys)
+        # values near 2^64 force wrap-around
+        vals = [int(x) for x in rng.integers(0, 2 ** 63, n, dtype=np.int64)]
+        vals = [(MOD - 1 - v) if i % 2 else v for i, v in enumerate(vals)]
+        k = np.array(keys, dtype=np.uint64)
+        v = np.array(vals, dtype=np.uint64)
+        hk, hc = O.histogram(k)
+        ck, cs = O.collect_reduce(k, v)
+        uniq = sorted(set(keys))
+        assert [int(x) for x in hk] == uniq and [int(x) for x in ck] == uniq
+        for j, u in enumerate(uniq):
+            assert int(hc[j]) == sum(1 for x in keys if x == u)
+            assert int(cs[j]) == sum(vals[i] for i in range(n) if keys[i] == u) % MOD
+        assert int(hc.sum()) == n
+
+
+def test_collect_reduce_wraps_mod_2_64():
+    k = np.array([5, 5, 5], dtype=np.uint64)
+    v = np.array([MOD - 1, MOD - 1, 3], dtype=np.uint64)
+    ck, cs = O.collect_reduce(k, v)
+    assert list(ck) == [5] and int(cs[0]) == (2 * (MOD - 1) + 3) % MOD
+
+
+def test_random_medium_inputs_meet_the_definition():
+    rng = np.random.default_rng(3)
+    for n, M in [(1000, 10), (5000, 1000), (20000, 1 << 62)]:
+        keys = rng.integers(0, M, n, dtype=np.int64).astype(np.uint64)
+        v = np.arange(n, dtype=np.uint64)
+        ko, vo = O.semisort_equal(keys, v)
+        _check_semisort_equal([int(x) for x in keys], ko, vo)
+        lo, lv = O.semisort_less(keys, v.astype(np.uint32))
+        order = np.argsort(keys, kind="stable")
+        assert np.array_equal(lv, order.astype(np.uint32)) and np.array_equal(lo, keys[order])
+        hk, hc = O.histogram(keys)
+        u, c = np.unique(keys, return_counts=True)
+        assert np.array_equal(hk, u) and np.array_equal(hc, c.astype(np.uint64))
+
+
+def test_identity_hash_orders_groups_by_key():
+    keys = np.array([9, 3, 9, 1, 3, 3], dtype=np.uint64)
+    ko, vo = O.semisort_equal(keys, np.arange(6, dtype=np.uint64), O.HASH_IDENTITY)
+    assert list(ko) == [1, 3, 3, 3, 9, 9] and list(vo) == [3, 1, 4, 5, 0, 2]
+
+
+# ----------------------------------------------------------- canonicalizer
+
+
+def _groups_of(ko, vo):
+    groups = []
+    for p in range(len(ko)):
+        if p == 0 or ko[p] != ko[p - 1]:
+            groups.append([])
+        groups[-1].append((int(ko[p]), int(vo[p])))
+    return groups
+
+
+def test_canonicalizer_accepts_every_group_order():
+    keys = np.array([4, 2, 4, 7, 2, 9, 4, 11, 7], dtype=np.uint64)
+    v = np.arange(keys.size, dtype=np.uint64)
+    rk, rv = O.semisort_equal(keys, v)
+    groups = _groups_of(rk, rv)
+    assert len(groups) == 5
+    for perm in itertools.permutations(groups):
+        flat = [x for g in perm for x in g]
+        ck_in = np.array([x[0] for x in flat], dtype=np.uint64)
+        cv_in = np.array([x[1] for x in flat], dtype=np.uint64)
+        bad, ck, cv = O.canonicalize_equal(ck_in, cv_in)
+        assert bad == -1
+        assert np.array_equal(ck, rk) and np.array_equal(cv, rv)
+
+
+def test_canonicalizer_rejects_each_mutation():
+    keys = np.array([4, 2, 4, 7, 2, 9, 4, 11, 7], dtype=np.uint64)
+    v = np.arange(keys.size, dtype=np.uint64)
+    rk, rv = O.semisort_equal(keys, v)
+    flat = [(int(a), int(b)) for a, b in zip(rk, rv)]
+
+    def verdict(f):
+        k = np.array([x[0] for x in f], dtype=np.uint64)
+        w = np.array([x[1] for x in f], dtype=np.uint64)
+        bad, ck, cv = O.canonicalize_equal(k, w)
+        return bad == -1 and np.array_equal(ck, rk) and np.array_equal(cv, rv)
+
+    assert verdict(flat)
+    # split a group: move the last record of the first multi-record group to the end
+    p = next(i for i in range(1, len(flat)) if flat[i][0] == flat[i - 1][0])
+    split = flat[:p] + flat[p + 1:] + [flat[p]]
+    assert not verdict(split)
+    # swap two records inside a group (breaks stability)
+    sw = list(flat)
+    sw[p - 1], sw[p] = sw[p], sw[p - 1]
+    assert not verdict(sw)
+    # duplicate one record over another
+    dup = list(flat)
+    dup[0] = dup[1] if dup[1][0] == dup[0][0] else dup[0]
+    dup[-1] = dup[0]
+    assert not verdict(dup)
+    # change a value
+    cv = list(flat)
+    cv[3] = (cv[3][0], cv[3][1] + 100)
+    assert not verdict(cv)
+
+
+# -------------------------------------------------- stage model of one level
+
+
+def test_sample_indices_in_range_deterministic_and_uniform():
+    idx = O.sample_indices(11, 0, 0, 1000, 20000)
+    assert idx.max() < 1000
+    assert np.array_equal(idx, O.sample_indices(11, 0, 0, 1000, 20000))
+    assert not np.array_equal(idx[:100], O.sample_indices(11, 1, 0, 1000, 100))
+    counts = np.bincount(idx.astype(np.int64), minlength=1000)
+    chi2 = float(((counts - 20.0) ** 2 / 20.0).sum())
+    assert chi2 < 999 + 6 * math.sqrt(2 * 999)
+
+
+def test_sample_size_and_threshold_use_natural_log():
+    # Section 3.6: |S| = 500 log n; natural log reproduces Table 3's heavy column
+    assert O.sample_size(10 ** 9, 500) == math.ceil(500 * math.log(1e9))
+    assert O.heavy_threshold(10 ** 9) == 21
+    assert O.heavy_threshold(16) == 3  # Fig. 2: 'more than 2 samples' with n = 16
+
+
+def test_select_heavy_brute_force():
+    rng = np.random.default_rng(5)
+    s = rng.choice(np.array([3, 8, 8, 8, 1 << 40, 77, 77], dtype=np.uint64), 400)
+    for tau in (1, 30, 60, 120):
+        hk = O.select_heavy(s, tau)
+        cnt = Counter(int(x) for x in s)
+        want = sorted([k for k, c in cnt.items() if c >= tau], key=lambda k: (O.hash64(k), k))
+        assert [int(x) for x in hk] == want
+
+
+def test_count_prefix_distribute_against_definitions():
+    rng = np.random.default_rng(9)
+    n, tile = 10007, 1000
+    keys = rng.integers(0, 3000, n, dtype=np.int64).astype(np.uint64)
+    keys[rng.random(n) < 0.3] = 17  # one heavy key
+    vals = np.arange(n, dtype=np.uint64)
+    heavy = O.select_heavy(keys[rng.integers(0, n, 500)], 40)
+    assert 17 in [int(x) for x in heavy]
+    nl_bits = 4
+    nb = (1 << nl_bits) + heavy.size
+    bids = O.bucket_ids(keys, heavy, nl_bits, 0)
+    # bucket ids: heavy keys get n_L + rank, light keys the low hash bits
+    for j in range(0, n, 97):
+        k = int(keys[j])
+        if k in [int(x) for x in heavy]:
+            assert bids[j] == (1 << nl_bits) + [int(x) for x in heavy].index(k)
+        else:
+            assert bids[j] == O.hash64(k) & ((1 << nl_bits) - 1)
+    C = O.count_matrix(bids, tile, nb)
+    tiles = (n + tile - 1) // tile
+    for i in range(tiles):
+        seg = bids[i * tile:(i + 1) * tile].astype(np.int64)
+        assert np.array_equal(C[i], np.bincount(seg, minlength=nb).astype(np.uint32))
+    X, off = O.column_prefix(C, n)
+    flat = C.T.reshape(-1).astype(np.int64)  # column-major walk
+    excl = np.concatenate([[0], np.cumsum(flat)[:-1]])
+    assert np.array_equal(X.T.reshape(-1), excl.astype(np.uint32))
+    assert off[-1] == n and np.all(np.diff(off.astype(np.int64)) >= 0)
+    tk, tv = O.distribute(keys, vals, bids, tile, nb, X)
+    order = np.argsort(bids, kind="stable")  # a stable counting sort by bucket id
+    assert np.array_equal(tv, order.astype(np.uint64)) and np.array_equal(tk, keys[order])
+    # each heavy bucket holds exactly one key
+    for h in range(heavy.size):
+        a, b = int(off[(1 << nl_bits) + h]), int(off[(1 << nl_bits) + h + 1])
+        assert np.all(tk[a:b] == heavy[h])
