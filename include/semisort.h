@@ -1,0 +1,119 @@
+/*
+ * semisort.h -- C-ABI of libsemisort_hip.so, an MI355X (gfx950) implementation
+ * of the semisort family of Dong, Wu, Wang, Dhulipala, Gu and Sun,
+ * "High-Performance and Flexible Parallel Algorithms for Semisort and Related
+ * Problems" (SPAA 2023).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Keys are uint64.  Values are uint32 or uint64 (val_bytes = 4 or 8).
+ *   Arrays are structure-of-arrays: keys[n] and vals[n] side by side.
+ * - Every array pointer is a DEVICE pointer on the context's device, owned by
+ *   the caller.  The library owns only its workspace (temporary array T,
+ *   counting matrices, heavy tables, work lists), which it grows on demand
+ *   and frees in ss_destroy.
+ * - Calls are ordered on the context's HIP stream.  A call returns after its
+ *   work is enqueued; it synchronizes the stream once per recursion level to
+ *   size the next level's launches, so it is not capture-safe.  Results are
+ *   ready when the stream is.
+ * - Errors: SS_EINVAL for bad arguments (checked before anything is
+ *   enqueued), SS_ENOMEM when the workspace cannot grow, SS_EHIP for a failed
+ *   HIP call, SS_EDEVICE for a condition detected on the device.
+ *   ss_last_error() returns a message for the last failure on the context.
+ *   Nothing throws across the ABI.
+ * - n = 0 is a no-op returning SS_OK.  n must be below 2^32 (positions are
+ *   32-bit on the device).
+ * - Output arrays must not overlap the inputs, except that keys_out == keys
+ *   together with vals_out == vals is allowed for semisort (the paper's
+ *   in-place form, Section 3.4).
+ * - Randomness (sample positions) comes from a counter-based generator keyed
+ *   by ss_params.seed, so results are deterministic for a fixed seed
+ *   (race-free and internally deterministic, Section 2.2).
+ */
+#ifndef SEMISORT_HIP_H
+#define SEMISORT_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ss_ctx ss_ctx;
+
+typedef enum {
+    SS_OK = 0,
+    SS_EINVAL = -1,
+    SS_ENOMEM = -2,
+    SS_EHIP = -3,
+    SS_EDEVICE = -4
+} ss_status;
+
+/* User hash h of Section 2.1.  SS_HASH_MIX64 is the 64-bit MurmurHash3
+ * finalizer (a bijection); SS_HASH_IDENTITY uses the key itself, the "-i"
+ * variants of Section 4.1 (Flexible Interface). */
+typedef enum { SS_HASH_MIX64 = 0, SS_HASH_IDENTITY = 1 } ss_hash_mode;
+
+/* Tunable parameters (Table 1 and Section 3.6).  Zero fields take defaults. */
+typedef struct {
+    uint32_t n_light_log2; /* b, n_L = 2^b light buckets on the top level (1..10; default 10) */
+    uint32_t base_case;    /* alpha: subproblems below this are finished in LDS (64..4096; default 4096) */
+    uint32_t sample_mult;  /* c in |S| = ceil(c ln n') (1..511; default 500) */
+    uint32_t tile_min;     /* smallest subarray size l in records (power of two, 8192..65536) */
+    uint32_t tile_max;     /* largest subarray size l (power of two, tile_min..65536; default 65536) */
+    uint32_t hash_mode;    /* ss_hash_mode */
+    uint64_t seed;         /* sampling seed */
+} ss_params;
+
+/* Fill *p with the defaults. */
+ss_status ss_default_params(ss_params* p);
+
+/* Create a context on HIP device `device` issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+ss_status ss_create(int device, void* hip_stream, ss_ctx** out);
+ss_status ss_destroy(ss_ctx* ctx);
+ss_status ss_set_stream(ss_ctx* ctx, void* hip_stream);
+const char* ss_last_error(ss_ctx* ctx);
+/* Wait for the context's stream. */
+ss_status ss_sync(ss_ctx* ctx);
+/* Bytes of workspace currently held by the context. */
+ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
+
+/* semisort_= (Section 2.1; Algorithm 1 with the hash-table base case of
+ * Section 3.3): reorders the n records so that equal keys are contiguous and
+ * records with equal keys keep their input order (stable, Section 2.2).
+ * The order of the groups is unspecified but deterministic for a seed.
+ * params may be NULL (defaults). */
+ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                            uint32_t val_bytes, uint64_t n, uint64_t* keys_out,
+                            void* vals_out, const ss_params* params);
+
+/* Batched semisort_=: `nseg` independent instances packed back to back;
+ * instance i occupies [seg_offsets[i], seg_offsets[i+1]) of keys/vals and of
+ * the outputs.  seg_offsets is a HOST array of nseg+1 non-decreasing
+ * uint64 with seg_offsets[0] = 0 and seg_offsets[nseg] = total n.  Each
+ * instance's result is the one ss_semisort_equal gives for it alone. */
+ss_status ss_semisort_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                  uint32_t val_bytes, const uint64_t* seg_offsets,
+                                  uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                  const ss_params* params);
+
+/* One level of Algorithm 1 on one subproblem, for inspection: Step 1
+ * (sampling, heavy keys, heavy table) and Step 2 (counting matrix, column-major
+ * prefix, distribution), without Step 3.  Writes the distributed array T to
+ * keys_out/vals_out, the n_L + n_H + 1 bucket offsets to offsets_out (device,
+ * uint64, capacity 2^n_light_log2 + 512 + 1), the heavy keys' hashes in
+ * bucket-id order to heavy_hashes_out (device, capacity 512) and n_H to
+ * *n_heavy_out (host).  Light bucket ids use hash bits [0, n_light_log2). */
+ss_status ss_partition_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                             uint32_t val_bytes, uint64_t n, uint64_t* keys_out,
+                             void* vals_out, uint64_t* offsets_out,
+                             uint64_t* heavy_hashes_out, uint32_t* n_heavy_out,
+                             const ss_params* params);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

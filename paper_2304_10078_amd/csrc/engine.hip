@@ -1,0 +1,541 @@
+// Host driver and C-ABI of libsemisort_hip.so (declared in include/semisort.h).
+//
+// The driver runs Algorithm 1 level by level over a list of subproblems: all
+// subproblems of one recursion level are processed by the same kernel
+// launches (sampling, counting, scan, distribution), then a planning kernel
+// turns every bucket into a next-level subproblem, a base-case job or a copy
+// job.  One host synchronization per level reads the sizes of the next level.
+// Buffers alternate between the output and the temporary array T as in the
+// in-place optimization of Section 3.4.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "semisort.h"
+#include "ss_device.h"
+
+using namespace ssd;
+
+namespace {
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct ss_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    DevBuf t_keys, t_vals;
+    DevBuf segs[2];
+    DevBuf jobs;
+    DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id;
+    DevBuf info;
+    LevelInfo* info_host = nullptr;  // pinned
+    std::vector<Seg> host_segs;
+    std::vector<Job> host_jobs;
+    Seg* seg_stage = nullptr;        // pinned staging for the first level
+    size_t seg_stage_cap = 0;
+    Job* job_stage = nullptr;
+    size_t job_stage_cap = 0;
+};
+
+namespace {
+
+ss_status fail(ss_ctx* c, ss_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                          \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), SS_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+ss_status ensure(ss_ctx* c, DevBuf& b, size_t bytes)
+{
+    if (bytes <= b.cap) return SS_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 255) & ~(size_t)255;
+    if (b.p) {
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        HIP_OR_FAIL(c, hipFree(b.p));
+        b.p = nullptr;
+        b.cap = 0;
+    }
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, SS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.cap = want;
+    return SS_OK;
+}
+
+ss_status ensure_pinned(ss_ctx* c, void** p, size_t* cap, size_t bytes)
+{
+    if (bytes <= *cap) return SS_OK;
+    if (*p) {
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        HIP_OR_FAIL(c, hipHostFree(*p));
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t want = std::max<size_t>(bytes, 4096);
+    HIP_OR_FAIL(c, hipHostMalloc(p, want, hipHostMallocDefault));
+    *cap = want;
+    return SS_OK;
+}
+
+struct Params {
+    uint32_t nl0, alpha, c, tmin, tmax, mode;
+    uint64_t seed;
+};
+
+ss_status resolve_params(ss_ctx* c, const ss_params* in, Params* p)
+{
+    ss_params d;
+    ss_default_params(&d);
+    const ss_params& s = in ? *in : d;
+    p->nl0 = s.n_light_log2 ? s.n_light_log2 : d.n_light_log2;
+    p->alpha = s.base_case ? s.base_case : d.base_case;
+    p->c = s.sample_mult ? s.sample_mult : d.sample_mult;
+    p->tmin = s.tile_min ? s.tile_min : d.tile_min;
+    p->tmax = s.tile_max ? s.tile_max : d.tile_max;
+    p->mode = s.hash_mode;
+    p->seed = s.seed;
+    if (p->nl0 < 1 || p->nl0 > kLightBitsMax) return fail(c, SS_EINVAL, "n_light_log2 must be in [1, 10]");
+    if (p->alpha < 64 || p->alpha > kAlphaMax) return fail(c, SS_EINVAL, "base_case must be in [64, 4096]");
+    if (p->c < 1 || p->c >= kHeavyMax) return fail(c, SS_EINVAL, "sample_mult must be in [1, 511]");
+    auto pow2 = [](uint32_t x) { return x && !(x & (x - 1)); };
+    if (!pow2(p->tmin) || !pow2(p->tmax) || p->tmin < 8192 || p->tmax > 65536 || p->tmin > p->tmax)
+        return fail(c, SS_EINVAL, "tile_min/tile_max must be powers of two with 8192 <= tile_min <= tile_max <= 65536");
+    if (p->mode > 1) return fail(c, SS_EINVAL, "hash_mode must be SS_HASH_MIX64 or SS_HASH_IDENTITY");
+    return SS_OK;
+}
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+// ---------------------------------------------------------------- launches
+
+template <typename V>
+void launch_finish(ss_ctx* c, uint32_t mode, uint32_t njobs, const uint64_t* sk, const void* sv,
+                   uint64_t* ok, void* ov)
+{
+    const Job* jobs = (const Job*)c->jobs.p;
+    LevelInfo* info = (LevelInfo*)c->info.p;
+    if (mode == 1)
+        hipLaunchKernelGGL((k_finish<1, V>), dim3(njobs), dim3(512), 0, c->stream, jobs, sk, (const V*)sv, ok, (V*)ov, info);
+    else
+        hipLaunchKernelGGL((k_finish<0, V>), dim3(njobs), dim3(512), 0, c->stream, jobs, sk, (const V*)sv, ok, (V*)ov, info);
+}
+
+template <int MODE, typename V>
+void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks)
+{
+    hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan_buckets, dim3(a.nsegs * kBucketGroups), dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan_offsets, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan_fill, dim3(chunks), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_distribute<MODE, V, 16, 8>), dim3(tiles), dim3(1024), 0, c->stream, a);
+}
+
+template <typename V>
+void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks)
+{
+    if (mode == 1) launch_level<1, V>(c, a, tiles, chunks);
+    else launch_level<0, V>(c, a, tiles, chunks);
+}
+
+// Sizes a level needs: per-subproblem tables, counting matrix rows, chunk rows.
+ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunks)
+{
+    ss_status s;
+    if ((s = ensure(c, c->C, (size_t)tiles * kNbStride * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->P, (size_t)std::max(chunks, 1u) * kNbStride * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->tot, (size_t)nsegs * kNbStride * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->bstart, (size_t)nsegs * (kNbStride + 1) * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->heavy_list, (size_t)nsegs * kHeavyMax * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->tab_h, (size_t)nsegs * kHeavySlotsMax * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->tab_id, (size_t)nsegs * kHeavySlotsMax * 2)) != SS_OK) return s;
+    return SS_OK;
+}
+
+LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint32_t nsegs, uint32_t tile,
+                    const uint64_t* sk, const void* sv, uint64_t* dk, void* dv)
+{
+    LevelArgs a;
+    a.src_keys = sk;
+    a.src_vals = sv;
+    a.dst_keys = dk;
+    a.dst_vals = dv;
+    a.segs = segs;
+    a.nsegs = nsegs;
+    a.tile = tile;
+    a.C = (uint32_t*)c->C.p;
+    a.P = (uint32_t*)c->P.p;
+    a.tot = (uint32_t*)c->tot.p;
+    a.bstart = (uint32_t*)c->bstart.p;
+    a.heavy_list = (uint64_t*)c->heavy_list.p;
+    a.tab_h = (uint64_t*)c->tab_h.p;
+    a.tab_id = (uint16_t*)c->tab_id.p;
+    a.info = (LevelInfo*)c->info.p;
+    a.seed = p.seed;
+    a.level = level;
+    a.sample_mult = p.c;
+    return a;
+}
+
+// Host-side prefix for the first level (same rule as k_seg_prefix).
+void host_prefix(std::vector<Seg>& segs, const Params& p, uint32_t* tiles, uint32_t* chunks, uint32_t* tile)
+{
+    uint64_t total = 0;
+    for (auto& s : segs) total += s.len;
+    *tile = choose_tile(total, p.tmin, p.tmax);
+    uint32_t rt = 0, rc = 0;
+    for (auto& s : segs) {
+        s.ntiles = (s.len + *tile - 1) / *tile;
+        s.tile0 = rt;
+        s.chunk0 = rc;
+        rt += s.ntiles;
+        rc += (s.ntiles + kChunk - 1) / kChunk;
+    }
+    *tiles = rt;
+    *chunks = rc;
+}
+
+// The whole engine: `offs` are instance boundaries (host), total n = offs.back().
+template <typename V>
+ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
+                             uint64_t ninst, uint64_t* keys_out, void* vals_out, const Params& p)
+{
+    const uint64_t n = offs[ninst];
+    const bool inplace = keys_out == keys;
+    // first level: classify instances on the host
+    c->host_segs.clear();
+    c->host_jobs.clear();
+    for (uint64_t i = 0; i < ninst; ++i) {
+        const uint32_t st = (uint32_t)offs[i];
+        const uint32_t len = (uint32_t)(offs[i + 1] - offs[i]);
+        if (len >= p.alpha) {
+            Seg s{};
+            s.start = st;
+            s.len = len;
+            s.ibase = st;
+            s.nl_bits = (uint16_t)std::min(p.nl0, choose_nl(len, p.alpha, kLightBitsMax, 0));
+            s.shift = 0;
+            c->host_segs.push_back(s);
+        } else if (len >= 2) {
+            c->host_jobs.push_back(Job{st, len});
+        } else if (len == 1 && !inplace) {
+            c->host_jobs.push_back(Job{st, 1u | kJobCopy});
+        }
+    }
+    ss_status s;
+    uint32_t nsegs = (uint32_t)c->host_segs.size();
+    uint32_t tiles = 0, chunks = 0, tile = p.tmin;
+    if (nsegs) {
+        host_prefix(c->host_segs, p, &tiles, &chunks, &tile);
+        if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->t_vals, n * sizeof(V))) != SS_OK) return s;
+    }
+    if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
+    uint32_t seg_cap = std::max<uint32_t>(nsegs, 1024);
+    if ((s = ensure(c, c->segs[0], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
+    if ((s = ensure(c, c->segs[1], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
+    seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
+    const uint32_t nj0 = (uint32_t)c->host_jobs.size();
+    if ((s = ensure(c, c->jobs, (size_t)std::max<uint32_t>(nj0, 4096) * sizeof(Job))) != SS_OK) return s;
+
+    if (nj0) {
+        if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, nj0 * sizeof(Job))) != SS_OK) return s;
+        memcpy(c->job_stage, c->host_jobs.data(), nj0 * sizeof(Job));
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->jobs.p, c->job_stage, nj0 * sizeof(Job), hipMemcpyHostToDevice, c->stream));
+        launch_finish<V>(c, p.mode, nj0, keys, vals, keys_out, vals_out);
+        HIP_OR_FAIL(c, hipGetLastError());
+    }
+    if (!nsegs) return SS_OK;
+    if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, nsegs * sizeof(Seg))) != SS_OK) return s;
+    memcpy(c->seg_stage, c->host_segs.data(), nsegs * sizeof(Seg));
+    int cur = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, c->seg_stage, nsegs * sizeof(Seg), hipMemcpyHostToDevice, c->stream));
+
+    const uint64_t* loc_k = keys;
+    const void* loc_v = vals;
+    uint64_t* T_k = (uint64_t*)c->t_keys.p;
+    void* T_v = c->t_vals.p;
+    for (uint32_t level = 0; nsegs; ++level) {
+        uint64_t* dst_k;
+        void* dst_v;
+        if (level == 0) {
+            dst_k = inplace ? T_k : keys_out;
+            dst_v = inplace ? T_v : vals_out;
+        } else {
+            const bool at_out = loc_k == keys_out;
+            dst_k = at_out ? T_k : keys_out;
+            dst_v = at_out ? T_v : vals_out;
+        }
+        if ((s = ensure_level(c, nsegs, tiles, chunks)) != SS_OK) return s;
+        HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v);
+        launch_level_v<V>(c, p.mode, a, tiles, chunks);
+        HIP_OR_FAIL(c, hipGetLastError());
+
+        // plan the next level; grow the lists and plan again if they overflow
+        for (int attempt = 0;; ++attempt) {
+            if (attempt) HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, 2 * sizeof(uint32_t), c->stream));
+            PlanArgs pa;
+            pa.segs = (const Seg*)c->segs[cur].p;
+            pa.nsegs = nsegs;
+            pa.bstart = (const uint32_t*)c->bstart.p;
+            pa.next = (Seg*)c->segs[cur ^ 1].p;
+            pa.next_cap = seg_cap;
+            pa.jobs = (Job*)c->jobs.p;
+            pa.job_cap = (uint32_t)(c->jobs.cap / sizeof(Job));
+            pa.info = (LevelInfo*)c->info.p;
+            pa.alpha = p.alpha;
+            pa.dst_is_out = dst_k == keys_out;
+            hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
+            hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, seg_cap,
+                               (LevelInfo*)c->info.p, p.tmin, p.tmax);
+            HIP_OR_FAIL(c, hipGetLastError());
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+            const LevelInfo li = *c->info_host;
+            if (li.status) return fail(c, SS_EDEVICE, "device status " + std::to_string(li.status) + " at level " + std::to_string(level));
+            bool again = false;
+            if (li.nsegs > seg_cap) {
+                // the current list must survive: copy it aside while both lists grow
+                DevBuf keep;
+                if ((s = ensure(c, keep, (size_t)nsegs * sizeof(Seg))) != SS_OK) return s;
+                HIP_OR_FAIL(c, hipMemcpyAsync(keep.p, c->segs[cur].p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
+                if ((s = ensure(c, c->segs[0], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
+                if ((s = ensure(c, c->segs[1], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
+                HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, keep.p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
+                HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+                HIP_OR_FAIL(c, hipFree(keep.p));
+                seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
+                again = true;
+            }
+            if (li.njobs > c->jobs.cap / sizeof(Job)) {
+                if ((s = ensure(c, c->jobs, (size_t)li.njobs * sizeof(Job))) != SS_OK) return s;
+                again = true;
+            }
+            if (again) continue;
+            if (li.njobs) {
+                launch_finish<V>(c, p.mode, li.njobs, dst_k, dst_v, keys_out, vals_out);
+                HIP_OR_FAIL(c, hipGetLastError());
+            }
+            nsegs = li.nsegs;
+            tiles = li.tiles;
+            chunks = li.chunks;
+            tile = li.tile;
+            break;
+        }
+        loc_k = dst_k;
+        loc_v = dst_v;
+        cur ^= 1;
+    }
+    return SS_OK;
+}
+
+ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t vb, uint64_t n,
+                       const void* ko, const void* vo, bool allow_inplace)
+{
+    if (!c) return SS_EINVAL;
+    if (vb != 4 && vb != 8) return fail(c, SS_EINVAL, "val_bytes must be 4 or 8");
+    if (n >= (1ull << 32)) return fail(c, SS_EINVAL, "n must be below 2^32");
+    if (n == 0) return SS_OK;
+    if (!keys || !vals || !ko || !vo) return fail(c, SS_EINVAL, "null array pointer");
+    const bool inplace = ko == keys && vo == vals;
+    if (inplace && !allow_inplace) return fail(c, SS_EINVAL, "in-place is not allowed here");
+    if (!inplace) {
+        if (ko == keys || vo == vals) return fail(c, SS_EINVAL, "in-place needs keys_out == keys and vals_out == vals");
+        if (overlaps(ko, n * 8, keys, n * 8) || overlaps(ko, n * 8, vals, n * vb) ||
+            overlaps(vo, n * vb, keys, n * 8) || overlaps(vo, n * vb, vals, n * vb))
+            return fail(c, SS_EINVAL, "outputs overlap inputs");
+    }
+    if (overlaps(ko, n * 8, vo, n * vb)) return fail(c, SS_EINVAL, "keys_out overlaps vals_out");
+    return SS_OK;
+}
+
+}  // namespace
+
+// ==================================================================== C-ABI
+
+extern "C" {
+
+ss_status ss_default_params(ss_params* p)
+{
+    if (!p) return SS_EINVAL;
+    p->n_light_log2 = 10;
+    p->base_case = kAlphaMax;
+    p->sample_mult = 500;
+    p->tile_min = 8192;
+    p->tile_max = 65536;
+    p->hash_mode = SS_HASH_MIX64;
+    p->seed = 0x5eed5eed2023ULL;
+    return SS_OK;
+}
+
+ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
+{
+    if (!out) return SS_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SS_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return SS_EHIP;
+    ss_ctx* c = new (std::nothrow) ss_ctx();
+    if (!c) return SS_ENOMEM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipHostMalloc((void**)&c->info_host, sizeof(LevelInfo), hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return SS_EHIP;
+    }
+    *out = c;
+    return SS_OK;
+}
+
+ss_status ss_destroy(ss_ctx* c)
+{
+    if (!c) return SS_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
+                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info};
+    for (DevBuf* b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->info_host) (void)hipHostFree(c->info_host);
+    if (c->seg_stage) (void)hipHostFree(c->seg_stage);
+    if (c->job_stage) (void)hipHostFree(c->job_stage);
+    delete c;
+    return SS_OK;
+}
+
+ss_status ss_set_stream(ss_ctx* c, void* hip_stream)
+{
+    if (!c) return SS_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return SS_OK;
+}
+
+const char* ss_last_error(ss_ctx* c)
+{
+    return c ? c->err.c_str() : "null context";
+}
+
+ss_status ss_sync(ss_ctx* c)
+{
+    if (!c) return SS_EINVAL;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return SS_OK;
+}
+
+ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
+{
+    if (!c || !bytes) return SS_EINVAL;
+    const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
+                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info};
+    size_t t = 0;
+    for (const DevBuf* b : bufs) t += b->cap;
+    *bytes = t;
+    return SS_OK;
+}
+
+ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
+                            uint64_t* keys_out, void* vals_out, const ss_params* params)
+{
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    const uint64_t offs[2] = {0, n};
+    return vb == 8 ? run_semisort_equal<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
+                   : run_semisort_equal<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
+}
+
+ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                  const uint64_t* offs, uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                  const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (!offs) return fail(c, SS_EINVAL, "null seg_offsets");
+    if (nseg == 0) return SS_OK;
+    if (offs[0] != 0) return fail(c, SS_EINVAL, "seg_offsets[0] must be 0");
+    for (uint64_t i = 0; i < nseg; ++i)
+        if (offs[i + 1] < offs[i]) return fail(c, SS_EINVAL, "seg_offsets must be non-decreasing");
+    const uint64_t n = offs[nseg];
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    return vb == 8 ? run_semisort_equal<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
+                   : run_semisort_equal<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+}
+
+ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
+                             uint64_t* keys_out, void* vals_out, uint64_t* offsets_out,
+                             uint64_t* heavy_out, uint32_t* n_heavy_out, const ss_params* params)
+{
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, false);
+    if (s != SS_OK) return s;
+    if (!offsets_out || !heavy_out || !n_heavy_out) return fail(c, SS_EINVAL, "null output pointer");
+    if (n == 0) return fail(c, SS_EINVAL, "partition needs n >= 1");
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    std::vector<Seg> segs(1);
+    segs[0] = Seg{};
+    segs[0].start = 0;
+    segs[0].len = (uint32_t)n;
+    segs[0].ibase = 0;
+    segs[0].nl_bits = (uint16_t)p.nl0;
+    segs[0].shift = 0;
+    uint32_t tiles, chunks, tile;
+    host_prefix(segs, p, &tiles, &chunks, &tile);
+    if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
+    if ((s = ensure(c, c->segs[0], sizeof(Seg))) != SS_OK) return s;
+    if ((s = ensure_level(c, 1, tiles, chunks)) != SS_OK) return s;
+    if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, sizeof(Seg))) != SS_OK) return s;
+    memcpy(c->seg_stage, segs.data(), sizeof(Seg));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[0].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+    LevelArgs a = make_args(c, p, 0, (Seg*)c->segs[0].p, 1, tile, keys, vals, keys_out, vals_out);
+    if (vb == 8) launch_level_v<uint64_t>(c, p.mode, a, tiles, chunks);
+    else launch_level_v<uint32_t>(c, p.mode, a, tiles, chunks);
+    hipLaunchKernelGGL(k_export_partition, dim3(1), dim3(1024), 0, c->stream, (const uint32_t*)c->bstart.p,
+                       (const Seg*)c->segs[0].p, (const uint64_t*)c->heavy_list.p, offsets_out, heavy_out);
+    HIP_OR_FAIL(c, hipGetLastError());
+    Seg back;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->seg_stage, c->segs[0].p, sizeof(Seg), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    memcpy(&back, c->seg_stage, sizeof(Seg));
+    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    *n_heavy_out = back.nheavy;
+    return SS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,201 @@
+"""Python binding of libsemisort_hip.so (C-ABI in include/semisort.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Arrays are torch tensors on the GPU; uint64 keys and values travel
+as int64 tensors holding the same bit patterns (uint32 values as int32).
+Work is issued on torch's current HIP stream.  If the library is not built,
+importing the functions raises immediately -- there is no fallback.
+"""
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsemisort_hip.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "semisort.h")
+
+SS_OK, SS_EINVAL, SS_ENOMEM, SS_EHIP, SS_EDEVICE = 0, -1, -2, -3, -4
+HASH_MIX64, HASH_IDENTITY = 0, 1
+HEAVY_MAX = 512
+LIGHT_BITS_MAX = 10
+
+_STATUS = {SS_EINVAL: "SS_EINVAL", SS_ENOMEM: "SS_ENOMEM", SS_EHIP: "SS_EHIP", SS_EDEVICE: "SS_EDEVICE"}
+
+
+class SemisortError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class ss_params(ctypes.Structure):
+    _fields_ = [
+        ("n_light_log2", ctypes.c_uint32),
+        ("base_case", ctypes.c_uint32),
+        ("sample_mult", ctypes.c_uint32),
+        ("tile_min", ctypes.c_uint32),
+        ("tile_max", ctypes.c_uint32),
+        ("hash_mode", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+_lib = None
+
+
+def declared_symbols():
+    """Entry points declared in include/semisort.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:ss_status|const char\*)\s+(ss_\w+)\s*\(", txt, re.M)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(the GPU path has no fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        P = ctypes.POINTER(ss_params)
+        L.ss_default_params.argtypes = [P]
+        L.ss_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+        L.ss_destroy.argtypes = [vp]
+        L.ss_set_stream.argtypes = [vp, vp]
+        L.ss_last_error.argtypes = [vp]
+        L.ss_last_error.restype = ctypes.c_char_p
+        L.ss_sync.argtypes = [vp]
+        L.ss_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ss_semisort_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
+        L.ss_semisort_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
+        L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
+        for name in declared_symbols():
+            if name != "ss_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def default_params(**kw):
+    p = ss_params()
+    lib().ss_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "hash_mode" and isinstance(v, str):
+            v = {"mix64": HASH_MIX64, "identity": HASH_IDENTITY}[v]
+        setattr(p, k, v)
+    return p
+
+
+class Context:
+    """One library context (ss_ctx) on a device; reuses its workspace across calls."""
+
+    def __init__(self, device=0):
+        import torch
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib().ss_create(device, ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream), ctypes.byref(h))
+        if st != SS_OK:
+            raise SemisortError(st, "ss_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ss_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        import torch
+        lib().ss_set_stream(self.h, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def check(self, st):
+        if st != SS_OK:
+            raise SemisortError(st, lib().ss_last_error(self.h).decode())
+
+    def workspace_bytes(self):
+        b = ctypes.c_size_t()
+        self.check(lib().ss_workspace_bytes(self.h, ctypes.byref(b)))
+        return b.value
+
+
+_ctx = {}
+
+
+def context(device=0):
+    if device not in _ctx:
+        _ctx[device] = Context(device)
+    return _ctx[device]
+
+
+def _check_kv(keys, vals):
+    import torch
+    if not (keys.is_cuda and vals.is_cuda):
+        raise ValueError("keys and vals must be device tensors")
+    if keys.dtype != torch.int64 or vals.dtype not in (torch.int64, torch.int32):
+        raise ValueError("keys must be int64 (uint64 bits), vals int64 or int32 (uint bits)")
+    if keys.dim() != 1 or vals.shape != keys.shape or not keys.is_contiguous() or not vals.is_contiguous():
+        raise ValueError("keys and vals must be contiguous 1-D tensors of equal length")
+    return vals.element_size()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def semisort_equal(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
+    """ss_semisort_equal: equal keys contiguous, stable.  Returns (keys_out, vals_out)."""
+    import torch
+    vb = _check_kv(keys, vals)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    ctx.check(lib().ss_semisort_equal(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out),
+                                      _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def semisort_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, params=None, ctx=None):
+    """ss_semisort_equal_batch: independent instances packed back to back.
+    seg_offsets: host sequence of nseg+1 boundaries."""
+    import numpy as np
+    import torch
+    vb = _check_kv(keys, vals)
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.uint64))
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    ctx.check(lib().ss_semisort_equal_batch(ctx.h, _ptr(keys), _ptr(vals), vb,
+                                            ctypes.c_void_p(offs.ctypes.data), offs.size - 1, _ptr(keys_out),
+                                            _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def partition_equal(keys, vals, params=None, ctx=None):
+    """ss_partition_equal: one level of Steps 1-2.  Returns (T_keys, T_vals, offsets, heavy_hashes)."""
+    import torch
+    vb = _check_kv(keys, vals)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if params is None:
+        params = default_params()
+    tk = torch.empty_like(keys)
+    tv = torch.empty_like(vals)
+    nb_cap = (1 << params.n_light_log2) + HEAVY_MAX + 1
+    off = torch.zeros(nb_cap, dtype=torch.int64, device=keys.device)
+    hv = torch.zeros(HEAVY_MAX, dtype=torch.int64, device=keys.device)
+    nh = ctypes.c_uint32()
+    ctx.check(lib().ss_partition_equal(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(tk), _ptr(tv),
+                                       _ptr(off), _ptr(hv), ctypes.byref(nh), ctypes.byref(params)))
+    nb = (1 << params.n_light_log2) + nh.value
+    return tk, tv, off[:nb + 1], hv[:nh.value]

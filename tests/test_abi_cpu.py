@@ -1,0 +1,50 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports every
+entry point include/semisort.h declares, and its argument checks refuse bad
+calls before touching a device."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2304_10078_amd import semisort as S
+
+
+def _lib_or_skip():
+    if not os.path.exists(S.LIB_PATH):
+        pytest.skip("libsemisort_hip.so not built")
+    return S.lib()
+
+
+def test_header_declares_the_boundary():
+    names = S.declared_symbols()
+    for want in ["ss_create", "ss_destroy", "ss_semisort_equal", "ss_semisort_equal_batch",
+                 "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync"]:
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    missing = [n for n in S.declared_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_default_params():
+    _lib_or_skip()
+    p = S.default_params()
+    assert (p.n_light_log2, p.base_case, p.sample_mult) == (10, 4096, 500)
+    assert p.tile_min == 8192 and p.tile_max == 65536 and p.hash_mode == S.HASH_MIX64
+
+
+def test_null_context_is_rejected():
+    L = _lib_or_skip()
+    assert L.ss_semisort_equal(None, None, None, 8, 10, None, None, None) == S.SS_EINVAL
+    assert L.ss_destroy(None) == S.SS_EINVAL
+    assert L.ss_sync(None) == S.SS_EINVAL
+    assert L.ss_last_error(None) == b"null context"
+
+
+def test_create_without_a_device_fails_cleanly():
+    L = _lib_or_skip()
+    h = ctypes.c_void_p()
+    st = L.ss_create(999, None, ctypes.byref(h))
+    assert st == S.SS_EINVAL and not h.value
