@@ -21,8 +21,8 @@
  *   HIP call, SS_EDEVICE for a condition detected on the device.
  *   ss_last_error() returns a message for the last failure on the context.
  *   Nothing throws across the ABI.
- * - n = 0 is a no-op returning SS_OK.  n must be below 2^32 (positions are
- *   32-bit on the device).
+ * - n = 0 is a no-op returning SS_OK.  n must be below 2^31 (positions are
+ *   31-bit on the device).
  * - Output arrays must not overlap the inputs, except that keys_out == keys
  *   together with vals_out == vals is allowed for semisort (the paper's
  *   in-place form, Section 3.4).
@@ -79,6 +79,37 @@ const char* ss_last_error(ss_ctx* ctx);
 ss_status ss_sync(ss_ctx* ctx);
 /* Bytes of workspace currently held by the context. */
 ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
+
+/* Engine options (tuning knobs that are not part of ss_params).
+ * SS_OPT_DIST_VARIANT selects the shape of the distribution kernel:
+ *   0: 16 waves per block, 8192-record sub-tiles (default)
+ *   1: 8 waves per block, 4096-record sub-tiles (two blocks per CU)
+ *   2: as 0, with non-temporal (streaming) stores for the scattered writes
+ * Every variant gives the same result. */
+enum { SS_OPT_DIST_VARIANT = 1 };
+ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
+
+/* Kernel timing.  While enabled, every kernel launch of the engine is
+ * bracketed by HIP events on the context's stream, grouped by pass:
+ * SS_PROF_SAMPLE (Step 1; units = subproblems), SS_PROF_COUNT (counting pass;
+ * units = records read), SS_PROF_SCAN (column-major prefix, four kernels;
+ * units = subarrays), SS_PROF_DISTRIBUTE (distribution; units = records
+ * moved), SS_PROF_PLAN (next-level planning; units = subproblems) and
+ * SS_PROF_FINISH (base cases and copies; units = records).  ss_profile_enable
+ * resets the totals; ss_profile_read waits for the stream and returns the
+ * total milliseconds, launch count and units of one pass. */
+enum {
+    SS_PROF_SAMPLE = 0,
+    SS_PROF_COUNT = 1,
+    SS_PROF_SCAN = 2,
+    SS_PROF_DISTRIBUTE = 3,
+    SS_PROF_PLAN = 4,
+    SS_PROF_FINISH = 5,
+    SS_PROF_KINDS = 6
+};
+ss_status ss_profile_enable(ss_ctx* ctx, int on);
+ss_status ss_profile_read(ss_ctx* ctx, int kind, double* total_ms, uint64_t* launches,
+                          uint64_t* units);
 
 /* semisort_= (Section 2.1; Algorithm 1 with the hash-table base case of
  * Section 3.3): reorders the n records so that equal keys are contiguous and

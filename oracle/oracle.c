@@ -273,8 +273,13 @@ int orc_stats(const uint64_t* keys, uint64_t n, double heavy_threshold,
 
 uint32_t orc_sample_size(uint64_t len, uint32_t c)
 {
+    /* ceil(c ln n'), capped at n'/8 so that small subproblems are not sampled
+     * almost entirely, and at 16384 */
     if (len < 2) return 0;
-    return (uint32_t)ceil((double)c * log((double)len));
+    uint64_t s = (uint64_t)ceil((double)c * log((double)len));
+    if (s > len / 8) s = len / 8;
+    if (s > 16384) s = 16384;
+    return (uint32_t)s;
 }
 
 uint32_t orc_heavy_threshold(uint64_t len)

@@ -74,8 +74,9 @@ int orc_stats(const uint64_t* keys, uint64_t n, double heavy_threshold,
 
 /* ---- one level of Algorithm 1, step by step ---------------------------- */
 
-/* Step 1 sample size |S| = ceil(c * ln n') and heavy threshold ceil(ln n')
- * (Algorithm 1 and Section 3.6, natural logarithm). */
+/* Step 1 sample size |S| = ceil(c * ln n') (Algorithm 1 and Section 3.6,
+ * natural logarithm), capped at n'/8 and at 16384, and heavy threshold
+ * ceil(ln n'). */
 uint32_t orc_sample_size(uint64_t len, uint32_t c);
 uint32_t orc_heavy_threshold(uint64_t len);
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -37,15 +38,29 @@ struct ss_ctx {
     DevBuf t_keys, t_vals;
     DevBuf segs[2];
     DevBuf jobs;
-    DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id;
+    DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink;
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     std::vector<Seg> host_segs;
-    std::vector<Job> host_jobs;
+    std::vector<Job> host_jobs[kJobClasses];
+    uint32_t job_cap = 0;  // entries per class list
     Seg* seg_stage = nullptr;        // pinned staging for the first level
     size_t seg_stage_cap = 0;
     Job* job_stage = nullptr;
     size_t job_stage_cap = 0;
+    int dist_variant = 0;  // distribution kernel shape (ss_set_option)
+    // kernel timing with HIP events on the context's stream (ss_profile_*)
+    bool prof_on = false;
+    struct Pending {
+        hipEvent_t a, b;
+        int kind;
+        uint64_t units;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double prof_ms[SS_PROF_KINDS] = {};
+    uint64_t prof_launches[SS_PROF_KINDS] = {};
+    uint64_t prof_units[SS_PROF_KINDS] = {};
 };
 
 namespace {
@@ -99,6 +114,70 @@ ss_status ensure_pinned(ss_ctx* c, void** p, size_t* cap, size_t bytes)
     return SS_OK;
 }
 
+hipEvent_t take_event(ss_ctx* c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+    ss_ctx* c;
+    ss_ctx::Pending p;
+    bool on;
+    ProfScope(ss_ctx* ctx, int kind, uint64_t units) : c(ctx), on(ctx->prof_on)
+    {
+        if (!on) return;
+        p.kind = kind;
+        p.units = units;
+        p.a = take_event(c);
+        p.b = take_event(c);
+        if (!p.a || !p.b) {
+            on = false;
+            return;
+        }
+        (void)hipEventRecord(p.a, c->stream);
+    }
+    ~ProfScope()
+    {
+        if (!on) return;
+        (void)hipEventRecord(p.b, c->stream);
+        c->pending.push_back(p);
+    }
+};
+
+ss_status resolve_profile(ss_ctx* c)
+{
+    if (c->pending.empty()) return SS_OK;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        HIP_OR_FAIL(c, hipEventElapsedTime(&ms, p.a, p.b));
+        c->prof_ms[p.kind] += ms;
+        c->prof_launches[p.kind] += 1;
+        c->prof_units[p.kind] += p.units;
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    c->pending.clear();
+    return SS_OK;
+}
+
+// Clears the per-level counters of the device LevelInfo, keeping the sticky status word.
+ss_status reset_counters(ss_ctx* c)
+{
+    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, (1 + kJobClasses) * sizeof(uint32_t), c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync((char*)c->info.p + offsetof(LevelInfo, records), 0,
+                                  2 * sizeof(unsigned long long), c->stream));
+    return SS_OK;
+}
+
 struct Params {
     uint32_t nl0, alpha, c, tmin, tmax, mode;
     uint64_t seed;
@@ -135,35 +214,89 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
 
 // ---------------------------------------------------------------- launches
 
-template <typename V>
-void launch_finish(ss_ctx* c, uint32_t mode, uint32_t njobs, const uint64_t* sk, const void* sv,
+// Base-case and copy jobs of one level: one launch per non-empty class.
+// jobs holds kJobClasses lists of `cap` entries.
+template <int MODE, typename V>
+void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
                    uint64_t* ok, void* ov)
 {
     const Job* jobs = (const Job*)c->jobs.p;
     LevelInfo* info = (LevelInfo*)c->info.p;
-    if (mode == 1)
-        hipLaunchKernelGGL((k_finish<1, V>), dim3(njobs), dim3(512), 0, c->stream, jobs, sk, (const V*)sv, ok, (V*)ov, info);
-    else
-        hipLaunchKernelGGL((k_finish<0, V>), dim3(njobs), dim3(512), 0, c->stream, jobs, sk, (const V*)sv, ok, (V*)ov, info);
-}
-
-template <int MODE, typename V>
-void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks)
-{
-    hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan_buckets, dim3(a.nsegs * kBucketGroups), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan_offsets, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan_fill, dim3(chunks), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL((k_distribute<MODE, V, 16, 8>), dim3(tiles), dim3(1024), 0, c->stream, a);
+    const V* svv = (const V*)sv;
+    V* ovv = (V*)ov;
+    if (njobs[0])
+        hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv, info);
+    if (njobs[1])
+        hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, jobs + cap, sk, svv, ok,
+                           ovv, info);
+    if (njobs[2])
+        hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, jobs + 2 * (size_t)cap, sk,
+                           svv, ok, ovv, info);
+    if (njobs[3])
+        hipLaunchKernelGGL((k_base_2pass<MODE, V>), dim3(njobs[3]), dim3(512), 0, c->stream, jobs + 3 * (size_t)cap,
+                           sk, svv, ok, ovv, info);
+    if (njobs[kCopyClass])
+        hipLaunchKernelGGL((k_copy<V>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
+                           jobs + (size_t)kCopyClass * cap, sk, svv, ok, ovv);
 }
 
 template <typename V>
-void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks)
+void launch_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
+                 uint64_t* ok, void* ov, uint64_t records)
 {
-    if (mode == 1) launch_level<1, V>(c, a, tiles, chunks);
-    else launch_level<0, V>(c, a, tiles, chunks);
+    ProfScope ps(c, SS_PROF_FINISH, records);
+    if (mode == 1) launch_jobs_m<1, V>(c, njobs, cap, sk, sv, ok, ov);
+    else launch_jobs_m<0, V>(c, njobs, cap, sk, sv, ok, ov);
+}
+
+template <int MODE, typename V>
+void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks, uint64_t records)
+{
+    {
+        ProfScope ps(c, SS_PROF_SAMPLE, a.nsegs);
+        hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_COUNT, records);
+        hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_SCAN, tiles);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_buckets, dim3(a.nsegs * kBucketGroups), dim3(1024), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_offsets, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_fill, dim3(chunks), dim3(256), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
+        switch (c->dist_variant) {
+        case 1:
+            hipLaunchKernelGGL((k_distribute<V, 8, 8>), dim3(tiles), dim3(512), 0, c->stream, a);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 4>), dim3(tiles), dim3(512), 0, c->stream, a);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 6>), dim3(tiles), dim3(512), 0, c->stream, a);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_distribute_direct<V, 16, 8, 4>), dim3(tiles), dim3(1024), 0, c->stream, a);
+            break;
+        case 5:
+            hipLaunchKernelGGL((k_distribute_direct<V, 4, 16, 6>), dim3(tiles), dim3(256), 0, c->stream, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k_distribute<V, 16, 8>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        }
+    }
+}
+
+template <typename V>
+void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks,
+                    uint64_t records)
+{
+    if (mode == 1) launch_level<1, V>(c, a, tiles, chunks, records);
+    else launch_level<0, V>(c, a, tiles, chunks, records);
 }
 
 // Sizes a level needs: per-subproblem tables, counting matrix rows, chunk rows.
@@ -175,19 +308,23 @@ ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunk
     if ((s = ensure(c, c->tot, (size_t)nsegs * kNbStride * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->bstart, (size_t)nsegs * (kNbStride + 1) * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->heavy_list, (size_t)nsegs * kHeavyMax * 8)) != SS_OK) return s;
-    if ((s = ensure(c, c->tab_h, (size_t)nsegs * kHeavySlotsMax * 8)) != SS_OK) return s;
-    if ((s = ensure(c, c->tab_id, (size_t)nsegs * kHeavySlotsMax * 2)) != SS_OK) return s;
+    if ((s = ensure(c, c->tab_h, (size_t)nsegs * 2 * kHeavySlotsMax * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->tab_id, (size_t)nsegs * 2 * kHeavySlotsMax * 2)) != SS_OK) return s;
     return SS_OK;
 }
 
 LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint32_t nsegs, uint32_t tile,
-                    const uint64_t* sk, const void* sv, uint64_t* dk, void* dv)
+                    const uint64_t* sk, const void* sv, uint64_t* dk, void* dv, uint64_t* fk, void* fv)
 {
     LevelArgs a;
     a.src_keys = sk;
     a.src_vals = sv;
     a.dst_keys = dk;
     a.dst_vals = dv;
+    a.fin_keys = fk;
+    a.fin_vals = fv;
+    a.bids = (uint16_t*)c->bids.p;
+    a.sink = (uint64_t*)c->sink.p;
     a.segs = segs;
     a.nsegs = nsegs;
     a.tile = tile;
@@ -202,6 +339,8 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.seed = p.seed;
     a.level = level;
     a.sample_mult = p.c;
+    a.alpha = p.alpha;
+    a.adaptive_nl = 1;
     return a;
 }
 
@@ -232,7 +371,8 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     const bool inplace = keys_out == keys;
     // first level: classify instances on the host
     c->host_segs.clear();
-    c->host_jobs.clear();
+    for (auto& v : c->host_jobs) v.clear();
+    uint64_t jrec = 0;
     for (uint64_t i = 0; i < ninst; ++i) {
         const uint32_t st = (uint32_t)offs[i];
         const uint32_t len = (uint32_t)(offs[i + 1] - offs[i]);
@@ -245,35 +385,69 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
             s.shift = 0;
             c->host_segs.push_back(s);
         } else if (len >= 2) {
-            c->host_jobs.push_back(Job{st, len});
+            c->host_jobs[base_class(len)].push_back(Job{st, len});
+            jrec += len;
         } else if (len == 1 && !inplace) {
-            c->host_jobs.push_back(Job{st, 1u | kJobCopy});
+            c->host_jobs[kCopyClass].push_back(Job{st, 1u});
+            jrec += 1;
         }
     }
     ss_status s;
     uint32_t nsegs = (uint32_t)c->host_segs.size();
     uint32_t tiles = 0, chunks = 0, tile = p.tmin;
+    uint64_t records = 0;
+    for (const Seg& sg : c->host_segs) records += sg.len;
     if (nsegs) {
         host_prefix(c->host_segs, p, &tiles, &chunks, &tile);
         if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
         if ((s = ensure(c, c->t_vals, n * sizeof(V))) != SS_OK) return s;
+        if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     }
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
     uint32_t seg_cap = std::max<uint32_t>(nsegs, 1024);
     if ((s = ensure(c, c->segs[0], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
     if ((s = ensure(c, c->segs[1], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
     seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
-    const uint32_t nj0 = (uint32_t)c->host_jobs.size();
-    if ((s = ensure(c, c->jobs, (size_t)std::max<uint32_t>(nj0, 4096) * sizeof(Job))) != SS_OK) return s;
+    uint32_t nj0[kJobClasses], nj0_max = 0, nj0_tot = 0;
+    for (int k = 0; k < kJobClasses; ++k) {
+        nj0[k] = (uint32_t)c->host_jobs[k].size();
+        nj0_max = std::max(nj0_max, nj0[k]);
+        nj0_tot += nj0[k];
+    }
+    auto ensure_jobs = [&](uint32_t per_class) -> ss_status {
+        if (per_class <= c->job_cap) return SS_OK;
+        uint32_t want = std::max<uint32_t>(per_class, std::max<uint32_t>(4096, c->job_cap + c->job_cap / 2));
+        ss_status r = ensure(c, c->jobs, (size_t)want * kJobClasses * sizeof(Job));
+        if (r == SS_OK) c->job_cap = want;
+        return r;
+    };
+    if ((s = ensure_jobs(std::max<uint32_t>(nj0_max, 4096))) != SS_OK) return s;
 
-    if (nj0) {
-        if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, nj0 * sizeof(Job))) != SS_OK) return s;
-        memcpy(c->job_stage, c->host_jobs.data(), nj0 * sizeof(Job));
-        HIP_OR_FAIL(c, hipMemcpyAsync(c->jobs.p, c->job_stage, nj0 * sizeof(Job), hipMemcpyHostToDevice, c->stream));
-        launch_finish<V>(c, p.mode, nj0, keys, vals, keys_out, vals_out);
+    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+    if (nj0_tot) {
+        if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, (size_t)nj0_tot * sizeof(Job))) != SS_OK)
+            return s;
+        size_t o = 0;
+        for (int k = 0; k < kJobClasses; ++k) {
+            if (!nj0[k]) continue;
+            memcpy(c->job_stage + o, c->host_jobs[k].data(), nj0[k] * sizeof(Job));
+            HIP_OR_FAIL(c, hipMemcpyAsync((Job*)c->jobs.p + (size_t)k * c->job_cap, c->job_stage + o,
+                                          nj0[k] * sizeof(Job), hipMemcpyHostToDevice, c->stream));
+            o += nj0[k];
+        }
+        launch_jobs<V>(c, p.mode, nj0, c->job_cap, keys, vals, keys_out, vals_out, jrec);
         HIP_OR_FAIL(c, hipGetLastError());
     }
-    if (!nsegs) return SS_OK;
+    if (!nsegs) {
+        if (nj0_tot) {
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+            if (c->info_host->status)
+                return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+        }
+        return SS_OK;
+    }
     if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, nsegs * sizeof(Seg))) != SS_OK) return s;
     memcpy(c->seg_stage, c->host_segs.data(), nsegs * sizeof(Seg));
     int cur = 0;
@@ -284,25 +458,35 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     uint64_t* T_k = (uint64_t*)c->t_keys.p;
     void* T_v = c->t_vals.p;
     for (uint32_t level = 0; nsegs; ++level) {
+        // Where this level writes: buckets that need more work go to the buffer
+        // that is not the source; final buckets go straight to the output
+        // unless the output is the source (other blocks still read it).
         uint64_t* dst_k;
         void* dst_v;
-        if (level == 0) {
-            dst_k = inplace ? T_k : keys_out;
-            dst_v = inplace ? T_v : vals_out;
-        } else {
-            const bool at_out = loc_k == keys_out;
-            dst_k = at_out ? T_k : keys_out;
-            dst_v = at_out ? T_v : vals_out;
+        uint64_t* fin_k;
+        void* fin_v;
+        if (loc_k == keys_out) {
+            dst_k = fin_k = T_k;
+            dst_v = fin_v = T_v;
+        } else if (loc_k == T_k) {
+            dst_k = fin_k = keys_out;
+            dst_v = fin_v = vals_out;
+        } else {  // the caller's input, distinct from the output
+            dst_k = T_k;
+            dst_v = T_v;
+            fin_k = keys_out;
+            fin_v = vals_out;
         }
         if ((s = ensure_level(c, nsegs, tiles, chunks)) != SS_OK) return s;
-        HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
-        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v);
-        launch_level_v<V>(c, p.mode, a, tiles, chunks);
+        if ((s = reset_counters(c)) != SS_OK) return s;
+        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, fin_k,
+                                fin_v);
+        launch_level_v<V>(c, p.mode, a, tiles, chunks, records);
         HIP_OR_FAIL(c, hipGetLastError());
 
         // plan the next level; grow the lists and plan again if they overflow
         for (int attempt = 0;; ++attempt) {
-            if (attempt) HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, 2 * sizeof(uint32_t), c->stream));
+            if (attempt && (s = reset_counters(c)) != SS_OK) return s;
             PlanArgs pa;
             pa.segs = (const Seg*)c->segs[cur].p;
             pa.nsegs = nsegs;
@@ -310,13 +494,16 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
             pa.next = (Seg*)c->segs[cur ^ 1].p;
             pa.next_cap = seg_cap;
             pa.jobs = (Job*)c->jobs.p;
-            pa.job_cap = (uint32_t)(c->jobs.cap / sizeof(Job));
+            pa.job_cap = c->job_cap;
             pa.info = (LevelInfo*)c->info.p;
             pa.alpha = p.alpha;
-            pa.dst_is_out = dst_k == keys_out;
-            hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
-            hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, seg_cap,
-                               (LevelInfo*)c->info.p, p.tmin, p.tmax);
+            pa.finals_in_out = fin_k == keys_out;
+            {
+                ProfScope ps(c, SS_PROF_PLAN, nsegs);
+                hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
+                hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p,
+                                   seg_cap, (LevelInfo*)c->info.p, p.tmin, p.tmax);
+            }
             HIP_OR_FAIL(c, hipGetLastError());
             HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
             HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
@@ -336,16 +523,17 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
                 seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
                 again = true;
             }
-            if (li.njobs > c->jobs.cap / sizeof(Job)) {
-                if ((s = ensure(c, c->jobs, (size_t)li.njobs * sizeof(Job))) != SS_OK) return s;
+            uint32_t jmax = 0;
+            for (int k = 0; k < kJobClasses; ++k) jmax = std::max(jmax, li.njobs[k]);
+            if (jmax > c->job_cap) {
+                if ((s = ensure_jobs(jmax)) != SS_OK) return s;
                 again = true;
             }
             if (again) continue;
-            if (li.njobs) {
-                launch_finish<V>(c, p.mode, li.njobs, dst_k, dst_v, keys_out, vals_out);
-                HIP_OR_FAIL(c, hipGetLastError());
-            }
+            launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
+            HIP_OR_FAIL(c, hipGetLastError());
             nsegs = li.nsegs;
+            records = li.records;
             tiles = li.tiles;
             chunks = li.chunks;
             tile = li.tile;
@@ -355,6 +543,10 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
         loc_v = dst_v;
         cur ^= 1;
     }
+    // base cases of the last level report range errors through the status word
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
     return SS_OK;
 }
 
@@ -363,7 +555,7 @@ ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t v
 {
     if (!c) return SS_EINVAL;
     if (vb != 4 && vb != 8) return fail(c, SS_EINVAL, "val_bytes must be 4 or 8");
-    if (n >= (1ull << 32)) return fail(c, SS_EINVAL, "n must be below 2^32");
+    if (n >= (1ull << 31)) return fail(c, SS_EINVAL, "n must be below 2^31");
     if (n == 0) return SS_OK;
     if (!keys || !vals || !ko || !vo) return fail(c, SS_EINVAL, "null array pointer");
     const bool inplace = ko == keys && vo == vals;
@@ -422,9 +614,14 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info};
+                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
+    for (auto& p : c->pending) {
+        c->event_pool.push_back(p.a);
+        c->event_pool.push_back(p.b);
+    }
+    for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     if (c->info_host) (void)hipHostFree(c->info_host);
     if (c->seg_stage) (void)hipHostFree(c->seg_stage);
     if (c->job_stage) (void)hipHostFree(c->job_stage);
@@ -451,11 +648,49 @@ ss_status ss_sync(ss_ctx* c)
     return SS_OK;
 }
 
+ss_status ss_set_option(ss_ctx* c, int option, int64_t value)
+{
+    if (!c) return SS_EINVAL;
+    switch (option) {
+    case SS_OPT_DIST_VARIANT:
+        if (value < 0 || value > 5) return fail(c, SS_EINVAL, "distribution variant must be 0..5");
+        c->dist_variant = (int)value;
+        return SS_OK;
+    default:
+        return fail(c, SS_EINVAL, "unknown option");
+    }
+}
+
+ss_status ss_profile_enable(ss_ctx* c, int on)
+{
+    if (!c) return SS_EINVAL;
+    ss_status s = resolve_profile(c);
+    if (s != SS_OK) return s;
+    for (int k = 0; k < SS_PROF_KINDS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_launches[k] = 0;
+        c->prof_units[k] = 0;
+    }
+    c->prof_on = on != 0;
+    return SS_OK;
+}
+
+ss_status ss_profile_read(ss_ctx* c, int kind, double* total_ms, uint64_t* launches, uint64_t* units)
+{
+    if (!c || kind < 0 || kind >= SS_PROF_KINDS || !total_ms || !launches || !units) return SS_EINVAL;
+    ss_status s = resolve_profile(c);
+    if (s != SS_OK) return s;
+    *total_ms = c->prof_ms[kind];
+    *launches = c->prof_launches[kind];
+    *units = c->prof_units[kind];
+    return SS_OK;
+}
+
 ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
 {
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info};
+                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -522,9 +757,12 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     memcpy(c->seg_stage, segs.data(), sizeof(Seg));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[0].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
     HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
-    LevelArgs a = make_args(c, p, 0, (Seg*)c->segs[0].p, 1, tile, keys, vals, keys_out, vals_out);
-    if (vb == 8) launch_level_v<uint64_t>(c, p.mode, a, tiles, chunks);
-    else launch_level_v<uint32_t>(c, p.mode, a, tiles, chunks);
+    if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
+    LevelArgs a = make_args(c, p, 0, (Seg*)c->segs[0].p, 1, tile, keys, vals, keys_out, vals_out, keys_out, vals_out);
+    a.adaptive_nl = 0;  // the inspected level uses exactly n_light_log2 bits
+    if (vb == 8) launch_level_v<uint64_t>(c, p.mode, a, tiles, chunks, n);
+    else launch_level_v<uint32_t>(c, p.mode, a, tiles, chunks, n);
     hipLaunchKernelGGL(k_export_partition, dim3(1), dim3(1024), 0, c->stream, (const uint32_t*)c->bstart.p,
                        (const Seg*)c->segs[0].p, (const uint64_t*)c->heavy_list.p, offsets_out, heavy_out);
     HIP_OR_FAIL(c, hipGetLastError());

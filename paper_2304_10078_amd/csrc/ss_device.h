@@ -21,19 +21,19 @@ constexpr uint32_t kHeavyMax = 512;          // n_H cap per subproblem
 constexpr uint32_t kLightBitsMax = 10;       // n_L <= 2^10
 constexpr uint32_t kNbStride = (1u << kLightBitsMax) + kHeavyMax;  // 1536 buckets max
 constexpr uint32_t kSampleMax = 16384;       // |S| cap (LDS bitonic capacity)
-constexpr uint32_t kHeavySlotsMax = 1024;    // heavy table slots (load <= 1/2)
+constexpr uint32_t kHeavySlotsMax = 1024;    // slots per heavy table; two tables (load <= 1/4)
 constexpr uint32_t kAlphaMax = 4096;         // largest base case held in LDS
 constexpr uint32_t kChunk = 32;              // subarrays per scan chunk
 constexpr uint32_t kCopyChunk = 65536;       // records per copy job
 constexpr uint32_t kBucketGroups = kNbStride / 64;  // 24 column groups in the bucket scan
 constexpr uint16_t kEmpty16 = 0xFFFF;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
-constexpr uint32_t kJobCopy = 0x80000000u;
 
 // device status bits
 constexpr uint32_t kStatusSizeMismatch = 1u;   // bucket sizes do not add up to the subproblem
 constexpr uint32_t kStatusScatterRange = 2u;   // a distribution target fell outside its subproblem
 constexpr uint32_t kStatusBaseIndex = 4u;      // a base-case permutation entry out of range
+constexpr uint32_t kStatusHeavyTable = 8u;     // the heavy table could not be built
 
 struct Seg {
     uint32_t start;    // absolute first record
@@ -45,30 +45,44 @@ struct Seg {
     uint16_t nl_bits;  // light id bits b (n_L = 2^b)
     uint16_t shift;    // first hash bit of the light id
     uint16_t nheavy;   // n_H, written by the sampling kernel
-    uint16_t hlog2;    // log2 heavy-table slots, 0 when n_H = 0
+    uint16_t hlog2;    // bits 0-7: log2 slots per heavy table (0 when n_H = 0); bits 8-15: table salt
 };
 static_assert(sizeof(Seg) == 32, "Seg layout");
 
 struct Job {
     uint32_t start;
-    uint32_t len;      // kJobCopy bit set: plain copy to the output
+    uint32_t len;
 };
 
+// Job classes: base cases by capacity (512, 1024, 2048, 4096 records), then copies.
+constexpr int kJobClasses = 5;
+constexpr int kCopyClass = 4;
+
+__host__ __device__ __forceinline__ int base_class(uint32_t len)
+{
+    return len <= 512 ? 0 : len <= 1024 ? 1 : len <= 2048 ? 2 : 3;
+}
+
 struct LevelInfo {
-    uint32_t nsegs;         // subproblems emitted for the next level
-    uint32_t njobs;         // jobs emitted by this level
-    uint32_t tiles;         // tiles of the next level
-    uint32_t chunks;        // scan chunks of the next level
-    uint32_t tile;          // subarray size of the next level
-    uint32_t status;        // device-detected errors
-    uint32_t pad0, pad1;
+    uint32_t nsegs;                  // subproblems emitted for the next level
+    uint32_t njobs[kJobClasses];     // jobs emitted by this level, per class
+    uint32_t tiles;                  // tiles of the next level
+    uint32_t chunks;                 // scan chunks of the next level
+    uint32_t tile;                   // subarray size of the next level
+    uint32_t status;                 // device-detected errors
+    unsigned long long records;      // records in the next level's subproblems
+    unsigned long long job_records;  // records covered by this level's jobs
 };
 
 struct LevelArgs {
     const uint64_t* src_keys;
     const void* src_vals;
-    uint64_t* dst_keys;
+    uint64_t* dst_keys;    // destination of buckets that need more work
     void* dst_vals;
+    uint64_t* fin_keys;    // destination of buckets that are final (may equal dst)
+    void* fin_vals;
+    uint16_t* bids;        // bucket id of every record, written by the counting pass
+    uint64_t* sink;        // 512 bytes that absorb the stores of lanes without a record
     Seg* segs;
     uint32_t nsegs;
     uint32_t tile;
@@ -77,12 +91,14 @@ struct LevelArgs {
     uint32_t* tot;         // [nsegs][kNbStride]
     uint32_t* bstart;      // [nsegs][kNbStride + 1]
     uint64_t* heavy_list;  // [nsegs][kHeavyMax]  heavy hashes in id order
-    uint64_t* tab_h;       // [nsegs][kHeavySlotsMax]
-    uint16_t* tab_id;      // [nsegs][kHeavySlotsMax]
+    uint64_t* tab_h;       // [nsegs][2][kHeavySlotsMax]  two-choice heavy table
+    uint16_t* tab_id;      // [nsegs][2][kHeavySlotsMax]
     LevelInfo* info;
     uint64_t seed;
     uint32_t level;
     uint32_t sample_mult;
+    uint32_t alpha;
+    uint32_t adaptive_nl;  // choose n_L per subproblem from the sample's light fraction
 };
 
 // ---------------------------------------------------------------- hashing
@@ -113,29 +129,41 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
     return z ^ (z >> 31);
 }
 
-// Table slot from a hash: Fibonacci hashing keeps the top bits of h * 2^64/phi,
-// so identity-hashed small integers still spread.
+// Table slot from a hash: fold to 32 bits and keep the top bits of the
+// product with 2^32/phi (Fibonacci hashing), so identity-hashed small
+// integers still spread; one 32-bit multiply.
 __device__ __forceinline__ uint32_t fib_slot(uint64_t h, uint32_t log2slots)
 {
-    return (uint32_t)((h * 0x9e3779b97f4a7c15ULL) >> (64 - log2slots));
+    const uint32_t x = (uint32_t)h ^ (uint32_t)(h >> 32);
+    return (x * 0x9e3779b1u) >> (32 - log2slots);
 }
 
-// GetBucketId (Algorithm 1): heavy id from the heavy table, else the light id
-// from nl_bits bits of the hash starting at `shift`.
-__device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, const uint16_t* tid,
-                                              uint32_t hlog2, uint32_t shift, uint32_t lmask)
+// Second slot of the two-choice heavy table: an independent 32-bit mix of
+// the hash, perturbed by a per-table salt.
+__device__ __forceinline__ uint32_t slot2(uint64_t h, uint32_t log2slots, uint32_t salt)
 {
+    const uint32_t x = ((uint32_t)(h >> 32) + salt * 0x632be5abu) * 0x85ebca6bu ^ (uint32_t)h * 0xc2b2ae35u;
+    return x >> (32 - log2slots);
+}
+
+// GetBucketId (Algorithm 1): the heavy id when the key is in the heavy table,
+// else the light id from nl_bits bits of the hash starting at `shift`.  The
+// heavy table has two choices per key (cuckoo hashing), so a lookup is four
+// independent LDS reads and no probe loop.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, const uint16_t* tid,
+                                              uint32_t hfield, uint32_t shift, uint32_t lmask)
+{
+    const uint32_t hlog2 = hfield & 0xFFu;
+    uint32_t b = (uint32_t)(h >> shift) & lmask;
     if (hlog2) {
-        const uint32_t mask = (1u << hlog2) - 1;
-        uint32_t s = fib_slot(h, hlog2);
-        while (true) {
-            uint16_t id = tid[s];
-            if (id == kEmpty16) break;
-            if (th[s] == h) return id;
-            s = (s + 1) & mask;
-        }
+        const uint32_t s1 = fib_slot(h, hlog2);
+        const uint32_t s2 = slot2(h, hlog2, hfield >> 8) + kHeavySlotsMax;
+        const uint16_t i1 = tid[s1], i2 = tid[s2];
+        const uint64_t h1 = th[s1], h2 = th[s2];
+        if (i2 != kEmpty16 && h2 == h) b = i2;
+        if (i1 != kEmpty16 && h1 == h) b = i1;
     }
-    return (uint32_t)(h >> shift) & lmask;
+    return b;
 }
 
 // ---------------------------------------------------------------- wave / block helpers
@@ -210,6 +238,15 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
     return base + x - v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X.  Give
+// each XCD a contiguous range of tiles so that neighbouring tiles, whose
+// output runs for a bucket are adjacent, share that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G)
+{
+    const uint32_t q = G >> 3, r = G & 7u, x = b & 7u, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ uint32_t find_by_tile(const Seg* segs, uint32_t nsegs, uint32_t t)
 {
     uint32_t lo = 0, hi = nsegs - 1;
@@ -240,12 +277,12 @@ __host__ __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t x)
 }
 
 // Light bucket bits for a subproblem of `len` records so that buckets hold
-// about alpha/2 records (at least 1 bit, at most kLightBitsMax and the hash
-// bits left).
+// about alpha/4 records, leaving room below alpha for the spread of bucket
+// sizes (at least 1 bit, at most kLightBitsMax and the hash bits left).
 __host__ __device__ __forceinline__ uint32_t choose_nl(uint32_t len, uint32_t alpha, uint32_t cap,
                                                        uint32_t shift)
 {
-    uint32_t target = alpha / 2 ? alpha / 2 : 1;
+    uint32_t target = alpha / 4 ? alpha / 4 : 1;
     uint32_t q = (len + target - 1) / target;
     uint32_t nl = ceil_log2_u32(q);
     if (nl < 1) nl = 1;
@@ -276,7 +313,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     constexpr int BS = 1024;
     __shared__ uint64_t smp[kSampleMax];
     __shared__ uint64_t hv[kHeavyMax];
-    __shared__ uint32_t owner[kHeavySlotsMax];
+    __shared__ uint32_t owner[2 * kHeavySlotsMax];
     __shared__ uint32_t tmp[20];
     __shared__ uint32_t sh_s, sh_tau;
 
@@ -284,9 +321,12 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     const uint32_t tid = threadIdx.x;
     const Seg sg = a.segs[sid];
     if (tid == 0) {
+        // |S| = ceil(c ln n'), at most n'/8 (small subproblems are not
+        // sampled almost entirely) and at most the LDS capacity
         const double L = log((double)sg.len);
         double sd = ceil((double)a.sample_mult * L);
         uint32_t s = sg.len < 2 ? 0u : (uint32_t)sd;
+        if (s > sg.len / 8) s = sg.len / 8;
         if (s > kSampleMax) s = kSampleMax;
         sh_s = s;
         sh_tau = sg.len < 3 ? 1u : (uint32_t)ceil(L);
@@ -349,33 +389,105 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
             ++id;
         }
     }
+    // records of the sample that fall on heavy keys
+    __shared__ uint32_t sh_hs;
+    if (tid == 0) sh_hs = 0;
+    __syncthreads();
+    uint32_t hs = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const bool start = (i == 0) || smp[i] != smp[i - 1];
+        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) {
+            // end of the run: first position in (i, s) holding a larger value
+            uint32_t l = i + tau - 1, r = s;
+            while (r - l > 1) {
+                const uint32_t mid = (l + r) >> 1;
+                if (smp[mid] == smp[i]) l = mid;
+                else r = mid;
+            }
+            hs += r - i;
+        }
+    }
+    if (hs) atomicAdd(&sh_hs, hs);
+
+    // Light bucket count.  With adaptive_nl, n_L is the smallest power of two
+    // that lets the light records finish in the fewest levels: one level if
+    // buckets of ~alpha/2 can be reached with at most nl_bits bits, else two.
+    __shared__ uint32_t sh_nl;
+    if (tid == 0) sh_nl = sg.nl_bits;
+    __syncthreads();
+    if (tid == 0 && a.adaptive_nl && s) {
+        const double light = (double)sg.len * (double)(s - sh_hs) / (double)s;
+        const double target = (double)(a.alpha / 2);
+        const uint32_t cap = sg.nl_bits;
+        uint32_t nl1 = 1;
+        while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
+        uint32_t nl = cap;
+        if (nl1 <= cap) {
+            nl = nl1;
+        } else {
+            uint32_t nl2 = 1;
+            while (nl2 < 31 && (double)(1u << nl2) * (double)(1u << kLightBitsMax) * target < light) ++nl2;
+            if (nl2 <= cap) nl = nl2;
+        }
+        sh_nl = nl;
+    }
+
+    // Two-choice (cuckoo) heavy table: two tables of 2^hlog2 slots, at most
+    // a quarter full.  Built by one thread; on a cycle the salt of the second
+    // hash changes and the build starts again.
+    __shared__ uint32_t sh_hfield;
     uint32_t hlog2 = 0;
     if (nh) {
         hlog2 = ceil_log2_u32(2 * nh);
         if (hlog2 < 4) hlog2 = 4;
     }
     const uint32_t slots = nh ? (1u << hlog2) : 0u;
-    for (uint32_t i = tid; i < slots; i += BS) owner[i] = kEmpty32;
+    for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) owner[i] = kEmpty32;
     __syncthreads();
-    for (uint32_t t = tid; t < nh; t += BS) {
-        const uint64_t h = hv[t];
-        uint32_t sl = fib_slot(h, hlog2);
-        while (true) {
-            uint32_t old = atomicCAS(&owner[sl], kEmpty32, t);
-            if (old == kEmpty32) break;
-            sl = (sl + 1) & (slots - 1);
+    if (tid == 0) {
+        uint32_t salt = 0;
+        bool built = nh == 0;
+        for (; !built && salt < 16; ++salt) {
+            if (salt)
+                for (uint32_t i = 0; i < 2 * kHeavySlotsMax; ++i) owner[i] = kEmpty32;
+            built = true;
+            for (uint32_t t = 0; t < nh && built; ++t) {
+                uint32_t cur = t;
+                int side = 0;
+                uint32_t kicks = 0;
+                while (true) {
+                    const uint64_t h = hv[cur];
+                    const uint32_t sl = side == 0 ? fib_slot(h, hlog2) : kHeavySlotsMax + slot2(h, hlog2, salt);
+                    const uint32_t prev = owner[sl];
+                    owner[sl] = cur;
+                    if (prev == kEmpty32) break;
+                    // evicted key moves to its other table
+                    cur = prev;
+                    side = (sl < kHeavySlotsMax) ? 1 : 0;
+                    if (++kicks > 4 * nh + 16) {
+                        built = false;
+                        break;
+                    }
+                }
+            }
+            if (built) break;
         }
+        if (!built) atomicOr(&a.info->status, kStatusHeavyTable);
+        sh_hfield = nh ? (hlog2 | (salt << 8)) : 0u;
     }
     __syncthreads();
-    const uint32_t nL = 1u << sg.nl_bits;
-    for (uint32_t i = tid; i < slots; i += BS) {
+    const uint32_t nL = 1u << sh_nl;
+    for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) {
+        const bool used = (i & (kHeavySlotsMax - 1)) < slots;
+        if (!used) continue;
         const uint32_t o = owner[i];
-        a.tab_h[(size_t)sid * kHeavySlotsMax + i] = o != kEmpty32 ? hv[o] : 0ull;
-        a.tab_id[(size_t)sid * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
+        a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? hv[o] : 0ull;
+        a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
     }
     if (tid == 0) {
         a.segs[sid].nheavy = (uint16_t)nh;
-        a.segs[sid].hlog2 = (uint16_t)hlog2;
+        a.segs[sid].hlog2 = (uint16_t)sh_hfield;
+        a.segs[sid].nl_bits = (uint16_t)sh_nl;
     }
 }
 
@@ -389,10 +501,10 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
 {
     constexpr int BS = 1024;
     __shared__ uint32_t cnt[kNbStride];
-    __shared__ uint64_t th[kHeavySlotsMax];
-    __shared__ uint16_t tidh[kHeavySlotsMax];
+    __shared__ uint64_t th[2 * kHeavySlotsMax];
+    __shared__ uint16_t tidh[2 * kHeavySlotsMax];
 
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
     const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
     const Seg sg = a.segs[sid];
@@ -402,29 +514,40 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = nL + sg.nheavy;
-    const uint32_t hlog2 = sg.hlog2;
-    const uint32_t slots = hlog2 ? (1u << hlog2) : 0u;
+    const uint32_t hlog2 = sg.hlog2;  // slot bits and salt
+    const uint32_t slots = (hlog2 & 0xFFu) ? (1u << (hlog2 & 0xFFu)) : 0u;
 
     for (uint32_t b = tid; b < nb; b += BS) cnt[b] = 0;
-    for (uint32_t i = tid; i < slots; i += BS) {
-        th[i] = a.tab_h[(size_t)sid * kHeavySlotsMax + i];
-        tidh[i] = a.tab_id[(size_t)sid * kHeavySlotsMax + i];
+    for (uint32_t i = tid; i < 2 * slots; i += BS) {
+        const uint32_t j = i < slots ? i : kHeavySlotsMax + (i - slots);
+        th[j] = a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + j];
+        tidh[j] = a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + j];
     }
     __syncthreads();
 
     const uint32_t shift = sg.shift;
     const uint32_t lmask = nL - 1;
     const uint64_t* keys = a.src_keys;
+    uint16_t* bids = a.bids;
+    auto tally = [&](uint32_t b) { atomicAdd(&cnt[b], 1u); };
+    constexpr int U = 8;  // loads in flight per thread
     uint64_t i = r0 + tid;
-    for (; i + 3 * BS < r1; i += 4 * BS) {
-        uint64_t k0 = keys[i], k1 = keys[i + BS], k2 = keys[i + 2 * BS], k3 = keys[i + 3 * BS];
-        atomicAdd(&cnt[bucket_of(user_hash<MODE>(k0), th, tidh, hlog2, shift, lmask)], 1u);
-        atomicAdd(&cnt[bucket_of(user_hash<MODE>(k1), th, tidh, hlog2, shift, lmask)], 1u);
-        atomicAdd(&cnt[bucket_of(user_hash<MODE>(k2), th, tidh, hlog2, shift, lmask)], 1u);
-        atomicAdd(&cnt[bucket_of(user_hash<MODE>(k3), th, tidh, hlog2, shift, lmask)], 1u);
+    for (; i + (U - 1) * BS < r1; i += U * BS) {
+        uint64_t kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) kk[u] = keys[i + (uint64_t)u * BS];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t b = bucket_of(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
+            bids[i + (uint64_t)u * BS] = (uint16_t)b;
+            tally(b);
+        }
     }
-    for (; i < r1; i += BS)
-        atomicAdd(&cnt[bucket_of(user_hash<MODE>(keys[i]), th, tidh, hlog2, shift, lmask)], 1u);
+    for (; i < r1; i += BS) {
+        const uint32_t b = bucket_of(user_hash<MODE>(keys[i]), th, tidh, hlog2, shift, lmask);
+        bids[i] = (uint16_t)b;
+        tally(b);
+    }
     __syncthreads();
     uint32_t* row = a.C + (size_t)t * kNbStride;
     for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b];
@@ -530,28 +653,39 @@ __global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
 // ================================================================ Step 2c
 // Distribution (Section 3.2): each subarray, in order, moves every record to
 // T[X[i][id]++].  One block per subarray walks it in sub-tiles of W*64*E
-// records; each wave ranks its contiguous chunk stably (ballot match plus
-// per-wave LDS counters), the block turns ranks into bucket-grouped LDS
-// positions, and the staged sub-tile is written out so that consecutive
-// threads write consecutive addresses of a bucket's run.  Keys go first,
-// then values through the same staging buffer.
+// records.  Bucket ids come from the counting pass, so no hashing or table
+// lookup is repeated here.  Each wave ranks its contiguous chunk stably
+// (ballot match plus per-wave LDS counters), the block turns ranks into
+// bucket-grouped LDS positions, and the staged sub-tile is written out so
+// that consecutive threads write consecutive addresses of a bucket's run.
+// Keys go first, then values through the same staging buffer; the next
+// sub-tile's loads are issued before the current one is ranked.  Buckets that
+// are final (heavy, single record, or all hash bits used) go to fin_* -- the
+// output -- when that is safe, so they are never copied again.
 
-template <int MODE, typename V, int W, int E>
-__global__ __launch_bounds__(W * 64) void k_distribute(LevelArgs a)
+__device__ __forceinline__ bool bucket_is_final(uint32_t b, uint32_t nL, uint32_t sz, bool all_bits_used)
 {
+    return b >= nL || sz <= 1 || all_bits_used;
+}
+
+template <typename V, int W, int E>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
+{
+    // Every global load and store in the sub-tile loop is issued
+    // unconditionally (clamped load indices, a sink address for lanes without
+    // a record): with no branches around memory instructions the compiler can
+    // count outstanding accesses and wait only for the ones it needs instead
+    // of draining all stores before each sub-tile.
     constexpr int BS = W * 64;
     constexpr int SUB = BS * E;
-    __shared__ uint64_t th[kHeavySlotsMax];
-    __shared__ uint16_t tidh[kHeavySlotsMax];
-    __shared__ uint32_t gbase[kNbStride];
-    __shared__ uint32_t lst[kNbStride];
-    __shared__ uint32_t ltot[kNbStride];
+    __shared__ uint32_t gbase[kNbStride];      // bit 31: bucket goes to fin_*
+    __shared__ uint32_t lst[kNbStride + 1];
     __shared__ uint16_t wc[W * kNbStride];
     __shared__ uint64_t stage[SUB];
     __shared__ uint16_t stage_b[SUB];
     __shared__ uint32_t tmp[20];
 
-    const uint32_t t = blockIdx.x;
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, w = tid >> 6;
     const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
@@ -560,111 +694,291 @@ __global__ __launch_bounds__(W * 64) void k_distribute(LevelArgs a)
     const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * a.tile;
     const uint64_t send = (uint64_t)sg.start + sg.len;
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
+    const uint64_t rlast = r1 - 1;
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = nL + sg.nheavy;
     const uint32_t nbits = 32 - __clz(nb - 1);
-    const uint32_t hlog2 = sg.hlog2;
-    const uint32_t slots = hlog2 ? (1u << hlog2) : 0u;
-    const uint32_t shift = sg.shift;
-    const uint32_t lmask = nL - 1;
+    const bool split = a.fin_keys != a.dst_keys;
+    const bool all_bits = (uint32_t)sg.shift + sg.nl_bits >= 64;
+    const uint32_t* bsz = a.bstart + (size_t)sid * (kNbStride + 1);
     const V* src_vals = (const V*)a.src_vals;
     V* dst_vals = (V*)a.dst_vals;
+    V* fin_vals = (V*)a.fin_vals;
     V* stage_v = (V*)stage;
+    uint64_t* sink_k = a.sink + lane;
+    V* sink_v = (V*)(a.sink + lane);
+    const uint32_t per = (nb + BS - 1) / BS;  // buckets per thread in the scans
+    const uint32_t pb0 = tid * per;
 
-    for (uint32_t i = tid; i < slots; i += BS) {
-        th[i] = a.tab_h[(size_t)sid * kHeavySlotsMax + i];
-        tidh[i] = a.tab_id[(size_t)sid * kHeavySlotsMax + i];
+    for (uint32_t b = tid; b < nb; b += BS) {
+        uint32_t g = a.C[(size_t)t * kNbStride + b];
+        if (split && bucket_is_final(b, nL, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
+        gbase[b] = g;
     }
-    for (uint32_t b = tid; b < nb; b += BS) gbase[b] = a.C[(size_t)t * kNbStride + b];
+    for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
 
+    // keys and bucket ids are loaded one sub-tile ahead; values at the top of
+    // their own iteration (needed only after the ranking)
+    uint64_t kn[E];
+    uint16_t bn[E];
+    {
+        const uint64_t bi = r0 + (uint64_t)w * 64 * E + lane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uint64_t i = bi + (uint64_t)e * 64;
+            i = i < rlast ? i : rlast;
+            kn[e] = a.src_keys[i];
+            bn[e] = a.bids[i];
+        }
+    }
+    __syncthreads();
+
+    bool out_of_range = false;
     for (uint64_t sub = r0; sub < r1; sub += SUB) {
-        for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
-        __syncthreads();
-
         uint64_t k[E];
         V v[E];
         uint32_t bk[E], pos[E];
         const uint64_t base_i = sub + (uint64_t)w * 64 * E + lane;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const uint64_t i = base_i + (uint64_t)e * 64;
-            const bool valid = i < r1;
-            k[e] = valid ? a.src_keys[i] : 0ull;
-            v[e] = valid ? src_vals[i] : (V)0;
+            uint64_t i = base_i + (uint64_t)e * 64;
+            i = i < rlast ? i : rlast;
+            v[e] = src_vals[i];
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            bk[e] = bucket_of(user_hash<MODE>(k[e]), th, tidh, hlog2, shift, lmask);
+        for (int e = 0; e < E; ++e) {
+            k[e] = kn[e];
+            bk[e] = bn[e];
+        }
+        {
+            // next sub-tile (the last iteration re-reads its own, clamped)
+            const uint64_t bi = base_i + SUB;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                uint64_t i = bi + (uint64_t)e * 64;
+                i = i < rlast ? i : rlast;
+                kn[e] = a.src_keys[i];
+                bn[e] = a.bids[i];
+            }
+        }
         uint16_t* wcw = wc + w * nb;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool valid = base_i + (uint64_t)e * 64 < r1;
-            pos[e] = wave_rank(bk[e], valid, nbits, wcw);
-        }
+        for (int e = 0; e < E; ++e) pos[e] = wave_rank(bk[e], base_i + (uint64_t)e * 64 < r1, nbits, wcw);
         __syncthreads();
 
-        // per-bucket prefix over waves and the sub-tile's bucket totals
-        for (uint32_t b = tid; b < nb; b += BS) {
-            uint32_t run = 0;
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = wc[ww * nb + b];
-                wc[ww * nb + b] = (uint16_t)run;
+        // per bucket: exclusive prefix over waves, sub-tile total, and the
+        // exclusive scan of the totals over buckets (contiguous pieces per thread)
+        uint32_t s = 0;
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t b = pb0 + j;
+            if (b < nb) {
+                uint32_t run = 0;
+#pragma unroll 4
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = wc[ww * nb + b];
+                    wc[ww * nb + b] = (uint16_t)run;
+                    run += c;
+                }
+                lst[b] = run;  // total for now
+                s += run;
+            }
+        }
+        uint32_t tot = 0;
+        uint32_t run = block_excl_scan<BS>(s, tmp, &tot);
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t b = pb0 + j;
+            if (b < nb) {
+                const uint32_t c = lst[b];
+                lst[b] = run;
                 run += c;
             }
-            ltot[b] = run;
+        }
+        if (tid == 0) lst[nb] = tot;
+        __syncthreads();
+
+        // stage keys in bucket order
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (base_i + (uint64_t)e * 64 < r1) {
+                const uint32_t b = bk[e];
+                const uint32_t p = lst[b] + wc[w * nb + b] + pos[e];
+                pos[e] = p;
+                stage[p] = k[e];
+                stage_b[p] = (uint16_t)b;
+            }
         }
         __syncthreads();
+        const uint32_t m = lst[nb];
+        uint32_t dest[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t j = tid + e * BS;
+            const uint32_t jj = j < m ? j : 0u;
+            const uint32_t b = stage_b[jj];
+            const uint32_t dd = gbase[b] + (jj - lst[b]);
+            const uint32_t d = dd & 0x7FFFFFFFu;
+            const bool in_range = d - sg.start < sg.len;
+            out_of_range |= (j < m) && !in_range;
+            dest[e] = (j < m && in_range) ? dd : 0xFFFFFFFFu;
+            uint64_t* out = (dd >> 31) ? a.fin_keys : a.dst_keys;
+            uint64_t* addr = dest[e] != 0xFFFFFFFFu ? out + d : sink_k;
+            *addr = stage[jj];
+        }
+        for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            if (base_i + (uint64_t)e * 64 < r1) stage_v[pos[e]] = v[e];
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t j = tid + e * BS;
+            const uint32_t dd = dest[e];
+            V* out = (dd >> 31) ? fin_vals : dst_vals;
+            V* addr = dd != 0xFFFFFFFFu ? out + (dd & 0x7FFFFFFFu) : sink_v;
+            *addr = stage_v[j < m ? j : 0u];
+        }
+        __syncthreads();
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t b = pb0 + j;
+            if (b < nb) gbase[b] += lst[b + 1] - lst[b];
+        }
+    }
+    if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
+}
+
+// Direct form of the distribution: the same stable ranking, but every record
+// is written straight from registers to its destination, without staging
+// the sub-tile in LDS.  Lanes of a wave that share a bucket in a round hold
+// consecutive ranks, so heavy buckets still produce contiguous stores; the L2
+// merges the short runs of light buckets.  LDS holds only the per-wave
+// counters (double-buffered) and the bucket bases, so several blocks share a
+// CU and one block's ranking overlaps another's stores.
+template <typename V, int W, int E, int WPE>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) void k_distribute_direct(LevelArgs a)
+{
+    constexpr int BS = W * 64;
+    constexpr int SUB = BS * E;
+    __shared__ uint32_t gbase[kNbStride];      // bit 31: bucket goes to fin_*
+    __shared__ uint32_t ptot[kNbStride];       // previous sub-tile's bucket totals
+    __shared__ uint16_t wc[2][W * kNbStride];
+    __shared__ uint32_t tmp[20];
+
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u, w = tid >> 6;
+    const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
+    const Seg sg = a.segs[sid];
+    const uint32_t lt = t - sg.tile0;
+    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * a.tile;
+    const uint64_t send = (uint64_t)sg.start + sg.len;
+    const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
+    const uint64_t rlast = r1 - 1;
+    const uint32_t nL = 1u << sg.nl_bits;
+    const uint32_t nb = nL + sg.nheavy;
+    const uint32_t nbits = 32 - __clz(nb - 1);
+    const bool split = a.fin_keys != a.dst_keys;
+    const bool all_bits = (uint32_t)sg.shift + sg.nl_bits >= 64;
+    const uint32_t* bsz = a.bstart + (size_t)sid * (kNbStride + 1);
+    const V* src_vals = (const V*)a.src_vals;
+    V* dst_vals = (V*)a.dst_vals;
+    V* fin_vals = (V*)a.fin_vals;
+    uint64_t* sink_k = a.sink + lane;
+    V* sink_v = (V*)(a.sink + lane);
+    const uint32_t per = (nb + BS - 1) / BS;  // buckets per thread in the scans
+    const uint32_t pb0 = tid * per;
+
+    for (uint32_t b = tid; b < nb; b += BS) {
+        uint32_t g = a.C[(size_t)t * kNbStride + b];
+        if (split && bucket_is_final(b, nL, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
+        gbase[b] = g;
+        ptot[b] = 0;
+    }
+    for (uint32_t i = tid; i < W * nb; i += BS) {
+        wc[0][i] = 0;
+        wc[1][i] = 0;
+    }
+
+    uint16_t bn[E];
+    {
+        const uint64_t bi = r0 + (uint64_t)w * 64 * E + lane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uint64_t i = bi + (uint64_t)e * 64;
+            i = i < rlast ? i : rlast;
+            bn[e] = a.bids[i];
+        }
+    }
+    __syncthreads();
+
+    bool out_of_range = false;
+    uint32_t cur = 0;
+    for (uint64_t sub = r0; sub < r1; sub += SUB, cur ^= 1u) {
+        uint64_t k[E];
+        V v[E];
+        uint32_t bk[E], pos[E];
+        const uint64_t base_i = sub + (uint64_t)w * 64 * E + lane;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uint64_t i = base_i + (uint64_t)e * 64;
+            i = i < rlast ? i : rlast;
+            k[e] = a.src_keys[i];
+            v[e] = src_vals[i];
+            bk[e] = bn[e];
+        }
         {
-            // exclusive scan of ltot over the nb buckets, contiguous pieces per thread
-            const uint32_t per = (nb + BS - 1) / BS;
-            const uint32_t b0 = tid * per;
-            uint32_t s = 0;
-            for (uint32_t j = 0; j < per; ++j)
-                if (b0 + j < nb) s += ltot[b0 + j];
-            uint32_t run = block_excl_scan<BS>(s, tmp, nullptr);
-            for (uint32_t j = 0; j < per; ++j)
-                if (b0 + j < nb) {
-                    lst[b0 + j] = run;
-                    run += ltot[b0 + j];
+            const uint64_t bi = base_i + SUB;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                uint64_t i = bi + (uint64_t)e * 64;
+                i = i < rlast ? i : rlast;
+                bn[e] = a.bids[i];
+            }
+        }
+        uint16_t* wcc = wc[cur];
+        uint16_t* wcw = wcc + w * nb;
+#pragma unroll
+        for (int e = 0; e < E; ++e) pos[e] = wave_rank(bk[e], base_i + (uint64_t)e * 64 < r1, nbits, wcw);
+        __syncthreads();
+
+        // The other counter buffer was last read by the previous sub-tile's
+        // stores, which every thread finished before the barrier above; clear
+        // it for the next sub-tile (the barrier below orders it before use).
+        for (uint32_t i = tid; i < W * nb; i += BS) wc[cur ^ 1][i] = 0;
+        // per bucket: advance the base past the previous sub-tile, then turn
+        // the wave counters into bucket-local prefixes
+        for (uint32_t j = 0; j < per; ++j) {
+            const uint32_t b = pb0 + j;
+            if (b < nb) {
+                gbase[b] += ptot[b];
+                uint32_t run = 0;
+#pragma unroll 4
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = wcc[ww * nb + b];
+                    wcc[ww * nb + b] = (uint16_t)run;
+                    run += c;
                 }
+                ptot[b] = run;
+            }
         }
         __syncthreads();
 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const bool valid = base_i + (uint64_t)e * 64 < r1;
-            if (valid) {
-                const uint32_t p = lst[bk[e]] + wc[w * nb + bk[e]] + pos[e];
-                pos[e] = p;
-                stage[p] = k[e];
-                stage_b[p] = (uint16_t)bk[e];
-            }
+            const uint32_t b = bk[e];
+            const uint32_t dd = gbase[b] + wcc[w * nb + b] + pos[e];
+            const uint32_t d = dd & 0x7FFFFFFFu;
+            const bool in_range = d - sg.start < sg.len;
+            out_of_range |= valid && !in_range;
+            const bool ok = valid && in_range;
+            uint64_t* ko = (dd >> 31) ? a.fin_keys : a.dst_keys;
+            V* vo = (dd >> 31) ? fin_vals : dst_vals;
+            *(ok ? ko + d : sink_k) = k[e];
+            *(ok ? vo + d : sink_v) = v[e];
         }
-        __syncthreads();
-        const uint32_t m = (uint32_t)((r1 - sub) < (uint64_t)SUB ? (r1 - sub) : (uint64_t)SUB);
-        bool out_of_range = false;
-        for (uint32_t j = tid; j < m; j += BS) {
-            const uint32_t b = stage_b[j];
-            const uint32_t d = gbase[b] + (j - lst[b]);
-            if (d - sg.start < sg.len) a.dst_keys[d] = stage[j];
-            else out_of_range = true;
-        }
-        if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
-        __syncthreads();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const bool valid = base_i + (uint64_t)e * 64 < r1;
-            if (valid) stage_v[pos[e]] = v[e];
-        }
-        __syncthreads();
-        for (uint32_t j = tid; j < m; j += BS) {
-            const uint32_t b = stage_b[j];
-            const uint32_t d = gbase[b] + (j - lst[b]);
-            if (d - sg.start < sg.len) dst_vals[d] = stage_v[j];
-        }
-        __syncthreads();
-        for (uint32_t b = tid; b < nb; b += BS) gbase[b] += ltot[b];
     }
+    if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
 }
 
 // ================================================================ Step 3 planning
@@ -672,7 +986,8 @@ __global__ __launch_bounds__(W * 64) void k_distribute(LevelArgs a)
 // of: a subproblem of the next level (light, >= alpha records: the recursive
 // call of Algorithm 1), a base-case job (light, 2 .. alpha-1 records), a copy
 // job (a bucket that is already final but sits in T, Section 3.4), or nothing.
-// Heavy buckets are final (Section 3.3).  Appends are aggregated per block.
+// Heavy buckets are final (Section 3.3).  Base-case jobs are sorted into
+// capacity classes; appends are aggregated per block.
 
 struct PlanArgs {
     const Seg* segs;
@@ -680,81 +995,100 @@ struct PlanArgs {
     const uint32_t* bstart;
     Seg* next;
     uint32_t next_cap;
-    Job* jobs;
+    Job* jobs;          // kJobClasses lists of job_cap entries
     uint32_t job_cap;
     LevelInfo* info;
     uint32_t alpha;
-    uint32_t dst_is_out;
+    uint32_t finals_in_out;  // final buckets were written to the output by the distribution
 };
 
-__device__ __forceinline__ void plan_bucket(const PlanArgs& p, const Seg& sg, uint32_t b, uint32_t nL,
-                                            uint32_t& nseg, uint32_t& njob, bool emit,
-                                            uint32_t& seg_at, uint32_t& job_at)
+struct PlanCount {
+    uint32_t seg;
+    uint32_t job[kJobClasses];
+    uint32_t rec;
+};
+
+// What bucket b of subproblem sg turns into; with emit, write it at the
+// cursors (seg_at, job_at[class]).
+__device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, const Seg& sg, uint32_t b,
+                                            uint32_t nL, PlanCount& cnt, bool emit, uint32_t* seg_at,
+                                            uint32_t* job_at)
 {
-    const uint32_t* bs = p.bstart + (size_t)(&sg - p.segs) * (kNbStride + 1);
+    const uint32_t* bs = p.bstart + (size_t)sidx * (kNbStride + 1);
     const uint32_t st = bs[b];
     const uint32_t sz = bs[b + 1] - st;
     if (sz == 0) return;
     const uint32_t shift2 = sg.shift + sg.nl_bits;
-    const bool heavy = b >= nL;
     const bool all_bits_used = shift2 >= 64;
-    bool final_copy = false;
-    if (heavy || sz == 1 || (all_bits_used && sz >= p.alpha)) {
-        final_copy = !p.dst_is_out;
-    } else if (sz >= p.alpha) {
-        if (emit && seg_at < p.next_cap) {
-            Seg ns;
-            ns.start = st;
-            ns.len = sz;
-            ns.ibase = sg.ibase;
-            ns.tile0 = ns.chunk0 = ns.ntiles = 0;
-            ns.nl_bits = (uint16_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2);
-            ns.shift = (uint16_t)shift2;
-            ns.nheavy = 0;
-            ns.hlog2 = 0;
-            p.next[seg_at] = ns;
-        }
-        ++seg_at;
-        ++nseg;
-        return;
-    } else {
-        if (emit && job_at < p.job_cap) p.jobs[job_at] = Job{st, sz};
-        ++job_at;
-        ++njob;
-        return;
-    }
-    if (final_copy) {
+    if (bucket_is_final(b, nL, sz, all_bits_used)) {
+        if (p.finals_in_out) return;  // already in place
         for (uint32_t o = 0; o < sz; o += kCopyChunk) {
             const uint32_t l = sz - o < kCopyChunk ? sz - o : kCopyChunk;
-            if (emit && job_at < p.job_cap) p.jobs[job_at] = Job{st + o, l | kJobCopy};
-            ++job_at;
-            ++njob;
+            if (emit && job_at[kCopyClass] < p.job_cap)
+                p.jobs[(size_t)kCopyClass * p.job_cap + job_at[kCopyClass]] = Job{st + o, l};
+            if (emit) ++job_at[kCopyClass];
+            ++cnt.job[kCopyClass];
         }
+        cnt.rec += sz;
+        return;
     }
+    if (sz >= p.alpha) {
+        if (emit) {
+            if (*seg_at < p.next_cap) {
+                Seg ns;
+                ns.start = st;
+                ns.len = sz;
+                ns.ibase = sg.ibase;
+                ns.tile0 = ns.chunk0 = ns.ntiles = 0;
+                ns.nl_bits = (uint16_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2);
+                ns.shift = (uint16_t)shift2;
+                ns.nheavy = 0;
+                ns.hlog2 = 0;
+                p.next[*seg_at] = ns;
+            }
+            ++*seg_at;
+        }
+        ++cnt.seg;
+        return;
+    }
+    const int c = base_class(sz);
+    if (emit) {
+        if (job_at[c] < p.job_cap) p.jobs[(size_t)c * p.job_cap + job_at[c]] = Job{st, sz};
+        ++job_at[c];
+    }
+    ++cnt.job[c];
+    cnt.rec += sz;
 }
 
 __global__ __launch_bounds__(256) void k_plan(PlanArgs p)
 {
     __shared__ uint32_t tmp[20];
-    __shared__ uint32_t sh_seg, sh_job;
-    const Seg& sg = p.segs[blockIdx.x];
+    __shared__ uint32_t sh_base[kJobClasses + 1];
+    const uint32_t sidx = blockIdx.x;
+    const Seg sg = p.segs[sidx];
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = nL + sg.nheavy;
-    uint32_t nseg = 0, njob = 0, dummy_s = 0, dummy_j = 0;
-    for (uint32_t b = threadIdx.x; b < nb; b += 256)
-        plan_bucket(p, sg, b, nL, nseg, njob, false, dummy_s, dummy_j);
-    uint32_t tot_s = 0, tot_j = 0;
-    uint32_t off_s = block_excl_scan<256>(nseg, tmp, &tot_s);
-    uint32_t off_j = block_excl_scan<256>(njob, tmp, &tot_j);
-    if (threadIdx.x == 0) {
-        sh_seg = tot_s ? atomicAdd(&p.info->nsegs, tot_s) : 0u;
-        sh_job = tot_j ? atomicAdd(&p.info->njobs, tot_j) : 0u;
+    PlanCount cnt{};
+    uint32_t dummy_s = 0, dummy_j[kJobClasses] = {};
+    for (uint32_t b = threadIdx.x; b < nb; b += 256) plan_bucket(p, sidx, sg, b, nL, cnt, false, &dummy_s, dummy_j);
+    uint32_t tot = 0;
+    uint32_t seg_at = block_excl_scan<256>(cnt.seg, tmp, &tot);
+    if (threadIdx.x == 0) sh_base[kJobClasses] = tot ? atomicAdd(&p.info->nsegs, tot) : 0u;
+    uint32_t job_at[kJobClasses];
+#pragma unroll
+    for (int c = 0; c < kJobClasses; ++c) {
+        job_at[c] = block_excl_scan<256>(cnt.job[c], tmp, &tot);
+        if (threadIdx.x == 0) sh_base[c] = tot ? atomicAdd(&p.info->njobs[c], tot) : 0u;
     }
+    uint32_t rtot = 0;
+    (void)block_excl_scan<256>(cnt.rec, tmp, &rtot);
+    if (threadIdx.x == 0 && rtot) atomicAdd(&p.info->job_records, (unsigned long long)rtot);
     __syncthreads();
-    uint32_t seg_at = sh_seg + off_s, job_at = sh_job + off_j;
-    nseg = njob = 0;
-    for (uint32_t b = threadIdx.x; b < nb; b += 256)
-        plan_bucket(p, sg, b, nL, nseg, njob, true, seg_at, job_at);
+    seg_at += sh_base[kJobClasses];
+#pragma unroll
+    for (int c = 0; c < kJobClasses; ++c) job_at[c] += sh_base[c];
+    PlanCount again{};
+    for (uint32_t b = threadIdx.x; b < nb; b += 256) plan_bucket(p, sidx, sg, b, nL, again, true, &seg_at, job_at);
 }
 
 // Prefix over the next level's subproblems: subarray size for the level,
@@ -795,121 +1129,238 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
         info->tiles = run_t;
         info->chunks = run_c;
         info->tile = tile;
+        info->records = sh_total;
     }
 }
 
 // ================================================================ Step 3
 // Local refining base case for semisort_= (Section 3.3).  The paper packs a
-// sequential chained hash table in table order.  Here one block per bucket:
-// the keys go to LDS, an LDS hash table (open addressing, CAS on slot
-// owners, keys compared through the owner's index) yields f(i) = the first
-// index of record i's key, and a stable two-pass LDS radix sort on f(i)
-// groups equal keys in order of first occurrence while keeping input order
-// inside a group.  Copy jobs move final buckets from T to the output.
+// sequential chained hash table in table order.  Here one block per bucket of
+// at most CAP = W*512 records, keys and values held in registers:
+//   1. keys go to LDS and into an LDS hash table (open addressing; a slot is
+//      claimed by CAS and holds the index of a record with that key, keys are
+//      compared through that index);
+//   2. each record lowers its slot to the smallest index of its key
+//      (atomicMin), so f(i) = first occurrence of record i's key, a value
+//      that does not depend on scheduling;
+//   3. a stable one-pass multisplit on f(i) (ballot match plus per-wave LDS
+//      counters) gives every record its output slot: groups in order of first
+//      occurrence, input order inside a group (stable).
+// Values never touch LDS; results are written straight from registers.
 
-template <int MODE, typename V>
-__global__ __launch_bounds__(512) void k_finish(const Job* jobs, const uint64_t* src_keys,
-                                                const V* src_vals, uint64_t* out_keys, V* out_vals,
-                                                LevelInfo* info)
+template <int MODE, typename V, int W>
+__global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                                 uint64_t* out_keys, V* out_vals, LevelInfo* info)
 {
-    constexpr int W = 8, BS = 512, E = kAlphaMax / BS;  // 8 records per thread
-    __shared__ uint64_t kl[kAlphaMax];
-    __shared__ uint32_t tab[2 * kAlphaMax];   // slot owners, then the two sort buffers
-    __shared__ uint32_t fmin[2 * kAlphaMax];
-    __shared__ uint16_t wc[W * 128];
-    __shared__ uint32_t dtot[128];
-    __shared__ uint32_t dst_[128];
+    constexpr int BS = W * 64, E = 8, CAP = BS * E;
+    __shared__ uint64_t kl[CAP];
+    __shared__ uint32_t tab[2 * CAP];  // slot owners; reused for digit starts
+    __shared__ uint16_t wc[W * CAP];
     __shared__ uint32_t tmp[20];
 
     const Job j = jobs[blockIdx.x];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-    const uint32_t len = j.len & ~kJobCopy;
+    const uint32_t m = j.len;  // 2 .. CAP
     const uint64_t start = j.start;
-    if (j.len & kJobCopy) {
-        for (uint32_t i = tid; i < len; i += BS) {
-            out_keys[start + i] = src_keys[start + i];
-            out_vals[start + i] = src_vals[start + i];
-        }
-        return;
-    }
-    const uint32_t m = len;  // 2 .. kAlphaMax-1
     const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
     const uint32_t slots = 1u << lg, smask = slots - 1;
-    for (uint32_t i = tid; i < m; i += BS) kl[i] = src_keys[start + i];
-    for (uint32_t i = tid; i < slots; i += BS) {
-        tab[i] = kEmpty32;
-        fmin[i] = kEmpty32;
-    }
-    __syncthreads();
+    const uint32_t nbits = ceil_log2_u32(m);
 
-    uint32_t myslot[E], f[E];
+    uint64_t k[E];
+    V v[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t i = w * 64 * E + e * 64 + lane;
-        myslot[e] = 0;
+        k[e] = i < m ? src_keys[start + i] : 0ull;
+        v[e] = i < m ? src_vals[start + i] : (V)0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) kl[i] = k[e];
+    }
+    for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
+    for (uint32_t i = tid; i < (uint32_t)(W * CAP) / 2; i += BS) ((uint32_t*)wc)[i] = 0;
+    __syncthreads();
+
+    uint32_t sl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        sl[e] = 0;
         if (i < m) {
-            const uint64_t key = kl[i];
-            uint32_t sl = fib_slot(user_hash<MODE>(key), lg);
+            uint32_t s = fib_slot(user_hash<MODE>(k[e]), lg);
             while (true) {
-                uint32_t o = tab[sl];
+                uint32_t o = tab[s];
                 if (o == kEmpty32) {
-                    o = atomicCAS(&tab[sl], kEmpty32, i);
+                    o = atomicCAS(&tab[s], kEmpty32, i);
                     if (o == kEmpty32) break;
                 }
-                if (kl[o] == key) break;
-                sl = (sl + 1) & smask;
+                if (kl[o] == k[e]) break;
+                s = (s + 1) & smask;
             }
-            myslot[e] = sl;
-            atomicMin(&fmin[sl], i);
+            sl[e] = s;
         }
     }
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < E; ++e) f[e] = fmin[myslot[e]];
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) atomicMin(&tab[sl[e]], i);
+    }
     __syncthreads();
-
-    uint32_t* A = tab;              // after pass 1
-    uint32_t* B = tab + kAlphaMax;  // after pass 2
-    // element carried through the sort: (index << 16) | f
-    uint32_t el[E];
+    uint32_t f[E], rk[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) el[e] = ((w * 64 * E + e * 64 + lane) << 16) | (f[e] & 0xFFFFu);
+    for (int e = 0; e < E; ++e) f[e] = tab[sl[e]];
+    uint16_t* wcw = wc + w * CAP;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        rk[e] = wave_rank(f[e], i < m, nbits, wcw);
+    }
+    __syncthreads();
+    // per digit: prefix over waves, total; exclusive scan of totals over the m digits
+    uint32_t* dstart = tab;  // the table is no longer needed
+    uint32_t s = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t d = tid * E + e;
+        if (d < m) {
+            uint32_t run = 0;
+#pragma unroll
+            for (int ww = 0; ww < W; ++ww) {
+                const uint32_t c = wc[ww * CAP + d];
+                wc[ww * CAP + d] = (uint16_t)run;
+                run += c;
+            }
+            s += run;
+            dstart[CAP + d] = run;  // total, in the upper half
+        }
+    }
+    uint32_t run = block_excl_scan<BS>(s, tmp, nullptr);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t d = tid * E + e;
+        if (d < m) {
+            dstart[d] = run;
+            run += dstart[CAP + d];
+        }
+    }
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) {
+            const uint32_t p = dstart[f[e]] + wc[w * CAP + f[e]] + rk[e];
+            if (p < m) {
+                out_keys[start + p] = k[e];
+                out_vals[start + p] = v[e];
+            } else {
+                bad = true;
+            }
+        }
+    }
+    if (bad) atomicOr(&info->status, kStatusBaseIndex);
+}
 
+// The same base case for buckets of up to 4096 records, with the stable
+// multisplit on f(i) done as two 6-bit passes (small per-wave counters) so two
+// blocks fit on a CU.  Values are gathered from the source by index after the
+// sort (the bucket was just read, so the gather hits in L2); all reads finish
+// before the first write, so the output may be the source.
+template <int MODE, typename V>
+__global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                                    uint64_t* out_keys, V* out_vals, LevelInfo* info)
+{
+    constexpr int W = 8, BS = 512, E = 8, CAP = 4096;
+    __shared__ uint64_t kl[CAP];
+    __shared__ uint32_t tab[2 * CAP];  // slot owners, then the two sort buffers
+    __shared__ uint16_t wc[W * 64];
+    __shared__ uint32_t dst_[64];
+    __shared__ uint32_t tmp[20];
+
+    const Job j = jobs[blockIdx.x];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t m = j.len;  // 2 .. CAP
+    const uint64_t start = j.start;
+    const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
+    const uint32_t slots = 1u << lg, smask = slots - 1;
+
+    uint64_t k[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        k[e] = i < m ? src_keys[start + i] : 0ull;
+        if (i < m) kl[i] = k[e];
+    }
+    for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
+    __syncthreads();
+    uint32_t sl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        sl[e] = 0;
+        if (i < m) {
+            uint32_t sx = fib_slot(user_hash<MODE>(k[e]), lg);
+            while (true) {
+                uint32_t o = tab[sx];
+                if (o == kEmpty32) {
+                    o = atomicCAS(&tab[sx], kEmpty32, i);
+                    if (o == kEmpty32) break;
+                }
+                if (kl[o] == k[e]) break;
+                sx = (sx + 1) & smask;
+            }
+            sl[e] = sx;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) atomicMin(&tab[sl[e]], i);
+    }
+    __syncthreads();
+    uint32_t el[E];  // (index << 12) | f
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        el[e] = (i << 12) | (i < m ? tab[sl[e]] : 0u);
+    }
+    __syncthreads();
+    uint32_t* A = tab;
+    uint32_t* B = tab + CAP;
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
-        const uint32_t sh = pass ? 7u : 0u;
-        const uint32_t nbits = pass ? 5u : 7u;
-        for (uint32_t i = tid; i < W * 128; i += BS) wc[i] = 0;
+        const uint32_t sh = pass ? 6u : 0u;
+        for (uint32_t i = tid; i < W * 64; i += BS) wc[i] = 0;
         __syncthreads();
         uint32_t rk[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t q = w * 64 * E + e * 64 + lane;
-            const uint32_t d = ((el[e] & 0xFFFFu) >> sh) & ((1u << nbits) - 1);
-            rk[e] = wave_rank(d, q < m, nbits, wc + w * 128);
+            rk[e] = wave_rank((el[e] >> sh) & 63u, q < m, 6, wc + w * 64);
         }
         __syncthreads();
-        if (tid < 128) {
-            uint32_t run = 0;
+        uint32_t dtot = 0;
+        if (tid < 64) {
             for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = wc[ww * 128 + tid];
-                wc[ww * 128 + tid] = (uint16_t)run;
-                run += c;
+                const uint32_t c = wc[ww * 64 + tid];
+                wc[ww * 64 + tid] = (uint16_t)dtot;
+                dtot += c;
             }
-            dtot[tid] = run;
         }
-        __syncthreads();
-        const uint32_t dv = tid < 128 ? dtot[tid] : 0u;
-        const uint32_t ds = block_excl_scan<BS>(dv, tmp, nullptr);
-        if (tid < 128) dst_[tid] = ds;
+        const uint32_t ds = block_excl_scan<BS>(tid < 64 ? dtot : 0u, tmp, nullptr);
+        if (tid < 64) dst_[tid] = ds;
         __syncthreads();
         uint32_t* out = pass ? B : A;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t q = w * 64 * E + e * 64 + lane;
             if (q < m) {
-                const uint32_t d = ((el[e] & 0xFFFFu) >> sh) & ((1u << nbits) - 1);
-                out[dst_[d] + wc[w * 128 + d] + rk[e]] = el[e];
+                const uint32_t d = (el[e] >> sh) & 63u;
+                out[dst_[d] + wc[w * 64 + d] + rk[e]] = el[e];
             }
         }
         __syncthreads();
@@ -921,17 +1372,16 @@ __global__ __launch_bounds__(512) void k_finish(const Job* jobs, const uint64_t*
             }
         }
     }
-
-    // gather, then write (the output may be the source: in-place within the block)
     uint64_t ok[E];
     V ov[E];
+    bool bad = false;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t q = tid + e * BS;
         if (q < m) {
-            uint32_t i = B[q] >> 16;
+            uint32_t i = B[q] >> 12;
             if (i >= m) {
-                atomicOr(&info->status, kStatusBaseIndex);
+                bad = true;
                 i = 0;
             }
             ok[e] = kl[i];
@@ -946,6 +1396,20 @@ __global__ __launch_bounds__(512) void k_finish(const Job* jobs, const uint64_t*
             out_keys[start + q] = ok[e];
             out_vals[start + q] = ov[e];
         }
+    }
+    if (bad) atomicOr(&info->status, kStatusBaseIndex);
+}
+
+// Copy jobs: buckets that are final but sit in T (Section 3.4).
+template <typename V>
+__global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                              uint64_t* out_keys, V* out_vals)
+{
+    const Job j = jobs[blockIdx.x];
+    const uint64_t st = j.start;
+    for (uint32_t i = threadIdx.x; i < j.len; i += 256) {
+        out_keys[st + i] = src_keys[st + i];
+        out_vals[st + i] = src_vals[st + i];
     }
 }
 

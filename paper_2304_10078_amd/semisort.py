@@ -66,6 +66,10 @@ def lib():
         L.ss_last_error.restype = ctypes.c_char_p
         L.ss_sync.argtypes = [vp]
         L.ss_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ss_profile_enable.argtypes = [vp, i32]
+        L.ss_set_option.argtypes = [vp, i32, ctypes.c_int64]
+        L.ss_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
+                                      ctypes.POINTER(u64)]
         L.ss_semisort_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
         L.ss_semisort_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
@@ -116,6 +120,26 @@ class Context:
     def check(self, st):
         if st != SS_OK:
             raise SemisortError(st, lib().ss_last_error(self.h).decode())
+
+    PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish")
+    OPT_DIST_VARIANT = 1
+
+    def set_option(self, option, value):
+        self.check(lib().ss_set_option(self.h, int(option), int(value)))
+
+    def profile_enable(self, on=True):
+        self.check(lib().ss_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        """{pass: (total_ms, launches, units)} accumulated since profile_enable."""
+        out = {}
+        for k, name in enumerate(self.PROF_KINDS):
+            ms = ctypes.c_double()
+            la = ctypes.c_uint64()
+            un = ctypes.c_uint64()
+            self.check(lib().ss_profile_read(self.h, k, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un)))
+            out[name] = (ms.value, la.value, un.value)
+        return out
 
     def workspace_bytes(self):
         b = ctypes.c_size_t()

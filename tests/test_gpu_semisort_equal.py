@@ -163,3 +163,20 @@ def test_batch_matches_each_instance_alone():
         if b > a:
             ak, av = run_equal(k[a:b], v[a:b])
             assert np.array_equal(ak, ko[a:b]) and np.array_equal(av, vo[a:b]), f"instance {i} differs from alone"
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_every_distribution_variant_gives_the_same_result(variant):
+    ctx = S.context(0)
+    try:
+        for name, n in [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 2_000_003)]:
+            k, v = I.np_workload(name, n, 13)
+            ctx.set_option(ctx.OPT_DIST_VARIANT, 0)
+            ref = run_equal(k, v)
+            ctx.set_option(ctx.OPT_DIST_VARIANT, variant)
+            _say(f"case: variant {variant} {name} n={n}")
+            ko, vo = run_equal(k, v)
+            assert_semisort_equal(k, v, ko, vo, ctx=f"variant {variant} {name}")
+            assert np.array_equal(ko, ref[0]) and np.array_equal(vo, ref[1])
+    finally:
+        ctx.set_option(ctx.OPT_DIST_VARIANT, 0)

@@ -228,6 +228,7 @@ def test_sample_indices_in_range_deterministic_and_uniform():
 def test_sample_size_and_threshold_use_natural_log():
     # Section 3.6: |S| = 500 log n; natural log reproduces Table 3's heavy column
     assert O.sample_size(10 ** 9, 500) == math.ceil(500 * math.log(1e9))
+    assert O.sample_size(5000, 500) == 5000 // 8  # capped for small subproblems
     assert O.heavy_threshold(10 ** 9) == 21
     assert O.heavy_threshold(16) == 3  # Fig. 2: 'more than 2 samples' with n = 16
 
