@@ -130,6 +130,23 @@ ss_status ss_semisort_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void*
                                   uint64_t nseg, uint64_t* keys_out, void* vals_out,
                                   const ss_params* params);
 
+/* semisort_< (Section 2.1 with the comparison base case of Section 3.3):
+ * reorders the records into ascending key order, records with equal keys in
+ * input order (stable).  The result is unique: a stable sort by key.
+ * Buckets come from sorted splitters instead of hash bits (keys sampled
+ * often enough get their own equality buckets, placed in key order), so the
+ * concatenated buckets are already in key order; hash_mode is ignored.
+ * params may be NULL (defaults). */
+ss_status ss_semisort_less(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                           uint32_t val_bytes, uint64_t n, uint64_t* keys_out,
+                           void* vals_out, const ss_params* params);
+
+/* Batched semisort_<: packed instances as in ss_semisort_equal_batch. */
+ss_status ss_semisort_less_batch(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                 uint32_t val_bytes, const uint64_t* seg_offsets,
+                                 uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                 const ss_params* params);
+
 /* One level of Algorithm 1 on one subproblem, for inspection: Step 1
  * (sampling, heavy keys, heavy table) and Step 2 (counting matrix, column-major
  * prefix, distribution), without Step 3.  Writes the distributed array T to

@@ -38,7 +38,7 @@ struct ss_ctx {
     DevBuf t_keys, t_vals;
     DevBuf segs[2];
     DevBuf jobs;
-    DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink;
+    DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     std::vector<Seg> host_segs;
@@ -216,6 +216,9 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
 
 // Base-case and copy jobs of one level: one launch per non-empty class.
 // jobs holds kJobClasses lists of `cap` entries.
+// Base-case and copy jobs of one level: one launch per non-empty class.
+// jobs holds kJobClasses lists of `cap` entries.  MODE 0/1: semisort_= with
+// the mixing / identity hash; MODE 2: semisort_<.
 template <int MODE, typename V>
 void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
                    uint64_t* ok, void* ov)
@@ -224,17 +227,25 @@ void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_
     LevelInfo* info = (LevelInfo*)c->info.p;
     const V* svv = (const V*)sv;
     V* ovv = (V*)ov;
-    if (njobs[0])
-        hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv, info);
-    if (njobs[1])
-        hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, jobs + cap, sk, svv, ok,
-                           ovv, info);
-    if (njobs[2])
-        hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, jobs + 2 * (size_t)cap, sk,
-                           svv, ok, ovv, info);
-    if (njobs[3])
-        hipLaunchKernelGGL((k_base_2pass<MODE, V>), dim3(njobs[3]), dim3(512), 0, c->stream, jobs + 3 * (size_t)cap,
-                           sk, svv, ok, ovv, info);
+    const Job* j1 = jobs + cap;
+    const Job* j2 = jobs + 2 * (size_t)cap;
+    const Job* j3 = jobs + 3 * (size_t)cap;
+    if constexpr (MODE == 2) {
+        if (njobs[0]) hipLaunchKernelGGL((k_base_less<V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv);
+        if (njobs[1]) hipLaunchKernelGGL((k_base_less<V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, j1, sk, svv, ok, ovv);
+        if (njobs[2]) hipLaunchKernelGGL((k_base_less<V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv);
+        if (njobs[3]) hipLaunchKernelGGL((k_base_less<V, 8>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv);
+    } else {
+        if (njobs[0])
+            hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv, info);
+        if (njobs[1])
+            hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, j1, sk, svv, ok, ovv, info);
+        if (njobs[2])
+            hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv, info);
+        if (njobs[3])
+            hipLaunchKernelGGL((k_base_2pass<MODE, V>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv,
+                               info);
+    }
     if (njobs[kCopyClass])
         hipLaunchKernelGGL((k_copy<V>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
                            jobs + (size_t)kCopyClass * cap, sk, svv, ok, ovv);
@@ -245,7 +256,8 @@ void launch_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, 
                  uint64_t* ok, void* ov, uint64_t records)
 {
     ProfScope ps(c, SS_PROF_FINISH, records);
-    if (mode == 1) launch_jobs_m<1, V>(c, njobs, cap, sk, sv, ok, ov);
+    if (mode == 2) launch_jobs_m<2, V>(c, njobs, cap, sk, sv, ok, ov);
+    else if (mode == 1) launch_jobs_m<1, V>(c, njobs, cap, sk, sv, ok, ov);
     else launch_jobs_m<0, V>(c, njobs, cap, sk, sv, ok, ov);
 }
 
@@ -254,11 +266,13 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
 {
     {
         ProfScope ps(c, SS_PROF_SAMPLE, a.nsegs);
-        hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        if constexpr (MODE == 2) hipLaunchKernelGGL(k_sample_less, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
     }
     {
         ProfScope ps(c, SS_PROF_COUNT, records);
-        hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        if constexpr (MODE == 2) hipLaunchKernelGGL(k_count_less, dim3(tiles), dim3(1024), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
     }
     {
         ProfScope ps(c, SS_PROF_SCAN, tiles);
@@ -295,7 +309,8 @@ template <typename V>
 void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks,
                     uint64_t records)
 {
-    if (mode == 1) launch_level<1, V>(c, a, tiles, chunks, records);
+    if (mode == 2) launch_level<2, V>(c, a, tiles, chunks, records);
+    else if (mode == 1) launch_level<1, V>(c, a, tiles, chunks, records);
     else launch_level<0, V>(c, a, tiles, chunks, records);
 }
 
@@ -310,6 +325,7 @@ ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunk
     if ((s = ensure(c, c->heavy_list, (size_t)nsegs * kHeavyMax * 8)) != SS_OK) return s;
     if ((s = ensure(c, c->tab_h, (size_t)nsegs * 2 * kHeavySlotsMax * 8)) != SS_OK) return s;
     if ((s = ensure(c, c->tab_id, (size_t)nsegs * 2 * kHeavySlotsMax * 2)) != SS_OK) return s;
+    if ((s = ensure(c, c->bfin, (size_t)nsegs * kNbStride)) != SS_OK) return s;
     return SS_OK;
 }
 
@@ -341,6 +357,8 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.sample_mult = p.c;
     a.alpha = p.alpha;
     a.adaptive_nl = 1;
+    a.ordered = p.mode == 2;
+    a.bfin = (uint8_t*)c->bfin.p;
     return a;
 }
 
@@ -364,7 +382,7 @@ void host_prefix(std::vector<Seg>& segs, const Params& p, uint32_t* tiles, uint3
 
 // The whole engine: `offs` are instance boundaries (host), total n = offs.back().
 template <typename V>
-ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
+ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
                              uint64_t ninst, uint64_t* keys_out, void* vals_out, const Params& p)
 {
     const uint64_t n = offs[ninst];
@@ -381,7 +399,7 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
             s.start = st;
             s.len = len;
             s.ibase = st;
-            s.nl_bits = (uint16_t)std::min(p.nl0, choose_nl(len, p.alpha, kLightBitsMax, 0));
+            s.nl_bits = (uint8_t)std::min(p.nl0, choose_nl(len, p.alpha, kLightBitsMax, 0));
             s.shift = 0;
             c->host_segs.push_back(s);
         } else if (len >= 2) {
@@ -498,6 +516,8 @@ ss_status run_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
             pa.info = (LevelInfo*)c->info.p;
             pa.alpha = p.alpha;
             pa.finals_in_out = fin_k == keys_out;
+            pa.ordered = p.mode == 2;
+            pa.bfin = (const uint8_t*)c->bfin.p;
             {
                 ProfScope ps(c, SS_PROF_PLAN, nsegs);
                 hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
@@ -614,7 +634,7 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink};
+                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto& p : c->pending) {
@@ -690,7 +710,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
 {
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink};
+                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -706,8 +726,8 @@ ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, u
     if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     const uint64_t offs[2] = {0, n};
-    return vb == 8 ? run_semisort_equal<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
-                   : run_semisort_equal<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
+    return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
+                   : run_semisort<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
 }
 
 ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
@@ -726,8 +746,43 @@ ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* v
     Params p;
     if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
-    return vb == 8 ? run_semisort_equal<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
-                   : run_semisort_equal<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+    return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
+                   : run_semisort<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+}
+
+ss_status ss_semisort_less(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
+                           uint64_t* keys_out, void* vals_out, const ss_params* params)
+{
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    p.mode = 2;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    const uint64_t offs[2] = {0, n};
+    return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
+                   : run_semisort<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
+}
+
+ss_status ss_semisort_less_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                 const uint64_t* offs, uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                 const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (!offs) return fail(c, SS_EINVAL, "null seg_offsets");
+    if (nseg == 0) return SS_OK;
+    if (offs[0] != 0) return fail(c, SS_EINVAL, "seg_offsets[0] must be 0");
+    for (uint64_t i = 0; i < nseg; ++i)
+        if (offs[i + 1] < offs[i]) return fail(c, SS_EINVAL, "seg_offsets must be non-decreasing");
+    const uint64_t n = offs[nseg];
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    p.mode = 2;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
+                   : run_semisort<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
 }
 
 ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
@@ -746,7 +801,7 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     segs[0].start = 0;
     segs[0].len = (uint32_t)n;
     segs[0].ibase = 0;
-    segs[0].nl_bits = (uint16_t)p.nl0;
+    segs[0].nl_bits = (uint8_t)p.nl0;
     segs[0].shift = 0;
     uint32_t tiles, chunks, tile;
     host_prefix(segs, p, &tiles, &chunks, &tile);

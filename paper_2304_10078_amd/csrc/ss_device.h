@@ -42,8 +42,9 @@ struct Seg {
     uint32_t tile0;    // first tile of the subproblem in the level's tile list
     uint32_t chunk0;   // first scan chunk
     uint32_t ntiles;
-    uint16_t nl_bits;  // light id bits b (n_L = 2^b)
-    uint16_t shift;    // first hash bit of the light id
+    uint8_t nl_bits;   // light id bits b (n_L = 2^b); a cap until the sampling kernel refines it
+    uint8_t shift;     // first hash bit of the light id (hash-bucketed subproblems)
+    uint16_t nbk;      // number of buckets, written by the sampling kernel
     uint16_t nheavy;   // n_H, written by the sampling kernel
     uint16_t hlog2;    // bits 0-7: log2 slots per heavy table (0 when n_H = 0); bits 8-15: table salt
 };
@@ -99,6 +100,8 @@ struct LevelArgs {
     uint32_t sample_mult;
     uint32_t alpha;
     uint32_t adaptive_nl;  // choose n_L per subproblem from the sample's light fraction
+    uint32_t ordered;      // buckets from sorted splitters (semisort_<) instead of hash bits
+    uint8_t* bfin;         // [nsegs][kNbStride]: 1 for buckets that are final (one key each)
 };
 
 // ---------------------------------------------------------------- hashing
@@ -484,10 +487,12 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? hv[o] : 0ull;
         a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
     }
+    for (uint32_t b = tid; b < nL + nh; b += BS) a.bfin[(size_t)sid * kNbStride + b] = b >= nL ? 1 : 0;
     if (tid == 0) {
         a.segs[sid].nheavy = (uint16_t)nh;
         a.segs[sid].hlog2 = (uint16_t)sh_hfield;
-        a.segs[sid].nl_bits = (uint16_t)sh_nl;
+        a.segs[sid].nl_bits = (uint8_t)sh_nl;
+        a.segs[sid].nbk = (uint16_t)(nL + nh);
     }
 }
 
@@ -513,7 +518,7 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     const uint64_t send = (uint64_t)sg.start + sg.len;
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint32_t nL = 1u << sg.nl_bits;
-    const uint32_t nb = nL + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     const uint32_t hlog2 = sg.hlog2;  // slot bits and salt
     const uint32_t slots = (hlog2 & 0xFFu) ? (1u << (hlog2 & 0xFFu)) : 0u;
 
@@ -553,6 +558,275 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b];
 }
 
+// ================================================================ semisort_<
+// Order-preserving buckets (semisort_< with groups in ascending key order).
+// The sample is sorted by key; keys sampled at least ceil(ln n') times are
+// heavy and get equality buckets; splitters are taken evenly from the
+// remaining sorted samples.  Boundaries B_0 < ... < B_{m-1} (splitters and
+// heavy keys) give buckets in key order: range R_0, then for each boundary
+// its equality bucket (heavy keys only) and the next range.  A key k falls
+// in R_j with j = #{boundaries <= k}, unless B_{j-1} = k is heavy.  Per
+// subproblem the boundaries go to tab_h and, in tab_id, rid[j] = id of R_j
+// (bit 15 of rid[j], j < m: B_j is heavy; its equality bucket is rid[j] + 1).
+
+__device__ __forceinline__ uint32_t lower_bound_u64(const uint64_t* a, uint32_t n, uint64_t x)
+{
+    uint32_t lo = 0, len = n;
+    while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (a[lo + half] < x) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t n, uint64_t x)
+{
+    uint32_t lo = 0, len = n;
+    while (len > 0) {
+        const uint32_t half = len >> 1;
+        if (a[lo + half] <= x) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t less_bucket(uint64_t k, const uint64_t* bnd, const uint16_t* rid, uint32_t m)
+{
+    const uint32_t j = upper_bound_u64(bnd, m, k);
+    if (j > 0 && (rid[j - 1] & 0x8000u) && bnd[j - 1] == k) return (rid[j - 1] & 0x7FFFu) + 1;
+    return rid[j] & 0x7FFFu;
+}
+
+__global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
+{
+    constexpr int BS = 1024;
+    __shared__ uint64_t smp[kSampleMax];
+    __shared__ uint64_t spl[kNbStride];
+    __shared__ uint64_t hv[kHeavyMax];
+    __shared__ uint32_t hf[kNbStride];
+    __shared__ uint32_t tmp[20];
+    __shared__ uint32_t sh_s, sh_tau, sh_R, sh_nl;
+
+    const uint32_t sid = blockIdx.x;
+    const uint32_t tid = threadIdx.x;
+    const Seg sg = a.segs[sid];
+    if (tid == 0) {
+        const double L = log((double)sg.len);
+        double sd = ceil((double)a.sample_mult * L);
+        uint32_t s = sg.len < 2 ? 0u : (uint32_t)sd;
+        if (s > sg.len / 8) s = sg.len / 8;
+        if (s > kSampleMax) s = kSampleMax;
+        sh_s = s;
+        sh_tau = sg.len < 3 ? 1u : (uint32_t)ceil(L);
+    }
+    __syncthreads();
+    const uint32_t s = sh_s, tau = sh_tau;
+    uint32_t P = 2;
+    while (P < s) P <<= 1;
+    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
+    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
+    const uint64_t k1 = splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
+    for (uint32_t i = tid; i < P; i += BS) {
+        uint64_t v = ~0ull;
+        if (i < s) {
+            uint64_t r = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
+            uint64_t idx = __umul64hi(r, (uint64_t)sg.len);
+            v = a.src_keys[(uint64_t)sg.start + idx];
+        }
+        smp[i] = v;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t t = tid; t < (P >> 1); t += BS) {
+                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                const uint32_t l = i + j;
+                const bool up = (i & k) == 0;
+                const uint64_t x = smp[i], y = smp[l];
+                if ((x > y) == up) {
+                    smp[i] = y;
+                    smp[l] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // heavy keys in ascending key order; per sample: heavy or not, and the
+    // rank of the non-heavy ones
+    const uint32_t per = (s + BS - 1) / BS;
+    const uint32_t lo = tid * per;
+    const uint32_t hi = lo + per < s ? lo + per : s;
+    uint32_t nhs = 0, nls = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const bool start = (i == 0) || smp[i] != smp[i - 1];
+        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) ++nhs;
+        const uint32_t lb = lower_bound_u64(smp, s, smp[i]);
+        const uint32_t ub = upper_bound_u64(smp, s, smp[i]);
+        if (ub - lb < tau) ++nls;
+    }
+    uint32_t tot_h = 0, tot_l = 0;
+    uint32_t hid = block_excl_scan<BS>(nhs, tmp, &tot_h);
+    uint32_t lrank = block_excl_scan<BS>(nls, tmp, &tot_l);
+    const uint32_t nh = tot_h < kHeavyMax ? tot_h : kHeavyMax;
+    if (tot_h > kHeavyMax && tid == 0) atomicOr(&a.info->status, kStatusHeavyTable);
+    if (tid == 0) {
+        // number of ranges: the fewest-levels rule on the estimated light
+        // records, within the bucket budget and the distinct light samples
+        uint32_t nl = sg.nl_bits;
+        if (a.adaptive_nl && s) {
+            const double light = (double)sg.len * (double)tot_l / (double)s;
+            const double target = (double)(a.alpha / 2);
+            const uint32_t cap = sg.nl_bits;
+            uint32_t nl1 = 1;
+            while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
+            if (nl1 <= cap) {
+                nl = nl1;
+            } else {
+                uint32_t nl2 = 1;
+                while (nl2 < 31 && (double)(1u << nl2) * (double)(1u << kLightBitsMax) * target < light) ++nl2;
+                nl = nl2 <= cap ? nl2 : cap;
+            }
+        }
+        uint32_t R = 1u << nl;
+        if (R > kNbStride - 2 * nh) R = kNbStride - 2 * nh;
+        if (R > tot_l) R = tot_l ? tot_l : 1u;
+        sh_R = R;
+        sh_nl = nl;
+    }
+    __syncthreads();
+    const uint32_t R = sh_R;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const bool start = (i == 0) || smp[i] != smp[i - 1];
+        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) {
+            if (hid < kHeavyMax) {
+                hv[hid] = smp[i];
+                a.heavy_list[(size_t)sid * kHeavyMax + hid] = smp[i];
+            }
+            ++hid;
+        }
+        const uint32_t lb = lower_bound_u64(smp, s, smp[i]);
+        const uint32_t ub = upper_bound_u64(smp, s, smp[i]);
+        if (ub - lb < tau) {
+            // splitter j (j < R-1) sits at light rank floor((j+1) * tot_l / R);
+            // with R <= tot_l the ranks of different j differ, and the only
+            // candidate for rank r is j+1 = ceil(r * R / tot_l)
+            const uint64_t r = lrank;
+            const uint64_t jp1 = (r * R + tot_l - 1) / tot_l;
+            if (jp1 >= 1 && jp1 < R && (jp1 * tot_l) / R == r) spl[jp1 - 1] = smp[i];
+            ++lrank;
+        }
+    }
+    __syncthreads();
+    // distinct splitters, compacted into smp (the sample is no longer needed)
+    const uint32_t nc = R - 1;
+    const uint32_t per2 = (nc + BS - 1) / BS;
+    const uint32_t c0 = tid * per2;
+    const uint32_t c1 = c0 + per2 < nc ? c0 + per2 : nc;
+    uint32_t nv = 0;
+    for (uint32_t j = c0; j < c1; ++j) nv += (j == 0 || spl[j] != spl[j - 1]) ? 1u : 0u;
+    uint32_t ns = 0;
+    uint32_t vat = block_excl_scan<BS>(nv, tmp, &ns);
+    for (uint32_t j = c0; j < c1; ++j)
+        if (j == 0 || spl[j] != spl[j - 1]) smp[vat++] = spl[j];
+    __syncthreads();
+    // merge splitters and heavy keys into the sorted boundary list
+    const uint32_t m = ns + nh;
+    uint64_t* bnd = a.tab_h + (size_t)sid * 2 * kHeavySlotsMax;
+    uint16_t* rid = a.tab_id + (size_t)sid * 2 * kHeavySlotsMax;
+    for (uint32_t j = tid; j < ns; j += BS) {
+        const uint32_t pos = j + lower_bound_u64(hv, nh, smp[j]);
+        bnd[pos] = smp[j];
+        hf[pos] = 0;
+    }
+    for (uint32_t i = tid; i < nh; i += BS) {
+        const uint32_t pos = i + lower_bound_u64(smp, ns, hv[i]);
+        bnd[pos] = hv[i];
+        hf[pos] = 1;
+    }
+    __syncthreads();
+    // rid[j] = j + #heavy boundaries before j, for j = 0..m
+    const uint32_t per3 = (m + 1 + BS - 1) / BS;
+    const uint32_t d0 = tid * per3;
+    const uint32_t d1 = d0 + per3 < m + 1 ? d0 + per3 : m + 1;
+    uint32_t hcount = 0;
+    for (uint32_t j = d0; j < d1; ++j) hcount += (j < m) ? hf[j] : 0u;
+    uint32_t hbefore = block_excl_scan<BS>(hcount, tmp, nullptr);
+    const uint32_t nb = m + 1 + nh;
+    uint8_t* fin = a.bfin + (size_t)sid * kNbStride;
+    for (uint32_t b = tid; b < nb; b += BS) fin[b] = 0;
+    __syncthreads();
+    for (uint32_t j = d0; j < d1; ++j) {
+        const uint32_t r = j + hbefore;
+        const bool heavy = j < m && hf[j];
+        rid[j] = (uint16_t)(r | (heavy ? 0x8000u : 0u));
+        if (heavy) fin[r + 1] = 1;
+        hbefore += heavy ? 1u : 0u;
+    }
+    if (tid == 0) {
+        a.segs[sid].nheavy = (uint16_t)nh;
+        a.segs[sid].nbk = (uint16_t)nb;
+        a.segs[sid].nl_bits = (uint8_t)sh_nl;
+        a.segs[sid].hlog2 = 0;
+    }
+}
+
+// Counting pass for splitter buckets: binary search over the boundaries in LDS.
+__global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
+{
+    constexpr int BS = 1024;
+    __shared__ uint32_t cnt[kNbStride];
+    __shared__ uint64_t bnd[kNbStride];
+    __shared__ uint16_t rid[kNbStride + 1];
+    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tid = threadIdx.x;
+    const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
+    const Seg sg = a.segs[sid];
+    const uint32_t lt = t - sg.tile0;
+    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * a.tile;
+    const uint64_t send = (uint64_t)sg.start + sg.len;
+    const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
+    const uint32_t nb = sg.nbk;
+    const uint32_t m = nb - 1 - sg.nheavy;
+    for (uint32_t b = tid; b < nb; b += BS) cnt[b] = 0;
+    for (uint32_t j = tid; j <= m; j += BS) {
+        if (j < m) bnd[j] = a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + j];
+        rid[j] = a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + j];
+    }
+    __syncthreads();
+    const uint64_t* keys = a.src_keys;
+    uint16_t* bids = a.bids;
+    constexpr int U = 8;
+    uint64_t i = r0 + tid;
+    for (; i + (U - 1) * BS < r1; i += U * BS) {
+        uint64_t kk[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) kk[u] = keys[i + (uint64_t)u * BS];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t b = less_bucket(kk[u], bnd, rid, m);
+            bids[i + (uint64_t)u * BS] = (uint16_t)b;
+            atomicAdd(&cnt[b], 1u);
+        }
+    }
+    for (; i < r1; i += BS) {
+        const uint32_t b = less_bucket(keys[i], bnd, rid, m);
+        bids[i] = (uint16_t)b;
+        atomicAdd(&cnt[b], 1u);
+    }
+    __syncthreads();
+    uint32_t* row = a.C + (size_t)t * kNbStride;
+    for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b];
+}
+
 // ================================================================ Step 2b
 // Column-major prefix X of the counting matrix (Algorithm 1): per bucket, the
 // records of all earlier buckets plus that bucket's records in earlier
@@ -568,7 +842,7 @@ __global__ __launch_bounds__(256) void k_scan_chunks(LevelArgs a)
     const uint32_t t0 = sg.tile0 + lc * kChunk;
     const uint32_t tend = sg.tile0 + sg.ntiles;
     const uint32_t t1 = t0 + kChunk < tend ? t0 + kChunk : tend;
-    const uint32_t nb = (1u << sg.nl_bits) + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     for (uint32_t b = threadIdx.x; b < nb; b += 256) {
         uint32_t s = 0;
         for (uint32_t t = t0; t < t1; ++t) s += a.C[(size_t)t * kNbStride + b];
@@ -582,7 +856,7 @@ __global__ __launch_bounds__(1024) void k_scan_buckets(LevelArgs a)
     const uint32_t sid = blockIdx.x / kBucketGroups;
     const uint32_t bg = blockIdx.x % kBucketGroups;
     const Seg sg = a.segs[sid];
-    const uint32_t nb = (1u << sg.nl_bits) + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     if (bg * 64 >= nb) return;  // uniform over the block
     const uint32_t col = threadIdx.x & 63u, row = threadIdx.x >> 6;
     const uint32_t b = bg * 64 + col;
@@ -613,7 +887,7 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(LevelArgs a)
     __shared__ uint32_t tmp[20];
     const uint32_t sid = blockIdx.x;
     const Seg sg = a.segs[sid];
-    const uint32_t nb = (1u << sg.nl_bits) + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     const uint32_t b0 = 2 * threadIdx.x, b1 = b0 + 1;
     const uint32_t v0 = b0 < nb ? a.tot[(size_t)sid * kNbStride + b0] : 0u;
     const uint32_t v1 = b1 < nb ? a.tot[(size_t)sid * kNbStride + b1] : 0u;
@@ -637,7 +911,7 @@ __global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
     const uint32_t t0 = sg.tile0 + lc * kChunk;
     const uint32_t tend = sg.tile0 + sg.ntiles;
     const uint32_t t1 = t0 + kChunk < tend ? t0 + kChunk : tend;
-    const uint32_t nb = (1u << sg.nl_bits) + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     const uint32_t* bs = a.bstart + (size_t)sid * (kNbStride + 1);
     for (uint32_t b = threadIdx.x; b < nb; b += 256) {
         uint32_t x = bs[b] + a.P[(size_t)ch * kNbStride + b];
@@ -663,9 +937,9 @@ __global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
 // are final (heavy, single record, or all hash bits used) go to fin_* -- the
 // output -- when that is safe, so they are never copied again.
 
-__device__ __forceinline__ bool bucket_is_final(uint32_t b, uint32_t nL, uint32_t sz, bool all_bits_used)
+__device__ __forceinline__ bool bucket_is_final(bool one_key_bucket, uint32_t sz, bool all_bits_used)
 {
-    return b >= nL || sz <= 1 || all_bits_used;
+    return one_key_bucket || sz <= 1 || all_bits_used;
 }
 
 template <typename V, int W, int E>
@@ -696,11 +970,12 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint64_t rlast = r1 - 1;
     const uint32_t nL = 1u << sg.nl_bits;
-    const uint32_t nb = nL + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     const uint32_t nbits = 32 - __clz(nb - 1);
     const bool split = a.fin_keys != a.dst_keys;
-    const bool all_bits = (uint32_t)sg.shift + sg.nl_bits >= 64;
+    const bool all_bits = a.ordered == 0 && (uint32_t)sg.shift + sg.nl_bits >= 64;
     const uint32_t* bsz = a.bstart + (size_t)sid * (kNbStride + 1);
+    const uint8_t* fin = a.bfin + (size_t)sid * kNbStride;
     const V* src_vals = (const V*)a.src_vals;
     V* dst_vals = (V*)a.dst_vals;
     V* fin_vals = (V*)a.fin_vals;
@@ -712,7 +987,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     for (uint32_t b = tid; b < nb; b += BS) {
         uint32_t g = a.C[(size_t)t * kNbStride + b];
-        if (split && bucket_is_final(b, nL, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
+        if (split && bucket_is_final(fin[b] != 0, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
         gbase[b] = g;
     }
     for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
@@ -875,11 +1150,12 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint64_t rlast = r1 - 1;
     const uint32_t nL = 1u << sg.nl_bits;
-    const uint32_t nb = nL + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     const uint32_t nbits = 32 - __clz(nb - 1);
     const bool split = a.fin_keys != a.dst_keys;
-    const bool all_bits = (uint32_t)sg.shift + sg.nl_bits >= 64;
+    const bool all_bits = a.ordered == 0 && (uint32_t)sg.shift + sg.nl_bits >= 64;
     const uint32_t* bsz = a.bstart + (size_t)sid * (kNbStride + 1);
+    const uint8_t* fin = a.bfin + (size_t)sid * kNbStride;
     const V* src_vals = (const V*)a.src_vals;
     V* dst_vals = (V*)a.dst_vals;
     V* fin_vals = (V*)a.fin_vals;
@@ -890,7 +1166,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
 
     for (uint32_t b = tid; b < nb; b += BS) {
         uint32_t g = a.C[(size_t)t * kNbStride + b];
-        if (split && bucket_is_final(b, nL, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
+        if (split && bucket_is_final(fin[b] != 0, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
         gbase[b] = g;
         ptot[b] = 0;
     }
@@ -1000,6 +1276,8 @@ struct PlanArgs {
     LevelInfo* info;
     uint32_t alpha;
     uint32_t finals_in_out;  // final buckets were written to the output by the distribution
+    uint32_t ordered;        // splitter buckets: no hash bits are consumed
+    const uint8_t* bfin;     // [nsegs][kNbStride] one-key bucket flags
 };
 
 struct PlanCount {
@@ -1018,9 +1296,9 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
     const uint32_t st = bs[b];
     const uint32_t sz = bs[b + 1] - st;
     if (sz == 0) return;
-    const uint32_t shift2 = sg.shift + sg.nl_bits;
+    const uint32_t shift2 = p.ordered ? 0u : (uint32_t)sg.shift + sg.nl_bits;
     const bool all_bits_used = shift2 >= 64;
-    if (bucket_is_final(b, nL, sz, all_bits_used)) {
+    if (bucket_is_final(p.bfin[(size_t)sidx * kNbStride + b] != 0, sz, all_bits_used)) {
         if (p.finals_in_out) return;  // already in place
         for (uint32_t o = 0; o < sz; o += kCopyChunk) {
             const uint32_t l = sz - o < kCopyChunk ? sz - o : kCopyChunk;
@@ -1040,8 +1318,9 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
                 ns.len = sz;
                 ns.ibase = sg.ibase;
                 ns.tile0 = ns.chunk0 = ns.ntiles = 0;
-                ns.nl_bits = (uint16_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2);
-                ns.shift = (uint16_t)shift2;
+                ns.nl_bits = (uint8_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2);
+                ns.shift = (uint8_t)shift2;
+                ns.nbk = 0;
                 ns.nheavy = 0;
                 ns.hlog2 = 0;
                 p.next[*seg_at] = ns;
@@ -1067,7 +1346,7 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs p)
     const uint32_t sidx = blockIdx.x;
     const Seg sg = p.segs[sidx];
     const uint32_t nL = 1u << sg.nl_bits;
-    const uint32_t nb = nL + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     PlanCount cnt{};
     uint32_t dummy_s = 0, dummy_j[kJobClasses] = {};
     for (uint32_t b = threadIdx.x; b < nb; b += 256) plan_bucket(p, sidx, sg, b, nL, cnt, false, &dummy_s, dummy_j);
@@ -1400,6 +1679,131 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
 }
 
+// Base case of semisort_< (Section 3.3: a stable comparison sort of a small
+// bucket).  On the GPU a stable LSD radix sort of the bucket in LDS: keys
+// are offset by the bucket's minimum and only the bytes in which they differ
+// are sorted, 8 bits per pass, each pass a stable multisplit (ballot match
+// plus per-wave counters).  All loads precede all stores, so the output may
+// be the source.
+template <typename V, int W>
+__global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                                      uint64_t* out_keys, V* out_vals)
+{
+    constexpr int BS = W * 64, E = 8, CAP = BS * E;
+    __shared__ uint64_t sk[CAP];
+    __shared__ V sv[CAP];
+    __shared__ uint16_t wc[W * 256];
+    __shared__ uint32_t dst_[256];
+    __shared__ uint32_t tmp[20];
+    __shared__ unsigned long long sh_min, sh_max;
+
+    const Job j = jobs[blockIdx.x];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t m = j.len;
+    const uint64_t start = j.start;
+    uint64_t k[E];
+    V v[E];
+    uint64_t mn = ~0ull, mx = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t q = w * 64 * E + e * 64 + lane;
+        k[e] = q < m ? src_keys[start + q] : 0ull;
+        v[e] = q < m ? src_vals[start + q] : (V)0;
+        if (q < m) {
+            mn = k[e] < mn ? k[e] : mn;
+            mx = k[e] > mx ? k[e] : mx;
+        }
+    }
+    if (tid == 0) {
+        sh_min = ~0ull;
+        sh_max = 0;
+    }
+    __syncthreads();
+    atomicMin(&sh_min, (unsigned long long)mn);
+    atomicMax(&sh_max, (unsigned long long)mx);
+    __syncthreads();
+    const uint64_t kmin = sh_min;
+    const uint64_t span = sh_max - kmin;
+    const uint32_t bits = span ? 64u - (uint32_t)__clzll(span) : 0u;
+    const uint32_t npass = (bits + 7) / 8;
+    for (uint32_t pass = 0; pass < npass; ++pass) {
+        const uint32_t sh = 8 * pass;
+        for (uint32_t i = tid; i < W * 256; i += BS) wc[i] = 0;
+        __syncthreads();
+        uint32_t rk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t q = w * 64 * E + e * 64 + lane;
+            rk[e] = wave_rank((uint32_t)((k[e] - kmin) >> sh) & 255u, q < m, 8, wc + w * 256);
+        }
+        __syncthreads();
+        // per digit: exclusive prefix over waves, then an exclusive scan of the
+        // 256 digit totals
+        if constexpr (BS >= 256) {
+            uint32_t dtot = 0;
+            if (tid < 256) {
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = wc[ww * 256 + tid];
+                    wc[ww * 256 + tid] = (uint16_t)dtot;
+                    dtot += c;
+                }
+            }
+            const uint32_t ds = block_excl_scan<BS>(tid < 256 ? dtot : 0u, tmp, nullptr);
+            if (tid < 256) dst_[tid] = ds;
+        } else {
+            // fewer than 256 threads: each thread owns 256/BS digits
+            constexpr int PD = 256 / BS;
+            uint32_t loc[PD];
+            uint32_t sum = 0;
+            for (int d = 0; d < PD; ++d) {
+                const uint32_t dg = tid * PD + d;
+                uint32_t t2 = 0;
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = wc[ww * 256 + dg];
+                    wc[ww * 256 + dg] = (uint16_t)t2;
+                    t2 += c;
+                }
+                loc[d] = t2;
+                sum += t2;
+            }
+            uint32_t run = block_excl_scan<BS>(sum, tmp, nullptr);
+            for (int d = 0; d < PD; ++d) {
+                dst_[tid * PD + d] = run;
+                run += loc[d];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t q = w * 64 * E + e * 64 + lane;
+            if (q < m) {
+                const uint32_t d = (uint32_t)((k[e] - kmin) >> sh) & 255u;
+                const uint32_t p = dst_[d] + wc[w * 256 + d] + rk[e];
+                sk[p] = k[e];
+                sv[p] = v[e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t q = w * 64 * E + e * 64 + lane;
+            if (q < m) {
+                k[e] = sk[q];
+                v[e] = sv[q];
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t q = w * 64 * E + e * 64 + lane;
+        if (q < m) {
+            out_keys[start + q] = k[e];
+            out_vals[start + q] = v[e];
+        }
+    }
+}
+
 // Copy jobs: buckets that are final but sit in T (Section 3.4).
 template <typename V>
 __global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
@@ -1418,7 +1822,7 @@ __global__ void k_export_partition(const uint32_t* bstart, const Seg* segs, cons
                                    uint64_t* offsets_out, uint64_t* heavy_out)
 {
     const Seg sg = segs[0];
-    const uint32_t nb = (1u << sg.nl_bits) + sg.nheavy;
+    const uint32_t nb = sg.nbk;
     for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) offsets_out[b] = bstart[b] - sg.start;
     for (uint32_t h = threadIdx.x; h < sg.nheavy; h += blockDim.x) heavy_out[h] = heavy_list[h];
 }

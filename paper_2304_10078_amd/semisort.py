@@ -72,6 +72,8 @@ def lib():
                                       ctypes.POINTER(u64)]
         L.ss_semisort_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
         L.ss_semisort_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
+        L.ss_semisort_less.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
+        L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
         for name in declared_symbols():
             if name != "ss_last_error":
@@ -183,6 +185,39 @@ def semisort_equal(keys, vals, keys_out=None, vals_out=None, params=None, ctx=No
         vals_out = torch.empty_like(vals)
     ctx.check(lib().ss_semisort_equal(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out),
                                       _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def semisort_less(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
+    """ss_semisort_less: ascending keys, stable.  Returns (keys_out, vals_out)."""
+    import torch
+    vb = _check_kv(keys, vals)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    ctx.check(lib().ss_semisort_less(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out),
+                                     _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def semisort_less_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, params=None, ctx=None):
+    """ss_semisort_less_batch: independent instances packed back to back."""
+    import numpy as np
+    import torch
+    vb = _check_kv(keys, vals)
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.uint64))
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    ctx.check(lib().ss_semisort_less_batch(ctx.h, _ptr(keys), _ptr(vals), vb, ctypes.c_void_p(offs.ctypes.data),
+                                           offs.size - 1, _ptr(keys_out), _ptr(vals_out),
+                                           ctypes.byref(params) if params is not None else None))
     return keys_out, vals_out
 
 
