@@ -81,11 +81,12 @@ ss_status ss_sync(ss_ctx* ctx);
 ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
 
 /* Engine options (tuning knobs that are not part of ss_params).
- * SS_OPT_DIST_VARIANT selects the shape of the distribution kernel:
- *   0: 16 waves per block, 8192-record sub-tiles (default)
- *   1: 8 waves per block, 4096-record sub-tiles (two blocks per CU)
- *   2: as 0, with non-temporal (streaming) stores for the scattered writes
- * Every variant gives the same result. */
+ * SS_OPT_DIST_VARIANT selects the shape of the semisort distribution kernel:
+ *   0: LDS-staged writes, 16 waves per block, 8192-record sub-tiles (default)
+ *   1: LDS-staged writes, 8 waves per block, 4096-record sub-tiles
+ *   2..5: direct writes from registers (8 waves / 4 per SIMD, 8 waves / 6,
+ *         16 waves / 4, 4 waves with 16 records per lane / 6)
+ * Every variant gives the same result.  Values outside 0..5: SS_EINVAL. */
 enum { SS_OPT_DIST_VARIANT = 1 };
 ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
 
@@ -94,8 +95,10 @@ ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
  * SS_PROF_SAMPLE (Step 1; units = subproblems), SS_PROF_COUNT (counting pass;
  * units = records read), SS_PROF_SCAN (column-major prefix, four kernels;
  * units = subarrays), SS_PROF_DISTRIBUTE (distribution; units = records
- * moved), SS_PROF_PLAN (next-level planning; units = subproblems) and
- * SS_PROF_FINISH (base cases and copies; units = records).  ss_profile_enable
+ * moved), SS_PROF_PLAN (next-level planning and, for collect-reduce, the
+ * heavy keys' results; units = subproblems), SS_PROF_FINISH (base cases and
+ * copies; units = records) and SS_PROF_COMPACT (packing of collect-reduce
+ * and histogram results; units = positions scanned).  ss_profile_enable
  * resets the totals; ss_profile_read waits for the stream and returns the
  * total milliseconds, launch count and units of one pass. */
 enum {
@@ -105,7 +108,8 @@ enum {
     SS_PROF_DISTRIBUTE = 3,
     SS_PROF_PLAN = 4,
     SS_PROF_FINISH = 5,
-    SS_PROF_KINDS = 6
+    SS_PROF_COMPACT = 6,
+    SS_PROF_KINDS = 7
 };
 ss_status ss_profile_enable(ss_ctx* ctx, int on);
 ss_status ss_profile_read(ss_ctx* ctx, int kind, double* total_ms, uint64_t* launches,
@@ -159,6 +163,28 @@ ss_status ss_partition_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals
                              void* vals_out, uint64_t* offsets_out,
                              uint64_t* heavy_hashes_out, uint32_t* n_heavy_out,
                              const ss_params* params);
+
+/* collect-reduce (Section 3.5) with map = the record's value and the monoid
+ * (+ mod 2^64, 0): for each distinct key k, the wrapping sum of the values of
+ * the records with key k.  Heavy keys are reduced while their level is
+ * distributed (their records are never moved); light buckets recurse as in
+ * semisort_= and are reduced in LDS.  keys and vals are device arrays of n
+ * uint64; out_keys and out_sums are device arrays with room for n entries
+ * (the number m of distinct keys is not known in advance) that receive the m
+ * pairs in an unspecified order that is deterministic for a seed; *m_out
+ * (host) receives m.  The call waits for its stream before returning.
+ * Outputs must not overlap the inputs or each other.  hash_mode selects the
+ * user hash as for semisort_= (both are bijections, so a bucket in which all
+ * 64 hash bits are used holds one key). */
+ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals,
+                            uint64_t n, uint64_t* out_keys, uint64_t* out_sums,
+                            uint64_t* m_out, const ss_params* params);
+
+/* histogram (Section 3.5): collect-reduce with every value 1, so no value
+ * array is read or moved.  out_counts[i] is the number of records with key
+ * out_keys[i].  Same conventions as ss_collect_reduce. */
+ss_status ss_histogram(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
+                       uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,7 @@ struct ss_ctx {
     DevBuf segs[2];
     DevBuf jobs;
     DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
+    DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     std::vector<Seg> host_segs;
@@ -285,7 +286,7 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
         ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
         switch (c->dist_variant) {
         case 1:
-            hipLaunchKernelGGL((k_distribute<V, 8, 8>), dim3(tiles), dim3(512), 0, c->stream, a);
+            hipLaunchKernelGGL((k_distribute<V, 8, 8, 0>), dim3(tiles), dim3(512), 0, c->stream, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 4>), dim3(tiles), dim3(512), 0, c->stream, a);
@@ -300,7 +301,7 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
             hipLaunchKernelGGL((k_distribute_direct<V, 4, 16, 6>), dim3(tiles), dim3(256), 0, c->stream, a);
             break;
         default:
-            hipLaunchKernelGGL((k_distribute<V, 16, 8>), dim3(tiles), dim3(1024), 0, c->stream, a);
+            hipLaunchKernelGGL((k_distribute<V, 16, 8, 0>), dim3(tiles), dim3(1024), 0, c->stream, a);
         }
     }
 }
@@ -359,6 +360,11 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.adaptive_nl = 1;
     a.ordered = p.mode == 2;
     a.bfin = (uint8_t*)c->bfin.p;
+    a.reduce = 0;
+    a.hsum = nullptr;
+    a.res_keys = nullptr;
+    a.res_vals = nullptr;
+    a.rflag = nullptr;
     return a;
 }
 
@@ -378,6 +384,76 @@ void host_prefix(std::vector<Seg>& segs, const Params& p, uint32_t* tiles, uint3
     }
     *tiles = rt;
     *chunks = rc;
+}
+
+ss_status ensure_jobs(ss_ctx* c, uint32_t per_class)
+{
+    if (per_class <= c->job_cap) return SS_OK;
+    uint32_t want = std::max<uint32_t>(per_class, std::max<uint32_t>(4096, c->job_cap + c->job_cap / 2));
+    ss_status r = ensure(c, c->jobs, (size_t)want * kJobClasses * sizeof(Job));
+    if (r == SS_OK) c->job_cap = want;
+    return r;
+}
+
+// Plans the next level from the buckets of the current one (subproblem list
+// segs[cur] -> segs[cur ^ 1], job lists) and reads the level's counters back
+// to the host; grows the lists and plans again when they overflow.
+ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs, int cur, uint32_t* seg_cap,
+                     bool finals_in_out, bool reduce, LevelInfo* out)
+{
+    ss_status s;
+    for (int attempt = 0;; ++attempt) {
+        if (attempt && (s = reset_counters(c)) != SS_OK) return s;
+        PlanArgs pa;
+        pa.segs = (const Seg*)c->segs[cur].p;
+        pa.nsegs = nsegs;
+        pa.bstart = (const uint32_t*)c->bstart.p;
+        pa.next = (Seg*)c->segs[cur ^ 1].p;
+        pa.next_cap = *seg_cap;
+        pa.jobs = (Job*)c->jobs.p;
+        pa.job_cap = c->job_cap;
+        pa.info = (LevelInfo*)c->info.p;
+        pa.alpha = p.alpha;
+        pa.finals_in_out = finals_in_out;
+        pa.ordered = p.mode == 2;
+        pa.bfin = (const uint8_t*)c->bfin.p;
+        pa.reduce = reduce;
+        {
+            ProfScope ps(c, SS_PROF_PLAN, nsegs);
+            hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
+            hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, *seg_cap,
+                               (LevelInfo*)c->info.p, p.tmin, p.tmax);
+        }
+        HIP_OR_FAIL(c, hipGetLastError());
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        const LevelInfo li = *c->info_host;
+        if (li.status)
+            return fail(c, SS_EDEVICE, "device status " + std::to_string(li.status) + " at level " + std::to_string(level));
+        bool again = false;
+        if (li.nsegs > *seg_cap) {
+            // the current list must survive: copy it aside while both lists grow
+            DevBuf keep;
+            if ((s = ensure(c, keep, (size_t)nsegs * sizeof(Seg))) != SS_OK) return s;
+            HIP_OR_FAIL(c, hipMemcpyAsync(keep.p, c->segs[cur].p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
+            if ((s = ensure(c, c->segs[0], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
+            if ((s = ensure(c, c->segs[1], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, keep.p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+            HIP_OR_FAIL(c, hipFree(keep.p));
+            *seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
+            again = true;
+        }
+        uint32_t jmax = 0;
+        for (int k = 0; k < kJobClasses; ++k) jmax = std::max(jmax, li.njobs[k]);
+        if (jmax > c->job_cap) {
+            if ((s = ensure_jobs(c, jmax)) != SS_OK) return s;
+            again = true;
+        }
+        if (again) continue;
+        *out = li;
+        return SS_OK;
+    }
 }
 
 // The whole engine: `offs` are instance boundaries (host), total n = offs.back().
@@ -433,14 +509,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         nj0_max = std::max(nj0_max, nj0[k]);
         nj0_tot += nj0[k];
     }
-    auto ensure_jobs = [&](uint32_t per_class) -> ss_status {
-        if (per_class <= c->job_cap) return SS_OK;
-        uint32_t want = std::max<uint32_t>(per_class, std::max<uint32_t>(4096, c->job_cap + c->job_cap / 2));
-        ss_status r = ensure(c, c->jobs, (size_t)want * kJobClasses * sizeof(Job));
-        if (r == SS_OK) c->job_cap = want;
-        return r;
-    };
-    if ((s = ensure_jobs(std::max<uint32_t>(nj0_max, 4096))) != SS_OK) return s;
+    if ((s = ensure_jobs(c, std::max<uint32_t>(nj0_max, 4096))) != SS_OK) return s;
 
     HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
     if (nj0_tot) {
@@ -502,63 +571,15 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         launch_level_v<V>(c, p.mode, a, tiles, chunks, records);
         HIP_OR_FAIL(c, hipGetLastError());
 
-        // plan the next level; grow the lists and plan again if they overflow
-        for (int attempt = 0;; ++attempt) {
-            if (attempt && (s = reset_counters(c)) != SS_OK) return s;
-            PlanArgs pa;
-            pa.segs = (const Seg*)c->segs[cur].p;
-            pa.nsegs = nsegs;
-            pa.bstart = (const uint32_t*)c->bstart.p;
-            pa.next = (Seg*)c->segs[cur ^ 1].p;
-            pa.next_cap = seg_cap;
-            pa.jobs = (Job*)c->jobs.p;
-            pa.job_cap = c->job_cap;
-            pa.info = (LevelInfo*)c->info.p;
-            pa.alpha = p.alpha;
-            pa.finals_in_out = fin_k == keys_out;
-            pa.ordered = p.mode == 2;
-            pa.bfin = (const uint8_t*)c->bfin.p;
-            {
-                ProfScope ps(c, SS_PROF_PLAN, nsegs);
-                hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
-                hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p,
-                                   seg_cap, (LevelInfo*)c->info.p, p.tmin, p.tmax);
-            }
-            HIP_OR_FAIL(c, hipGetLastError());
-            HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
-            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-            const LevelInfo li = *c->info_host;
-            if (li.status) return fail(c, SS_EDEVICE, "device status " + std::to_string(li.status) + " at level " + std::to_string(level));
-            bool again = false;
-            if (li.nsegs > seg_cap) {
-                // the current list must survive: copy it aside while both lists grow
-                DevBuf keep;
-                if ((s = ensure(c, keep, (size_t)nsegs * sizeof(Seg))) != SS_OK) return s;
-                HIP_OR_FAIL(c, hipMemcpyAsync(keep.p, c->segs[cur].p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
-                if ((s = ensure(c, c->segs[0], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
-                if ((s = ensure(c, c->segs[1], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
-                HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, keep.p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
-                HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-                HIP_OR_FAIL(c, hipFree(keep.p));
-                seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
-                again = true;
-            }
-            uint32_t jmax = 0;
-            for (int k = 0; k < kJobClasses; ++k) jmax = std::max(jmax, li.njobs[k]);
-            if (jmax > c->job_cap) {
-                if ((s = ensure_jobs(jmax)) != SS_OK) return s;
-                again = true;
-            }
-            if (again) continue;
-            launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
-            HIP_OR_FAIL(c, hipGetLastError());
-            nsegs = li.nsegs;
-            records = li.records;
-            tiles = li.tiles;
-            chunks = li.chunks;
-            tile = li.tile;
-            break;
-        }
+        LevelInfo li;
+        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, &li)) != SS_OK) return s;
+        launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
+        HIP_OR_FAIL(c, hipGetLastError());
+        nsegs = li.nsegs;
+        records = li.records;
+        tiles = li.tiles;
+        chunks = li.chunks;
+        tile = li.tile;
         loc_k = dst_k;
         loc_v = dst_v;
         cur ^= 1;
@@ -567,6 +588,190 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    return SS_OK;
+}
+
+// ---------------------------------------------------------------- collect-reduce
+
+// Reduce-mode jobs of a level: base cases in LDS, sum jobs in the copy class.
+template <int MODE, int ONES>
+void launch_red_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const uint64_t* sv,
+                       uint64_t* rk, uint64_t* rv, uint8_t* rf)
+{
+    const Job* jobs = (const Job*)c->jobs.p;
+    if (njobs[0]) hipLaunchKernelGGL((k_base_red<MODE, 1, ONES>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, sv, rk, rv, rf);
+    if (njobs[1])
+        hipLaunchKernelGGL((k_base_red<MODE, 2, ONES>), dim3(njobs[1]), dim3(128), 0, c->stream, jobs + cap, sk, sv, rk, rv, rf);
+    if (njobs[2])
+        hipLaunchKernelGGL((k_base_red<MODE, 4, ONES>), dim3(njobs[2]), dim3(256), 0, c->stream, jobs + 2 * (size_t)cap, sk, sv,
+                           rk, rv, rf);
+    if (njobs[3])
+        hipLaunchKernelGGL((k_base_red<MODE, 8, ONES>), dim3(njobs[3]), dim3(512), 0, c->stream, jobs + 3 * (size_t)cap, sk, sv,
+                           rk, rv, rf);
+    if (njobs[kCopyClass])
+        hipLaunchKernelGGL((k_sum_job<ONES>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
+                           jobs + (size_t)kCopyClass * cap, sk, sv, rk, rv, rf);
+}
+
+template <int RED>
+void launch_red_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, const uint64_t* sk,
+                     const uint64_t* sv, uint64_t* rk, uint64_t* rv, uint8_t* rf, uint64_t records)
+{
+    ProfScope ps(c, SS_PROF_FINISH, records);
+    if (mode == 1) launch_red_jobs_m<1, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf);
+    else launch_red_jobs_m<0, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf);
+}
+
+template <int MODE, int RED>
+void launch_red_level_m(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks, uint64_t records)
+{
+    {
+        ProfScope ps(c, SS_PROF_SAMPLE, a.nsegs);
+        hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_COUNT, records);
+        hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_SCAN, tiles);
+        hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(256), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_buckets, dim3(a.nsegs * kBucketGroups), dim3(1024), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_offsets, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        hipLaunchKernelGGL(k_scan_fill, dim3(chunks), dim3(256), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
+        hipLaunchKernelGGL((k_distribute<uint64_t, 16, 8, RED>), dim3(tiles), dim3(1024), 0, c->stream, a);
+    }
+    {
+        ProfScope ps(c, SS_PROF_PLAN, a.nsegs);
+        hipLaunchKernelGGL((k_heavy_results<MODE>), dim3(a.nsegs), dim3(256), 0, c->stream, a);
+    }
+}
+
+// Collect-reduce (RED = 1, u64 values, wrapping sums) or histogram (RED = 2,
+// no values) of n records.  Data moves between T and the caller's output
+// arrays; results are written to T at positions flagged in rflag (positions
+// of finished work are never touched again by later levels, which only work
+// inside the ranges of unfinished buckets), then compacted into the output.
+template <int RED>
+ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
+                     uint64_t* out_vals, uint64_t* m_out, const Params& p)
+{
+    ss_status s;
+    const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
+    if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->t_vals, n * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->rflag, nblk * kFlagBlock)) != SS_OK) return s;
+    if ((s = ensure(c, c->bcnt, nblk * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
+    if ((s = ensure_jobs(c, 4096)) != SS_OK) return s;
+    uint32_t seg_cap = 1024;
+    if ((s = ensure(c, c->segs[0], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
+    if ((s = ensure(c, c->segs[1], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
+    seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
+    uint64_t* T_k = (uint64_t*)c->t_keys.p;
+    uint64_t* T_v = (uint64_t*)c->t_vals.p;
+    uint8_t* rf = (uint8_t*)c->rflag.p;
+    HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+
+    if (n < p.alpha) {
+        // one job: a sum job for a single record, else a base case
+        Job j{0u, (uint32_t)n};
+        uint32_t nj[kJobClasses] = {};
+        const int cls = n == 1 ? kCopyClass : base_class((uint32_t)n);
+        nj[cls] = 1;
+        if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, sizeof(Job))) != SS_OK) return s;
+        *c->job_stage = j;
+        HIP_OR_FAIL(c, hipMemcpyAsync((Job*)c->jobs.p + (size_t)cls * c->job_cap, c->job_stage, sizeof(Job),
+                                      hipMemcpyHostToDevice, c->stream));
+        launch_red_jobs<RED>(c, p.mode, nj, c->job_cap, keys, vals, T_k, T_v, rf, n);
+        HIP_OR_FAIL(c, hipGetLastError());
+    } else {
+        if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
+        std::vector<Seg> first(1);
+        first[0] = Seg{};
+        first[0].start = 0;
+        first[0].len = (uint32_t)n;
+        first[0].ibase = 0;
+        first[0].nl_bits = (uint8_t)std::min(p.nl0, choose_nl((uint32_t)n, p.alpha, kLightBitsMax, 0));
+        first[0].shift = 0;
+        uint32_t tiles, chunks, tile;
+        host_prefix(first, p, &tiles, &chunks, &tile);
+        if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, sizeof(Seg))) != SS_OK) return s;
+        memcpy(c->seg_stage, first.data(), sizeof(Seg));
+        int cur = 0;
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
+        uint32_t nsegs = 1;
+        uint64_t records = n;
+        const uint64_t* loc_k = keys;
+        const uint64_t* loc_v = vals;
+        for (uint32_t level = 0; nsegs; ++level) {
+            uint64_t* dst_k = loc_k == T_k ? out_keys : T_k;
+            uint64_t* dst_v = loc_k == T_k ? out_vals : T_v;
+            if ((s = ensure_level(c, nsegs, tiles, chunks)) != SS_OK) return s;
+            if ((s = ensure(c, c->hsum, (size_t)nsegs * kHeavyMax * 8)) != SS_OK) return s;
+            if ((s = reset_counters(c)) != SS_OK) return s;
+            LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, dst_k,
+                                    dst_v);
+            a.reduce = 1;
+            a.hsum = (unsigned long long*)c->hsum.p;
+            a.res_keys = T_k;
+            a.res_vals = T_v;
+            a.rflag = rf;
+            if (p.mode == 1) launch_red_level_m<1, RED>(c, a, tiles, chunks, records);
+            else launch_red_level_m<0, RED>(c, a, tiles, chunks, records);
+            HIP_OR_FAIL(c, hipGetLastError());
+            LevelInfo li;
+            if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, false, true, &li)) != SS_OK) return s;
+            launch_red_jobs<RED>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, T_k, T_v, rf, li.job_records);
+            HIP_OR_FAIL(c, hipGetLastError());
+            nsegs = li.nsegs;
+            records = li.records;
+            tiles = li.tiles;
+            chunks = li.chunks;
+            tile = li.tile;
+            loc_k = dst_k;
+            loc_v = dst_v;
+            cur ^= 1;
+        }
+    }
+    {
+        ProfScope ps(c, SS_PROF_COMPACT, n);
+        hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf,
+                           (uint32_t*)c->bcnt.p);
+        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, (uint32_t*)c->bcnt.p, (uint32_t)nblk,
+                           (unsigned long long*)c->mdev.p);
+        hipLaunchKernelGGL(k_flag_scatter, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf,
+                           (const uint32_t*)c->bcnt.p, (const uint64_t*)T_k, (const uint64_t*)T_v, out_keys, out_vals);
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, c->mdev.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    *m_out = c->info_host->records;
+    return SS_OK;
+}
+
+ss_status check_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, const uint64_t* ok,
+                       const uint64_t* ov, const uint64_t* m_out, const ss_params* params, Params* p)
+{
+    if (!c) return SS_EINVAL;
+    if (!m_out) return fail(c, SS_EINVAL, "null m_out");
+    if (n >= (1ull << 31)) return fail(c, SS_EINVAL, "n must be below 2^31");
+    ss_status s = resolve_params(c, params, p);
+    if (s != SS_OK) return s;
+    if (n == 0) return SS_OK;
+    if (!keys || !ok || !ov) return fail(c, SS_EINVAL, "null array pointer");
+    const size_t b = n * 8;
+    if (overlaps(ok, b, keys, b) || overlaps(ov, b, keys, b) || (vals && (overlaps(ok, b, vals, b) || overlaps(ov, b, vals, b))))
+        return fail(c, SS_EINVAL, "outputs overlap inputs");
+    if (overlaps(ok, b, ov, b)) return fail(c, SS_EINVAL, "out_keys overlaps the second output");
     return SS_OK;
 }
 
@@ -634,7 +839,8 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin};
+                      &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto& p : c->pending) {
@@ -710,7 +916,8 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
 {
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin};
+                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
+                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -829,6 +1036,31 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
     *n_heavy_out = back.nheavy;
     return SS_OK;
+}
+
+ss_status ss_collect_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
+                            uint64_t* out_sums, uint64_t* m_out, const ss_params* params)
+{
+    Params p;
+    ss_status s = check_reduce(c, keys, vals, n, out_keys, out_sums, m_out, params, &p);
+    if (s != SS_OK) return s;
+    *m_out = 0;
+    if (n == 0) return SS_OK;
+    if (!vals) return fail(c, SS_EINVAL, "null vals");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    return run_reduce<1>(c, keys, vals, n, out_keys, out_sums, m_out, p);
+}
+
+ss_status ss_histogram(ss_ctx* c, const uint64_t* keys, uint64_t n, uint64_t* out_keys, uint64_t* out_counts,
+                       uint64_t* m_out, const ss_params* params)
+{
+    Params p;
+    ss_status s = check_reduce(c, keys, nullptr, n, out_keys, out_counts, m_out, params, &p);
+    if (s != SS_OK) return s;
+    *m_out = 0;
+    if (n == 0) return SS_OK;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    return run_reduce<2>(c, keys, nullptr, n, out_keys, out_counts, m_out, p);
 }
 
 }  // extern "C"

@@ -102,6 +102,12 @@ struct LevelArgs {
     uint32_t adaptive_nl;  // choose n_L per subproblem from the sample's light fraction
     uint32_t ordered;      // buckets from sorted splitters (semisort_<) instead of hash bits
     uint8_t* bfin;         // [nsegs][kNbStride]: 1 for buckets that are final (one key each)
+    // collect-reduce / histogram (Section 3.5)
+    uint32_t reduce;                // heavy records are summed where they are, not moved
+    unsigned long long* hsum;       // [nsegs][kHeavyMax] sums of heavy records per heavy id
+    uint64_t* res_keys;             // results at position coordinates (n entries)
+    uint64_t* res_vals;
+    uint8_t* rflag;                 // 1 where a result sits
 };
 
 // ---------------------------------------------------------------- hashing
@@ -488,6 +494,8 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
     }
     for (uint32_t b = tid; b < nL + nh; b += BS) a.bfin[(size_t)sid * kNbStride + b] = b >= nL ? 1 : 0;
+    if (a.reduce)
+        for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = 0;
     if (tid == 0) {
         a.segs[sid].nheavy = (uint16_t)nh;
         a.segs[sid].hlog2 = (uint16_t)sh_hfield;
@@ -506,6 +514,7 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
 {
     constexpr int BS = 1024;
     __shared__ uint32_t cnt[kNbStride];
+    __shared__ uint8_t finl[kNbStride];
     __shared__ uint64_t th[2 * kHeavySlotsMax];
     __shared__ uint16_t tidh[2 * kHeavySlotsMax];
 
@@ -522,7 +531,10 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     const uint32_t hlog2 = sg.hlog2;  // slot bits and salt
     const uint32_t slots = (hlog2 & 0xFFu) ? (1u << (hlog2 & 0xFFu)) : 0u;
 
-    for (uint32_t b = tid; b < nb; b += BS) cnt[b] = 0;
+    for (uint32_t b = tid; b < nb; b += BS) {
+        cnt[b] = 0;
+        finl[b] = a.reduce ? a.bfin[(size_t)sid * kNbStride + b] : 0;
+    }
     for (uint32_t i = tid; i < 2 * slots; i += BS) {
         const uint32_t j = i < slots ? i : kHeavySlotsMax + (i - slots);
         th[j] = a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + j];
@@ -534,7 +546,7 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     const uint32_t lmask = nL - 1;
     const uint64_t* keys = a.src_keys;
     uint16_t* bids = a.bids;
-    auto tally = [&](uint32_t b) { atomicAdd(&cnt[b], 1u); };
+    auto tally = [&](uint32_t b) { if (!finl[b]) atomicAdd(&cnt[b], 1u); };
     constexpr int U = 8;  // loads in flight per thread
     uint64_t i = r0 + tid;
     for (; i + (U - 1) * BS < r1; i += U * BS) {
@@ -554,8 +566,10 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
         tally(b);
     }
     __syncthreads();
+    // collect-reduce: heavy records stay where they are; each heavy bucket
+    // keeps one slot (in the subproblem's first subarray) for its result
     uint32_t* row = a.C + (size_t)t * kNbStride;
-    for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b];
+    for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b] + ((finl[b] && lt == 0) ? 1u : 0u);
 }
 
 // ================================================================ semisort_<
@@ -784,6 +798,7 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
 {
     constexpr int BS = 1024;
     __shared__ uint32_t cnt[kNbStride];
+    __shared__ uint8_t finl[kNbStride];
     __shared__ uint64_t bnd[kNbStride];
     __shared__ uint16_t rid[kNbStride + 1];
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
@@ -796,7 +811,10 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint32_t nb = sg.nbk;
     const uint32_t m = nb - 1 - sg.nheavy;
-    for (uint32_t b = tid; b < nb; b += BS) cnt[b] = 0;
+    for (uint32_t b = tid; b < nb; b += BS) {
+        cnt[b] = 0;
+        finl[b] = a.reduce ? a.bfin[(size_t)sid * kNbStride + b] : 0;
+    }
     for (uint32_t j = tid; j <= m; j += BS) {
         if (j < m) bnd[j] = a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + j];
         rid[j] = a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + j];
@@ -814,17 +832,19 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
         for (int u = 0; u < U; ++u) {
             const uint32_t b = less_bucket(kk[u], bnd, rid, m);
             bids[i + (uint64_t)u * BS] = (uint16_t)b;
-            atomicAdd(&cnt[b], 1u);
+            if (!finl[b]) atomicAdd(&cnt[b], 1u);
         }
     }
     for (; i < r1; i += BS) {
         const uint32_t b = less_bucket(keys[i], bnd, rid, m);
         bids[i] = (uint16_t)b;
-        atomicAdd(&cnt[b], 1u);
+        if (!finl[b]) atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
+    // collect-reduce: heavy records stay where they are; each heavy bucket
+    // keeps one slot (in the subproblem's first subarray) for its result
     uint32_t* row = a.C + (size_t)t * kNbStride;
-    for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b];
+    for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b] + ((finl[b] && lt == 0) ? 1u : 0u);
 }
 
 // ================================================================ Step 2b
@@ -897,8 +917,9 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(LevelArgs a)
     if (b0 < nb) bs[b0] = sg.start + base;
     if (b1 < nb) bs[b1] = sg.start + base + v0;
     if (threadIdx.x == 0) {
-        bs[nb] = sg.start + sg.len;
-        if (total != sg.len) atomicOr(&a.info->status, kStatusSizeMismatch);
+        // collect-reduce keeps heavy records out of the buckets (one slot each)
+        bs[nb] = sg.start + total;
+        if (a.reduce ? total > sg.len : total != sg.len) atomicOr(&a.info->status, kStatusSizeMismatch);
     }
 }
 
@@ -942,7 +963,10 @@ __device__ __forceinline__ bool bucket_is_final(bool one_key_bucket, uint32_t sz
     return one_key_bucket || sz <= 1 || all_bits_used;
 }
 
-template <typename V, int W, int E>
+// RED = 0: semisort; RED = 1: collect-reduce (heavy records are summed in
+// LDS and added to the subproblem's heavy sums, light records move); RED = 2:
+// histogram (as 1 with every value 1 and no value array).
+template <typename V, int W, int E, int RED>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
 {
     // Every global load and store in the sub-tile loop is issued
@@ -958,6 +982,8 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint64_t stage[SUB];
     __shared__ uint16_t stage_b[SUB];
     __shared__ uint32_t tmp[20];
+    __shared__ unsigned long long hs[RED ? kNbStride : 1];
+    __shared__ uint8_t finl[RED ? kNbStride : 1];
 
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
@@ -989,6 +1015,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         uint32_t g = a.C[(size_t)t * kNbStride + b];
         if (split && bucket_is_final(fin[b] != 0, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
         gbase[b] = g;
+        if constexpr (RED != 0) {
+            hs[b] = 0;
+            finl[b] = fin[b];
+        }
     }
     for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
 
@@ -1018,7 +1048,8 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int e = 0; e < E; ++e) {
             uint64_t i = base_i + (uint64_t)e * 64;
             i = i < rlast ? i : rlast;
-            v[e] = src_vals[i];
+            if constexpr (RED == 2) v[e] = (V)1;
+            else v[e] = src_vals[i];
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1037,8 +1068,19 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         uint16_t* wcw = wc + w * nb;
+        bool mv[E];  // this record moves (heavy records of collect-reduce stay)
 #pragma unroll
-        for (int e = 0; e < E; ++e) pos[e] = wave_rank(bk[e], base_i + (uint64_t)e * 64 < r1, nbits, wcw);
+        for (int e = 0; e < E; ++e) {
+            mv[e] = base_i + (uint64_t)e * 64 < r1;
+            if constexpr (RED != 0) {
+                if (mv[e] && finl[bk[e]]) {
+                    atomicAdd(&hs[bk[e]], (unsigned long long)v[e]);
+                    mv[e] = false;
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) pos[e] = wave_rank(bk[e], mv[e], nbits, wcw);
         __syncthreads();
 
         // per bucket: exclusive prefix over waves, sub-tile total, and the
@@ -1074,7 +1116,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         // stage keys in bucket order
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            if (base_i + (uint64_t)e * 64 < r1) {
+            if (mv[e]) {
                 const uint32_t b = bk[e];
                 const uint32_t p = lst[b] + wc[w * nb + b] + pos[e];
                 pos[e] = p;
@@ -1101,23 +1143,30 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
         __syncthreads();
+        if constexpr (RED != 2) {
 #pragma unroll
-        for (int e = 0; e < E; ++e)
-            if (base_i + (uint64_t)e * 64 < r1) stage_v[pos[e]] = v[e];
-        __syncthreads();
+            for (int e = 0; e < E; ++e)
+                if (mv[e]) stage_v[pos[e]] = v[e];
+            __syncthreads();
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t j = tid + e * BS;
-            const uint32_t dd = dest[e];
-            V* out = (dd >> 31) ? fin_vals : dst_vals;
-            V* addr = dd != 0xFFFFFFFFu ? out + (dd & 0x7FFFFFFFu) : sink_v;
-            *addr = stage_v[j < m ? j : 0u];
+            for (int e = 0; e < E; ++e) {
+                const uint32_t j = tid + e * BS;
+                const uint32_t dd = dest[e];
+                V* out = (dd >> 31) ? fin_vals : dst_vals;
+                V* addr = dd != 0xFFFFFFFFu ? out + (dd & 0x7FFFFFFFu) : sink_v;
+                *addr = stage_v[j < m ? j : 0u];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         for (uint32_t j = 0; j < per; ++j) {
             const uint32_t b = pb0 + j;
             if (b < nb) gbase[b] += lst[b + 1] - lst[b];
         }
+    }
+    if constexpr (RED != 0) {
+        __syncthreads();
+        for (uint32_t b = tid; b < nb; b += BS)
+            if (finl[b] && hs[b]) atomicAdd(&a.hsum[(size_t)sid * kHeavyMax + (b - nL)], hs[b]);
     }
     if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
 }
@@ -1278,6 +1327,7 @@ struct PlanArgs {
     uint32_t finals_in_out;  // final buckets were written to the output by the distribution
     uint32_t ordered;        // splitter buckets: no hash bits are consumed
     const uint8_t* bfin;     // [nsegs][kNbStride] one-key bucket flags
+    uint32_t reduce;         // collect-reduce: heavy buckets are done, one-key buckets are summed
 };
 
 struct PlanCount {
@@ -1298,7 +1348,21 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
     if (sz == 0) return;
     const uint32_t shift2 = p.ordered ? 0u : (uint32_t)sg.shift + sg.nl_bits;
     const bool all_bits_used = shift2 >= 64;
-    if (bucket_is_final(p.bfin[(size_t)sidx * kNbStride + b] != 0, sz, all_bits_used)) {
+    if (p.reduce) {
+        // heavy bucket: its result was written with the level; a bucket of one
+        // record, or of one hash value (one key: the hash is a bijection),
+        // becomes a sum job in the copy class
+        if (p.bfin[(size_t)sidx * kNbStride + b]) return;
+        if (sz == 1 || all_bits_used) {
+            if (emit) {
+                if (job_at[kCopyClass] < p.job_cap) p.jobs[(size_t)kCopyClass * p.job_cap + job_at[kCopyClass]] = Job{st, sz};
+                ++job_at[kCopyClass];
+            }
+            ++cnt.job[kCopyClass];
+            cnt.rec += sz;
+            return;
+        }
+    } else if (bucket_is_final(p.bfin[(size_t)sidx * kNbStride + b] != 0, sz, all_bits_used)) {
         if (p.finals_in_out) return;  // already in place
         for (uint32_t o = 0; o < sz; o += kCopyChunk) {
             const uint32_t l = sz - o < kCopyChunk ? sz - o : kCopyChunk;
@@ -1825,6 +1889,228 @@ __global__ void k_export_partition(const uint32_t* bstart, const Seg* segs, cons
     const uint32_t nb = sg.nbk;
     for (uint32_t b = threadIdx.x; b <= nb; b += blockDim.x) offsets_out[b] = bstart[b] - sg.start;
     for (uint32_t h = threadIdx.x; h < sg.nheavy; h += blockDim.x) heavy_out[h] = heavy_list[h];
+}
+
+// ================================================================ Section 3.5
+// Collect-reduce and histogram on the semisort_= skeleton.  A heavy key needs
+// no further work once it is known: its records are summed while the level
+// is distributed (they never move) and the sum lands in the one slot its
+// bucket reserved.  Light buckets recurse as in the semisort; buckets of one
+// record or one key are summed directly, small buckets are reduced in LDS.
+// Every result sits at a position inside its bucket's range, marked in rflag;
+// a final compaction packs them.  The monoid is wrapping 64-bit addition;
+// for the histogram every value is 1.
+
+// Inverse of fmix64: xor-shift by 33 undoes itself on 64-bit words, and the
+// two multipliers are odd, so their inverses mod 2^64 exist.
+__device__ __forceinline__ uint64_t unfmix64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0x9cb4b2f8129337dbULL;
+    k ^= k >> 33;
+    k *= 0x4f74430c22a54005ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+template <int MODE>
+__device__ __forceinline__ uint64_t key_of_hash(uint64_t h)
+{
+    if constexpr (MODE == 0) return unfmix64(h);
+    else return h;
+}
+
+// Results of the heavy keys of every subproblem of the level.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_heavy_results(LevelArgs a)
+{
+    const uint32_t sid = blockIdx.x;
+    const Seg sg = a.segs[sid];
+    const uint32_t nL = 1u << sg.nl_bits;
+    const uint32_t* bs = a.bstart + (size_t)sid * (kNbStride + 1);
+    bool bad = false;
+    for (uint32_t h = threadIdx.x; h < sg.nheavy; h += 256) {
+        const uint32_t b = nL + h;
+        const uint32_t p = bs[b];
+        if (bs[b + 1] - p != 1u || p - sg.start >= sg.len) {
+            bad = true;
+            continue;
+        }
+        a.res_keys[p] = key_of_hash<MODE>(a.heavy_list[(size_t)sid * kHeavyMax + h]);
+        a.res_vals[p] = a.hsum[(size_t)sid * kHeavyMax + h];
+        a.rflag[p] = 1;
+    }
+    if (bad) atomicOr(&a.info->status, kStatusSizeMismatch);
+}
+
+// Sum jobs: a bucket whose records all share one key.  One block per job;
+// all reads finish (block reduction) before the single write.
+template <int ONES>
+__global__ __launch_bounds__(256) void k_sum_job(const Job* jobs, const uint64_t* src_keys, const uint64_t* src_vals,
+                                                 uint64_t* res_keys, uint64_t* res_vals, uint8_t* rflag)
+{
+    __shared__ unsigned long long acc;
+    const Job j = jobs[blockIdx.x];
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    unsigned long long s = 0;
+    if constexpr (ONES) {
+        s = threadIdx.x == 0 ? j.len : 0u;
+    } else {
+        for (uint32_t i = threadIdx.x; i < j.len; i += 256) s += src_vals[(uint64_t)j.start + i];
+    }
+    const uint64_t k = src_keys[j.start];
+    if (s) atomicAdd(&acc, s);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        res_keys[j.start] = k;
+        res_vals[j.start] = acc;
+        rflag[j.start] = 1;
+    }
+}
+
+// Base case of collect-reduce for a bucket of at most CAP = W*512 records:
+// an LDS hash table (slot claimed by CAS, keys compared through the owner's
+// index) accumulates each key's sum with LDS atomics and the smallest index
+// of the key, f; the record at f writes (key, sum) at start + f.  Positions
+// and sums do not depend on scheduling.  All reads precede all writes, so
+// the results may go to the source array.
+template <int MODE, int W, int ONES>
+__global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint64_t* src_keys,
+                                                     const uint64_t* src_vals, uint64_t* res_keys,
+                                                     uint64_t* res_vals, uint8_t* rflag)
+{
+    constexpr int BS = W * 64, E = 8, CAP = BS * E;
+    __shared__ uint64_t kl[CAP];
+    __shared__ uint32_t tab[2 * CAP];
+    __shared__ unsigned long long ssum[2 * CAP];
+
+    const Job j = jobs[blockIdx.x];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    const uint32_t m = j.len;  // 2 .. CAP
+    const uint64_t start = j.start;
+    const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
+    const uint32_t slots = 1u << lg, smask = slots - 1;
+
+    uint64_t k[E], v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        k[e] = i < m ? src_keys[start + i] : 0ull;
+        if constexpr (ONES) v[e] = 1;
+        else v[e] = i < m ? src_vals[start + i] : 0ull;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) kl[i] = k[e];
+    }
+    for (uint32_t i = tid; i < slots; i += BS) {
+        tab[i] = kEmpty32;
+        ssum[i] = 0;
+    }
+    __syncthreads();
+    uint32_t sl[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        sl[e] = 0;
+        if (i < m) {
+            uint32_t sidx = fib_slot(user_hash<MODE>(k[e]), lg);
+            while (true) {
+                uint32_t o = tab[sidx];
+                if (o == kEmpty32) {
+                    o = atomicCAS(&tab[sidx], kEmpty32, i);
+                    if (o == kEmpty32) break;
+                }
+                if (kl[o] == k[e]) break;
+                sidx = (sidx + 1) & smask;
+            }
+            sl[e] = sidx;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m) {
+            atomicMin(&tab[sl[e]], i);
+            atomicAdd(&ssum[sl[e]], (unsigned long long)v[e]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const uint32_t i = w * 64 * E + e * 64 + lane;
+        if (i < m && tab[sl[e]] == i) {
+            res_keys[start + i] = k[e];
+            res_vals[start + i] = ssum[sl[e]];
+            rflag[start + i] = 1;
+        }
+    }
+}
+
+// Compaction of the results: positions are cut into blocks of kFlagBlock;
+// each thread owns 64 consecutive flag bytes (flags are 0 or 1, so the
+// population count of a word counts its results).  The flag array is padded
+// to a whole number of blocks and cleared before the run.
+constexpr uint32_t kFlagBlock = 65536;
+
+__global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint32_t* bcnt)
+{
+    __shared__ uint32_t tmp[20];
+    const uint64_t* f = (const uint64_t*)(rflag + (size_t)blockIdx.x * kFlagBlock) + threadIdx.x * 8;
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c += __popcll(f[q]);
+    uint32_t tot = 0;
+    (void)block_excl_scan<1024>(c, tmp, &tot);
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+}
+
+// Exclusive scan of the block counts in place (one block); m to *m_out.
+__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* bcnt, uint32_t nblk, unsigned long long* m_out)
+{
+    __shared__ uint32_t tmp[20];
+    uint32_t run = 0;
+    for (uint32_t base = 0; base < nblk; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t x = i < nblk ? bcnt[i] : 0u;
+        uint32_t tot = 0;
+        const uint32_t o = block_excl_scan<1024>(x, tmp, &tot);
+        if (i < nblk) bcnt[i] = run + o;
+        run += tot;
+    }
+    if (threadIdx.x == 0) *m_out = run;
+}
+
+__global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, const uint32_t* bofs,
+                                                       const uint64_t* res_keys, const uint64_t* res_vals,
+                                                       uint64_t* out_keys, uint64_t* out_vals)
+{
+    __shared__ uint32_t tmp[20];
+    const size_t p0 = (size_t)blockIdx.x * kFlagBlock + threadIdx.x * 64;
+    const uint64_t* f = (const uint64_t*)(rflag + p0);
+    uint64_t wv[8];
+    uint32_t c = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        wv[q] = f[q];
+        c += __popcll(wv[q]);
+    }
+    uint32_t o = bofs[blockIdx.x] + block_excl_scan<1024>(c, tmp, nullptr);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint64_t x = wv[q];
+        while (x) {
+            const uint32_t bit = (uint32_t)__ffsll((long long)x) - 1;  // bit 0 of a flag byte
+            x &= x - 1;
+            const size_t p = p0 + q * 8 + bit / 8;
+            out_keys[o] = res_keys[p];
+            out_vals[o] = res_vals[p];
+            ++o;
+        }
+    }
 }
 
 }  // namespace ssd

@@ -75,6 +75,8 @@ def lib():
         L.ss_semisort_less.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
         L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
+        L.ss_collect_reduce.argtypes = [vp, vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
+        L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
         for name in declared_symbols():
             if name != "ss_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -123,7 +125,7 @@ class Context:
         if st != SS_OK:
             raise SemisortError(st, lib().ss_last_error(self.h).decode())
 
-    PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish")
+    PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish", "compact")
     OPT_DIST_VARIANT = 1
 
     def set_option(self, option, value):
@@ -258,3 +260,46 @@ def partition_equal(keys, vals, params=None, ctx=None):
                                        _ptr(off), _ptr(hv), ctypes.byref(nh), ctypes.byref(params)))
     nb = (1 << params.n_light_log2) + nh.value
     return tk, tv, off[:nb + 1], hv[:nh.value]
+
+
+def _check_keys(keys, name="keys"):
+    import torch
+    if not keys.is_cuda or keys.dtype != torch.int64 or keys.dim() != 1 or not keys.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D int64 device tensor (uint64 bits)")
+
+
+def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None):
+    """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values).
+
+    Returns views of length m of the two output tensors (capacity n each)."""
+    import torch
+    _check_keys(keys)
+    _check_keys(vals, "vals")
+    if vals.shape != keys.shape:
+        raise ValueError("keys and vals must have equal length")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_sums is None:
+        out_sums = torch.empty_like(keys)
+    m = ctypes.c_uint64()
+    ctx.check(lib().ss_collect_reduce(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(out_keys), _ptr(out_sums),
+                                      ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    return out_keys[:m.value], out_sums[:m.value]
+
+
+def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None):
+    """ss_histogram: (unique keys, occurrence counts) as views of length m."""
+    import torch
+    _check_keys(keys)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_counts is None:
+        out_counts = torch.empty_like(keys)
+    m = ctypes.c_uint64()
+    ctx.check(lib().ss_histogram(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
+                                 ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    return out_keys[:m.value], out_counts[:m.value]

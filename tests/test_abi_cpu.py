@@ -18,6 +18,7 @@ def _lib_or_skip():
 def test_header_declares_the_boundary():
     names = S.declared_symbols()
     for want in ["ss_create", "ss_destroy", "ss_semisort_equal", "ss_semisort_equal_batch",
+                 "ss_semisort_less", "ss_semisort_less_batch", "ss_collect_reduce", "ss_histogram",
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync"]:
         assert want in names
 
@@ -38,6 +39,10 @@ def test_default_params():
 def test_null_context_is_rejected():
     L = _lib_or_skip()
     assert L.ss_semisort_equal(None, None, None, 8, 10, None, None, None) == S.SS_EINVAL
+    assert L.ss_semisort_less(None, None, None, 8, 10, None, None, None) == S.SS_EINVAL
+    m = ctypes.c_uint64(7)
+    assert L.ss_collect_reduce(None, None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
+    assert L.ss_histogram(None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_destroy(None) == S.SS_EINVAL
     assert L.ss_sync(None) == S.SS_EINVAL
     assert L.ss_last_error(None) == b"null context"

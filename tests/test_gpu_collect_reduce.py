@@ -1,0 +1,156 @@
+"""GPU parity for collect-reduce and histogram (Section 3.5): the HIP path
+(through the C-ABI) against the CPU oracle.  The GPU returns the m pairs in
+an unspecified order, so both sides are compared after sorting by key; keys
+are unique on both sides, so the sorted pairs must match exactly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2304_10078_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2304_10078_amd import semisort as S  # noqa: E402
+from tests.gpu_util import to_dev, to_host  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _sorted_pairs(k, v):
+    o = np.argsort(k, kind="stable")
+    return k[o], v[o]
+
+
+def check_cr(keys, vals, params=None, ctx=""):
+    gk, gs = S.collect_reduce(to_dev(keys), to_dev(vals), params=params)
+    torch.cuda.synchronize()
+    gk, gs = _sorted_pairs(to_host(gk, np.uint64), to_host(gs, np.uint64))
+    rk, rs = O.collect_reduce(keys, vals)
+    assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"
+    assert np.array_equal(gk, rk), f"{ctx}: keys differ"
+    if not np.array_equal(gs, rs):
+        i = int(np.nonzero(gs != rs)[0][0])
+        raise AssertionError(f"{ctx}: sum of key {rk[i]} is {gs[i]}, oracle {rs[i]}")
+
+
+def check_hist(keys, params=None, ctx=""):
+    gk, gc = S.histogram(to_dev(keys), params=params)
+    torch.cuda.synchronize()
+    gk, gc = _sorted_pairs(to_host(gk, np.uint64), to_host(gc, np.uint64))
+    rk, rc = O.histogram(keys)
+    assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"
+    assert np.array_equal(gk, rk), f"{ctx}: keys differ"
+    if not np.array_equal(gc, rc):
+        i = int(np.nonzero(gc != rc)[0][0])
+        raise AssertionError(f"{ctx}: count of key {rk[i]} is {gc[i]}, oracle {rc[i]}")
+
+
+def test_config1_uniform_1e5_keys_n_1e6():
+    k, v = I.np_workload("uniform1e5_index", 10 ** 6, 1)
+    _say("case: CR uniform1e5_index n=1e6")
+    check_cr(k, v, ctx="CR C1")
+    _say("case: histogram uniform1e5_index n=1e6")
+    check_hist(k, ctx="hist C1")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 63, 64, 65, 1000, 4095, 4096, 4097, 8193, 65537, 65536 * 3 + 7, 300001])
+def test_ragged_sizes(n):
+    rng = np.random.default_rng(n + 100)
+    k = rng.integers(0, max(2, n // 7), n, dtype=np.int64).astype(np.uint64)
+    v = rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64)
+    _say(f"case: ragged CR/hist n={n}")
+    check_cr(k, v, ctx=f"CR n={n}")
+    check_hist(k, ctx=f"hist n={n}")
+
+
+@pytest.mark.parametrize("name,n", [("zipf1.2_hashed", 2_000_003), ("uniform1e9", 3_000_001),
+                                    ("uniform1e3", 1_000_000), ("exp1e-5_u32idx", 1_500_000),
+                                    ("zipf0.8_1e8_u32idx", 1_200_000)])
+def test_paper_distributions(name, n):
+    k, v = I.np_workload(name, n, 17)
+    v = v.astype(np.uint64)
+    _say(f"case: CR/hist {name} n={n}")
+    check_cr(k, v, ctx=f"CR {name}")
+    check_hist(k, ctx=f"hist {name}")
+
+
+def test_sums_wrap_modulo_2_64():
+    n = 300_000
+    rng = np.random.default_rng(3)
+    k = rng.integers(0, 50, n, dtype=np.int64).astype(np.uint64)
+    v = np.full(n, 0xFFFF_FFFF_FFFF_FFF0, dtype=np.uint64)
+    _say("case: wrapping sums")
+    check_cr(k, v, ctx="wrap")
+
+
+def test_identity_hash_and_deep_recursion():
+    k, v = I.np_workload("zipf0.8_1e8_u32idx", 500_000, 3)
+    v = v.astype(np.uint64)
+    _say("case: identity hash")
+    check_cr(k, v, S.default_params(hash_mode="identity"), ctx="identity")
+    rng = np.random.default_rng(5)
+    n = 150_000
+    k = rng.integers(0, 40_000, n, dtype=np.int64).astype(np.uint64)
+    v = rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64)
+    p = S.default_params(n_light_log2=1, base_case=64, sample_mult=20)
+    _say("case: deep recursion")
+    check_cr(k, v, p, ctx="deep")
+    check_hist(k, p, ctx="deep hist")
+
+
+def test_all_equal_and_all_distinct():
+    n = 200_000
+    k = np.full(n, 0xDEADBEEF, dtype=np.uint64)
+    v = np.arange(n, dtype=np.uint64)
+    _say("case: CR all equal")
+    check_cr(k, v, ctx="all equal")
+    check_hist(k, ctx="all equal hist")
+    k = np.arange(n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    _say("case: CR all distinct")
+    check_cr(k, v, ctx="distinct")
+    check_hist(k, ctx="distinct hist")
+
+
+def test_deterministic_for_a_seed():
+    k, v = I.np_workload("zipf1.2_hashed", 1_000_000, 2)
+    a = S.collect_reduce(to_dev(k), to_dev(v))
+    a = (to_host(a[0], np.uint64), to_host(a[1], np.uint64))
+    b = S.collect_reduce(to_dev(k), to_dev(v))
+    b = (to_host(b[0], np.uint64), to_host(b[1], np.uint64))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_empty_input():
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    gk, gs = S.collect_reduce(e, e)
+    assert gk.numel() == 0 and gs.numel() == 0
+    gk, gc = S.histogram(e)
+    assert gk.numel() == 0
+
+
+def test_rejects_overlapping_outputs():
+    k = torch.zeros(100, dtype=torch.int64, device="cuda")
+    v = torch.zeros(100, dtype=torch.int64, device="cuda")
+    with pytest.raises(S.SemisortError):
+        S.collect_reduce(k, v, out_keys=v)
+
+
+def test_histogram_after_semisort_on_one_context_reuses_workspace():
+    # the same context serves semisort and collect-reduce in turn
+    k, v = I.np_workload("exp1e-5_u32idx", 800_000, 4)
+    v = v.astype(np.uint64)
+    ctx = S.context(0)
+    _say("case: mixed calls on one context")
+    for _ in range(2):
+        ko, vo = S.semisort_equal(to_dev(k), to_dev(v), ctx=ctx)
+        check_hist(k, ctx="mixed hist")
+        check_cr(k, v, ctx="mixed CR")
