@@ -9,7 +9,6 @@ distribution pass, timed live with HIP events on the library's stream) and the
 CPU oracle timed on a bounded sample on the host.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -28,24 +27,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def source_digest():
-    h = hashlib.sha256()
-    for rel in ("paper_2304_10078_amd/csrc/ss_device.h", "paper_2304_10078_amd/csrc/engine.hip"):
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(workload, n):
     """HBM bytes per distribution launch from committed rocprofv3 counter runs,
     only if they were taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_distribute.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_k_distribute_{workload}_n{n}.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
     except Exception:
         return None
+    from paper_2304_10078_amd.profiling import source_digest
     if d.get("source_digest") != source_digest() or d.get("workload") != workload or d.get("n") != n:
         return None
     return d.get("bytes_per_launch")
@@ -79,7 +71,7 @@ def main():
     ap.add_argument("--alpha", type=int, default=0, help="base-case threshold (0 = library default)")
     ap.add_argument("--sample-mult", type=int, default=0, help="c in |S| = c ln n' (0 = library default)")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="after timing, copy 2^30 int64 (8 GiB) once: a plain copy of known size that "
+                    help="after timing, copy 2^28 int64 (2 GiB) once: a plain copy of known size that "
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -175,7 +167,7 @@ def main():
         "passes": passes,
     }
     if args.calib_copy:
-        src = torch.empty(1 << 30, dtype=torch.int64, device=dev).fill_(1)
+        src = torch.empty(1 << 28, dtype=torch.int64, device=dev).fill_(1)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
