@@ -70,6 +70,8 @@ def main():
     ap.add_argument("--nl0", type=int, default=0, help="top-level light bucket bits (0 = library default)")
     ap.add_argument("--alpha", type=int, default=0, help="base-case threshold (0 = library default)")
     ap.add_argument("--sample-mult", type=int, default=0, help="c in |S| = c ln n' (0 = library default)")
+    ap.add_argument("--heavy-min", type=int, default=-1, help="heavy threshold tau (-1 = library default, "
+                                                               "0 = ceil(ln n'))")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 2^28 int64 (2 GiB) once: a plain copy of known size that "
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
@@ -110,6 +112,8 @@ def main():
         params.base_case = args.alpha
     if args.sample_mult:
         params.sample_mult = args.sample_mult
+    if args.heavy_min >= 0:
+        params.heavy_min = args.heavy_min
     ko = torch.empty_like(keys)
     vo = torch.empty_like(vals)
     for i in range(args.warmup):
@@ -135,7 +139,11 @@ def main():
                         "units_per_step": units / args.steps}
         log(f"  {name:10s} {ms / args.steps:8.3f} ms/step  launches {launches / args.steps:.1f}")
     d_ms, d_launch, d_units = prof["distribute"]
-    bytes_per_launch = d_units * 2 * R / d_launch
+    # the distribution pass reads key and value of every record and writes
+    # every value; keys of one-key buckets bound for the output are written
+    # by the fill pass instead (counted there)
+    filled = prof["fill"][2]
+    bytes_per_launch = (d_units * 2 * R - filled * 8) / d_launch
     avg_launch_s = d_ms * 1e-3 / d_launch
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic = load_traffic(args.workload, n)
@@ -160,7 +168,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"semisort_= {args.workload} n={n} (u64 key, u{8 * vb} value)", "n": n,
                    "seed": args.seed, "n_light_log2": params.n_light_log2, "base_case": params.base_case,
-                   "sample_mult": params.sample_mult, "f_H": round(f_h, 4), "distinct": distinct, "max_freq": max_freq,
+                   "sample_mult": params.sample_mult, "heavy_min": params.heavy_min, "f_H": round(f_h, 4), "distinct": distinct, "max_freq": max_freq,
                    "B_alg_per_record": round(b_alg, 3)},
         "pct_hbm_roofline_whole_job": round(100 * whole_frac, 2),
         "roofline": roofline,

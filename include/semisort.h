@@ -7,7 +7,8 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Keys are uint64.  Values are uint32 or uint64 (val_bytes = 4 or 8).
- *   Arrays are structure-of-arrays: keys[n] and vals[n] side by side.
+ *   Arrays are structure-of-arrays: keys[n] and vals[n] side by side, each
+ *   aligned to its element size.
  * - Every array pointer is a DEVICE pointer on the context's device, owned by
  *   the caller.  The library owns only its workspace (temporary array T,
  *   counting matrices, heavy tables, work lists), which it grows on demand
@@ -59,10 +60,14 @@ typedef enum { SS_HASH_MIX64 = 0, SS_HASH_IDENTITY = 1 } ss_hash_mode;
 typedef struct {
     uint32_t n_light_log2; /* b, n_L = 2^b light buckets on the top level (1..10; default 10) */
     uint32_t base_case;    /* alpha: subproblems below this are finished in LDS (64..4096; default 4096) */
-    uint32_t sample_mult;  /* c in |S| = ceil(c ln n') (1..511; default 500) */
+    uint32_t sample_mult;  /* c in |S| = ceil(c ln n') (1..4096; default 800, the paper uses 500);
+                              |S| <= min(n'/8, 16384) */
     uint32_t tile_min;     /* smallest subarray size l in records (power of two, 8192..65536) */
     uint32_t tile_max;     /* largest subarray size l (power of two, tile_min..65536; default 65536) */
     uint32_t hash_mode;    /* ss_hash_mode */
+    uint32_t heavy_min;    /* tau: a key sampled at least tau times is heavy (default 3; 0 = ceil(ln n'),
+                              the paper's rule).  At most 512 keys per subproblem are heavy: if more
+                              reach tau, tau rises to the least value that leaves at most 512. */
     uint64_t seed;         /* sampling seed */
 } ss_params;
 
@@ -97,8 +102,10 @@ ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
  * units = subarrays), SS_PROF_DISTRIBUTE (distribution; units = records
  * moved), SS_PROF_PLAN (next-level planning and, for collect-reduce, the
  * heavy keys' results; units = subproblems), SS_PROF_FINISH (base cases and
- * copies; units = records) and SS_PROF_COMPACT (packing of collect-reduce
- * and histogram results; units = positions scanned).  ss_profile_enable
+ * copies; units = records), SS_PROF_COMPACT (packing of collect-reduce
+ * and histogram results; units = positions scanned) and SS_PROF_FILL (keys of
+ * one-key buckets written as constant runs; units = keys written; the
+ * distribution pass does not store these keys).  ss_profile_enable
  * resets the totals; ss_profile_read waits for the stream and returns the
  * total milliseconds, launch count and units of one pass. */
 enum {
@@ -109,7 +116,8 @@ enum {
     SS_PROF_PLAN = 4,
     SS_PROF_FINISH = 5,
     SS_PROF_COMPACT = 6,
-    SS_PROF_KINDS = 7
+    SS_PROF_FILL = 7,
+    SS_PROF_KINDS = 8
 };
 ss_status ss_profile_enable(ss_ctx* ctx, int on);
 ss_status ss_profile_read(ss_ctx* ctx, int kind, double* total_ms, uint64_t* launches,

@@ -168,7 +168,7 @@ def select_heavy(sample_keys, tau, hash_mode=HASH_MIX64, max_heavy=1 << 16):
     out = np.empty(max(1, min(max_heavy, s.size)), dtype=np.uint64)
     nh = lib().orc_select_heavy(_p(s), s.size, int(tau), hash_mode, out.size, _p(out))
     if nh < 0:
-        raise ValueError("too many heavy keys" if nh == -1 else "out of memory")
+        raise MemoryError("oracle select_heavy")
     return out[:nh].copy()
 
 

@@ -316,28 +316,42 @@ int64_t orc_select_heavy(const uint64_t* sample_keys, uint32_t s, uint32_t tau,
 {
     /* Count the occurrences of each distinct sampled key; a key seen at least
      * tau times is heavy (Section 3.1, Algorithm 1 Step 1).  Distinct keys are
-     * visited in ascending (h(k), k) order, so ids follow that order. */
+     * visited in ascending (h(k), k) order, so ids follow that order.
+     * The heavy table has room for max_heavy keys (the paper's table is
+     * unbounded): when more keys reach tau, tau is raised to the smallest
+     * value at which at most max_heavy keys reach it. */
     if (s == 0) return 0;
     uint64_t* t = (uint64_t*)malloc((uint64_t)s * sizeof(uint64_t));
-    if (!t) return -2;
+    uint32_t* runlen = (uint32_t*)malloc((uint64_t)s * sizeof(uint32_t));
+    if (!t || !runlen) {
+        free(t);
+        free(runlen);
+        return -2;
+    }
     memcpy(t, sample_keys, (uint64_t)s * sizeof(uint64_t));
     g_cmp_mode = hash_mode;
     qsort(t, s, sizeof(uint64_t), cmp_by_hash);
-    int64_t nh = 0;
+    /* run lengths, recorded at each run's first position */
     uint32_t p = 0;
     while (p < s) {
         uint32_t q = p;
         while (q < s && t[q] == t[p]) q++;
-        if (q - p >= tau) {
-            if ((uint64_t)nh >= max_heavy) {
-                free(t);
-                return -1;
-            }
-            heavy_keys[nh++] = t[p];
-        }
+        runlen[p] = q - p;
         p = q;
     }
+    uint32_t eff = tau < 1 ? 1 : tau;
+    for (;;) {
+        uint64_t reach = 0;
+        for (p = 0; p < s; p += runlen[p])
+            if (runlen[p] >= eff) reach++;
+        if (reach <= max_heavy) break;
+        eff++;
+    }
+    int64_t nh = 0;
+    for (p = 0; p < s; p += runlen[p])
+        if (runlen[p] >= eff) heavy_keys[nh++] = t[p];
     free(t);
+    free(runlen);
     return nh;
 }
 

@@ -86,8 +86,9 @@ uint64_t orc_sample_index(uint64_t seed, uint32_t level, uint64_t start, uint64_
                           uint64_t i);
 
 /* Heavy keys: the distinct sampled keys seen at least tau times, in ascending
- * (h(k), k) order; their bucket ids are n_L, n_L+1, ... in that order.
- * Returns n_H (at most max_heavy; -1 if more keys qualify, -2 on OOM). */
+ * (h(k), k) order; their bucket ids are n_L, n_L+1, ... in that order.  When
+ * more than max_heavy keys qualify, tau is raised to the least value at which
+ * at most max_heavy do.  Returns n_H, or -2 when out of memory. */
 int64_t orc_select_heavy(const uint64_t* sample_keys, uint32_t s, uint32_t tau,
                          int hash_mode, uint32_t max_heavy, uint64_t* heavy_keys);
 

@@ -40,6 +40,8 @@ struct ss_ctx {
     DevBuf jobs;
     DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
+    DevBuf bkey, fills;              // one-key bucket keys, key-fill jobs
+    uint32_t fill_cap = 0;
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     std::vector<Seg> host_segs;
@@ -173,14 +175,14 @@ ss_status resolve_profile(ss_ctx* c)
 // Clears the per-level counters of the device LevelInfo, keeping the sticky status word.
 ss_status reset_counters(ss_ctx* c)
 {
-    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, (1 + kJobClasses) * sizeof(uint32_t), c->stream));
+    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, (2 + kJobClasses) * sizeof(uint32_t), c->stream));
     HIP_OR_FAIL(c, hipMemsetAsync((char*)c->info.p + offsetof(LevelInfo, records), 0,
-                                  2 * sizeof(unsigned long long), c->stream));
+                                  3 * sizeof(unsigned long long), c->stream));
     return SS_OK;
 }
 
 struct Params {
-    uint32_t nl0, alpha, c, tmin, tmax, mode;
+    uint32_t nl0, alpha, c, tmin, tmax, mode, tau;
     uint64_t seed;
 };
 
@@ -195,10 +197,12 @@ ss_status resolve_params(ss_ctx* c, const ss_params* in, Params* p)
     p->tmin = s.tile_min ? s.tile_min : d.tile_min;
     p->tmax = s.tile_max ? s.tile_max : d.tile_max;
     p->mode = s.hash_mode;
+    p->tau = s.heavy_min;
     p->seed = s.seed;
     if (p->nl0 < 1 || p->nl0 > kLightBitsMax) return fail(c, SS_EINVAL, "n_light_log2 must be in [1, 10]");
     if (p->alpha < 64 || p->alpha > kAlphaMax) return fail(c, SS_EINVAL, "base_case must be in [64, 4096]");
-    if (p->c < 1 || p->c >= kHeavyMax) return fail(c, SS_EINVAL, "sample_mult must be in [1, 511]");
+    if (p->c < 1 || p->c > 4096) return fail(c, SS_EINVAL, "sample_mult must be in [1, 4096]");
+    if (p->tau > kSampleMax) return fail(c, SS_EINVAL, "heavy_min must be at most 16384");
     auto pow2 = [](uint32_t x) { return x && !(x & (x - 1)); };
     if (!pow2(p->tmin) || !pow2(p->tmax) || p->tmin < 8192 || p->tmax > 65536 || p->tmin > p->tmax)
         return fail(c, SS_EINVAL, "tile_min/tile_max must be powers of two with 8192 <= tile_min <= tile_max <= 65536");
@@ -327,6 +331,7 @@ ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunk
     if ((s = ensure(c, c->tab_h, (size_t)nsegs * 2 * kHeavySlotsMax * 8)) != SS_OK) return s;
     if ((s = ensure(c, c->tab_id, (size_t)nsegs * 2 * kHeavySlotsMax * 2)) != SS_OK) return s;
     if ((s = ensure(c, c->bfin, (size_t)nsegs * kNbStride)) != SS_OK) return s;
+    if ((s = ensure(c, c->bkey, (size_t)nsegs * kNbStride * 8)) != SS_OK) return s;
     return SS_OK;
 }
 
@@ -356,10 +361,13 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.seed = p.seed;
     a.level = level;
     a.sample_mult = p.c;
+    a.heavy_min = p.tau;
     a.alpha = p.alpha;
     a.adaptive_nl = 1;
     a.ordered = p.mode == 2;
     a.bfin = (uint8_t*)c->bfin.p;
+    a.bkey = (uint64_t*)c->bkey.p;
+    a.fill_heavy = 0;
     a.reduce = 0;
     a.hsum = nullptr;
     a.res_keys = nullptr;
@@ -399,9 +407,13 @@ ss_status ensure_jobs(ss_ctx* c, uint32_t per_class)
 // segs[cur] -> segs[cur ^ 1], job lists) and reads the level's counters back
 // to the host; grows the lists and plans again when they overflow.
 ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs, int cur, uint32_t* seg_cap,
-                     bool finals_in_out, bool reduce, LevelInfo* out)
+                     bool finals_in_out, bool reduce, bool fill, LevelInfo* out)
 {
     ss_status s;
+    if (fill && c->fill_cap == 0) {
+        if ((s = ensure(c, c->fills, 4096 * sizeof(FillJob))) != SS_OK) return s;
+        c->fill_cap = (uint32_t)(c->fills.cap / sizeof(FillJob));
+    }
     for (int attempt = 0;; ++attempt) {
         if (attempt && (s = reset_counters(c)) != SS_OK) return s;
         PlanArgs pa;
@@ -418,6 +430,10 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         pa.ordered = p.mode == 2;
         pa.bfin = (const uint8_t*)c->bfin.p;
         pa.reduce = reduce;
+        pa.fill = fill;
+        pa.bkey = (const uint64_t*)c->bkey.p;
+        pa.fills = (FillJob*)c->fills.p;
+        pa.fill_cap = c->fill_cap;
         {
             ProfScope ps(c, SS_PROF_PLAN, nsegs);
             hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
@@ -448,6 +464,11 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         for (int k = 0; k < kJobClasses; ++k) jmax = std::max(jmax, li.njobs[k]);
         if (jmax > c->job_cap) {
             if ((s = ensure_jobs(c, jmax)) != SS_OK) return s;
+            again = true;
+        }
+        if (li.nfills > c->fill_cap) {
+            if ((s = ensure(c, c->fills, (size_t)li.nfills * sizeof(FillJob))) != SS_OK) return s;
+            c->fill_cap = (uint32_t)(c->fills.cap / sizeof(FillJob));
             again = true;
         }
         if (again) continue;
@@ -568,11 +589,20 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         if ((s = reset_counters(c)) != SS_OK) return s;
         LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, fin_k,
                                 fin_v);
+        // one-key buckets written to the output: only their values move,
+        // their keys are filled as constant runs after the level
+        const bool fill = fin_k == keys_out;
+        a.fill_heavy = fill;
         launch_level_v<V>(c, p.mode, a, tiles, chunks, records);
         HIP_OR_FAIL(c, hipGetLastError());
 
         LevelInfo li;
-        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, &li)) != SS_OK) return s;
+        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, fill, &li)) != SS_OK)
+            return s;
+        if (li.nfills) {
+            ProfScope ps(c, SS_PROF_FILL, li.fill_records);
+            hipLaunchKernelGGL(k_fill, dim3(li.nfills), dim3(1024), 0, c->stream, (const FillJob*)c->fills.p, keys_out);
+        }
         launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
         HIP_OR_FAIL(c, hipGetLastError());
         nsegs = li.nsegs;
@@ -727,7 +757,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
             else launch_red_level_m<0, RED>(c, a, tiles, chunks, records);
             HIP_OR_FAIL(c, hipGetLastError());
             LevelInfo li;
-            if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, false, true, &li)) != SS_OK) return s;
+            if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, false, true, false, &li)) != SS_OK) return s;
             launch_red_jobs<RED>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, T_k, T_v, rf, li.job_records);
             HIP_OR_FAIL(c, hipGetLastError());
             nsegs = li.nsegs;
@@ -806,10 +836,11 @@ ss_status ss_default_params(ss_params* p)
     if (!p) return SS_EINVAL;
     p->n_light_log2 = 10;
     p->base_case = kAlphaMax;
-    p->sample_mult = 500;
+    p->sample_mult = 800;
     p->tile_min = 8192;
     p->tile_max = 65536;
     p->hash_mode = SS_HASH_MIX64;
+    p->heavy_min = 3;
     p->seed = 0x5eed5eed2023ULL;
     return SS_OK;
 }
@@ -840,7 +871,7 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev};
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills};
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto& p : c->pending) {
@@ -917,7 +948,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev};
+                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;

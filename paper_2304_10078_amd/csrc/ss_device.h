@@ -25,6 +25,7 @@ constexpr uint32_t kHeavySlotsMax = 1024;    // slots per heavy table; two table
 constexpr uint32_t kAlphaMax = 4096;         // largest base case held in LDS
 constexpr uint32_t kChunk = 32;              // subarrays per scan chunk
 constexpr uint32_t kCopyChunk = 65536;       // records per copy job
+constexpr uint32_t kFillChunk = 262144;      // records per key-fill job
 constexpr uint32_t kBucketGroups = kNbStride / 64;  // 24 column groups in the bucket scan
 constexpr uint16_t kEmpty16 = 0xFFFF;
 constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
@@ -55,6 +56,14 @@ struct Job {
     uint32_t len;
 };
 
+// Keys of a one-key final bucket, written as a constant run instead of being
+// moved record by record.
+struct FillJob {
+    uint32_t start;
+    uint32_t len;
+    uint64_t key;
+};
+
 // Job classes: base cases by capacity (512, 1024, 2048, 4096 records), then copies.
 constexpr int kJobClasses = 5;
 constexpr int kCopyClass = 4;
@@ -67,12 +76,14 @@ __host__ __device__ __forceinline__ int base_class(uint32_t len)
 struct LevelInfo {
     uint32_t nsegs;                  // subproblems emitted for the next level
     uint32_t njobs[kJobClasses];     // jobs emitted by this level, per class
+    uint32_t nfills;                 // key-fill jobs emitted by this level
     uint32_t tiles;                  // tiles of the next level
     uint32_t chunks;                 // scan chunks of the next level
     uint32_t tile;                   // subarray size of the next level
     uint32_t status;                 // device-detected errors
     unsigned long long records;      // records in the next level's subproblems
     unsigned long long job_records;  // records covered by this level's jobs
+    unsigned long long fill_records; // records whose keys this level's fill jobs write
 };
 
 struct LevelArgs {
@@ -98,10 +109,13 @@ struct LevelArgs {
     uint64_t seed;
     uint32_t level;
     uint32_t sample_mult;
+    uint32_t heavy_min;    // heavy threshold tau; 0 = ceil(ln n')
     uint32_t alpha;
     uint32_t adaptive_nl;  // choose n_L per subproblem from the sample's light fraction
     uint32_t ordered;      // buckets from sorted splitters (semisort_<) instead of hash bits
     uint8_t* bfin;         // [nsegs][kNbStride]: 1 for buckets that are final (one key each)
+    uint64_t* bkey;        // [nsegs][kNbStride]: the key of each one-key bucket
+    uint32_t fill_heavy;   // one-key buckets bound for keys_out: values move, keys are filled later
     // collect-reduce / histogram (Section 3.5)
     uint32_t reduce;                // heavy records are summed where they are, not moved
     unsigned long long* hsum;       // [nsegs][kHeavyMax] sums of heavy records per heavy id
@@ -129,6 +143,26 @@ __device__ __forceinline__ uint64_t user_hash(uint64_t k)
     if constexpr (MODE == 1) return k;
     else return fmix64(k);
 }
+
+// Inverse of fmix64: xor-shift by 33 undoes itself on 64-bit words, and the
+// two multipliers are odd, so their inverses mod 2^64 exist.
+__device__ __forceinline__ uint64_t unfmix64(uint64_t k)
+{
+    k ^= k >> 33;
+    k *= 0x9cb4b2f8129337dbULL;
+    k ^= k >> 33;
+    k *= 0x4f74430c22a54005ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+template <int MODE>
+__device__ __forceinline__ uint64_t key_of_hash(uint64_t h)
+{
+    if constexpr (MODE == 0) return unfmix64(h);
+    else return h;
+}
+
 
 // SplitMix64's output function (Steele, Lea, Flood 2014).
 __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
@@ -338,7 +372,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         if (s > sg.len / 8) s = sg.len / 8;
         if (s > kSampleMax) s = kSampleMax;
         sh_s = s;
-        sh_tau = sg.len < 3 ? 1u : (uint32_t)ceil(L);
+        sh_tau = a.heavy_min ? a.heavy_min : (sg.len < 3 ? 1u : (uint32_t)ceil(L));
     }
     __syncthreads();
     const uint32_t s = sh_s, tau = sh_tau;
@@ -376,21 +410,55 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         }
     }
 
-    // heavy run starts: a run of equal hashes of length >= tau among the s real samples
+    // Run lengths of the distinct sampled hashes (histogram of min(length, 63)).
+    // The heavy table holds kHeavyMax keys: if more runs reach tau, the
+    // threshold rises to the least value that leaves at most kHeavyMax of
+    // them (the most frequent keys stay heavy).  At most 16384/32 = 512 runs
+    // can reach 32, so the search ends below 63.
     const uint32_t per = (s + BS - 1) / BS;
     const uint32_t lo = tid * per;
     const uint32_t hi = lo + per < s ? lo + per : s;
+    __shared__ uint32_t rh[64];
+    __shared__ uint32_t sh_te;
+    if (tid < 64) rh[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = lo; i < hi; ++i) {
+        if (i != 0 && smp[i] == smp[i - 1]) continue;
+        uint32_t l = i, r = s;  // end of the run: first position in (i, s] with a larger value
+        while (r - l > 1) {
+            const uint32_t mid = (l + r) >> 1;
+            if (smp[mid] == smp[i]) l = mid;
+            else r = mid;
+        }
+        const uint32_t len = r - i;
+        atomicAdd(&rh[len < 63 ? len : 63], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = tau < 1 ? 1u : tau;
+        while (t < 63) {
+            uint32_t c = 0;
+            for (uint32_t L = t; L < 64; ++L) c += rh[L];
+            if (c <= kHeavyMax) break;
+            ++t;
+        }
+        sh_te = t;
+    }
+    __syncthreads();
+    const uint32_t te = sh_te;
+
+    // heavy run starts: a run of equal hashes of length >= te among the s real samples
     uint32_t cnt = 0;
     for (uint32_t i = lo; i < hi; ++i) {
         const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) ++cnt;
+        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) ++cnt;
     }
     uint32_t total = 0;
     uint32_t id = block_excl_scan<BS>(cnt, tmp, &total);
     const uint32_t nh = total < kHeavyMax ? total : kHeavyMax;
     for (uint32_t i = lo; i < hi; ++i) {
         const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) {
+        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) {
             if (id < kHeavyMax) {
                 hv[id] = smp[i];
                 a.heavy_list[(size_t)sid * kHeavyMax + id] = smp[i];
@@ -405,9 +473,9 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     uint32_t hs = 0;
     for (uint32_t i = lo; i < hi; ++i) {
         const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) {
+        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) {
             // end of the run: first position in (i, s) holding a larger value
-            uint32_t l = i + tau - 1, r = s;
+            uint32_t l = i + te - 1, r = s;
             while (r - l > 1) {
                 const uint32_t mid = (l + r) >> 1;
                 if (smp[mid] == smp[i]) l = mid;
@@ -494,6 +562,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
     }
     for (uint32_t b = tid; b < nL + nh; b += BS) a.bfin[(size_t)sid * kNbStride + b] = b >= nL ? 1 : 0;
+    for (uint32_t h = tid; h < nh; h += BS) a.bkey[(size_t)sid * kNbStride + nL + h] = key_of_hash<MODE>(hv[h]);
     if (a.reduce)
         for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = 0;
     if (tid == 0) {
@@ -640,7 +709,7 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
         if (s > sg.len / 8) s = sg.len / 8;
         if (s > kSampleMax) s = kSampleMax;
         sh_s = s;
-        sh_tau = sg.len < 3 ? 1u : (uint32_t)ceil(L);
+        sh_tau = a.heavy_min ? a.heavy_min : (sg.len < 3 ? 1u : (uint32_t)ceil(L));
     }
     __syncthreads();
     const uint32_t s = sh_s, tau = sh_tau;
@@ -679,13 +748,37 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
     const uint32_t per = (s + BS - 1) / BS;
     const uint32_t lo = tid * per;
     const uint32_t hi = lo + per < s ? lo + per : s;
+    // threshold raised, if needed, so that at most kHeavyMax keys are heavy
+    // (the same rule as for semisort_=)
+    __shared__ uint32_t rh[64];
+    __shared__ uint32_t sh_te;
+    if (tid < 64) rh[tid] = 0;
+    __syncthreads();
+    for (uint32_t i = lo; i < hi; ++i) {
+        if (i != 0 && smp[i] == smp[i - 1]) continue;
+        const uint32_t len = upper_bound_u64(smp, s, smp[i]) - i;
+        atomicAdd(&rh[len < 63 ? len : 63], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = tau < 1 ? 1u : tau;
+        while (t < 63) {
+            uint32_t c = 0;
+            for (uint32_t L = t; L < 64; ++L) c += rh[L];
+            if (c <= kHeavyMax) break;
+            ++t;
+        }
+        sh_te = t;
+    }
+    __syncthreads();
+    const uint32_t te = sh_te;
     uint32_t nhs = 0, nls = 0;
     for (uint32_t i = lo; i < hi; ++i) {
         const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) ++nhs;
+        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) ++nhs;
         const uint32_t lb = lower_bound_u64(smp, s, smp[i]);
         const uint32_t ub = upper_bound_u64(smp, s, smp[i]);
-        if (ub - lb < tau) ++nls;
+        if (ub - lb < te) ++nls;
     }
     uint32_t tot_h = 0, tot_l = 0;
     uint32_t hid = block_excl_scan<BS>(nhs, tmp, &tot_h);
@@ -720,7 +813,7 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
     const uint32_t R = sh_R;
     for (uint32_t i = lo; i < hi; ++i) {
         const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + tau - 1 < s && smp[i + tau - 1] == smp[i]) {
+        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) {
             if (hid < kHeavyMax) {
                 hv[hid] = smp[i];
                 a.heavy_list[(size_t)sid * kHeavyMax + hid] = smp[i];
@@ -729,7 +822,7 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
         }
         const uint32_t lb = lower_bound_u64(smp, s, smp[i]);
         const uint32_t ub = upper_bound_u64(smp, s, smp[i]);
-        if (ub - lb < tau) {
+        if (ub - lb < te) {
             // splitter j (j < R-1) sits at light rank floor((j+1) * tot_l / R);
             // with R <= tot_l the ranks of different j differ, and the only
             // candidate for rank r is j+1 = ceil(r * R / tot_l)
@@ -782,7 +875,10 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
         const uint32_t r = j + hbefore;
         const bool heavy = j < m && hf[j];
         rid[j] = (uint16_t)(r | (heavy ? 0x8000u : 0u));
-        if (heavy) fin[r + 1] = 1;
+        if (heavy) {
+            fin[r + 1] = 1;
+            a.bkey[(size_t)sid * kNbStride + r + 1] = bnd[j];
+        }
         hbefore += heavy ? 1u : 0u;
     }
     if (tid == 0) {
@@ -983,7 +1079,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint16_t stage_b[SUB];
     __shared__ uint32_t tmp[20];
     __shared__ unsigned long long hs[RED ? kNbStride : 1];
-    __shared__ uint8_t finl[RED ? kNbStride : 1];
+    __shared__ uint8_t finl[kNbStride];
 
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
@@ -1010,15 +1106,14 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     V* sink_v = (V*)(a.sink + lane);
     const uint32_t per = (nb + BS - 1) / BS;  // buckets per thread in the scans
     const uint32_t pb0 = tid * per;
+    const bool fillk = RED == 0 && a.fill_heavy != 0;
 
     for (uint32_t b = tid; b < nb; b += BS) {
         uint32_t g = a.C[(size_t)t * kNbStride + b];
         if (split && bucket_is_final(fin[b] != 0, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
         gbase[b] = g;
-        if constexpr (RED != 0) {
-            hs[b] = 0;
-            finl[b] = fin[b];
-        }
+        finl[b] = fin[b];
+        if constexpr (RED != 0) hs[b] = 0;
     }
     for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
 
@@ -1121,7 +1216,8 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
                 const uint32_t p = lst[b] + wc[w * nb + b] + pos[e];
                 pos[e] = p;
                 stage[p] = k[e];
-                stage_b[p] = (uint16_t)b;
+                // bit 15: the key is not stored (one-key bucket, filled later)
+                stage_b[p] = (uint16_t)(b | ((fillk && finl[b]) ? 0x8000u : 0u));
             }
         }
         __syncthreads();
@@ -1131,7 +1227,8 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         for (int e = 0; e < E; ++e) {
             const uint32_t j = tid + e * BS;
             const uint32_t jj = j < m ? j : 0u;
-            const uint32_t b = stage_b[jj];
+            const uint32_t sb = stage_b[jj];
+            const uint32_t b = sb & 0x7FFFu;
             const uint32_t dd = gbase[b] + (jj - lst[b]);
             const uint32_t d = dd & 0x7FFFFFFFu;
             const bool in_range = d - sg.start < sg.len;
@@ -1139,7 +1236,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             dest[e] = (j < m && in_range) ? dd : 0xFFFFFFFFu;
             uint64_t* out = (dd >> 31) ? a.fin_keys : a.dst_keys;
             uint64_t* addr = dest[e] != 0xFFFFFFFFu ? out + d : sink_k;
-            *addr = stage[jj];
+            if (!(sb >> 15)) *addr = stage[jj];
         }
         for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
         __syncthreads();
@@ -1328,19 +1425,25 @@ struct PlanArgs {
     uint32_t ordered;        // splitter buckets: no hash bits are consumed
     const uint8_t* bfin;     // [nsegs][kNbStride] one-key bucket flags
     uint32_t reduce;         // collect-reduce: heavy buckets are done, one-key buckets are summed
+    uint32_t fill;           // one-key final buckets in the output get key-fill jobs
+    const uint64_t* bkey;    // [nsegs][kNbStride] keys of one-key buckets
+    FillJob* fills;
+    uint32_t fill_cap;
 };
 
 struct PlanCount {
     uint32_t seg;
     uint32_t job[kJobClasses];
+    uint32_t fill;
     uint32_t rec;
+    uint32_t frec;
 };
 
 // What bucket b of subproblem sg turns into; with emit, write it at the
 // cursors (seg_at, job_at[class]).
 __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, const Seg& sg, uint32_t b,
                                             uint32_t nL, PlanCount& cnt, bool emit, uint32_t* seg_at,
-                                            uint32_t* job_at)
+                                            uint32_t* job_at, uint32_t* fill_at)
 {
     const uint32_t* bs = p.bstart + (size_t)sidx * (kNbStride + 1);
     const uint32_t st = bs[b];
@@ -1363,7 +1466,21 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
             return;
         }
     } else if (bucket_is_final(p.bfin[(size_t)sidx * kNbStride + b] != 0, sz, all_bits_used)) {
-        if (p.finals_in_out) return;  // already in place
+        if (p.finals_in_out) {  // already in place, except the keys of one-key buckets
+            if (p.fill && p.bfin[(size_t)sidx * kNbStride + b]) {
+                const uint64_t key = p.bkey[(size_t)sidx * kNbStride + b];
+                for (uint32_t o = 0; o < sz; o += kFillChunk) {
+                    const uint32_t l = sz - o < kFillChunk ? sz - o : kFillChunk;
+                    if (emit) {
+                        if (*fill_at < p.fill_cap) p.fills[*fill_at] = FillJob{st + o, l, key};
+                        ++*fill_at;
+                    }
+                    ++cnt.fill;
+                }
+                cnt.frec += sz;
+            }
+            return;
+        }
         for (uint32_t o = 0; o < sz; o += kCopyChunk) {
             const uint32_t l = sz - o < kCopyChunk ? sz - o : kCopyChunk;
             if (emit && job_at[kCopyClass] < p.job_cap)
@@ -1406,14 +1523,15 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
 __global__ __launch_bounds__(256) void k_plan(PlanArgs p)
 {
     __shared__ uint32_t tmp[20];
-    __shared__ uint32_t sh_base[kJobClasses + 1];
+    __shared__ uint32_t sh_base[kJobClasses + 2];
     const uint32_t sidx = blockIdx.x;
     const Seg sg = p.segs[sidx];
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = sg.nbk;
     PlanCount cnt{};
-    uint32_t dummy_s = 0, dummy_j[kJobClasses] = {};
-    for (uint32_t b = threadIdx.x; b < nb; b += 256) plan_bucket(p, sidx, sg, b, nL, cnt, false, &dummy_s, dummy_j);
+    uint32_t dummy_s = 0, dummy_j[kJobClasses] = {}, dummy_f = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += 256)
+        plan_bucket(p, sidx, sg, b, nL, cnt, false, &dummy_s, dummy_j, &dummy_f);
     uint32_t tot = 0;
     uint32_t seg_at = block_excl_scan<256>(cnt.seg, tmp, &tot);
     if (threadIdx.x == 0) sh_base[kJobClasses] = tot ? atomicAdd(&p.info->nsegs, tot) : 0u;
@@ -1423,15 +1541,21 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs p)
         job_at[c] = block_excl_scan<256>(cnt.job[c], tmp, &tot);
         if (threadIdx.x == 0) sh_base[c] = tot ? atomicAdd(&p.info->njobs[c], tot) : 0u;
     }
+    uint32_t fill_at = block_excl_scan<256>(cnt.fill, tmp, &tot);
+    if (threadIdx.x == 0) sh_base[kJobClasses + 1] = tot ? atomicAdd(&p.info->nfills, tot) : 0u;
     uint32_t rtot = 0;
     (void)block_excl_scan<256>(cnt.rec, tmp, &rtot);
     if (threadIdx.x == 0 && rtot) atomicAdd(&p.info->job_records, (unsigned long long)rtot);
+    (void)block_excl_scan<256>(cnt.frec, tmp, &rtot);
+    if (threadIdx.x == 0 && rtot) atomicAdd(&p.info->fill_records, (unsigned long long)rtot);
     __syncthreads();
     seg_at += sh_base[kJobClasses];
+    fill_at += sh_base[kJobClasses + 1];
 #pragma unroll
     for (int c = 0; c < kJobClasses; ++c) job_at[c] += sh_base[c];
     PlanCount again{};
-    for (uint32_t b = threadIdx.x; b < nb; b += 256) plan_bucket(p, sidx, sg, b, nL, again, true, &seg_at, job_at);
+    for (uint32_t b = threadIdx.x; b < nb; b += 256)
+        plan_bucket(p, sidx, sg, b, nL, again, true, &seg_at, job_at, &fill_at);
 }
 
 // Prefix over the next level's subproblems: subarray size for the level,
@@ -1881,6 +2005,23 @@ __global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* s
     }
 }
 
+// Key-fill jobs: the keys of a one-key bucket are one value repeated.
+// 16-byte stores after an odd first element, if any.
+__global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, uint64_t* out_keys)
+{
+    const FillJob j = jobs[blockIdx.x];
+    uint64_t* o = out_keys + j.start;
+    const uint32_t head = (((uintptr_t)o & 8u) && j.len) ? 1u : 0u;  // keys are 8-byte aligned
+    const uint32_t n2 = (j.len - head) / 2;
+    if (threadIdx.x == 0) {
+        if (head) o[0] = j.key;
+        if ((j.len - head) & 1u) o[j.len - 1] = j.key;
+    }
+    ulonglong2* o2 = (ulonglong2*)(o + head);
+    const ulonglong2 kk = make_ulonglong2(j.key, j.key);
+    for (uint32_t i = threadIdx.x; i < n2; i += 1024) o2[i] = kk;
+}
+
 // Offsets and heavy list of a single-subproblem level, for inspection.
 __global__ void k_export_partition(const uint32_t* bstart, const Seg* segs, const uint64_t* heavy_list,
                                    uint64_t* offsets_out, uint64_t* heavy_out)
@@ -1900,25 +2041,6 @@ __global__ void k_export_partition(const uint32_t* bstart, const Seg* segs, cons
 // Every result sits at a position inside its bucket's range, marked in rflag;
 // a final compaction packs them.  The monoid is wrapping 64-bit addition;
 // for the histogram every value is 1.
-
-// Inverse of fmix64: xor-shift by 33 undoes itself on 64-bit words, and the
-// two multipliers are odd, so their inverses mod 2^64 exist.
-__device__ __forceinline__ uint64_t unfmix64(uint64_t k)
-{
-    k ^= k >> 33;
-    k *= 0x9cb4b2f8129337dbULL;
-    k ^= k >> 33;
-    k *= 0x4f74430c22a54005ULL;
-    k ^= k >> 33;
-    return k;
-}
-
-template <int MODE>
-__device__ __forceinline__ uint64_t key_of_hash(uint64_t h)
-{
-    if constexpr (MODE == 0) return unfmix64(h);
-    else return h;
-}
 
 // Results of the heavy keys of every subproblem of the level.
 template <int MODE>

@@ -36,6 +36,7 @@ class ss_params(ctypes.Structure):
         ("tile_min", ctypes.c_uint32),
         ("tile_max", ctypes.c_uint32),
         ("hash_mode", ctypes.c_uint32),
+        ("heavy_min", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -125,7 +126,7 @@ class Context:
         if st != SS_OK:
             raise SemisortError(st, lib().ss_last_error(self.h).decode())
 
-    PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish", "compact")
+    PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish", "compact", "fill")
     OPT_DIST_VARIANT = 1
 
     def set_option(self, option, value):

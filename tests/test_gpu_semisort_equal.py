@@ -119,18 +119,22 @@ def test_rejects_overlapping_output():
         S.semisort_equal(k, v, keys_out=v, vals_out=k)
 
 
-def test_partition_matches_the_oracle_stage_model():
+@pytest.mark.parametrize("name,c,tau", [("zipf1.2_hashed", 300, 0), ("zipf1.2_hashed", 1500, 2),
+                                        ("uniform1e3", 1200, 0), ("uniform1e3", 1200, 3)])
+def test_partition_matches_the_oracle_stage_model(name, c, tau):
     # One level of Steps 1-2 against the oracle's step-by-step model with the
     # same seed: heavy set and ids, bucket offsets and the distributed array T.
+    # The uniform[0, 10^3) cases and the low thresholds put more than 512 keys
+    # over the threshold, so the bounded-table rule decides the heavy set.
     n = 400_000
-    k, v = I.np_workload("zipf1.2_hashed", n, 9)
-    p = S.default_params(n_light_log2=6, sample_mult=300)
-    _say("case: partition n=400000")
+    k, v = I.np_workload(name, n, 9)
+    p = S.default_params(n_light_log2=6, sample_mult=c, heavy_min=tau)
+    _say(f"case: partition n=400000 {name} c={c} tau={tau}")
     tk, tv, off, hv = S.partition_equal(to_dev(k), to_dev(v), params=p)
     torch.cuda.synchronize()
     s = O.sample_size(n, p.sample_mult)
     idx = np.array([O.lib().orc_sample_index(p.seed, 0, 0, n, i) for i in range(s)], dtype=np.uint64)
-    heavy = O.select_heavy(k[idx], O.heavy_threshold(n), max_heavy=512)
+    heavy = O.select_heavy(k[idx], tau or O.heavy_threshold(n), max_heavy=512)
     want_h = np.array([O.hash64(int(x)) for x in heavy], dtype=np.uint64)
     assert np.array_equal(to_host(hv, np.uint64), want_h)
     bids = O.bucket_ids(k, heavy, p.n_light_log2, 0)

@@ -243,6 +243,29 @@ def test_select_heavy_brute_force():
         assert [int(x) for x in hk] == want
 
 
+def test_select_heavy_bounded_table_keeps_the_most_frequent():
+    # more keys reach tau than the table holds: tau rises to the least value
+    # at which at most max_heavy keys reach it (checked by brute force over
+    # every candidate threshold)
+    rng = np.random.default_rng(8)
+    for trial in range(30):
+        pool = rng.integers(0, 2 ** 63, 40, dtype=np.int64).astype(np.uint64)
+        s = rng.choice(pool, int(rng.integers(50, 600)), p=rng.dirichlet(np.ones(40) * 0.5))
+        cnt = Counter(int(x) for x in s)
+        for tau in (1, 2, 5):
+            for cap in (1, 3, 7, 40):
+                hk = [int(x) for x in O.select_heavy(s, tau, max_heavy=cap)]
+                t = tau
+                while sum(1 for c in cnt.values() if c >= t) > cap:
+                    t += 1
+                want = sorted([k for k, c in cnt.items() if c >= t], key=lambda k: (O.hash64(k), k))
+                assert hk == want, (trial, tau, cap)
+                assert len(hk) <= cap
+                # nothing left out is more frequent than anything kept
+                if hk:
+                    assert min(cnt[k] for k in hk) > max([c for k, c in cnt.items() if k not in hk] or [0]) - 1
+
+
 def test_count_prefix_distribute_against_definitions():
     rng = np.random.default_rng(9)
     n, tile = 10007, 1000
