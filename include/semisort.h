@@ -19,7 +19,9 @@
  *   ready when the stream is.
  * - Errors: SS_EINVAL for bad arguments (checked before anything is
  *   enqueued), SS_ENOMEM when the workspace cannot grow, SS_EHIP for a failed
- *   HIP call, SS_EDEVICE for a condition detected on the device.
+ *   HIP call, SS_EDEVICE for a condition detected on the device.  A semisort
+ *   call returns without waiting for its last level's kernels; a condition
+ *   they raise is reported by ss_sync or by the next call on the context.
  *   ss_last_error() returns a message for the last failure on the context.
  *   Nothing throws across the ABI.
  * - n = 0 is a no-op returning SS_OK.  n must be below 2^31 (positions are
@@ -80,7 +82,8 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out);
 ss_status ss_destroy(ss_ctx* ctx);
 ss_status ss_set_stream(ss_ctx* ctx, void* hip_stream);
 const char* ss_last_error(ss_ctx* ctx);
-/* Wait for the context's stream. */
+/* Wait for the context's stream; SS_EDEVICE if a kernel of an earlier call
+ * on the context raised a device condition that was not reported yet. */
 ss_status ss_sync(ss_ctx* ctx);
 /* Bytes of workspace currently held by the context. */
 ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);

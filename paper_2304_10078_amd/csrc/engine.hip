@@ -40,8 +40,11 @@ struct ss_ctx {
     DevBuf jobs;
     DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
-    DevBuf bkey, fills;              // one-key bucket keys, key-fill jobs
-    uint32_t fill_cap = 0;
+    DevBuf bkey;                     // keys of one-key buckets
+    DevBuf fills[2];                 // key-fill job lists (alternating levels)
+    uint32_t fill_cap[2] = {0, 0};
+    hipStream_t aux = nullptr;       // second stream: key fills overlap the next level
+    hipEvent_t fill_done[2] = {nullptr, nullptr};
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     std::vector<Seg> host_segs;
@@ -134,7 +137,9 @@ struct ProfScope {
     ss_ctx* c;
     ss_ctx::Pending p;
     bool on;
-    ProfScope(ss_ctx* ctx, int kind, uint64_t units) : c(ctx), on(ctx->prof_on)
+    hipStream_t st;
+    ProfScope(ss_ctx* ctx, int kind, uint64_t units, hipStream_t stream = nullptr)
+        : c(ctx), on(ctx->prof_on), st(stream ? stream : ctx->stream)
     {
         if (!on) return;
         p.kind = kind;
@@ -145,12 +150,12 @@ struct ProfScope {
             on = false;
             return;
         }
-        (void)hipEventRecord(p.a, c->stream);
+        (void)hipEventRecord(p.a, st);
     }
     ~ProfScope()
     {
         if (!on) return;
-        (void)hipEventRecord(p.b, c->stream);
+        (void)hipEventRecord(p.b, st);
         c->pending.push_back(p);
     }
 };
@@ -179,6 +184,16 @@ ss_status reset_counters(ss_ctx* c)
     HIP_OR_FAIL(c, hipMemsetAsync((char*)c->info.p + offsetof(LevelInfo, records), 0,
                                   3 * sizeof(unsigned long long), c->stream));
     return SS_OK;
+}
+
+// Reads the device status word (after the stream has been synchronized by
+// the caller's copy) and, if it is set, clears it and fails.  The word is
+// sticky: a condition raised by the last kernels of a call that returned
+// without waiting is reported by the next check on the context.
+ss_status status_failure(ss_ctx* c, uint32_t status, const std::string& where)
+{
+    (void)hipMemsetAsync((char*)c->info.p + offsetof(LevelInfo, status), 0, sizeof(uint32_t), c->stream);
+    return fail(c, SS_EDEVICE, "device status " + std::to_string(status) + " " + where);
 }
 
 struct Params {
@@ -394,6 +409,15 @@ void host_prefix(std::vector<Seg>& segs, const Params& p, uint32_t* tiles, uint3
     *chunks = rc;
 }
 
+// The second stream and its events, created on first use (default priority).
+ss_status ensure_aux(ss_ctx* c)
+{
+    if (c->aux) return SS_OK;
+    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    for (hipEvent_t& e : c->fill_done) HIP_OR_FAIL(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    return SS_OK;
+}
+
 ss_status ensure_jobs(ss_ctx* c, uint32_t per_class)
 {
     if (per_class <= c->job_cap) return SS_OK;
@@ -410,9 +434,10 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
                      bool finals_in_out, bool reduce, bool fill, LevelInfo* out)
 {
     ss_status s;
-    if (fill && c->fill_cap == 0) {
-        if ((s = ensure(c, c->fills, 4096 * sizeof(FillJob))) != SS_OK) return s;
-        c->fill_cap = (uint32_t)(c->fills.cap / sizeof(FillJob));
+    const int fb = level & 1;  // fill list of this level
+    if (fill && c->fill_cap[fb] == 0) {
+        if ((s = ensure(c, c->fills[fb], 4096 * sizeof(FillJob))) != SS_OK) return s;
+        c->fill_cap[fb] = (uint32_t)(c->fills[fb].cap / sizeof(FillJob));
     }
     for (int attempt = 0;; ++attempt) {
         if (attempt && (s = reset_counters(c)) != SS_OK) return s;
@@ -432,8 +457,8 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         pa.reduce = reduce;
         pa.fill = fill;
         pa.bkey = (const uint64_t*)c->bkey.p;
-        pa.fills = (FillJob*)c->fills.p;
-        pa.fill_cap = c->fill_cap;
+        pa.fills = (FillJob*)c->fills[fb].p;
+        pa.fill_cap = c->fill_cap[fb];
         {
             ProfScope ps(c, SS_PROF_PLAN, nsegs);
             hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
@@ -444,8 +469,7 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
         HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
         const LevelInfo li = *c->info_host;
-        if (li.status)
-            return fail(c, SS_EDEVICE, "device status " + std::to_string(li.status) + " at level " + std::to_string(level));
+        if (li.status) return status_failure(c, li.status, "at level " + std::to_string(level));
         bool again = false;
         if (li.nsegs > *seg_cap) {
             // the current list must survive: copy it aside while both lists grow
@@ -466,9 +490,10 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
             if ((s = ensure_jobs(c, jmax)) != SS_OK) return s;
             again = true;
         }
-        if (li.nfills > c->fill_cap) {
-            if ((s = ensure(c, c->fills, (size_t)li.nfills * sizeof(FillJob))) != SS_OK) return s;
-            c->fill_cap = (uint32_t)(c->fills.cap / sizeof(FillJob));
+        if (li.nfills > c->fill_cap[fb]) {
+            if (c->aux) HIP_OR_FAIL(c, hipStreamSynchronize(c->aux));  // a running fill may read the old list
+            if ((s = ensure(c, c->fills[fb], (size_t)li.nfills * sizeof(FillJob))) != SS_OK) return s;
+            c->fill_cap[fb] = (uint32_t)(c->fills[fb].cap / sizeof(FillJob));
             again = true;
         }
         if (again) continue;
@@ -532,7 +557,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     }
     if ((s = ensure_jobs(c, std::max<uint32_t>(nj0_max, 4096))) != SS_OK) return s;
 
-    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+    if ((s = reset_counters(c)) != SS_OK) return s;
     if (nj0_tot) {
         if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, (size_t)nj0_tot * sizeof(Job))) != SS_OK)
             return s;
@@ -548,11 +573,11 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         HIP_OR_FAIL(c, hipGetLastError());
     }
     if (!nsegs) {
+        // wait: the next call reuses the pinned job staging buffer
         if (nj0_tot) {
             HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
             HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-            if (c->info_host->status)
-                return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+            if (c->info_host->status) return status_failure(c, c->info_host->status, "in the base cases");
         }
         return SS_OK;
     }
@@ -565,6 +590,16 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     const void* loc_v = vals;
     uint64_t* T_k = (uint64_t*)c->t_keys.p;
     void* T_v = c->t_vals.p;
+    bool fill_used[2] = {false, false};
+    // on an early error return, do not leave a fill running into the caller's buffers
+    struct AuxGuard {
+        ss_ctx* c;
+        bool armed = false;
+        ~AuxGuard()
+        {
+            if (armed && c->aux) (void)hipStreamSynchronize(c->aux);
+        }
+    } guard{c};
     for (uint32_t level = 0; nsegs; ++level) {
         // Where this level writes: buckets that need more work go to the buffer
         // that is not the source; final buckets go straight to the output
@@ -590,18 +625,28 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, fin_k,
                                 fin_v);
         // one-key buckets written to the output: only their values move,
-        // their keys are filled as constant runs after the level
+        // their keys are filled as constant runs on the second stream while
+        // the next level runs (the two touch disjoint ranges)
         const bool fill = fin_k == keys_out;
+        const int fb = level & 1;
         a.fill_heavy = fill;
         launch_level_v<V>(c, p.mode, a, tiles, chunks, records);
         HIP_OR_FAIL(c, hipGetLastError());
+        if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         LevelInfo li;
         if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, fill, &li)) != SS_OK)
             return s;
         if (li.nfills) {
-            ProfScope ps(c, SS_PROF_FILL, li.fill_records);
-            hipLaunchKernelGGL(k_fill, dim3(li.nfills), dim3(1024), 0, c->stream, (const FillJob*)c->fills.p, keys_out);
+            if ((s = ensure_aux(c)) != SS_OK) return s;
+            {
+                ProfScope ps(c, SS_PROF_FILL, li.fill_records, c->aux);
+                hipLaunchKernelGGL(k_fill, dim3(li.nfills), dim3(1024), 0, c->aux, (const FillJob*)c->fills[fb].p,
+                                   keys_out);
+            }
+            HIP_OR_FAIL(c, hipEventRecord(c->fill_done[fb], c->aux));
+            fill_used[fb] = true;
+            guard.armed = true;
         }
         launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
         HIP_OR_FAIL(c, hipGetLastError());
@@ -614,10 +659,13 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         loc_v = dst_v;
         cur ^= 1;
     }
-    // base cases of the last level report range errors through the status word
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    // The last level's base cases and fills are left running: the call
+    // returns once they are enqueued (the stream waits for the fills), and a
+    // range error they raise is reported by the next check of the status word
+    // (ss_sync or the next call).
+    for (int b = 0; b < 2; ++b)
+        if (fill_used[b]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[b], 0));
+    guard.armed = false;
     return SS_OK;
 }
 
@@ -707,7 +755,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
     uint64_t* T_v = (uint64_t*)c->t_vals.p;
     uint8_t* rf = (uint8_t*)c->rflag.p;
     HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
-    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+    if ((s = reset_counters(c)) != SS_OK) return s;
 
     if (n < p.alpha) {
         // one job: a sum job for a single record, else a base case
@@ -783,7 +831,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
     HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, c->mdev.p, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    if (c->info_host->status) return status_failure(c, c->info_host->status, "in collect-reduce");
     *m_out = c->info_host->records;
     return SS_OK;
 }
@@ -860,6 +908,13 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
         delete c;
         return SS_EHIP;
     }
+    if (ensure(c, c->info, sizeof(LevelInfo)) != SS_OK || hipMemset(c->info.p, 0, sizeof(LevelInfo)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        if (c->info.p) (void)hipFree(c->info.p);
+        (void)hipHostFree(c->info_host);
+        delete c;
+        return SS_EHIP;
+    }
     *out = c;
     return SS_OK;
 }
@@ -871,7 +926,8 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills};
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills[0], &c->fills[1]};
+    if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
     for (auto& p : c->pending) {
@@ -879,6 +935,9 @@ ss_status ss_destroy(ss_ctx* c)
         c->event_pool.push_back(p.b);
     }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->fill_done)
+        if (e) (void)hipEventDestroy(e);
+    if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->info_host) (void)hipHostFree(c->info_host);
     if (c->seg_stage) (void)hipHostFree(c->seg_stage);
     if (c->job_stage) (void)hipHostFree(c->job_stage);
@@ -901,7 +960,9 @@ const char* ss_last_error(ss_ctx* c)
 ss_status ss_sync(ss_ctx* c)
 {
     if (!c) return SS_EINVAL;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->info_host->status) return status_failure(c, c->info_host->status, "reported at ss_sync");
     return SS_OK;
 }
 
@@ -948,7 +1009,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills};
+                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills[0], &c->fills[1]};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -1049,7 +1110,7 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, sizeof(Seg))) != SS_OK) return s;
     memcpy(c->seg_stage, segs.data(), sizeof(Seg));
     HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[0].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
-    HIP_OR_FAIL(c, hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream));
+    if ((s = reset_counters(c)) != SS_OK) return s;
     if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
     LevelArgs a = make_args(c, p, 0, (Seg*)c->segs[0].p, 1, tile, keys, vals, keys_out, vals_out, keys_out, vals_out);
@@ -1064,7 +1125,7 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     memcpy(&back, c->seg_stage, sizeof(Seg));
-    if (c->info_host->status) return fail(c, SS_EDEVICE, "device status " + std::to_string(c->info_host->status));
+    if (c->info_host->status) return status_failure(c, c->info_host->status, "in the partition");
     *n_heavy_out = back.nheavy;
     return SS_OK;
 }

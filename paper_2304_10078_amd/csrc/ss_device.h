@@ -346,9 +346,216 @@ __host__ __device__ __forceinline__ uint32_t choose_tile(uint64_t total, uint32_
 
 // ================================================================ Step 1
 // Sampling and Bucketing (Section 3.1): |S| = ceil(c ln n') sampled keys,
-// sorted by hash in LDS; keys seen at least ceil(ln n') times are heavy and get
-// ids n_L, n_L + 1, ... in ascending hash order; an open-addressing heavy
-// table is built for the later passes.  One block per subproblem.
+// sorted by hash in LDS; keys seen at least tau times are heavy and get ids
+// n_L, n_L + 1, ... in ascending hash order; a two-choice heavy table is
+// built for the later passes.  One block per subproblem.
+
+// Compare-exchange of a bitonic stage: ascending where (index & k) == 0.
+__device__ __forceinline__ void bitonic_cx(uint64_t& x, uint64_t& y, bool up)
+{
+    const bool sw = (x > y) == up;
+    const uint64_t a = sw ? y : x, b = sw ? x : y;
+    x = a;
+    y = b;
+}
+
+// Stages of one k whose distance j is below C, on the thread's C contiguous
+// elements held in registers; base = logical index of e[0].
+template <int C>
+__device__ __forceinline__ void bitonic_regs(uint64_t (&e)[C], uint32_t base, uint32_t k, uint32_t jmax)
+{
+#pragma unroll
+    for (int j = C / 2; j >= 1; j >>= 1) {
+        if ((uint32_t)j > jmax) continue;
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+            if ((q & j) == 0) bitonic_cx(e[q], e[q + j], ((base + q) & k) == 0);
+    }
+}
+
+// The sample, gathered straight into registers: thread t holds samples
+// t*C .. t*C + C - 1 (h(key) when hashed, else the key); positions past s are
+// padded with ~0.  Positions are drawn with replacement from the
+// counter-based generator; all loads of a thread are issued before use.
+template <int MODE, int C>
+__device__ __forceinline__ void gather_regs(const LevelArgs& a, const Seg& sg, uint32_t s, bool hashed,
+                                            uint64_t (&e)[C])
+{
+    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
+    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
+    const uint64_t k1 = splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
+    const uint32_t base = threadIdx.x * C;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const uint32_t i = base + q;
+        e[q] = ~0ull;
+        if (i < s) {
+            const uint64_t x = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
+            e[q] = a.src_keys[(uint64_t)sg.start + __umul64hi(x, (uint64_t)sg.len)];
+        }
+    }
+    if (hashed) {
+#pragma unroll
+        for (int q = 0; q < C; ++q)
+            if (base + q < s) e[q] = user_hash<MODE>(e[q]);
+    }
+}
+
+// Ascending bitonic sort of P = C * nt elements, thread t < nt holding the
+// logical elements t*C + q in e[q] (nt = BS for C >= 2; nt = P <= BS for
+// C = 1).  Stages of distance j < C run in registers.  Longer stages go
+// through LDS in a q-major layout (element t*C + q at smp[q*nt + t]) with
+// pairs handed out so that neighbouring lanes touch neighbouring words.  On
+// return e[] is sorted in the same layout and smp holds the sorted sequence
+// in logical order.
+template <int BS, int C>
+__device__ void bitonic_sort_block(uint64_t (&e)[C], uint64_t* smp, uint32_t P)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t nt = P / C;
+    const bool own = t < nt;
+    const uint32_t base = t * C;
+#pragma unroll
+    for (uint32_t k = 2; k <= (uint32_t)C; k <<= 1) bitonic_regs<C>(e, base, k, k >> 1);
+    for (uint32_t k = 2 * C; k <= P; k <<= 1) {
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) smp[q * nt + t] = e[q];
+        }
+        __syncthreads();
+        for (uint32_t j = k >> 1; j >= (uint32_t)C; j >>= 1) {
+            const uint32_t jt = j / C;  // distance in threads
+            for (uint32_t pp = t; pp < (P >> 1); pp += BS) {
+                const uint32_t q = pp / (nt >> 1);
+                const uint32_t u = pp % (nt >> 1);
+                const uint32_t ta = ((u & ~(jt - 1)) << 1) | (u & (jt - 1));
+                uint64_t* pa = smp + q * nt + ta;
+                uint64_t x = pa[0], y = pa[jt];
+                bitonic_cx(x, y, ((ta * C + q) & k) == 0);
+                pa[0] = x;
+                pa[jt] = y;
+            }
+            __syncthreads();
+        }
+        if (own) {
+#pragma unroll
+            for (int q = 0; q < C; ++q) e[q] = smp[q * nt + t];
+        }
+        bitonic_regs<C>(e, base, k, C / 2);
+        __syncthreads();
+    }
+    if (own) {
+#pragma unroll
+        for (int q = 0; q < C; ++q) smp[base + q] = e[q];
+    }
+    __syncthreads();
+}
+
+// Heavy keys of the sorted sample (thread t holds sorted elements t*C + q in
+// e[q], smp the whole sequence in order).  Run lengths of the distinct hashes
+// (histogram of min(length, 63)); the heavy table holds kHeavyMax keys, so if
+// more runs reach tau, the threshold rises to the least value that leaves at
+// most kHeavyMax of them (the most frequent keys stay heavy; at most
+// 16384/32 = 512 runs can reach 32, so the search ends below 63).  Heavy
+// hashes go to hv and heavy_list in ascending order; returns n_H and adds the
+// samples on heavy keys to *sh_hs.
+template <int BS, int C>
+__device__ uint32_t select_heavy_runs(const uint64_t (&e)[C], const uint64_t* smp, uint32_t s, uint32_t tau,
+                                      uint32_t* rh, uint32_t* tmp, uint32_t* sh_te, uint32_t* sh_hs, uint64_t* hv,
+                                      uint64_t* heavy_out)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t base = t * C;
+    uint32_t rl[C];
+    uint64_t prev = (base > 0 && base - 1 < s) ? smp[base - 1] : 0ull;
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+        const uint32_t i = base + q;
+        rl[q] = 0;
+        const uint64_t pv = q ? e[q - 1] : prev;
+        if (i < s && (i == 0 || e[q] != pv)) {
+            // run end: within the thread's registers if it ends there, else a
+            // binary search over smp for the first position in (i, s] past it
+            uint32_t len = 1;
+            bool open = true;
+#pragma unroll
+            for (int r = q + 1; r < C; ++r) {
+                if (open && base + r < s && e[r] == e[q]) ++len;
+                else open = false;
+            }
+            if (open && base + C < s && smp[base + C] == e[q]) {
+                uint32_t l = base + C, r = s;
+                while (r - l > 1) {
+                    const uint32_t mid = (l + r) >> 1;
+                    if (smp[mid] == e[q]) l = mid;
+                    else r = mid;
+                }
+                len = r - i;
+            } else if (open && base + C >= s) {
+                len = s - i;
+            }
+            rl[q] = len;
+            atomicAdd(&rh[len < 63 ? len : 63], 1u);
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t tt = tau < 1 ? 1u : tau;
+        while (tt < 63) {
+            uint32_t c = 0;
+            for (uint32_t L = tt; L < 64; ++L) c += rh[L];
+            if (c <= kHeavyMax) break;
+            ++tt;
+        }
+        *sh_te = tt;
+    }
+    __syncthreads();
+    const uint32_t te = *sh_te;
+    uint32_t cnt = 0, hs = 0;
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (rl[q] >= te) {
+            ++cnt;
+            hs += rl[q];
+        }
+    uint32_t total = 0;
+    uint32_t id = block_excl_scan<BS>(cnt, tmp, &total);
+#pragma unroll
+    for (int q = 0; q < C; ++q)
+        if (rl[q] >= te) {
+            if (id < kHeavyMax) {
+                hv[id] = e[q];
+                heavy_out[id] = e[q];
+            }
+            ++id;
+        }
+    if (hs) atomicAdd(sh_hs, hs);
+    __syncthreads();
+    return total < kHeavyMax ? total : kHeavyMax;
+}
+
+// Gather, sort and heavy selection for one sample size class (P = C * BS,
+// or P <= BS with C = 1).  Returns n_H.
+template <int MODE, int BS, int C>
+__device__ uint32_t sample_select(const LevelArgs& a, const Seg& sg, uint32_t sid, uint32_t s, uint32_t tau,
+                                  uint32_t P, uint64_t* smp, uint32_t* rh, uint32_t* tmp, uint32_t* sh_te,
+                                  uint32_t* sh_hs, uint64_t* hv)
+{
+    uint64_t e[C];
+    gather_regs<MODE, C>(a, sg, s, true, e);
+    bitonic_sort_block<BS, C>(e, smp, P);
+    return select_heavy_runs<BS, C>(e, smp, s, tau, rh, tmp, sh_te, sh_hs, hv,
+                                    a.heavy_list + (size_t)sid * kHeavyMax);
+}
+
+// Gather and sort of raw keys (semisort_<): smp holds the sorted sample.
+template <int BS, int C>
+__device__ void sample_sort_keys(const LevelArgs& a, const Seg& sg, uint32_t s, uint32_t P, uint64_t* smp)
+{
+    uint64_t e[C];
+    gather_regs<0, C>(a, sg, s, false, e);
+    bitonic_sort_block<BS, C>(e, smp, P);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
@@ -358,7 +565,8 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     __shared__ uint64_t hv[kHeavyMax];
     __shared__ uint32_t owner[2 * kHeavySlotsMax];
     __shared__ uint32_t tmp[20];
-    __shared__ uint32_t sh_s, sh_tau;
+    __shared__ uint32_t rh[64];
+    __shared__ uint32_t sh_s, sh_tau, sh_te, sh_hs, sh_nl, sh_fail;
 
     const uint32_t sid = blockIdx.x;
     const uint32_t tid = threadIdx.x;
@@ -373,186 +581,85 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         if (s > kSampleMax) s = kSampleMax;
         sh_s = s;
         sh_tau = a.heavy_min ? a.heavy_min : (sg.len < 3 ? 1u : (uint32_t)ceil(L));
+        sh_hs = 0;
     }
+    if (tid < 64) rh[tid] = 0;
     __syncthreads();
     const uint32_t s = sh_s, tau = sh_tau;
     uint32_t P = 2;
     while (P < s) P <<= 1;
-
-    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
-    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
-    const uint64_t k1 = splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
-    for (uint32_t i = tid; i < P; i += BS) {
-        uint64_t v = ~0ull;
-        if (i < s) {
-            uint64_t r = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
-            uint64_t idx = __umul64hi(r, (uint64_t)sg.len);
-            v = user_hash<MODE>(a.src_keys[(uint64_t)sg.start + idx]);
-        }
-        smp[i] = v;
-    }
-    __syncthreads();
-
-    // bitonic sort of smp[0, P), ascending
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = tid; t < (P >> 1); t += BS) {
-                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const uint32_t l = i + j;
-                const bool up = (i & k) == 0;
-                const uint64_t x = smp[i], y = smp[l];
-                if ((x > y) == up) {
-                    smp[i] = y;
-                    smp[l] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-
-    // Run lengths of the distinct sampled hashes (histogram of min(length, 63)).
-    // The heavy table holds kHeavyMax keys: if more runs reach tau, the
-    // threshold rises to the least value that leaves at most kHeavyMax of
-    // them (the most frequent keys stay heavy).  At most 16384/32 = 512 runs
-    // can reach 32, so the search ends below 63.
-    const uint32_t per = (s + BS - 1) / BS;
-    const uint32_t lo = tid * per;
-    const uint32_t hi = lo + per < s ? lo + per : s;
-    __shared__ uint32_t rh[64];
-    __shared__ uint32_t sh_te;
-    if (tid < 64) rh[tid] = 0;
-    __syncthreads();
-    for (uint32_t i = lo; i < hi; ++i) {
-        if (i != 0 && smp[i] == smp[i - 1]) continue;
-        uint32_t l = i, r = s;  // end of the run: first position in (i, s] with a larger value
-        while (r - l > 1) {
-            const uint32_t mid = (l + r) >> 1;
-            if (smp[mid] == smp[i]) l = mid;
-            else r = mid;
-        }
-        const uint32_t len = r - i;
-        atomicAdd(&rh[len < 63 ? len : 63], 1u);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t t = tau < 1 ? 1u : tau;
-        while (t < 63) {
-            uint32_t c = 0;
-            for (uint32_t L = t; L < 64; ++L) c += rh[L];
-            if (c <= kHeavyMax) break;
-            ++t;
-        }
-        sh_te = t;
-    }
-    __syncthreads();
-    const uint32_t te = sh_te;
-
-    // heavy run starts: a run of equal hashes of length >= te among the s real samples
-    uint32_t cnt = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) ++cnt;
-    }
-    uint32_t total = 0;
-    uint32_t id = block_excl_scan<BS>(cnt, tmp, &total);
-    const uint32_t nh = total < kHeavyMax ? total : kHeavyMax;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) {
-            if (id < kHeavyMax) {
-                hv[id] = smp[i];
-                a.heavy_list[(size_t)sid * kHeavyMax + id] = smp[i];
-            }
-            ++id;
-        }
-    }
-    // records of the sample that fall on heavy keys
-    __shared__ uint32_t sh_hs;
-    if (tid == 0) sh_hs = 0;
-    __syncthreads();
-    uint32_t hs = 0;
-    for (uint32_t i = lo; i < hi; ++i) {
-        const bool start = (i == 0) || smp[i] != smp[i - 1];
-        if (start && i + te - 1 < s && smp[i + te - 1] == smp[i]) {
-            // end of the run: first position in (i, s) holding a larger value
-            uint32_t l = i + te - 1, r = s;
-            while (r - l > 1) {
-                const uint32_t mid = (l + r) >> 1;
-                if (smp[mid] == smp[i]) l = mid;
-                else r = mid;
-            }
-            hs += r - i;
-        }
-    }
-    if (hs) atomicAdd(&sh_hs, hs);
+    uint32_t nh;
+    if (P == 16 * BS) nh = sample_select<MODE, BS, 16>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
+    else if (P == 8 * BS) nh = sample_select<MODE, BS, 8>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
+    else if (P == 4 * BS) nh = sample_select<MODE, BS, 4>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
+    else if (P == 2 * BS) nh = sample_select<MODE, BS, 2>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
+    else nh = sample_select<MODE, BS, 1>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
 
     // Light bucket count.  With adaptive_nl, n_L is the smallest power of two
     // that lets the light records finish in the fewest levels: one level if
     // buckets of ~alpha/2 can be reached with at most nl_bits bits, else two.
-    __shared__ uint32_t sh_nl;
-    if (tid == 0) sh_nl = sg.nl_bits;
-    __syncthreads();
-    if (tid == 0 && a.adaptive_nl && s) {
-        const double light = (double)sg.len * (double)(s - sh_hs) / (double)s;
-        const double target = (double)(a.alpha / 2);
-        const uint32_t cap = sg.nl_bits;
-        uint32_t nl1 = 1;
-        while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
-        uint32_t nl = cap;
-        if (nl1 <= cap) {
-            nl = nl1;
-        } else {
-            uint32_t nl2 = 1;
-            while (nl2 < 31 && (double)(1u << nl2) * (double)(1u << kLightBitsMax) * target < light) ++nl2;
-            if (nl2 <= cap) nl = nl2;
+    if (tid == 0) {
+        uint32_t nl = sg.nl_bits;
+        if (a.adaptive_nl && s) {
+            const double light = (double)sg.len * (double)(s - sh_hs) / (double)s;
+            const double target = (double)(a.alpha / 2);
+            const uint32_t cap = sg.nl_bits;
+            uint32_t nl1 = 1;
+            while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
+            if (nl1 <= cap) {
+                nl = nl1;
+            } else {
+                uint32_t nl2 = 1;
+                while (nl2 < 31 && (double)(1u << nl2) * (double)(1u << kLightBitsMax) * target < light) ++nl2;
+                if (nl2 <= cap) nl = nl2;
+            }
         }
         sh_nl = nl;
     }
 
-    // Two-choice (cuckoo) heavy table: two tables of 2^hlog2 slots, at most
-    // a quarter full.  Built by one thread; on a cycle the salt of the second
-    // hash changes and the build starts again.
-    __shared__ uint32_t sh_hfield;
+    // Two-choice (cuckoo) heavy table: two tables of 2^hlog2 slots, at most a
+    // quarter full.  Built in parallel: each key is placed by atomic exchange
+    // and an evicted key moves on to its slot in the other table.  If some
+    // chain grows too long, the salt of the second hash changes and the build
+    // starts again.  The layout may vary from run to run; every key sits in
+    // one of its two slots, so lookups do not.
     uint32_t hlog2 = 0;
     if (nh) {
         hlog2 = ceil_log2_u32(2 * nh);
         if (hlog2 < 4) hlog2 = 4;
     }
     const uint32_t slots = nh ? (1u << hlog2) : 0u;
-    for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) owner[i] = kEmpty32;
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t salt = 0;
-        bool built = nh == 0;
-        for (; !built && salt < 16; ++salt) {
-            if (salt)
-                for (uint32_t i = 0; i < 2 * kHeavySlotsMax; ++i) owner[i] = kEmpty32;
-            built = true;
-            for (uint32_t t = 0; t < nh && built; ++t) {
-                uint32_t cur = t;
-                int side = 0;
-                uint32_t kicks = 0;
-                while (true) {
-                    const uint64_t h = hv[cur];
-                    const uint32_t sl = side == 0 ? fib_slot(h, hlog2) : kHeavySlotsMax + slot2(h, hlog2, salt);
-                    const uint32_t prev = owner[sl];
-                    owner[sl] = cur;
-                    if (prev == kEmpty32) break;
-                    // evicted key moves to its other table
-                    cur = prev;
-                    side = (sl < kHeavySlotsMax) ? 1 : 0;
-                    if (++kicks > 4 * nh + 16) {
-                        built = false;
-                        break;
-                    }
+    uint32_t salt = 0;
+    bool built = nh == 0;
+    while (!built) {
+        for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) owner[i] = kEmpty32;
+        if (tid == 0) sh_fail = 0;
+        __syncthreads();
+        if (tid < nh) {
+            uint32_t cur = tid;
+            int side = 0;
+            for (uint32_t it = 0;; ++it) {
+                if (it >= 64) {
+                    atomicOr(&sh_fail, 1u);
+                    break;
                 }
+                const uint64_t h = hv[cur];
+                const uint32_t sl = side == 0 ? fib_slot(h, hlog2) : kHeavySlotsMax + slot2(h, hlog2, salt);
+                const uint32_t prev = atomicExch(&owner[sl], cur);
+                if (prev == kEmpty32) break;
+                cur = prev;  // the evicted key moves to its other table
+                side = (sl < kHeavySlotsMax) ? 1 : 0;
             }
-            if (built) break;
         }
-        if (!built) atomicOr(&a.info->status, kStatusHeavyTable);
-        sh_hfield = nh ? (hlog2 | (salt << 8)) : 0u;
+        __syncthreads();
+        built = sh_fail == 0;
+        if (built || salt == 15) break;
+        ++salt;
+        __syncthreads();
     }
     __syncthreads();
+    if (!built && tid == 0) atomicOr(&a.info->status, kStatusHeavyTable);
+    const uint32_t hfield = nh ? (hlog2 | (salt << 8)) : 0u;
     const uint32_t nL = 1u << sh_nl;
     for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) {
         const bool used = (i & (kHeavySlotsMax - 1)) < slots;
@@ -567,7 +674,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = 0;
     if (tid == 0) {
         a.segs[sid].nheavy = (uint16_t)nh;
-        a.segs[sid].hlog2 = (uint16_t)sh_hfield;
+        a.segs[sid].hlog2 = (uint16_t)hfield;
         a.segs[sid].nl_bits = (uint8_t)sh_nl;
         a.segs[sid].nbk = (uint16_t)(nL + nh);
     }
@@ -715,34 +822,11 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
     const uint32_t s = sh_s, tau = sh_tau;
     uint32_t P = 2;
     while (P < s) P <<= 1;
-    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
-    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
-    const uint64_t k1 = splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
-    for (uint32_t i = tid; i < P; i += BS) {
-        uint64_t v = ~0ull;
-        if (i < s) {
-            uint64_t r = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
-            uint64_t idx = __umul64hi(r, (uint64_t)sg.len);
-            v = a.src_keys[(uint64_t)sg.start + idx];
-        }
-        smp[i] = v;
-    }
-    __syncthreads();
-    for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t t = tid; t < (P >> 1); t += BS) {
-                const uint32_t i = ((t & ~(j - 1)) << 1) | (t & (j - 1));
-                const uint32_t l = i + j;
-                const bool up = (i & k) == 0;
-                const uint64_t x = smp[i], y = smp[l];
-                if ((x > y) == up) {
-                    smp[i] = y;
-                    smp[l] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
+    if (P == 16 * BS) sample_sort_keys<BS, 16>(a, sg, s, P, smp);
+    else if (P == 8 * BS) sample_sort_keys<BS, 8>(a, sg, s, P, smp);
+    else if (P == 4 * BS) sample_sort_keys<BS, 4>(a, sg, s, P, smp);
+    else if (P == 2 * BS) sample_sort_keys<BS, 2>(a, sg, s, P, smp);
+    else sample_sort_keys<BS, 1>(a, sg, s, P, smp);
     // heavy keys in ascending key order; per sample: heavy or not, and the
     // rank of the non-heavy ones
     const uint32_t per = (s + BS - 1) / BS;

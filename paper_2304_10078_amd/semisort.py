@@ -129,6 +129,11 @@ class Context:
     PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish", "compact", "fill")
     OPT_DIST_VARIANT = 1
 
+    def sync(self):
+        """Wait for the context's stream; raises SemisortError for a device
+        condition raised by earlier calls (see ss_sync)."""
+        self.check(lib().ss_sync(self.h))
+
     def set_option(self, option, value):
         self.check(lib().ss_set_option(self.h, int(option), int(value)))
 
@@ -159,6 +164,11 @@ def context(device=0):
     if device not in _ctx:
         _ctx[device] = Context(device)
     return _ctx[device]
+
+
+def sync(device=0):
+    """ss_sync on the device's default context."""
+    context(device).sync()
 
 
 def _check_kv(keys, vals):

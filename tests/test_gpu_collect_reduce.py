@@ -32,7 +32,7 @@ def _sorted_pairs(k, v):
 
 def check_cr(keys, vals, params=None, ctx=""):
     gk, gs = S.collect_reduce(to_dev(keys), to_dev(vals), params=params)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     gk, gs = _sorted_pairs(to_host(gk, np.uint64), to_host(gs, np.uint64))
     rk, rs = O.collect_reduce(keys, vals)
     assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"
@@ -44,7 +44,7 @@ def check_cr(keys, vals, params=None, ctx=""):
 
 def check_hist(keys, params=None, ctx=""):
     gk, gc = S.histogram(to_dev(keys), params=params)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     gk, gc = _sorted_pairs(to_host(gk, np.uint64), to_host(gc, np.uint64))
     rk, rc = O.histogram(keys)
     assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"

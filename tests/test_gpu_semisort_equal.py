@@ -21,7 +21,7 @@ from tests.gpu_util import assert_semisort_equal, to_dev, to_host  # noqa: E402
 
 def run_equal(keys, vals, params=None):
     ko, vo = S.semisort_equal(to_dev(keys), to_dev(vals), params=params)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     return to_host(ko, np.uint64), to_host(vo, vals.dtype)
 
 
@@ -95,7 +95,7 @@ def test_in_place_and_u32_values():
     kd, vd = to_dev(k), to_dev(v)
     _say("case: in place u32")
     S.semisort_equal(kd, vd, keys_out=kd, vals_out=vd)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     assert_semisort_equal(k, v, to_host(kd, np.uint64), to_host(vd, np.uint32), ctx="inplace")
 
 
@@ -119,19 +119,21 @@ def test_rejects_overlapping_output():
         S.semisort_equal(k, v, keys_out=v, vals_out=k)
 
 
-@pytest.mark.parametrize("name,c,tau", [("zipf1.2_hashed", 300, 0), ("zipf1.2_hashed", 1500, 2),
-                                        ("uniform1e3", 1200, 0), ("uniform1e3", 1200, 3)])
-def test_partition_matches_the_oracle_stage_model(name, c, tau):
+@pytest.mark.parametrize("name,n,c,tau", [("zipf1.2_hashed", 400_000, 300, 0), ("zipf1.2_hashed", 400_000, 1500, 2),
+                                          ("uniform1e3", 400_000, 1200, 0), ("uniform1e3", 400_000, 1200, 3),
+                                          ("zipf1.2_hashed", 20_000, 800, 3), ("zipf1.2_hashed", 5_000, 800, 3),
+                                          ("zipf1.2_hashed", 50_000, 800, 3), ("uniform1e3", 9_000, 800, 2)])
+def test_partition_matches_the_oracle_stage_model(name, n, c, tau):
     # One level of Steps 1-2 against the oracle's step-by-step model with the
     # same seed: heavy set and ids, bucket offsets and the distributed array T.
     # The uniform[0, 10^3) cases and the low thresholds put more than 512 keys
-    # over the threshold, so the bounded-table rule decides the heavy set.
-    n = 400_000
+    # over the threshold, so the bounded-table rule decides the heavy set; the
+    # sizes cover every sample size class (|S| padded to 1K, 2K, 4K, 8K, 16K).
     k, v = I.np_workload(name, n, 9)
     p = S.default_params(n_light_log2=6, sample_mult=c, heavy_min=tau)
-    _say(f"case: partition n=400000 {name} c={c} tau={tau}")
+    _say(f"case: partition n={n} {name} c={c} tau={tau}")
     tk, tv, off, hv = S.partition_equal(to_dev(k), to_dev(v), params=p)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     s = O.sample_size(n, p.sample_mult)
     idx = np.array([O.lib().orc_sample_index(p.seed, 0, 0, n, i) for i in range(s)], dtype=np.uint64)
     heavy = O.select_heavy(k[idx], tau or O.heavy_threshold(n), max_heavy=512)
@@ -159,7 +161,7 @@ def test_batch_matches_each_instance_alone():
     v = np.arange(n, dtype=np.uint64)
     _say("case: batch of 10")
     ko, vo = S.semisort_equal_batch(to_dev(k), to_dev(v), offs)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     ko, vo = to_host(ko, np.uint64), to_host(vo, np.uint64)
     for i in range(len(sizes)):
         a, b = int(offs[i]), int(offs[i + 1])

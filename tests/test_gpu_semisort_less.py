@@ -25,7 +25,7 @@ def _say(msg):
 
 def check_less(k, v, params=None, ctx=""):
     ko, vo = S.semisort_less(to_dev(k), to_dev(v), params=params)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     ko, vo = to_host(ko, np.uint64), to_host(vo, v.dtype)
     rk, rv = O.semisort_less(k, v)
     if not np.array_equal(ko, rk):
@@ -92,7 +92,7 @@ def test_batch_and_in_place():
     kd, vd = to_dev(k), to_dev(v)
     _say("case: less batch in place")
     S.semisort_less_batch(kd, vd, offs, keys_out=kd, vals_out=vd)
-    torch.cuda.synchronize()
+    S.sync()  # waits and raises on a device-side error
     ko, vo = to_host(kd, np.uint64), to_host(vd, np.uint32)
     for i in range(len(sizes)):
         a, b = int(offs[i]), int(offs[i + 1])
