@@ -57,6 +57,52 @@ def cpu_baseline(keys_dev, vals_dev, m):
             "sample": f"first {m} records of the same input, single-threaded sort-based oracle, {dt:.2f} s"}
 
 
+def batched(args, S, I, torch):
+    """4096 independent semisort_= instances (sizes log-uniform in [1e3, 1e7]
+    scaled to a total of at most 5e8 records, per-instance key distribution
+    uniform[0, n/10), Zipf 0.8 / 1.2 hashed or uniform[0, 100); u64 keys,
+    u64 values): autotuned batched launch chain against one call per
+    instance with the same parameters."""
+    log(f"batched: generating {args.batch_count} instances, total <= {args.batch_total:.0f}")
+    keys, vals, offs, d = I.t_batch_workload(args.batch_count, 1e3, 1e7, args.batch_total, 7, "cuda")
+    n = keys.numel()
+    ko = torch.empty_like(keys)
+    vo = torch.empty_like(vals)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    best, tuned_ms = S.autotune_equal_batch(keys, vals, offs, ko, vo, reps=1)
+    tune_s = time.perf_counter() - t0
+    log(f"batched: autotune {tune_s:.1f} s, best ms {tuned_ms:.2f}: c={best.sample_mult} tau={best.heavy_min} "
+        f"nl={best.n_light_log2} alpha={best.base_case} tmax={best.tile_max}")
+    S.semisort_equal_batch(keys, vals, offs, ko, vo, params=best)
+    S.sync()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.semisort_equal_batch(keys, vals, offs, ko, vo, params=best)
+    S.sync()
+    b_ms = (time.perf_counter() - t0) * 1e3 / reps
+    o = [int(x) for x in offs]
+    t0 = time.perf_counter()
+    for i in range(len(o) - 1):
+        a, b = o[i], o[i + 1]
+        S.semisort_equal(keys[a:b], vals[a:b], ko[a:b], vo[a:b], params=best)
+    S.sync()
+    l_ms = (time.perf_counter() - t0) * 1e3
+    log(f"batched: {b_ms:.2f} ms ({n / b_ms / 1e6:.2f} Grec/s) vs per-instance loop {l_ms:.2f} ms "
+        f"({n / l_ms / 1e6:.2f} Grec/s)")
+    res = {"workload": f"semisort_= batch of {len(o) - 1} instances, n={n} (u64 key, u64 value)",
+           "instances": len(o) - 1, "n": n, "batched_ms": round(b_ms, 3),
+           "batched_grecs": round(n / b_ms / 1e6, 3), "per_instance_ms": round(l_ms, 3),
+           "per_instance_grecs": round(n / l_ms / 1e6, 3), "speedup": round(l_ms / b_ms, 2),
+           "autotune_s": round(tune_s, 2),
+           "tuned": {"sample_mult": best.sample_mult, "heavy_min": best.heavy_min,
+                     "n_light_log2": best.n_light_log2, "base_case": best.base_case, "tile_max": best.tile_max}}
+    del keys, vals, ko, vo
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +118,9 @@ def main():
     ap.add_argument("--sample-mult", type=int, default=0, help="c in |S| = c ln n' (0 = library default)")
     ap.add_argument("--heavy-min", type=int, default=-1, help="heavy threshold tau (-1 = library default, "
                                                                "0 = ceil(ln n'))")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-instance measurement")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-total", type=float, default=5e8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 2^28 int64 (2 GiB) once: a plain copy of known size that "
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
@@ -174,19 +223,24 @@ def main():
         "roofline": roofline,
         "passes": passes,
     }
-    if args.calib_copy:
-        src = torch.empty(1 << 28, dtype=torch.int64, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     if not args.no_cpu_baseline:
         m = min(args.cpu_sample, n)
         log(f"cpu baseline: oracle on {m} records")
         out["cpu_baseline"] = cpu_baseline(keys, vals, m)
     else:
         out["cpu_baseline"] = None
+    if args.calib_copy:
+        # the last GPU work of the run: a plain copy of known size
+        src = torch.empty(1 << 28, dtype=torch.int64, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    elif not args.no_batch:
+        del keys, vals, ko, vo
+        torch.cuda.empty_cache()
+        out["batched"] = batched(args, S, I, torch)
     print(json.dumps(out), flush=True)
 
 

@@ -145,6 +145,20 @@ ss_status ss_semisort_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void*
                                   uint64_t nseg, uint64_t* keys_out, void* vals_out,
                                   const ss_params* params);
 
+/* Autotuner for batched semisort_=: runs the batch with every parameter set
+ * of a fixed grid around the defaults (sample_mult in {500, 800}, heavy_min in
+ * {0, 3}, n_light_log2 in {8, 10}, base_case in {2048, 4096}, tile_max in
+ * {32768, 65536}), `reps` timed runs each (HIP events on the context's
+ * stream, after one warm-up run), and returns the fastest set in *best and
+ * its time per run in *best_ms (host).  The outputs are overwritten with the
+ * batch's result.  Arguments as for ss_semisort_equal_batch, except that the
+ * outputs may not be the inputs.  Waits for the stream before returning.
+ * Every parameter set gives a correct result; only the time differs. */
+ss_status ss_autotune_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                  uint32_t val_bytes, const uint64_t* seg_offsets, uint64_t nseg,
+                                  uint64_t* keys_out, void* vals_out, uint32_t reps,
+                                  ss_params* best, double* best_ms);
+
 /* semisort_< (Section 2.1 with the comparison base case of Section 3.3):
  * reorders the records into ascending key order, records with equal keys in
  * input order (stable).  The result is unique: a stable sort by key.
@@ -196,6 +210,72 @@ ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* v
  * out_keys[i].  Same conventions as ss_collect_reduce. */
 ss_status ss_histogram(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
                        uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
+
+/* ---- serving (continuous batching of group-by requests) ----------------
+ *
+ * A server owns `lanes` worker threads, each driving its own context on its
+ * own HIP stream (default priority), so requests on different lanes overlap
+ * on the device.  Requests wait in arrival order; a free lane takes the
+ * oldest request whose workspace estimate fits in hbm_budget together with
+ * what the other lanes hold (an idle lane first gives its own workspace back
+ * if nothing fits).  semisort_= requests of at most pack_max_records records
+ * that are waiting with the same value width join the lane's call: they are
+ * copied into the lane's packing buffers (batch_records records each for keys
+ * and values, in and out), run as one ss_semisort_equal_batch and copied out.
+ * Every request gets the result it gets alone (instances of a batch do not
+ * interact).  Inputs and outputs are caller-owned device arrays that must stay
+ * valid until the request is done.  Completion is taken on the host once the
+ * lane's stream has drained; latency runs from the arrival time to then. */
+typedef enum {
+    SS_OP_SEMISORT_EQUAL = 0,
+    SS_OP_SEMISORT_LESS = 1,
+    SS_OP_HISTOGRAM = 2,
+    SS_OP_COLLECT_REDUCE = 3
+} ss_op;
+
+typedef struct {
+    int32_t op;          /* ss_op */
+    uint32_t val_bytes;  /* 4 or 8 for semisort; ignored otherwise (collect-reduce values are u64) */
+    uint64_t n;
+    const uint64_t* keys;
+    const void* vals;    /* unused by the histogram */
+    void* out_a;         /* keys_out / out_keys, n entries */
+    void* out_b;         /* vals_out / out_sums / out_counts, n entries */
+} ss_request;
+
+typedef struct {
+    uint32_t lanes;             /* 1..16 (default 4) */
+    uint32_t pack_max_records;  /* largest semisort_= request that is packed (default 2^20; 0 = never) */
+    uint64_t batch_records;     /* packing buffer size in records (default 2^24) */
+    uint64_t hbm_budget;        /* bytes of device memory the server may hold (default 200 GiB) */
+    ss_params params;           /* parameters of every call (default ss_default_params) */
+} ss_server_config;
+
+typedef struct ss_server ss_server;
+
+ss_status ss_server_default_config(ss_server_config* cfg);
+/* cfg may be NULL (defaults).  SS_EINVAL for a bad device or lane count, or
+ * when the packing buffers alone exceed the budget. */
+ss_status ss_server_create(int device, const ss_server_config* cfg, ss_server** out);
+/* Seconds since the server was created (the clock of arrival times). */
+double ss_server_now(ss_server* srv);
+/* Queue a request (does not block on the device).  arrival_s: its arrival on
+ * the server clock, or <= 0 for now.  *ticket identifies it in ss_server_poll. */
+ss_status ss_server_submit(ss_server* srv, const ss_request* req, double arrival_s, uint64_t* ticket);
+/* *done = 1 once the request is complete; then *result is its status,
+ * *latency_s its latency and *m its group count (histogram and collect-reduce).
+ * result, latency_s and m may be NULL.  SS_EINVAL for an unknown ticket. */
+ss_status ss_server_poll(ss_server* srv, uint64_t ticket, int* done, ss_status* result,
+                         double* latency_s, uint64_t* m);
+/* Wait until every submitted request is complete. */
+ss_status ss_server_drain(ss_server* srv);
+/* Requests completed, device calls made, requests that were packed with
+ * others, and the largest device memory the server reserved (bytes). */
+ss_status ss_server_stats(ss_server* srv, uint64_t* completed, uint64_t* calls, uint64_t* packed,
+                          uint64_t* peak_reserved);
+/* Stop the lanes and free everything; requests still waiting are dropped
+ * (drain first). */
+ss_status ss_server_destroy(ss_server* srv);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsemisort_hip.so")
-SOURCES = [os.path.join(HERE, "csrc", "engine.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "engine.hip"), os.path.join(HERE, "csrc", "server.hip")]
 HEADERS = [os.path.join(HERE, "csrc", "ss_device.h"), os.path.join(ROOT, "include", "semisort.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -17,6 +17,7 @@ FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    "-pthread",
     # packed FP32 instructions stay off (no float math here, but keep codegen plain)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

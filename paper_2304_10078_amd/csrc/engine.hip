@@ -908,8 +908,9 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
         delete c;
         return SS_EHIP;
     }
-    if (ensure(c, c->info, sizeof(LevelInfo)) != SS_OK || hipMemset(c->info.p, 0, sizeof(LevelInfo)) != hipSuccess ||
-        hipDeviceSynchronize() != hipSuccess) {
+    if (ensure(c, c->info, sizeof(LevelInfo)) != SS_OK ||
+        hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
         if (c->info.p) (void)hipFree(c->info.p);
         (void)hipHostFree(c->info_host);
         delete c;
@@ -1047,6 +1048,85 @@ ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* v
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
                    : run_semisort<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+}
+
+ss_status ss_autotune_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                  const uint64_t* offs, uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                  uint32_t reps, ss_params* best, double* best_ms)
+{
+    if (!c) return SS_EINVAL;
+    if (!offs || !best || !best_ms) return fail(c, SS_EINVAL, "null argument");
+    if (nseg == 0) return fail(c, SS_EINVAL, "nothing to tune on");
+    if (offs[0] != 0) return fail(c, SS_EINVAL, "seg_offsets[0] must be 0");
+    for (uint64_t i = 0; i < nseg; ++i)
+        if (offs[i + 1] < offs[i]) return fail(c, SS_EINVAL, "seg_offsets must be non-decreasing");
+    const uint64_t n = offs[nseg];
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, false);
+    if (s != SS_OK) return s;
+    if (n == 0) return fail(c, SS_EINVAL, "nothing to tune on");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (reps < 1) reps = 1;
+    // candidate grid around the defaults: sample multiplier, heavy threshold,
+    // light-bucket cap, base-case size and largest subarray
+    std::vector<ss_params> cand;
+    const uint32_t cs[] = {500, 800};
+    const uint32_t taus[] = {0, 3};
+    const uint32_t nls[] = {8, 10};
+    const uint32_t alphas[] = {2048, 4096};
+    const uint32_t tmaxs[] = {32768, 65536};
+    for (uint32_t cc : cs)
+        for (uint32_t tau : taus)
+            for (uint32_t nl : nls)
+                for (uint32_t al : alphas)
+                    for (uint32_t tm : tmaxs) {
+                        ss_params q;
+                        ss_default_params(&q);
+                        q.sample_mult = cc;
+                        q.heavy_min = tau;
+                        q.n_light_log2 = nl;
+                        q.base_case = al;
+                        q.tile_max = tm;
+                        cand.push_back(q);
+                    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR_FAIL(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(c, SS_EHIP, "hipEventCreate");
+    }
+    auto run = [&](const ss_params& q, float* ms) -> ss_status {
+        Params p;
+        ss_status r = resolve_params(c, &q, &p);
+        if (r != SS_OK) return r;
+        if (hipEventRecord(e0, c->stream) != hipSuccess) return fail(c, SS_EHIP, "hipEventRecord");
+        for (uint32_t k = 0; k < reps; ++k) {
+            r = vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
+                        : run_semisort<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+            if (r != SS_OK) return r;
+        }
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return fail(c, SS_EHIP, "timing");
+        *ms /= (float)reps;
+        return SS_OK;
+    };
+    float ms = 0.f, best_t = 0.f;
+    size_t bi = 0;
+    s = run(cand[0], &ms);  // warm-up: grows the workspace once
+    for (size_t i = 0; s == SS_OK && i < cand.size(); ++i) {
+        s = run(cand[i], &ms);
+        if (s == SS_OK && (i == 0 || ms < best_t)) {
+            best_t = ms;
+            bi = i;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != SS_OK) return s;
+    if ((s = ss_sync(c)) != SS_OK) return s;
+    *best = cand[bi];
+    *best_ms = best_t;
+    return SS_OK;
 }
 
 ss_status ss_semisort_less(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,

@@ -77,6 +77,8 @@ def lib():
         L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
         L.ss_collect_reduce.argtypes = [vp, vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
+        L.ss_autotune_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, u32, P,
+                                              ctypes.POINTER(ctypes.c_double)]
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
         for name in declared_symbols():
             if name != "ss_last_error":
@@ -314,3 +316,24 @@ def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None):
     ctx.check(lib().ss_histogram(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
                                  ctypes.byref(m), ctypes.byref(params) if params is not None else None))
     return out_keys[:m.value], out_counts[:m.value]
+
+
+def autotune_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, reps=2, ctx=None):
+    """ss_autotune_equal_batch: (best ss_params, ms per run with them).  The
+    outputs hold the batch's semisort afterwards."""
+    import numpy as np
+    import torch
+    vb = _check_kv(keys, vals)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.uint64))
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    best = ss_params()
+    ms = ctypes.c_double()
+    ctx.check(lib().ss_autotune_equal_batch(ctx.h, _ptr(keys), _ptr(vals), vb, offs.ctypes.data_as(ctypes.c_void_p),
+                                            offs.size - 1, _ptr(keys_out), _ptr(vals_out), int(reps),
+                                            ctypes.byref(best), ctypes.byref(ms)))
+    return best, ms.value

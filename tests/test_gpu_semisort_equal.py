@@ -186,3 +186,32 @@ def test_every_distribution_variant_gives_the_same_result(variant):
             assert np.array_equal(ko, ref[0]) and np.array_equal(vo, ref[1])
     finally:
         ctx.set_option(ctx.OPT_DIST_VARIANT, 0)
+
+
+def test_batched_configuration_shape_matches_the_oracle():
+    # The batched configuration in miniature: log-uniform sizes (clamped at
+    # 10^3), each instance with its own distribution among uniform[0, n/10),
+    # Zipf 0.8 and 1.2 (hashed) and uniform[0, 100).
+    k, v, offs, d = I.np_batch_workload(192, 1e3, 1e5, 3e6, 7)
+    _say(f"case: batch of 192, n={k.size}")
+    ko, vo = S.semisort_equal_batch(to_dev(k), to_dev(v), offs)
+    S.sync()
+    ko, vo = to_host(ko, np.uint64), to_host(vo, np.uint64)
+    for i in range(192):
+        a, b = int(offs[i]), int(offs[i + 1])
+        assert_semisort_equal(k[a:b], v[a:b], ko[a:b], vo[a:b], ctx=f"instance {i} dist {d[i]}")
+
+
+def test_autotuner_returns_a_grid_point_and_a_correct_result():
+    k, v, offs, d = I.np_batch_workload(48, 1e3, 3e4, 5e5, 11)
+    _say(f"case: autotune on a batch of 48, n={k.size}")
+    best, ms = S.autotune_equal_batch(to_dev(k), to_dev(v), offs, reps=1)
+    assert ms > 0
+    assert best.sample_mult in (500, 800) and best.heavy_min in (0, 3) and best.n_light_log2 in (8, 10)
+    assert best.base_case in (2048, 4096) and best.tile_max in (32768, 65536)
+    ko, vo = S.semisort_equal_batch(to_dev(k), to_dev(v), offs, params=best)
+    S.sync()
+    ko, vo = to_host(ko, np.uint64), to_host(vo, np.uint64)
+    for i in range(48):
+        a, b = int(offs[i]), int(offs[i + 1])
+        assert_semisort_equal(k[a:b], v[a:b], ko[a:b], vo[a:b], ctx=f"tuned instance {i}")

@@ -95,3 +95,33 @@ def test_workloads_are_seeded_and_shaped():
     assert np.array_equal(k, k2)
     k3, v3 = I.np_workload("exp1e-5_u32idx", 1000, 5)
     assert v3.dtype == np.uint32
+
+
+def test_batch_sizes_follow_the_batched_configuration():
+    # 4096 log-uniform sizes in [1e3, 1e7], scaled to a total of at most 5e8,
+    # clamped at 1e3
+    sz = I.batch_sizes(4096, 1e3, 1e7, 5e8, 7)
+    assert sz.sum() <= 5e8 and sz.sum() > 0.99 * 5e8
+    assert sz.min() == 1000 and sz.max() < 1e7 * 0.2
+    # log-uniform before scaling: log10 of the unclamped sizes spreads evenly
+    u = np.log10(sz[sz > 1000])
+    assert np.ptp(u) > 2.5
+    d = I.batch_dists(4096, 7)
+    cnt = np.bincount(d, minlength=4)
+    assert cnt.sum() == 4096 and cnt.min() > 900
+
+
+def test_batch_workload_numpy_and_torch_agree():
+    torch = pytest.importorskip("torch")
+    k, v, o, d = I.np_batch_workload(24, 1e3, 2e4, 1e5, 3)
+    tk, tv, to, td = I.t_batch_workload(24, 1e3, 2e4, 1e5, 3, "cpu")
+    assert np.array_equal(o, to) and np.array_equal(d, td)
+    assert np.array_equal(tk.numpy().view(np.uint64), k)
+    assert np.array_equal(tv.numpy().view(np.uint64), v)
+    # each instance draws from its own distribution: uniform[0, n/10) keys stay below n/10
+    for i in range(24):
+        a, b = int(o[i]), int(o[i + 1])
+        if d[i] == 0:
+            assert k[a:b].max() < max(1, (b - a) // 10)
+        if d[i] == 3:
+            assert k[a:b].max() < 100
