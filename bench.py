@@ -103,6 +103,112 @@ def batched(args, S, I, torch):
     return res
 
 
+def serving(args, S, I, torch):
+    """Served group-by: a Poisson stream (rate 2000/s) of requests, sizes
+    log-uniform in [1e4, 1e8] records (u64 keys and values), operations
+    semisort_= / histogram / collect-reduce in equal parts, keys from the
+    exponential (rate 1e-5) or Zipf (0.8 over [1, 1e8]) distribution; inputs
+    are slices of a device-resident pool of one 1e8-record array per
+    distribution.  Served by the request server (lanes, packing, 200 GB
+    budget) against serial execution of the same trace one request at a time."""
+    import numpy as np
+    rng = np.random.default_rng(8)
+    R = args.serve_requests
+    gaps = rng.exponential(1.0 / 2000.0, R)
+    arrival = np.cumsum(gaps) - gaps[0]
+    sizes = np.floor(10 ** rng.uniform(4, 8, R)).astype(np.int64)
+    ops = rng.integers(0, 3, R)  # 0 semisort_=, 1 histogram, 2 collect-reduce
+    dists = rng.integers(0, 2, R)
+    P = 10 ** 8
+    log(f"serving: pool of 2 x {P} records; {R} requests, {sizes.sum() / 1e9:.2f} G records offered "
+        f"over {arrival[-1]:.3f} s")
+    pool = []
+    for name in ("exp1e-5_u32idx", "zipf0.8_1e8_u32idx"):
+        k, _ = I.t_workload(name, P, 8, "cuda")
+        v = I.t_u64(8, 9, torch.arange(P, dtype=torch.int64, device="cuda"))
+        pool.append((k, v))
+    offs = [int(rng.integers(0, P - int(n) + 1)) for n in sizes]
+    torch.cuda.synchronize()
+    opcode = {0: S.OP_SEMISORT_EQUAL, 1: S.OP_HISTOGRAM, 2: S.OP_COLLECT_REDUCE}
+
+    def req(i):
+        k, v = pool[int(dists[i])]
+        a, n = offs[i], int(sizes[i])
+        return opcode[int(ops[i])], k[a:a + n], v[a:a + n]
+
+    # served: submit at the arrival times, keep at most ~48 GB of outputs in flight
+    srv = S.Server(lanes=args.serve_lanes, hbm_budget=200 << 30)
+    lat = np.zeros(R)
+    pending = {}
+    out_bytes, cap = 0, 48 << 30
+
+    def reap(block):
+        nonlocal out_bytes
+        for i in list(pending):
+            t, nb = pending[i]
+            done, st, l, _ = srv.poll(t)
+            if done:
+                assert st == 0, f"request {i} failed with {st}"
+                lat[i] = l
+                out_bytes -= nb
+                del pending[i]
+        if block and pending:
+            time.sleep(0.0002)
+
+    base = srv.now()
+    for i in range(R):
+        op, k, v = req(i)
+        nb = k.numel() * 16
+        while out_bytes + nb > cap and pending:
+            reap(True)
+        while srv.now() - base < arrival[i]:
+            reap(False)
+        oa = torch.empty_like(k)
+        ob = torch.empty_like(k)
+        t = srv.submit(op, k, v if op != S.OP_HISTOGRAM else None, oa, ob, arrival=base + arrival[i])
+        pending[i] = (t, nb)
+        out_bytes += nb
+    srv.drain()
+    reap(False)
+    t_end = srv.now() - base
+    st = srv.stats()
+    srv.close()
+    served = {"requests": R, "records": int(sizes.sum()), "makespan_s": round(t_end, 4),
+              "grecs": round(sizes.sum() / t_end / 1e9, 3), "req_per_s": round(R / t_end, 1),
+              "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+              "calls": st["calls"], "packed": st["packed"], "peak_reserved_gb": round(st["peak_reserved"] / 2 ** 30, 2)}
+    log(f"serving: served {served}")
+
+    # serial: one request at a time in arrival order on one context
+    ctx = S.context(0)
+    lat2 = np.zeros(R)
+    t0 = time.perf_counter()
+    for i in range(R):
+        now = time.perf_counter() - t0
+        if now < arrival[i]:
+            time.sleep(arrival[i] - now)
+        op, k, v = req(i)
+        if op == S.OP_SEMISORT_EQUAL:
+            S.semisort_equal(k, v, ctx=ctx)
+        elif op == S.OP_HISTOGRAM:
+            S.histogram(k, ctx=ctx)
+        else:
+            S.collect_reduce(k, v, ctx=ctx)
+        ctx.sync()
+        lat2[i] = time.perf_counter() - t0 - arrival[i]
+    t2 = time.perf_counter() - t0
+    serial = {"makespan_s": round(t2, 4), "grecs": round(sizes.sum() / t2 / 1e9, 3),
+              "p50_ms": round(float(np.percentile(lat2, 50)) * 1e3, 3),
+              "p99_ms": round(float(np.percentile(lat2, 99)) * 1e3, 3)}
+    log(f"serving: serial {serial}")
+    del pool
+    torch.cuda.empty_cache()
+    return {"workload": f"Poisson 2000 req/s, {R} requests, sizes log-uniform [1e4, 1e8], "
+                        "semisort_= / histogram / collect-reduce", "lanes": args.serve_lanes,
+            "served": served, "serial": serial}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +227,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-instance measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-total", type=float, default=5e8)
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-lanes", type=int, default=4)
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 2^28 int64 (2 GiB) once: a plain copy of known size that "
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
@@ -237,10 +346,13 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    elif not args.no_batch:
+    else:
         del keys, vals, ko, vo
         torch.cuda.empty_cache()
-        out["batched"] = batched(args, S, I, torch)
+        if not args.no_batch:
+            out["batched"] = batched(args, S, I, torch)
+        if not args.no_serve:
+            out["serving"] = serving(args, S, I, torch)
     print(json.dumps(out), flush=True)
 
 

@@ -260,7 +260,11 @@ ss_status ss_server_create(int device, const ss_server_config* cfg, ss_server** 
 /* Seconds since the server was created (the clock of arrival times). */
 double ss_server_now(ss_server* srv);
 /* Queue a request (does not block on the device).  arrival_s: its arrival on
- * the server clock, or <= 0 for now.  *ticket identifies it in ss_server_poll. */
+ * the server clock, or <= 0 for now.  *ticket identifies it in ss_server_poll.
+ * SS_EINVAL for a malformed request, SS_ENOMEM for one whose workspace
+ * estimate (about (8 + value bytes + 2) bytes per record, plus 64 MiB) can
+ * never fit in the budget.  Inputs must be complete on the device: the lanes
+ * do not wait for other streams. */
 ss_status ss_server_submit(ss_server* srv, const ss_request* req, double arrival_s, uint64_t* ticket);
 /* *done = 1 once the request is complete; then *result is its status,
  * *latency_s its latency and *m its group count (histogram and collect-reduce).

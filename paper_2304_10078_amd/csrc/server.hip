@@ -204,6 +204,7 @@ void worker(ss_server* S, int li)
                         L.ctx = fresh;
                         S->reserved -= L.reserved - pack_bytes;
                         L.reserved = pack_bytes;
+                        S->cv.notify_all();  // other idle lanes look again (and give back too)
                         continue;
                     }
                 }
@@ -324,6 +325,11 @@ ss_status ss_server_submit(ss_server* S, const ss_request* r, double arrival_s, 
     if (r->n && (!r->keys || !r->out_a || !r->out_b || (r->op != SS_OP_HISTOGRAM && !r->vals))) return SS_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return SS_EINVAL;
+    // a request that cannot fit even with every lane's workspace given back
+    uint64_t pack_total = 0;
+    for (const Lane& L : S->lanes)
+        if (L.pk_in) pack_total += 4 * S->cfg.batch_records * 8;
+    if (r->n && workspace_estimate(*r) + pack_total > S->cfg.hbm_budget) return SS_ENOMEM;
     S->tickets.emplace_back();
     Ticket& t = S->tickets.back();
     t.req = *r;

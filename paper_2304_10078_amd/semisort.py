@@ -47,7 +47,7 @@ _lib = None
 def declared_symbols():
     """Entry points declared in include/semisort.h."""
     txt = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:ss_status|const char\*)\s+(ss_\w+)\s*\(", txt, re.M)))
+    return sorted(set(re.findall(r"^\s*(?:ss_status|const char\*|double)\s+(ss_\w+)\s*\(", txt, re.M)))
 
 
 def lib():
@@ -337,3 +337,126 @@ def autotune_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, 
                                             offs.size - 1, _ptr(keys_out), _ptr(vals_out), int(reps),
                                             ctypes.byref(best), ctypes.byref(ms)))
     return best, ms.value
+
+
+# ---------------------------------------------------------------- serving
+
+OP_SEMISORT_EQUAL, OP_SEMISORT_LESS, OP_HISTOGRAM, OP_COLLECT_REDUCE = 0, 1, 2, 3
+
+
+class ss_request(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("val_bytes", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("keys", ctypes.c_void_p),
+        ("vals", ctypes.c_void_p),
+        ("out_a", ctypes.c_void_p),
+        ("out_b", ctypes.c_void_p),
+    ]
+
+
+class ss_server_config(ctypes.Structure):
+    _fields_ = [
+        ("lanes", ctypes.c_uint32),
+        ("pack_max_records", ctypes.c_uint32),
+        ("batch_records", ctypes.c_uint64),
+        ("hbm_budget", ctypes.c_uint64),
+        ("params", ss_params),
+    ]
+
+
+def _bind_server(L):
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    L.ss_server_default_config.argtypes = [ctypes.POINTER(ss_server_config)]
+    L.ss_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(ss_server_config), ctypes.POINTER(vp)]
+    L.ss_server_now.argtypes = [vp]
+    L.ss_server_now.restype = ctypes.c_double
+    L.ss_server_submit.argtypes = [vp, ctypes.POINTER(ss_request), ctypes.c_double, ctypes.POINTER(u64)]
+    L.ss_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
+    L.ss_server_drain.argtypes = [vp]
+    L.ss_server_stats.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                  ctypes.POINTER(u64)]
+    L.ss_server_destroy.argtypes = [vp]
+    for name in ("ss_server_default_config", "ss_server_create", "ss_server_submit", "ss_server_poll",
+                 "ss_server_drain", "ss_server_stats", "ss_server_destroy"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+class Server:
+    """ss_server: group-by requests served by concurrent lanes with packing of
+    small semisort_= requests.  Inputs must be ready on the device when a
+    request is submitted (the lanes do not wait for other streams); tensors
+    handed to submit() are kept alive here until the request is polled done."""
+
+    def __init__(self, device=0, lanes=None, pack_max_records=None, batch_records=None, hbm_budget=None,
+                 params=None):
+        L = lib()
+        if not hasattr(L, "_server_bound"):
+            _bind_server(L)
+            L._server_bound = True
+        cfg = ss_server_config()
+        L.ss_server_default_config(ctypes.byref(cfg))
+        for k, v in (("lanes", lanes), ("pack_max_records", pack_max_records), ("batch_records", batch_records),
+                     ("hbm_budget", hbm_budget)):
+            if v is not None:
+                setattr(cfg, k, int(v))
+        if params is not None:
+            cfg.params = params
+        self.h = ctypes.c_void_p()
+        st = L.ss_server_create(int(device), ctypes.byref(cfg), ctypes.byref(self.h))
+        if st != SS_OK:
+            raise SemisortError(st, "ss_server_create failed")
+        self._keep = {}
+
+    def now(self):
+        return lib().ss_server_now(self.h)
+
+    def submit(self, op, keys, vals, out_a, out_b, arrival=0.0):
+        req = ss_request()
+        req.op = int(op)
+        req.val_bytes = vals.element_size() if vals is not None else 8
+        req.n = keys.numel()
+        req.keys = keys.data_ptr()
+        req.vals = vals.data_ptr() if vals is not None else None
+        req.out_a = out_a.data_ptr()
+        req.out_b = out_b.data_ptr()
+        t = ctypes.c_uint64()
+        st = lib().ss_server_submit(self.h, ctypes.byref(req), float(arrival), ctypes.byref(t))
+        if st != SS_OK:
+            raise SemisortError(st, "ss_server_submit rejected the request")
+        self._keep[t.value] = (keys, vals, out_a, out_b)
+        return t.value
+
+    def poll(self, ticket):
+        """(done, status, latency_s, m)."""
+        done, res = ctypes.c_int(), ctypes.c_int()
+        lat, m = ctypes.c_double(), ctypes.c_uint64()
+        st = lib().ss_server_poll(self.h, ticket, ctypes.byref(done), ctypes.byref(res), ctypes.byref(lat),
+                                  ctypes.byref(m))
+        if st != SS_OK:
+            raise SemisortError(st, "unknown ticket")
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value), res.value, lat.value, m.value
+
+    def drain(self):
+        lib().ss_server_drain(self.h)
+
+    def stats(self):
+        c, calls, p, peak = (ctypes.c_uint64() for _ in range(4))
+        lib().ss_server_stats(self.h, ctypes.byref(c), ctypes.byref(calls), ctypes.byref(p), ctypes.byref(peak))
+        return {"completed": c.value, "calls": calls.value, "packed": p.value, "peak_reserved": peak.value}
+
+    def close(self):
+        if self.h:
+            lib().ss_server_destroy(self.h)
+            self.h = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,6 +19,8 @@ def test_header_declares_the_boundary():
     names = S.declared_symbols()
     for want in ["ss_create", "ss_destroy", "ss_semisort_equal", "ss_semisort_equal_batch",
                  "ss_semisort_less", "ss_semisort_less_batch", "ss_collect_reduce", "ss_histogram",
+                 "ss_autotune_equal_batch", "ss_server_create", "ss_server_submit", "ss_server_poll",
+                 "ss_server_drain", "ss_server_stats", "ss_server_destroy", "ss_server_now",
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync"]:
         assert want in names
 
@@ -53,3 +55,11 @@ def test_create_without_a_device_fails_cleanly():
     h = ctypes.c_void_p()
     st = L.ss_create(999, None, ctypes.byref(h))
     assert st == S.SS_EINVAL and not h.value
+
+
+def test_server_without_a_device_fails_cleanly():
+    L = _lib_or_skip()
+    import paper_2304_10078_amd.semisort as SS
+    with pytest.raises(SS.SemisortError):
+        SS.Server(device=999)
+    assert L.ss_server_destroy(None) == S.SS_EINVAL
