@@ -95,7 +95,11 @@ ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
  *   2..5: direct writes from registers (8 waves / 4 per SIMD, 8 waves / 6,
  *         16 waves / 4, 4 waves with 16 records per lane / 6)
  * Every variant gives the same result.  Values outside 0..5: SS_EINVAL. */
-enum { SS_OPT_DIST_VARIANT = 1 };
+/* SS_OPT_DEEP_SAMPLE_DIV (1..64, default 1): below level 0 the sample size is
+ * ceil((c / div) ln n').  SS_OPT_NL_TARGET (10..100, default 50): the number of
+ * light buckets of a subproblem is chosen so that light buckets hold about
+ * base_case * target / 100 records. */
+enum { SS_OPT_DIST_VARIANT = 1, SS_OPT_DEEP_SAMPLE_DIV = 2, SS_OPT_NL_TARGET = 3 };
 ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
 
 /* Kernel timing.  While enabled, every kernel launch of the engine is

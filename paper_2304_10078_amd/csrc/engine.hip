@@ -55,6 +55,8 @@ struct ss_ctx {
     Job* job_stage = nullptr;
     size_t job_stage_cap = 0;
     int dist_variant = 0;  // distribution kernel shape (ss_set_option)
+    uint32_t deep_div = 1;    // sample multiplier divisor below level 0 (ss_set_option)
+    uint32_t nl_target = 50;  // adaptive light-bucket target, percent of alpha (ss_set_option)
     // kernel timing with HIP events on the context's stream (ss_profile_*)
     bool prof_on = false;
     struct Pending {
@@ -377,6 +379,8 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.level = level;
     a.sample_mult = p.c;
     a.heavy_min = p.tau;
+    a.deep_div = c->deep_div;
+    a.nl_target = c->nl_target;
     a.alpha = p.alpha;
     a.adaptive_nl = 1;
     a.ordered = p.mode == 2;
@@ -974,6 +978,14 @@ ss_status ss_set_option(ss_ctx* c, int option, int64_t value)
     case SS_OPT_DIST_VARIANT:
         if (value < 0 || value > 5) return fail(c, SS_EINVAL, "distribution variant must be 0..5");
         c->dist_variant = (int)value;
+        return SS_OK;
+    case SS_OPT_DEEP_SAMPLE_DIV:
+        if (value < 1 || value > 64) return fail(c, SS_EINVAL, "deep sample divisor must be 1..64");
+        c->deep_div = (uint32_t)value;
+        return SS_OK;
+    case SS_OPT_NL_TARGET:
+        if (value < 10 || value > 100) return fail(c, SS_EINVAL, "light-bucket target must be 10..100 percent");
+        c->nl_target = (uint32_t)value;
         return SS_OK;
     default:
         return fail(c, SS_EINVAL, "unknown option");

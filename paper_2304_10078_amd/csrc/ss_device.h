@@ -110,6 +110,8 @@ struct LevelArgs {
     uint32_t level;
     uint32_t sample_mult;
     uint32_t heavy_min;    // heavy threshold tau; 0 = ceil(ln n')
+    uint32_t deep_div;     // below level 0 the sample multiplier is divided by this
+    uint32_t nl_target;    // adaptive n_L aims at light buckets of alpha * nl_target / 100 records
     uint32_t alpha;
     uint32_t adaptive_nl;  // choose n_L per subproblem from the sample's light fraction
     uint32_t ordered;      // buckets from sorted splitters (semisort_<) instead of hash bits
@@ -279,6 +281,51 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, u
     if (total) *total = tmp[NW - 1];
     __syncthreads();
     return base + x - v;
+}
+
+// Exclusive scan over the block of E values per thread taken as rows: value
+// e of thread t stands for element e*BS + t, so ex[e] = (sum of all values of
+// rows e' < e) + (sum of row e over threads t' < t).  tmp holds E*BS/64 + E
+// u32.
+template <int BS, int E>
+__device__ __forceinline__ void block_excl_scan_rows(const uint32_t (&v)[E], uint32_t (&ex)[E], uint32_t* tmp)
+{
+    constexpr int NW = BS / 64;
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    uint32_t x[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) x[e] = v[e];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t y = __shfl_up(x[e], o, 64);
+            if (lane >= (uint32_t)o) x[e] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) tmp[e * NW + w] = x[e];
+    }
+    __syncthreads();
+    if (threadIdx.x < (uint32_t)E) {
+        const uint32_t e = threadIdx.x;
+        uint32_t run = 0;
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t t = tmp[e * NW + ww];
+            tmp[e * NW + ww] = run;
+            run += t;
+        }
+        tmp[E * NW + e] = run;  // row total
+    }
+    __syncthreads();
+    uint32_t rowoff = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        ex[e] = rowoff + tmp[e * NW + w] + x[e] - v[e];
+        rowoff += tmp[E * NW + e];
+    }
+    __syncthreads();
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the MI355X.  Give
@@ -575,7 +622,8 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         // |S| = ceil(c ln n'), at most n'/8 (small subproblems are not
         // sampled almost entirely) and at most the LDS capacity
         const double L = log((double)sg.len);
-        double sd = ceil((double)a.sample_mult * L);
+        const double cm = a.level ? (double)a.sample_mult / (double)a.deep_div : (double)a.sample_mult;
+        double sd = ceil(cm * L);
         uint32_t s = sg.len < 2 ? 0u : (uint32_t)sd;
         if (s > sg.len / 8) s = sg.len / 8;
         if (s > kSampleMax) s = kSampleMax;
@@ -602,7 +650,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         uint32_t nl = sg.nl_bits;
         if (a.adaptive_nl && s) {
             const double light = (double)sg.len * (double)(s - sh_hs) / (double)s;
-            const double target = (double)(a.alpha / 2);
+            const double target = (double)a.alpha * (double)a.nl_target / 100.0;
             const uint32_t cap = sg.nl_bits;
             uint32_t nl1 = 1;
             while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
@@ -811,7 +859,8 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
     const Seg sg = a.segs[sid];
     if (tid == 0) {
         const double L = log((double)sg.len);
-        double sd = ceil((double)a.sample_mult * L);
+        const double cm = a.level ? (double)a.sample_mult / (double)a.deep_div : (double)a.sample_mult;
+        double sd = ceil(cm * L);
         uint32_t s = sg.len < 2 ? 0u : (uint32_t)sd;
         if (s > sg.len / 8) s = sg.len / 8;
         if (s > kSampleMax) s = kSampleMax;
@@ -875,7 +924,7 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
         uint32_t nl = sg.nl_bits;
         if (a.adaptive_nl && s) {
             const double light = (double)sg.len * (double)tot_l / (double)s;
-            const double target = (double)(a.alpha / 2);
+            const double target = (double)a.alpha * (double)a.nl_target / 100.0;
             const uint32_t cap = sg.nl_bits;
             uint32_t nl1 = 1;
             while (nl1 < 31 && (double)(1u << nl1) * target < light) ++nl1;
@@ -1707,7 +1756,7 @@ __global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, const uint64_t
     __shared__ uint64_t kl[CAP];
     __shared__ uint32_t tab[2 * CAP];  // slot owners; reused for digit starts
     __shared__ uint16_t wc[W * CAP];
-    __shared__ uint32_t tmp[20];
+    __shared__ uint32_t tmp[8 * 16 + 8];
 
     const Job j = jobs[blockIdx.x];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
@@ -1770,32 +1819,31 @@ __global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, const uint64_t
         rk[e] = wave_rank(f[e], i < m, nbits, wcw);
     }
     __syncthreads();
-    // per digit: prefix over waves, total; exclusive scan of totals over the m digits
+    // per digit: prefix over waves, total; exclusive scan of the totals over
+    // the m digits.  Digit d = e*BS + tid belongs to thread tid, so that
+    // neighbouring lanes touch neighbouring counters (no bank conflicts).
     uint32_t* dstart = tab;  // the table is no longer needed
-    uint32_t s = 0;
+    uint32_t tot[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const uint32_t d = tid * E + e;
+        const uint32_t d = e * BS + tid;
+        uint32_t run = 0;
         if (d < m) {
-            uint32_t run = 0;
 #pragma unroll
             for (int ww = 0; ww < W; ++ww) {
                 const uint32_t c = wc[ww * CAP + d];
                 wc[ww * CAP + d] = (uint16_t)run;
                 run += c;
             }
-            s += run;
-            dstart[CAP + d] = run;  // total, in the upper half
         }
+        tot[e] = run;
     }
-    uint32_t run = block_excl_scan<BS>(s, tmp, nullptr);
+    uint32_t ex[E];
+    block_excl_scan_rows<BS, E>(tot, ex, tmp);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const uint32_t d = tid * E + e;
-        if (d < m) {
-            dstart[d] = run;
-            run += dstart[CAP + d];
-        }
+        const uint32_t d = e * BS + tid;
+        if (d < m) dstart[d] = ex[e];
     }
     __syncthreads();
     bool bad = false;

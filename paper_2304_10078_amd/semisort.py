@@ -130,6 +130,8 @@ class Context:
 
     PROF_KINDS = ("sample", "count", "scan", "distribute", "plan", "finish", "compact", "fill")
     OPT_DIST_VARIANT = 1
+    OPT_DEEP_SAMPLE_DIV = 2
+    OPT_NL_TARGET = 3
 
     def sync(self):
         """Wait for the context's stream; raises SemisortError for a device
