@@ -57,6 +57,58 @@ def cpu_baseline(keys_dev, vals_dev, m):
             "sample": f"first {m} records of the same input, single-threaded sort-based oracle, {dt:.2f} s"}
 
 
+def other_configs(args, S, I, torch):
+    """The remaining 10^9-record configurations, one timed call each after a
+    warm-up: semisort_= and collect-reduce on uniform[0, 1e9), uniform[0, 1e3)
+    and Zipf-1.2 (u64 keys and values), semisort_< and histogram on
+    exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values).  Whole-job
+    HBM fraction from the algorithmic bytes per record: semisort K + 2R +
+    2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; histogram 2K + 2K f_L +
+    16 m/n, with f_H the records whose key occurs more than 500 ln n times."""
+    n = 10 ** 9
+    res = {}
+    cases = [("uniform1e9", ("semisort_=", "collect_reduce")), ("uniform1e3", ("semisort_=", "collect_reduce")),
+             ("zipf1.2_hashed", ("collect_reduce",)),
+             ("exp1e-5_u32idx", ("semisort_<", "histogram")), ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram"))]
+    for wl, ops in cases:
+        keys, vals = I.t_workload(wl, n, 4, "cuda")
+        _, counts = torch.unique(keys, return_counts=True)
+        f_h = float(counts[counts > 500.0 * math.log(n)].sum().item()) / n
+        m = int(counts.numel())
+        del counts
+        torch.cuda.empty_cache()
+        R = 8 + vals.element_size()
+        for op in ops:
+            if op == "semisort_=":
+                fn = lambda: S.semisort_equal(keys, vals)  # noqa: E731
+                b = 8 + 2 * R + 2 * R * (1 - f_h)
+            elif op == "semisort_<":
+                fn = lambda: S.semisort_less(keys, vals)  # noqa: E731
+                b = 8 + 2 * R + 2 * R * (1 - f_h)
+            elif op == "collect_reduce":
+                v64 = vals if vals.element_size() == 8 else vals.to(torch.int64)
+                fn = lambda: S.collect_reduce(keys, v64)  # noqa: E731
+                b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
+            else:
+                fn = lambda: S.histogram(keys)  # noqa: E731
+                b = 16 + 16 * (1 - f_h) + 16.0 * m / n
+            fn()
+            S.sync()
+            t0 = time.perf_counter()
+            r = fn()
+            S.sync()
+            ms = (time.perf_counter() - t0) * 1e3
+            del r
+            torch.cuda.empty_cache()
+            key = f"{op} {wl}"
+            res[key] = {"ms": round(ms, 3), "grecs": round(n / ms / 1e6, 2), "f_H": round(f_h, 4),
+                        "B_alg_per_record": round(b, 2), "pct_hbm_roofline": round(100 * b * n / (ms * 1e-3) / 8e12, 1)}
+            log(f"configs: {key}: {res[key]}")
+        del keys, vals
+        torch.cuda.empty_cache()
+    return res
+
+
 def batched(args, S, I, torch):
     """4096 independent semisort_= instances (sizes log-uniform in [1e3, 1e7]
     scaled to a total of at most 5e8 records, per-instance key distribution
@@ -224,6 +276,7 @@ def main():
     ap.add_argument("--sample-mult", type=int, default=0, help="c in |S| = c ln n' (0 = library default)")
     ap.add_argument("--heavy-min", type=int, default=-1, help="heavy threshold tau (-1 = library default, "
                                                                "0 = ceil(ln n'))")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other 1e9-record configurations")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-instance measurement")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-total", type=float, default=5e8)
@@ -349,6 +402,8 @@ def main():
     else:
         del keys, vals, ko, vo
         torch.cuda.empty_cache()
+        if not args.no_configs:
+            out["configs"] = other_configs(args, S, I, torch)
         if not args.no_batch:
             out["batched"] = batched(args, S, I, torch)
         if not args.no_serve:

@@ -2304,66 +2304,84 @@ __global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint
     }
 }
 
-// Compaction of the results: positions are cut into blocks of kFlagBlock;
-// each thread owns 64 consecutive flag bytes (flags are 0 or 1, so the
-// population count of a word counts its results).  The flag array is padded
-// to a whole number of blocks and cleared before the run.
+// Compaction of the results.  Positions are cut into chunks of kFlagChunk,
+// one per wave (16 per block of kFlagBlock); a wave walks its chunk in rounds
+// of 256 positions, each lane owning 4 neighbouring flag bytes, so flag and
+// result reads and the packed writes are coalesced.  Flags are 0 or 1; the
+// flag array is padded to a whole number of blocks and cleared before the run.
 constexpr uint32_t kFlagBlock = 65536;
+constexpr uint32_t kFlagChunk = 4096;
 
-__global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint32_t* bcnt)
+__device__ __forceinline__ uint32_t wave_excl_sum(uint32_t v, uint32_t* total)
 {
-    __shared__ uint32_t tmp[20];
-    const uint64_t* f = (const uint64_t*)(rflag + (size_t)blockIdx.x * kFlagBlock) + threadIdx.x * 8;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    *total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+// Results per chunk.
+__global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint32_t* ccnt)
+{
+    const uint32_t chunk = blockIdx.x * 16 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t* f = (const uint64_t*)(rflag + (size_t)chunk * kFlagChunk) + lane * 8;
     uint32_t c = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) c += __popcll(f[q]);
     uint32_t tot = 0;
-    (void)block_excl_scan<1024>(c, tmp, &tot);
-    if (threadIdx.x == 0) bcnt[blockIdx.x] = tot;
+    (void)wave_excl_sum(c, &tot);
+    if (lane == 0) ccnt[chunk] = tot;
 }
 
-// Exclusive scan of the block counts in place (one block); m to *m_out.
-__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* bcnt, uint32_t nblk, unsigned long long* m_out)
+// Exclusive scan of the chunk counts in place (one block, contiguous runs of
+// chunks per thread); m to *m_out.
+__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* ccnt, uint32_t nchunk, unsigned long long* m_out)
 {
     __shared__ uint32_t tmp[20];
-    uint32_t run = 0;
-    for (uint32_t base = 0; base < nblk; base += 1024) {
-        const uint32_t i = base + threadIdx.x;
-        const uint32_t x = i < nblk ? bcnt[i] : 0u;
-        uint32_t tot = 0;
-        const uint32_t o = block_excl_scan<1024>(x, tmp, &tot);
-        if (i < nblk) bcnt[i] = run + o;
-        run += tot;
+    const uint32_t per = (nchunk + 1023) / 1024;
+    const uint32_t c0 = threadIdx.x * per;
+    const uint32_t c1 = c0 + per < nchunk ? c0 + per : nchunk;
+    uint32_t s = 0;
+    for (uint32_t c = c0; c < c1; ++c) s += ccnt[c];
+    uint32_t tot = 0;
+    uint32_t run = block_excl_scan<1024>(s, tmp, &tot);
+    for (uint32_t c = c0; c < c1; ++c) {
+        const uint32_t x = ccnt[c];
+        ccnt[c] = run;
+        run += x;
     }
-    if (threadIdx.x == 0) *m_out = run;
+    if (threadIdx.x == 0) *m_out = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, const uint32_t* bofs,
+__global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, const uint32_t* cofs,
                                                        const uint64_t* res_keys, const uint64_t* res_vals,
                                                        uint64_t* out_keys, uint64_t* out_vals)
 {
-    __shared__ uint32_t tmp[20];
-    const size_t p0 = (size_t)blockIdx.x * kFlagBlock + threadIdx.x * 64;
-    const uint64_t* f = (const uint64_t*)(rflag + p0);
-    uint64_t wv[8];
-    uint32_t c = 0;
+    const uint32_t chunk = blockIdx.x * 16 + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63u;
+    const size_t base = (size_t)chunk * kFlagChunk;
+    uint32_t o = cofs[chunk];
+    for (uint32_t r = 0; r < kFlagChunk / 256; ++r) {
+        const size_t p = base + r * 256 + lane * 4;
+        const uint32_t f = *(const uint32_t*)(rflag + p);
+        const uint32_t c = __popc(f);
+        uint32_t tot = 0;
+        uint32_t at = o + wave_excl_sum(c, &tot);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        wv[q] = f[q];
-        c += __popcll(wv[q]);
-    }
-    uint32_t o = bofs[blockIdx.x] + block_excl_scan<1024>(c, tmp, nullptr);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        uint64_t x = wv[q];
-        while (x) {
-            const uint32_t bit = (uint32_t)__ffsll((long long)x) - 1;  // bit 0 of a flag byte
-            x &= x - 1;
-            const size_t p = p0 + q * 8 + bit / 8;
-            out_keys[o] = res_keys[p];
-            out_vals[o] = res_vals[p];
-            ++o;
+        for (int b = 0; b < 4; ++b) {
+            if ((f >> (8 * b)) & 1u) {
+                out_keys[at] = res_keys[p + b];
+                out_vals[at] = res_vals[p + b];
+                ++at;
+            }
         }
+        o += tot;
     }
 }
 
