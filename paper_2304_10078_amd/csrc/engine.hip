@@ -41,6 +41,7 @@ struct ss_ctx {
     DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
     DevBuf bkey;                     // keys of one-key buckets
+    DevBuf top;                      // two most sampled heavy buckets per subproblem
     DevBuf fills[2];                 // key-fill job lists (alternating levels)
     uint32_t fill_cap[2] = {0, 0};
     hipStream_t aux = nullptr;       // second stream: key fills overlap the next level
@@ -349,6 +350,7 @@ ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunk
     if ((s = ensure(c, c->tab_id, (size_t)nsegs * 2 * kHeavySlotsMax * 2)) != SS_OK) return s;
     if ((s = ensure(c, c->bfin, (size_t)nsegs * kNbStride)) != SS_OK) return s;
     if ((s = ensure(c, c->bkey, (size_t)nsegs * kNbStride * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->top, (size_t)nsegs * 4)) != SS_OK) return s;
     return SS_OK;
 }
 
@@ -386,6 +388,7 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.ordered = p.mode == 2;
     a.bfin = (uint8_t*)c->bfin.p;
     a.bkey = (uint64_t*)c->bkey.p;
+    a.top = (uint32_t*)c->top.p;
     a.fill_heavy = 0;
     a.reduce = 0;
     a.hsum = nullptr;
@@ -932,7 +935,7 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills[0], &c->fills[1]};
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1]};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1023,7 +1026,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->fills[0], &c->fills[1]};
+                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1]};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;

@@ -117,6 +117,7 @@ struct LevelArgs {
     uint32_t ordered;      // buckets from sorted splitters (semisort_<) instead of hash bits
     uint8_t* bfin;         // [nsegs][kNbStride]: 1 for buckets that are final (one key each)
     uint64_t* bkey;        // [nsegs][kNbStride]: the key of each one-key bucket
+    uint32_t* top;         // [nsegs]: the two most sampled heavy buckets (16 bits each, 0xFFFF = none)
     uint32_t fill_heavy;   // one-key buckets bound for keys_out: values move, keys are filled later
     // collect-reduce / histogram (Section 3.5)
     uint32_t reduce;                // heavy records are summed where they are, not moved
@@ -509,7 +510,7 @@ __device__ void bitonic_sort_block(uint64_t (&e)[C], uint64_t* smp, uint32_t P)
 template <int BS, int C>
 __device__ uint32_t select_heavy_runs(const uint64_t (&e)[C], const uint64_t* smp, uint32_t s, uint32_t tau,
                                       uint32_t* rh, uint32_t* tmp, uint32_t* sh_te, uint32_t* sh_hs, uint64_t* hv,
-                                      uint64_t* heavy_out)
+                                      uint64_t* heavy_out, unsigned long long* top2)
 {
     const uint32_t t = threadIdx.x;
     const uint32_t base = t * C;
@@ -573,6 +574,10 @@ __device__ uint32_t select_heavy_runs(const uint64_t (&e)[C], const uint64_t* sm
             if (id < kHeavyMax) {
                 hv[id] = e[q];
                 heavy_out[id] = e[q];
+                // the two most sampled heavy keys: (run length, id) maxima
+                const unsigned long long tag = ((unsigned long long)rl[q] << 16) | id;
+                const unsigned long long prev = atomicMax(&top2[0], tag);
+                atomicMax(&top2[1], prev < tag ? prev : tag);
             }
             ++id;
         }
@@ -586,13 +591,13 @@ __device__ uint32_t select_heavy_runs(const uint64_t (&e)[C], const uint64_t* sm
 template <int MODE, int BS, int C>
 __device__ uint32_t sample_select(const LevelArgs& a, const Seg& sg, uint32_t sid, uint32_t s, uint32_t tau,
                                   uint32_t P, uint64_t* smp, uint32_t* rh, uint32_t* tmp, uint32_t* sh_te,
-                                  uint32_t* sh_hs, uint64_t* hv)
+                                  uint32_t* sh_hs, uint64_t* hv, unsigned long long* top2)
 {
     uint64_t e[C];
     gather_regs<MODE, C>(a, sg, s, true, e);
     bitonic_sort_block<BS, C>(e, smp, P);
     return select_heavy_runs<BS, C>(e, smp, s, tau, rh, tmp, sh_te, sh_hs, hv,
-                                    a.heavy_list + (size_t)sid * kHeavyMax);
+                                    a.heavy_list + (size_t)sid * kHeavyMax, top2);
 }
 
 // Gather and sort of raw keys (semisort_<): smp holds the sorted sample.
@@ -614,10 +619,12 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     __shared__ uint32_t tmp[20];
     __shared__ uint32_t rh[64];
     __shared__ uint32_t sh_s, sh_tau, sh_te, sh_hs, sh_nl, sh_fail;
+    __shared__ unsigned long long sh_top[2];
 
     const uint32_t sid = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const Seg sg = a.segs[sid];
+    if (tid < 2) sh_top[tid] = 0;
     if (tid == 0) {
         // |S| = ceil(c ln n'), at most n'/8 (small subproblems are not
         // sampled almost entirely) and at most the LDS capacity
@@ -637,11 +644,11 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     uint32_t P = 2;
     while (P < s) P <<= 1;
     uint32_t nh;
-    if (P == 16 * BS) nh = sample_select<MODE, BS, 16>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
-    else if (P == 8 * BS) nh = sample_select<MODE, BS, 8>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
-    else if (P == 4 * BS) nh = sample_select<MODE, BS, 4>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
-    else if (P == 2 * BS) nh = sample_select<MODE, BS, 2>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
-    else nh = sample_select<MODE, BS, 1>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv);
+    if (P == 16 * BS) nh = sample_select<MODE, BS, 16>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 8 * BS) nh = sample_select<MODE, BS, 8>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 4 * BS) nh = sample_select<MODE, BS, 4>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 2 * BS) nh = sample_select<MODE, BS, 2>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else nh = sample_select<MODE, BS, 1>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
 
     // Light bucket count.  With adaptive_nl, n_L is the smallest power of two
     // that lets the light records finish in the fewest levels: one level if
@@ -721,6 +728,10 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     if (a.reduce)
         for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = 0;
     if (tid == 0) {
+        // heavy ids of the two most sampled keys, for the counting pass
+        const uint32_t t0 = sh_top[0] ? nL + (uint32_t)(sh_top[0] & 0xFFFFu) : 0xFFFFu;
+        const uint32_t t1 = sh_top[1] ? nL + (uint32_t)(sh_top[1] & 0xFFFFu) : 0xFFFFu;
+        a.top[sid] = t0 | (t1 << 16);
         a.segs[sid].nheavy = (uint16_t)nh;
         a.segs[sid].hlog2 = (uint16_t)hfield;
         a.segs[sid].nl_bits = (uint8_t)sh_nl;
@@ -770,7 +781,22 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     const uint32_t lmask = nL - 1;
     const uint64_t* keys = a.src_keys;
     uint16_t* bids = a.bids;
-    auto tally = [&](uint32_t b) { if (!finl[b]) atomicAdd(&cnt[b], 1u); };
+    // The two most frequent heavy buckets are counted per wave by ballot
+    // (one LDS update per wave instead of one per record); the others by
+    // LDS atomics.  Collect-reduce does not count heavy records at all.
+    const uint32_t tp = a.reduce ? 0xFFFFFFFFu : a.top[sid];
+    const uint32_t top0 = tp & 0xFFFFu, top1 = tp >> 16;
+    const uint32_t lane = tid & 63u;
+    auto tally = [&](uint32_t b) {
+        const uint64_t b0 = __ballot(b == top0), b1 = __ballot(b == top1);
+        if (b == top0) {
+            if (lane == (uint32_t)__ffsll((long long)b0) - 1) atomicAdd(&cnt[top0], (uint32_t)__popcll(b0));
+        } else if (b == top1) {
+            if (lane == (uint32_t)__ffsll((long long)b1) - 1) atomicAdd(&cnt[top1], (uint32_t)__popcll(b1));
+        } else if (!finl[b]) {
+            atomicAdd(&cnt[b], 1u);
+        }
+    };
     constexpr int U = 8;  // loads in flight per thread
     uint64_t i = r0 + tid;
     for (; i + (U - 1) * BS < r1; i += U * BS) {
