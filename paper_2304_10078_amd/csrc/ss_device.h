@@ -254,6 +254,53 @@ __device__ __forceinline__ uint32_t wave_rank(uint32_t d, bool valid, uint32_t n
     return r;
 }
 
+constexpr int ilog2_c(uint32_t x) { return x <= 1 ? 0 : 1 + ilog2_c(x >> 1); }
+
+// wave_rank for the E records a lane holds in one round, digits below 2^NB.
+// The match masks come first, all E at once (their ballots are independent,
+// so they interleave, and with the bit count fixed the loop unrolls); only
+// the counter updates run in record order.  Bits above a digit's width are
+// zero in every lane and leave the masks unchanged.
+template <int E, int NB = 11>
+__device__ __forceinline__ void wave_rank_all(const uint32_t (&d)[E], const bool (&valid)[E], uint32_t nbits,
+                                              uint16_t* wcw, uint32_t (&r)[E])
+{
+    uint64_t peers[E];
+    if (NB <= 8 || nbits > 6) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            uint32_t lo = 0, hi = 0;  // lanes whose digit differs in some bit
+#pragma unroll
+            for (int bit = 0; bit < NB; ++bit) {
+                uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d[e], bit, 1);  // 0 or ~0
+                // opaque to the optimizer, so that the ballot compares m itself
+                // instead of recomputing the bit (one instruction less per bit)
+                __asm__("" : "+v"(m));
+                const uint64_t bal = __ballot(m != 0);
+                // x | (m ^ bal) in one instruction (truth table over m, x, bal)
+                lo = __builtin_amdgcn_bitop3_b32(m, lo, (uint32_t)bal, 0xDE);
+                hi = __builtin_amdgcn_bitop3_b32(m, hi, (uint32_t)(bal >> 32), 0xDE);
+            }
+            peers[e] = __ballot(valid[e]) & ~(((uint64_t)hi << 32) | lo);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) peers[e] = wave_match(d[e], nbits, __ballot(valid[e]));
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        uint32_t rr = 0;
+        if (valid[e]) {
+            const uint32_t pre = wcw[d[e]];
+            const uint32_t below = lanes_below(peers[e]);
+            if (below == 0) wcw[d[e]] = (uint16_t)(pre + __popcll(peers[e]));
+            rr = pre + below;
+        }
+        __builtin_amdgcn_wave_barrier();
+        r[e] = rr;
+    }
+}
+
 // Exclusive scan over the block of one u32 per thread; tmp holds >= 17 u32.
 template <int BS>
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* tmp, uint32_t* total)
@@ -1333,8 +1380,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
                 }
             }
         }
-#pragma unroll
-        for (int e = 0; e < E; ++e) pos[e] = wave_rank(bk[e], mv[e], nbits, wcw);
+        wave_rank_all<E>(bk, mv, nbits, wcw, pos);
         __syncthreads();
 
         // per bucket: exclusive prefix over waves, sub-tile total, and the
@@ -1839,10 +1885,11 @@ __global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, const uint64_t
 #pragma unroll
     for (int e = 0; e < E; ++e) f[e] = tab[sl[e]];
     uint16_t* wcw = wc + w * CAP;
+    {
+        bool ok[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        rk[e] = wave_rank(f[e], i < m, nbits, wcw);
+        for (int e = 0; e < E; ++e) ok[e] = w * 64 * E + e * 64 + lane < m;
+        wave_rank_all<E, ilog2_c(CAP)>(f, ok, nbits, wcw, rk);
     }
     __syncthreads();
     // per digit: prefix over waves, total; exclusive scan of the totals over
@@ -1962,10 +2009,15 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
         for (uint32_t i = tid; i < W * 64; i += BS) wc[i] = 0;
         __syncthreads();
         uint32_t rk[E];
+        {
+            uint32_t dg[E];
+            bool ok[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t q = w * 64 * E + e * 64 + lane;
-            rk[e] = wave_rank((el[e] >> sh) & 63u, q < m, 6, wc + w * 64);
+            for (int e = 0; e < E; ++e) {
+                dg[e] = (el[e] >> sh) & 63u;
+                ok[e] = w * 64 * E + e * 64 + lane < m;
+            }
+            wave_rank_all<E, 6>(dg, ok, 6, wc + w * 64, rk);
         }
         __syncthreads();
         uint32_t dtot = 0;
@@ -2077,10 +2129,15 @@ __global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uin
         for (uint32_t i = tid; i < W * 256; i += BS) wc[i] = 0;
         __syncthreads();
         uint32_t rk[E];
+        {
+            uint32_t dg[E];
+            bool ok[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t q = w * 64 * E + e * 64 + lane;
-            rk[e] = wave_rank((uint32_t)((k[e] - kmin) >> sh) & 255u, q < m, 8, wc + w * 256);
+            for (int e = 0; e < E; ++e) {
+                dg[e] = (uint32_t)((k[e] - kmin) >> sh) & 255u;
+                ok[e] = w * 64 * E + e * 64 + lane < m;
+            }
+            wave_rank_all<E, 8>(dg, ok, 8, wc + w * 256, rk);
         }
         __syncthreads();
         // per digit: exclusive prefix over waves, then an exclusive scan of the

@@ -175,7 +175,8 @@ def test_batch_matches_each_instance_alone():
 def test_every_distribution_variant_gives_the_same_result(variant):
     ctx = S.context(0)
     try:
-        for name, n in [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 2_000_003)]:
+        for name, n in [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 2_000_003),
+                        ("exp1e-5_u32idx", 1_000_003), ("uniform1e3", 700_001)]:
             k, v = I.np_workload(name, n, 13)
             ctx.set_option(ctx.OPT_DIST_VARIANT, 0)
             ref = run_equal(k, v)
