@@ -1272,14 +1272,20 @@ template <typename V, int W, int E, int RED>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
 {
     // Every global load and store in the sub-tile loop is issued
-    // unconditionally (clamped load indices, a sink address for lanes without
-    // a record): with no branches around memory instructions the compiler can
-    // count outstanding accesses and wait only for the ones it needs instead
-    // of draining all stores before each sub-tile.
+    // unconditionally (clamped 32-bit load offsets from the sub-tile's start,
+    // a sink address for lanes without a record to write): with no branches
+    // around memory instructions the compiler can count outstanding accesses
+    // and wait only for the ones it needs instead of draining all stores
+    // before the next loads are used.  Each bucket's output range for the
+    // sub-tile is checked once against its subproblem; a sub-tile with a bad
+    // range writes nothing and raises the status.
     constexpr int BS = W * 64;
     constexpr int SUB = BS * E;
     __shared__ uint32_t gbase[kNbStride];      // bit 31: bucket goes to fin_*
     __shared__ uint32_t lst[kNbStride + 1];
+    // output position - stage slot (31 bits, wrapping) | bit 31 of gbase
+    __shared__ uint32_t dl[kNbStride];
+    __shared__ uint32_t sh_bad;
     __shared__ uint16_t wc[W * kNbStride];
     __shared__ uint64_t stage[SUB];
     __shared__ uint16_t stage_b[SUB];
@@ -1308,8 +1314,6 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     V* dst_vals = (V*)a.dst_vals;
     V* fin_vals = (V*)a.fin_vals;
     V* stage_v = (V*)stage;
-    uint64_t* sink_k = a.sink + lane;
-    V* sink_v = (V*)(a.sink + lane);
     const uint32_t per = (nb + BS - 1) / BS;  // buckets per thread in the scans
     const uint32_t pb0 = tid * per;
     const bool fillk = RED == 0 && a.fill_heavy != 0;
@@ -1325,18 +1329,25 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
 
     // keys and bucket ids are loaded one sub-tile ahead; values at the top of
     // their own iteration (needed only after the ranking)
+    const uint32_t lofs = w * 64 * E + lane;  // this lane's first offset in a sub-tile
+    uint64_t* sink_k = a.sink + lane;
+    V* sink_v = (V*)(a.sink + lane);
+    const uint64_t kdiff = (uint64_t)a.fin_keys - (uint64_t)a.dst_keys;
+    const uint64_t vdiff = (uint64_t)fin_vals - (uint64_t)dst_vals;
     uint64_t kn[E];
     uint16_t bn[E];
     {
-        const uint64_t bi = r0 + (uint64_t)w * 64 * E + lane;
+        const uint64_t* ks = a.src_keys + r0;
+        const uint16_t* bs = a.bids + r0;
+        const uint32_t lim = (uint32_t)(rlast - r0 < SUB ? rlast - r0 : SUB);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            uint64_t i = bi + (uint64_t)e * 64;
-            i = i < rlast ? i : rlast;
-            kn[e] = a.src_keys[i];
-            bn[e] = a.bids[i];
+            const uint32_t o = min(lofs + e * 64u, lim);
+            kn[e] = ks[o];
+            bn[e] = bs[o];
         }
     }
+    if (tid == 0) sh_bad = 0;
     __syncthreads();
 
     bool out_of_range = false;
@@ -1344,13 +1355,15 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         uint64_t k[E];
         V v[E];
         uint32_t bk[E], pos[E];
-        const uint64_t base_i = sub + (uint64_t)w * 64 * E + lane;
+        const uint32_t left = (uint32_t)(r1 - sub < 2 * SUB ? r1 - sub : 2 * SUB);  // records from sub on
+        {
+            const V* vs = src_vals + sub;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            uint64_t i = base_i + (uint64_t)e * 64;
-            i = i < rlast ? i : rlast;
-            if constexpr (RED == 2) v[e] = (V)1;
-            else v[e] = src_vals[i];
+            for (int e = 0; e < E; ++e) {
+                const uint32_t o = min(lofs + e * 64u, left - 1);
+                if constexpr (RED == 2) v[e] = (V)1;
+                else v[e] = vs[o];
+            }
         }
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -1359,20 +1372,20 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         {
             // next sub-tile (the last iteration re-reads its own, clamped)
-            const uint64_t bi = base_i + SUB;
+            const uint64_t* ks = a.src_keys + sub;
+            const uint16_t* bs = a.bids + sub;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                uint64_t i = bi + (uint64_t)e * 64;
-                i = i < rlast ? i : rlast;
-                kn[e] = a.src_keys[i];
-                bn[e] = a.bids[i];
+                const uint32_t o = min(lofs + SUB + e * 64u, left - 1);
+                kn[e] = ks[o];
+                bn[e] = bs[o];
             }
         }
         uint16_t* wcw = wc + w * nb;
         bool mv[E];  // this record moves (heavy records of collect-reduce stay)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            mv[e] = base_i + (uint64_t)e * 64 < r1;
+            mv[e] = lofs + e * 64u < left;
             if constexpr (RED != 0) {
                 if (mv[e] && finl[bk[e]]) {
                     atomicAdd(&hs[bk[e]], (unsigned long long)v[e]);
@@ -1402,14 +1415,21 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
         uint32_t tot = 0;
         uint32_t run = block_excl_scan<BS>(s, tmp, &tot);
+        bool bad = false;
         for (uint32_t j = 0; j < per; ++j) {
             const uint32_t b = pb0 + j;
             if (b < nb) {
                 const uint32_t c = lst[b];
+                const uint32_t g = gbase[b];
+                const uint32_t p = g & 0x7FFFFFFFu;
+                // [p, p + c) must lie inside the subproblem
+                bad |= c != 0 && (c > sg.len || p - sg.start > sg.len - c);
                 lst[b] = run;
+                dl[b] = ((p - run) & 0x7FFFFFFFu) | (g & 0x80000000u);
                 run += c;
             }
         }
+        if (bad) sh_bad = 1;
         if (tid == 0) lst[nb] = tot;
         __syncthreads();
 
@@ -1426,22 +1446,26 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         __syncthreads();
-        const uint32_t m = lst[nb];
+        const uint32_t m = sh_bad ? 0u : lst[nb];  // a bad range: write nothing
+        out_of_range |= sh_bad != 0;
         uint32_t dest[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t j = tid + e * BS;
             const uint32_t jj = j < m ? j : 0u;
             const uint32_t sb = stage_b[jj];
-            const uint32_t b = sb & 0x7FFFu;
-            const uint32_t dd = gbase[b] + (jj - lst[b]);
-            const uint32_t d = dd & 0x7FFFFFFFu;
-            const bool in_range = d - sg.start < sg.len;
-            out_of_range |= (j < m) && !in_range;
-            dest[e] = (j < m && in_range) ? dd : 0xFFFFFFFFu;
-            uint64_t* out = (dd >> 31) ? a.fin_keys : a.dst_keys;
-            uint64_t* addr = dest[e] != 0xFFFFFFFFu ? out + d : sink_k;
-            if (!(sb >> 15)) *addr = stage[jj];
+            const uint32_t x = dl[__builtin_amdgcn_ubfe(sb, 0, 15)];
+            const uint32_t d = (jj + x) & 0x7FFFFFFFu;
+            dest[e] = j < m ? (d | (x & 0x80000000u)) : 0xFFFFFFFFu;
+            // dst_keys, or fin_keys when bit 31 is set: a masked difference
+            // (kept opaque, or the compiler turns it back into a select that
+            // copies both uniform pointers into VGPRs)
+            uint32_t msk = (uint32_t)((int32_t)x >> 31);
+            __asm__("" : "+v"(msk));
+            const uint64_t sel = ((uint64_t)msk << 32) | msk;
+            uint64_t* out = (uint64_t*)((char*)a.dst_keys + (kdiff & sel)) + d;
+            // bit 15: the key is not stored (one-key bucket, filled later)
+            *(j < m && !(sb >> 15) ? out : sink_k) = stage[jj];
         }
         for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
         __syncthreads();
@@ -1454,9 +1478,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             for (int e = 0; e < E; ++e) {
                 const uint32_t j = tid + e * BS;
                 const uint32_t dd = dest[e];
-                V* out = (dd >> 31) ? fin_vals : dst_vals;
-                V* addr = dd != 0xFFFFFFFFu ? out + (dd & 0x7FFFFFFFu) : sink_v;
-                *addr = stage_v[j < m ? j : 0u];
+                uint32_t msk = (uint32_t)((int32_t)dd >> 31);
+                __asm__("" : "+v"(msk));
+                const uint64_t sel = ((uint64_t)msk << 32) | msk;
+                V* out = (V*)((char*)dst_vals + (vdiff & sel)) + (dd & 0x7FFFFFFFu);
+                *(dd != 0xFFFFFFFFu ? out : sink_v) = stage_v[j < m ? j : 0u];
             }
             __syncthreads();
         }
