@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace ssd {
 
 constexpr uint32_t kHeavyMax = 512;          // n_H cap per subproblem
@@ -47,7 +49,8 @@ struct Seg {
     uint8_t shift;     // first hash bit of the light id (hash-bucketed subproblems)
     uint16_t nbk;      // number of buckets, written by the sampling kernel
     uint16_t nheavy;   // n_H, written by the sampling kernel
-    uint16_t hlog2;    // bits 0-7: log2 slots per heavy table (0 when n_H = 0); bits 8-15: table salt
+    uint16_t hlog2;    // bits 0-7: log2 slots per heavy table (0 when n_H = 0); bits 8-14: table salt;
+                       // bit 15: slots read directly from the hash (heavy_slot)
 };
 static_assert(sizeof(Seg) == 32, "Seg layout");
 
@@ -192,18 +195,37 @@ __device__ __forceinline__ uint32_t slot2(uint64_t h, uint32_t log2slots, uint32
     return x >> (32 - log2slots);
 }
 
+// Slots of the two-choice heavy table.  With a mixed hash and fewer than 32
+// hash bits consumed by the levels above (bit 15 of the table field), the
+// slots come from the hash directly: its top bits for the first table, one
+// salted multiply of bits 16..47 for the second.  Otherwise (identity keys,
+// very deep subproblems whose keys share many low bits) the hash is folded
+// and mixed first.
+constexpr uint32_t kDirectSlots = 0x8000u;
+
+__device__ __forceinline__ uint32_t heavy_slot(uint64_t h, uint32_t hfield, int side)
+{
+    const uint32_t lg = hfield & 0xFFu, salt = (hfield >> 8) & 0x7Fu;
+    if (hfield & kDirectSlots) {
+        if (side == 0) return (uint32_t)(h >> 32) >> (32 - lg);
+        return ((uint32_t)(h >> 16) * (0x85ebca6bu + 2u * salt)) >> (32 - lg);
+    }
+    return side == 0 ? fib_slot(h, lg) : slot2(h, lg, salt);
+}
+
 // GetBucketId (Algorithm 1): the heavy id when the key is in the heavy table,
 // else the light id from nl_bits bits of the hash starting at `shift`.  The
 // heavy table has two choices per key (cuckoo hashing), so a lookup is four
-// independent LDS reads and no probe loop.
+// independent LDS reads and no probe loop.  K: 0 = no heavy table, 1 = direct
+// slots, 2 = mixed slots (the caller branches once per subproblem).
+template <int K>
 __device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, const uint16_t* tid,
                                               uint32_t hfield, uint32_t shift, uint32_t lmask)
 {
-    const uint32_t hlog2 = hfield & 0xFFu;
     uint32_t b = (uint32_t)(h >> shift) & lmask;
-    if (hlog2) {
-        const uint32_t s1 = fib_slot(h, hlog2);
-        const uint32_t s2 = slot2(h, hlog2, hfield >> 8) + kHeavySlotsMax;
+    if constexpr (K != 0) {
+        const uint32_t s1 = heavy_slot(h, (hfield & 0x7FFFu) | (K == 1 ? kDirectSlots : 0u), 0);
+        const uint32_t s2 = heavy_slot(h, (hfield & 0x7FFFu) | (K == 1 ? kDirectSlots : 0u), 1) + kHeavySlotsMax;
         const uint16_t i1 = tid[s1], i2 = tid[s2];
         const uint64_t h1 = th[s1], h2 = th[s2];
         if (i2 != kEmpty16 && h2 == h) b = i2;
@@ -730,6 +752,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         hlog2 = ceil_log2_u32(2 * nh);
         if (hlog2 < 4) hlog2 = 4;
     }
+    const uint32_t direct = (MODE == 0 && sg.shift < 32) ? kDirectSlots : 0u;
     const uint32_t slots = nh ? (1u << hlog2) : 0u;
     uint32_t salt = 0;
     bool built = nh == 0;
@@ -746,7 +769,8 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
                     break;
                 }
                 const uint64_t h = hv[cur];
-                const uint32_t sl = side == 0 ? fib_slot(h, hlog2) : kHeavySlotsMax + slot2(h, hlog2, salt);
+                const uint32_t hf = hlog2 | (salt << 8) | direct;
+                const uint32_t sl = side == 0 ? heavy_slot(h, hf, 0) : kHeavySlotsMax + heavy_slot(h, hf, 1);
                 const uint32_t prev = atomicExch(&owner[sl], cur);
                 if (prev == kEmpty32) break;
                 cur = prev;  // the evicted key moves to its other table
@@ -761,7 +785,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     }
     __syncthreads();
     if (!built && tid == 0) atomicOr(&a.info->status, kStatusHeavyTable);
-    const uint32_t hfield = nh ? (hlog2 | (salt << 8)) : 0u;
+    const uint32_t hfield = nh ? (hlog2 | (salt << 8) | direct) : 0u;
     const uint32_t nL = 1u << sh_nl;
     for (uint32_t i = tid; i < 2 * kHeavySlotsMax; i += BS) {
         const bool used = (i & (kHeavySlotsMax - 1)) < slots;
@@ -845,23 +869,33 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
         }
     };
     constexpr int U = 8;  // loads in flight per thread
-    uint64_t i = r0 + tid;
-    for (; i + (U - 1) * BS < r1; i += U * BS) {
-        uint64_t kk[U];
+    // 32-bit offsets from the subarray's start (uniform base pointers)
+    const uint64_t* kt = keys + r0;
+    uint16_t* bt = bids + r0;
+    const uint32_t len = (uint32_t)(r1 - r0);
+    auto pass = [&](auto kind) {
+        constexpr int K = decltype(kind)::value;
+        uint32_t o = tid;
+        for (; o + (U - 1) * BS < len; o += U * BS) {
+            uint64_t kk[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) kk[u] = keys[i + (uint64_t)u * BS];
+            for (int u = 0; u < U; ++u) kk[u] = kt[o + u * BS];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t b = bucket_of(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
-            bids[i + (uint64_t)u * BS] = (uint16_t)b;
+            for (int u = 0; u < U; ++u) {
+                const uint32_t b = bucket_of<K>(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
+                bt[o + u * BS] = (uint16_t)b;
+                tally(b);
+            }
+        }
+        for (; o < len; o += BS) {
+            const uint32_t b = bucket_of<K>(user_hash<MODE>(kt[o]), th, tidh, hlog2, shift, lmask);
+            bt[o] = (uint16_t)b;
             tally(b);
         }
-    }
-    for (; i < r1; i += BS) {
-        const uint32_t b = bucket_of(user_hash<MODE>(keys[i]), th, tidh, hlog2, shift, lmask);
-        bids[i] = (uint16_t)b;
-        tally(b);
-    }
+    };
+    if (!(hlog2 & 0xFFu)) pass(std::integral_constant<int, 0>{});
+    else if (hlog2 & kDirectSlots) pass(std::integral_constant<int, 1>{});
+    else pass(std::integral_constant<int, 2>{});
     __syncthreads();
     // collect-reduce: heavy records stay where they are; each heavy bucket
     // keeps one slot (in the subproblem's first subarray) for its result
