@@ -944,9 +944,41 @@ __device__ __forceinline__ uint32_t upper_bound_u64(const uint64_t* a, uint32_t 
     return lo;
 }
 
-__device__ __forceinline__ uint32_t less_bucket(uint64_t k, const uint64_t* bnd, const uint16_t* rid, uint32_t m)
+// Lookup table for the boundary search of the counting pass.  A key's offset
+// x = k - B_0 from the smallest boundary falls in a cell: x itself below 64,
+// else 64 cells per octave (the octave of x and its next six bits), so the
+// cells are monotone in x and about as fine where boundaries are dense
+// (skewed keys) as where they are sparse.  lut[c] = number of boundaries in
+// cells below c; a key of cell c then has its upper bound among the
+// boundaries lut[c] .. lut[c + 1] - 1, usually a handful.
+constexpr uint32_t kLessCells = 64 + 58 * 64;  // octaves 6 .. 63
+
+__device__ __forceinline__ uint32_t less_cell(uint64_t x)
 {
-    const uint32_t j = upper_bound_u64(bnd, m, k);
+    if (x < 64) return (uint32_t)x;
+    const uint32_t e = 63u - (uint32_t)__clzll((long long)x);  // 6 .. 63
+    return 64u + (e - 6u) * 64u + (uint32_t)(x >> (e - 6u)) - 64u;
+}
+
+// Smallest offset whose cell is c (c < kLessCells).
+__device__ __forceinline__ uint64_t less_cell_start(uint32_t c)
+{
+    if (c < 64) return c;
+    const uint32_t e = (c - 64u) / 64u + 6u, m = (c - 64u) % 64u;
+    return (uint64_t)(64u + m) << (e - 6u);
+}
+
+// Bucket of k: j = #{boundaries <= k} (upper bound), searched only inside
+// k's cell; the equality bucket when B_{j-1} = k is heavy, else R_j.
+__device__ __forceinline__ uint32_t less_bucket_lut(uint64_t k, const uint64_t* bnd, const uint16_t* rid,
+                                                    const uint16_t* lut, uint32_t m)
+{
+    uint32_t j = 0;
+    if (m != 0 && k >= bnd[0]) {
+        const uint32_t c = less_cell(k - bnd[0]);
+        const uint32_t a0 = lut[c], a1 = lut[c + 1];
+        j = a0 + upper_bound_u64(bnd + a0, a1 - a0, k);
+    }
     if (j > 0 && (rid[j - 1] & 0x8000u) && bnd[j - 1] == k) return (rid[j - 1] & 0x7FFFu) + 1;
     return rid[j] & 0x7FFFu;
 }
@@ -1137,6 +1169,7 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
     __shared__ uint8_t finl[kNbStride];
     __shared__ uint64_t bnd[kNbStride];
     __shared__ uint16_t rid[kNbStride + 1];
+    __shared__ uint16_t lut[kLessCells + 1];
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
     const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
@@ -1156,24 +1189,34 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
         rid[j] = a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + j];
     }
     __syncthreads();
-    const uint64_t* keys = a.src_keys;
-    uint16_t* bids = a.bids;
+    if (m != 0) {
+        const uint64_t lo = bnd[0];
+        for (uint32_t c = tid; c <= kLessCells; c += BS) {
+            // boundaries whose offset lies in a cell below c
+            const uint64_t x = c < kLessCells ? less_cell_start(c) : ~0ull;
+            lut[c] = (uint16_t)(x > bnd[m - 1] - lo ? m : lower_bound_u64(bnd, m, lo + x));
+        }
+    }
+    __syncthreads();
     constexpr int U = 8;
-    uint64_t i = r0 + tid;
-    for (; i + (U - 1) * BS < r1; i += U * BS) {
+    const uint64_t* kt = a.src_keys + r0;
+    uint16_t* bt = a.bids + r0;
+    const uint32_t len = (uint32_t)(r1 - r0);
+    uint32_t o = tid;
+    for (; o + (U - 1) * BS < len; o += U * BS) {
         uint64_t kk[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) kk[u] = keys[i + (uint64_t)u * BS];
+        for (int u = 0; u < U; ++u) kk[u] = kt[o + u * BS];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const uint32_t b = less_bucket(kk[u], bnd, rid, m);
-            bids[i + (uint64_t)u * BS] = (uint16_t)b;
+            const uint32_t b = less_bucket_lut(kk[u], bnd, rid, lut, m);
+            bt[o + u * BS] = (uint16_t)b;
             if (!finl[b]) atomicAdd(&cnt[b], 1u);
         }
     }
-    for (; i < r1; i += BS) {
-        const uint32_t b = less_bucket(keys[i], bnd, rid, m);
-        bids[i] = (uint16_t)b;
+    for (; o < len; o += BS) {
+        const uint32_t b = less_bucket_lut(kt[o], bnd, rid, lut, m);
+        bt[o] = (uint16_t)b;
         if (!finl[b]) atomicAdd(&cnt[b], 1u);
     }
     __syncthreads();
