@@ -33,6 +33,7 @@ struct DevBuf {
 
 struct ss_ctx {
     int device = 0;
+    int ncu = 1;  // compute units of the device (persistent grids)
     hipStream_t stream = nullptr;
     std::string err;
     DevBuf t_keys, t_vals;
@@ -242,6 +243,20 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
 // Base-case and copy jobs of one level: one launch per non-empty class.
 // jobs holds kJobClasses lists of `cap` entries.  MODE 0/1: semisort_= with
 // the mixing / identity hash; MODE 2: semisort_<.
+// Grid of a persistent base-case launch: the blocks that fit on the device
+// at once (the occupancy of the kernel is queried once), at most one per job.
+template <int MODE, typename V, int W>
+uint32_t base_grid(const ss_ctx* c, uint32_t njobs)
+{
+    static const int per = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_base<MODE, V, W>, W * 64, 0) != hipSuccess || b < 1)
+            b = 1;
+        return b;
+    }();
+    return (uint32_t)std::min<uint64_t>(njobs, (uint64_t)per * (uint64_t)c->ncu);
+}
+
 template <int MODE, typename V>
 void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
                    uint64_t* ok, void* ov)
@@ -259,12 +274,16 @@ void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_
         if (njobs[2]) hipLaunchKernelGGL((k_base_less<V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv);
         if (njobs[3]) hipLaunchKernelGGL((k_base_less<V, 8>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv);
     } else {
+        uint64_t* sink = (uint64_t*)c->sink.p;
         if (njobs[0])
-            hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv, info);
+            hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(base_grid<MODE, V, 1>(c, njobs[0])), dim3(64), 0, c->stream,
+                               jobs, njobs[0], sk, svv, ok, ovv, sink, info);
         if (njobs[1])
-            hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, j1, sk, svv, ok, ovv, info);
+            hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(base_grid<MODE, V, 2>(c, njobs[1])), dim3(128), 0, c->stream,
+                               j1, njobs[1], sk, svv, ok, ovv, sink, info);
         if (njobs[2])
-            hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv, info);
+            hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(base_grid<MODE, V, 4>(c, njobs[2])), dim3(256), 0, c->stream,
+                               j2, njobs[2], sk, svv, ok, ovv, sink, info);
         if (njobs[3])
             hipLaunchKernelGGL((k_base_2pass<MODE, V>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv,
                                info);
@@ -912,6 +931,8 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
     if (!c) return SS_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu < 1)
+        c->ncu = 1;
     if (hipHostMalloc((void**)&c->info_host, sizeof(LevelInfo), hipHostMallocDefault) != hipSuccess) {
         delete c;
         return SS_EHIP;

@@ -1924,117 +1924,150 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
 // Values never touch LDS; results are written straight from registers.
 
 template <int MODE, typename V, int W>
-__global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                                 uint64_t* out_keys, V* out_vals, LevelInfo* info)
+__global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, uint32_t njobs, const uint64_t* src_keys,
+                                                 const V* src_vals, uint64_t* out_keys, V* out_vals,
+                                                 uint64_t* sink, LevelInfo* info)
 {
+    // Persistent: the grid holds as many blocks as fit on the device, each
+    // takes every gridDim.x-th job, and the next job's records are loaded
+    // into registers while the current one is refined.  Loads (clamped) and
+    // stores (a sink for lanes without a record) are issued unconditionally,
+    // so waiting for the prefetched records does not wait for the stores.
     constexpr int BS = W * 64, E = 8, CAP = BS * E;
     __shared__ uint64_t kl[CAP];
     __shared__ uint32_t tab[2 * CAP];  // slot owners; reused for digit starts
     __shared__ uint16_t wc[W * CAP];
     __shared__ uint32_t tmp[8 * 16 + 8];
 
-    const Job j = jobs[blockIdx.x];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
-    const uint32_t m = j.len;  // 2 .. CAP
-    const uint64_t start = j.start;
-    const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
-    const uint32_t slots = 1u << lg, smask = slots - 1;
-    const uint32_t nbits = ceil_log2_u32(m);
-
-    uint64_t k[E];
-    V v[E];
+    const uint32_t lofs = w * 64 * E + lane;
+    uint64_t* sink_k = sink + lane;
+    V* sink_v = (V*)(sink + lane);
+    uint32_t jb = blockIdx.x;
+    if (jb >= njobs) return;
+    Job jn = jobs[jb];
+    uint64_t kn[E];
+    V vn[E];
+    auto fetch = [&](const Job& jj) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        k[e] = i < m ? src_keys[start + i] : 0ull;
-        v[e] = i < m ? src_vals[start + i] : (V)0;
-    }
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        if (i < m) kl[i] = k[e];
-    }
-    for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
-    for (uint32_t i = tid; i < (uint32_t)(W * CAP) / 2; i += BS) ((uint32_t*)wc)[i] = 0;
-    __syncthreads();
-
-    uint32_t sl[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        sl[e] = 0;
-        if (i < m) {
-            uint32_t s = fib_slot(user_hash<MODE>(k[e]), lg);
-            while (true) {
-                uint32_t o = tab[s];
-                if (o == kEmpty32) {
-                    o = atomicCAS(&tab[s], kEmpty32, i);
-                    if (o == kEmpty32) break;
-                }
-                if (kl[o] == k[e]) break;
-                s = (s + 1) & smask;
-            }
-            sl[e] = s;
+        for (int e = 0; e < E; ++e) {
+            const uint32_t i = min(lofs + e * 64u, jj.len - 1);  // len >= 2
+            kn[e] = src_keys[jj.start + i];
+            vn[e] = src_vals[jj.start + i];
         }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        if (i < m) atomicMin(&tab[sl[e]], i);
-    }
-    __syncthreads();
-    uint32_t f[E], rk[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) f[e] = tab[sl[e]];
-    uint16_t* wcw = wc + w * CAP;
-    {
-        bool ok[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) ok[e] = w * 64 * E + e * 64 + lane < m;
-        wave_rank_all<E, ilog2_c(CAP)>(f, ok, nbits, wcw, rk);
-    }
-    __syncthreads();
-    // per digit: prefix over waves, total; exclusive scan of the totals over
-    // the m digits.  Digit d = e*BS + tid belongs to thread tid, so that
-    // neighbouring lanes touch neighbouring counters (no bank conflicts).
-    uint32_t* dstart = tab;  // the table is no longer needed
-    uint32_t tot[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t d = e * BS + tid;
-        uint32_t run = 0;
-        if (d < m) {
-#pragma unroll
-            for (int ww = 0; ww < W; ++ww) {
-                const uint32_t c = wc[ww * CAP + d];
-                wc[ww * CAP + d] = (uint16_t)run;
-                run += c;
-            }
-        }
-        tot[e] = run;
-    }
-    uint32_t ex[E];
-    block_excl_scan_rows<BS, E>(tot, ex, tmp);
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t d = e * BS + tid;
-        if (d < m) dstart[d] = ex[e];
-    }
-    __syncthreads();
+    };
+    fetch(jn);
     bool bad = false;
+    for (; jb < njobs; jb += gridDim.x) {
+        const Job j = jn;
+        uint64_t k[E];
+        V v[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const uint32_t i = w * 64 * E + e * 64 + lane;
-        if (i < m) {
-            const uint32_t p = dstart[f[e]] + wc[w * CAP + f[e]] + rk[e];
-            if (p < m) {
-                out_keys[start + p] = k[e];
-                out_vals[start + p] = v[e];
-            } else {
-                bad = true;
+        for (int e = 0; e < E; ++e) {
+            k[e] = kn[e];
+            v[e] = vn[e];
+        }
+        // the next job (the last one re-reads itself)
+        const uint32_t nx = jb + gridDim.x < njobs ? jb + gridDim.x : jb;
+        jn = jobs[nx];
+        fetch(jn);
+
+        const uint32_t m = j.len;  // 2 .. CAP
+        const uint64_t start = j.start;
+        const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
+        const uint32_t slots = 1u << lg, smask = slots - 1;
+        const uint32_t nbits = ceil_log2_u32(m);
+
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t i = lofs + e * 64u;
+            if (i < m) kl[i] = k[e];
+        }
+        for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
+        for (uint32_t i = tid; i < (uint32_t)(W * CAP) / 2; i += BS) ((uint32_t*)wc)[i] = 0;
+        __syncthreads();
+
+        // Insertion: a compare-and-swap claims an empty slot or returns its
+        // owner in one LDS round trip.  The slot comes from the key itself
+        // (Fibonacci hashing of the folded key): a bucket's keys agree only
+        // in bits of their mixed hash, not in bits of the key.
+        uint32_t sl[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t i = lofs + e * 64u;
+            sl[e] = 0;
+            if (i < m) {
+                uint32_t s = fib_slot(k[e], lg);
+                while (true) {
+                    const uint32_t o = atomicCAS(&tab[s], kEmpty32, i);
+                    if (o == kEmpty32 || kl[o] == k[e]) break;
+                    s = (s + 1) & smask;
+                }
+                sl[e] = s;
             }
         }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t i = lofs + e * 64u;
+            if (i < m) atomicMin(&tab[sl[e]], i);
+        }
+        __syncthreads();
+        uint32_t f[E], rk[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) f[e] = tab[sl[e]];
+        uint16_t* wcw = wc + w * CAP;
+        {
+            bool ok[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) ok[e] = lofs + e * 64u < m;
+            wave_rank_all<E, ilog2_c(CAP)>(f, ok, nbits, wcw, rk);
+        }
+        __syncthreads();
+        // per digit: prefix over waves, total; exclusive scan of the totals
+        // over the m digits.  Digit d = e*BS + tid belongs to thread tid, so
+        // that neighbouring lanes touch neighbouring counters (no bank
+        // conflicts).
+        uint32_t* dstart = tab;  // the table is no longer needed
+        uint32_t tot[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t d = e * BS + tid;
+            uint32_t run = 0;
+            if (d < m) {
+#pragma unroll
+                for (int ww = 0; ww < W; ++ww) {
+                    const uint32_t c = wc[ww * CAP + d];
+                    wc[ww * CAP + d] = (uint16_t)run;
+                    run += c;
+                }
+            }
+            tot[e] = run;
+        }
+        uint32_t ex[E];
+        block_excl_scan_rows<BS, E>(tot, ex, tmp);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t d = e * BS + tid;
+            if (d < m) dstart[d] = ex[e];
+        }
+        __syncthreads();
+        uint32_t pp[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const uint32_t i = lofs + e * 64u;
+            const uint32_t fe = i < m ? f[e] : 0u;
+            const uint32_t p = dstart[fe] + wc[w * CAP + fe] + rk[e];
+            bad |= i < m && p >= m;
+            pp[e] = (i < m && p < m) ? p : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const bool ok = pp[e] != 0xFFFFFFFFu;
+            *(ok ? out_keys + start + pp[e] : sink_k) = k[e];
+            *(ok ? out_vals + start + pp[e] : sink_v) = v[e];
+        }
+        __syncthreads();  // the next job reuses the LDS
     }
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
 }
