@@ -65,7 +65,8 @@ typedef struct {
     uint32_t sample_mult;  /* c in |S| = ceil(c ln n') (1..4096; default 800, the paper uses 500);
                               |S| <= min(n'/8, 16384) */
     uint32_t tile_min;     /* smallest subarray size l in records (power of two, 8192..65536) */
-    uint32_t tile_max;     /* largest subarray size l (power of two, tile_min..65536; default 65536) */
+    uint32_t tile_max;     /* largest subarray size l (power of two, tile_min..65536; default 0: for
+                              semisort_= 32768 on the first level and 16384 below, else 65536) */
     uint32_t hash_mode;    /* ss_hash_mode */
     uint32_t heavy_min;    /* tau: a key sampled at least tau times is heavy (default 3; 0 = ceil(ln n'),
                               the paper's rule).  At most 512 keys per subproblem are heavy: if more
@@ -99,7 +100,10 @@ ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
  * ceil((c / div) ln n').  SS_OPT_NL_TARGET (10..100, default 50): the number of
  * light buckets of a subproblem is chosen so that light buckets hold about
  * base_case * target / 100 records. */
-enum { SS_OPT_DIST_VARIANT = 1, SS_OPT_DEEP_SAMPLE_DIV = 2, SS_OPT_NL_TARGET = 3 };
+/* SS_OPT_TILE0 / SS_OPT_TILE_DEEP (0 or a power of two in [8192, 65536],
+ * default 0): the largest subarray of the first level / of the deeper levels,
+ * overriding tile_max of the call's parameters (0: tile_max applies). */
+enum { SS_OPT_DIST_VARIANT = 1, SS_OPT_DEEP_SAMPLE_DIV = 2, SS_OPT_NL_TARGET = 3, SS_OPT_TILE0 = 4, SS_OPT_TILE_DEEP = 5 };
 ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
 
 /* Kernel timing.  While enabled, every kernel launch of the engine is

@@ -132,6 +132,8 @@ class Context:
     OPT_DIST_VARIANT = 1
     OPT_DEEP_SAMPLE_DIV = 2
     OPT_NL_TARGET = 3
+    OPT_TILE0 = 4
+    OPT_TILE_DEEP = 5
 
     def sync(self):
         """Wait for the context's stream; raises SemisortError for a device

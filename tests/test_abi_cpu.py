@@ -35,7 +35,7 @@ def test_default_params():
     _lib_or_skip()
     p = S.default_params()
     assert (p.n_light_log2, p.base_case, p.sample_mult, p.heavy_min) == (10, 4096, 800, 3)
-    assert p.tile_min == 8192 and p.tile_max == 65536 and p.hash_mode == S.HASH_MIX64
+    assert p.tile_min == 8192 and p.tile_max == 0 and p.hash_mode == S.HASH_MIX64
 
 
 def test_null_context_is_rejected():
