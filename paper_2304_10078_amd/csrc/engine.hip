@@ -786,7 +786,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
     if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
     if ((s = ensure(c, c->t_vals, n * 8)) != SS_OK) return s;
     if ((s = ensure(c, c->rflag, nblk * kFlagBlock)) != SS_OK) return s;
-    if ((s = ensure(c, c->bcnt, nchunk * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->bcnt, (nchunk + nblk) * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
     if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
@@ -864,12 +864,15 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
     }
     {
         ProfScope ps(c, SS_PROF_COMPACT, n);
-        hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf,
-                           (uint32_t*)c->bcnt.p);
-        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, (uint32_t*)c->bcnt.p, (uint32_t)nchunk,
+        uint32_t* ccnt = (uint32_t*)c->bcnt.p;  // per chunk, then per block
+        uint32_t* btot = ccnt + nchunk;
+        hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf, ccnt,
+                           btot);
+        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, btot, (uint32_t)nblk,
                            (unsigned long long*)c->mdev.p);
         hipLaunchKernelGGL(k_flag_scatter, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf,
-                           (const uint32_t*)c->bcnt.p, (const uint64_t*)T_k, (const uint64_t*)T_v, out_keys, out_vals);
+                           (const uint32_t*)ccnt, (const uint32_t*)btot, n, (const uint64_t*)T_k, (const uint64_t*)T_v,
+                           out_keys, out_vals);
     }
     HIP_OR_FAIL(c, hipGetLastError());
     HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));

@@ -2544,10 +2544,12 @@ __device__ __forceinline__ uint32_t wave_excl_sum(uint32_t v, uint32_t* total)
     return x - v;
 }
 
-// Results per chunk.
-__global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint32_t* ccnt)
+// Results per chunk (one wave per chunk), and per block of 16 chunks.
+__global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint32_t* ccnt, uint32_t* btot)
 {
-    const uint32_t chunk = blockIdx.x * 16 + (threadIdx.x >> 6);
+    __shared__ uint32_t wt[16];
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t chunk = blockIdx.x * 16 + w;
     const uint32_t lane = threadIdx.x & 63u;
     const uint64_t* f = (const uint64_t*)(rflag + (size_t)chunk * kFlagChunk) + lane * 8;
     uint32_t c = 0;
@@ -2555,52 +2557,112 @@ __global__ __launch_bounds__(1024) void k_flag_count(const uint8_t* rflag, uint3
     for (int q = 0; q < 8; ++q) c += __popcll(f[q]);
     uint32_t tot = 0;
     (void)wave_excl_sum(c, &tot);
-    if (lane == 0) ccnt[chunk] = tot;
+    if (lane == 0) {
+        ccnt[chunk] = tot;
+        wt[w] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) t += wt[q];
+        btot[blockIdx.x] = t;
+    }
 }
 
-// Exclusive scan of the chunk counts in place (one block, contiguous runs of
-// chunks per thread); m to *m_out.
-__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* ccnt, uint32_t nchunk, unsigned long long* m_out)
+// Exclusive scan of the block totals in place (one block, contiguous runs per
+// thread); m to *m_out.
+__global__ __launch_bounds__(1024) void k_flag_scan(uint32_t* btot, uint32_t nblk, unsigned long long* m_out)
 {
     __shared__ uint32_t tmp[20];
-    const uint32_t per = (nchunk + 1023) / 1024;
+    const uint32_t per = (nblk + 1023) / 1024;
     const uint32_t c0 = threadIdx.x * per;
-    const uint32_t c1 = c0 + per < nchunk ? c0 + per : nchunk;
+    const uint32_t c1 = c0 + per < nblk ? c0 + per : nblk;
     uint32_t s = 0;
-    for (uint32_t c = c0; c < c1; ++c) s += ccnt[c];
+    for (uint32_t c = c0; c < c1; ++c) s += btot[c];
     uint32_t tot = 0;
     uint32_t run = block_excl_scan<1024>(s, tmp, &tot);
     for (uint32_t c = c0; c < c1; ++c) {
-        const uint32_t x = ccnt[c];
-        ccnt[c] = run;
+        const uint32_t x = btot[c];
+        btot[c] = run;
         run += x;
     }
     if (threadIdx.x == 0) *m_out = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, const uint32_t* cofs,
+// One wave per chunk; its offset is the block's (scanned) plus the counts of
+// the block's earlier chunks.  Four rounds of 256 positions at a time, each
+// lane owning 4 neighbouring positions: where a group holds at least 1/8
+// results, keys and values of all its positions are read with 16-byte loads
+// issued together (whole lines, no dependent gathers); sparser groups (and
+// the groups at the end of the array) gather only the flagged positions.
+__global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, const uint32_t* ccnt,
+                                                       const uint32_t* boff, uint64_t n,
                                                        const uint64_t* res_keys, const uint64_t* res_vals,
                                                        uint64_t* out_keys, uint64_t* out_vals)
 {
-    const uint32_t chunk = blockIdx.x * 16 + (threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63u;
+    constexpr int R = 4;
+    __shared__ uint32_t sc[16];
+    const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t chunk = blockIdx.x * 16 + w;
+    if (threadIdx.x < 16) sc[threadIdx.x] = ccnt[blockIdx.x * 16 + threadIdx.x];
+    __syncthreads();
+    uint32_t o = boff[blockIdx.x];
+    for (uint32_t q = 0; q < w; ++q) o += sc[q];
+    if (sc[w] == 0) return;
     const size_t base = (size_t)chunk * kFlagChunk;
-    uint32_t o = cofs[chunk];
-    for (uint32_t r = 0; r < kFlagChunk / 256; ++r) {
-        const size_t p = base + r * 256 + lane * 4;
-        const uint32_t f = *(const uint32_t*)(rflag + p);
-        const uint32_t c = __popc(f);
-        uint32_t tot = 0;
-        uint32_t at = o + wave_excl_sum(c, &tot);
+    for (uint32_t r0 = 0; r0 < kFlagChunk / 256; r0 += R) {
+        uint32_t f[R], at[R];
+        uint32_t gsum = 0;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            if ((f >> (8 * b)) & 1u) {
-                out_keys[at] = res_keys[p + b];
-                out_vals[at] = res_vals[p + b];
-                ++at;
+        for (int r = 0; r < R; ++r) {
+            f[r] = *(const uint32_t*)(rflag + base + (r0 + r) * 256 + lane * 4);
+            uint32_t tot = 0;
+            at[r] = o + wave_excl_sum(__popc(f[r]), &tot);
+            o += tot;
+            gsum += tot;
+        }
+        if (gsum == 0) continue;
+        const size_t g0 = base + r0 * 256;
+        if (gsum >= R * 32 && g0 + R * 256 <= n) {
+            ulonglong2 ka[R], kb[R], va[R], vb[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const size_t p = g0 + r * 256 + lane * 4;
+                ka[r] = *(const ulonglong2*)(res_keys + p);
+                kb[r] = *(const ulonglong2*)(res_keys + p + 2);
+                va[r] = *(const ulonglong2*)(res_vals + p);
+                vb[r] = *(const ulonglong2*)(res_vals + p + 2);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const uint64_t kx[4] = {ka[r].x, ka[r].y, kb[r].x, kb[r].y};
+                const uint64_t vx[4] = {va[r].x, va[r].y, vb[r].x, vb[r].y};
+                uint32_t a = at[r];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if ((f[r] >> (8 * b)) & 1u) {
+                        out_keys[a] = kx[b];
+                        out_vals[a] = vx[b];
+                        ++a;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const size_t p = g0 + r * 256 + lane * 4;
+                uint32_t a = at[r];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if ((f[r] >> (8 * b)) & 1u) {
+                        out_keys[a] = res_keys[p + b];
+                        out_vals[a] = res_vals[p + b];
+                        ++a;
+                    }
+                }
             }
         }
-        o += tot;
     }
 }
 
