@@ -2110,14 +2110,12 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
         const uint32_t i = w * 64 * E + e * 64 + lane;
         sl[e] = 0;
         if (i < m) {
-            uint32_t sx = fib_slot(user_hash<MODE>(k[e]), lg);
+            // one compare-and-swap claims the slot or returns its owner;
+            // Fibonacci hashing of the folded key (as in k_base)
+            uint32_t sx = fib_slot(k[e], lg);
             while (true) {
-                uint32_t o = tab[sx];
-                if (o == kEmpty32) {
-                    o = atomicCAS(&tab[sx], kEmpty32, i);
-                    if (o == kEmpty32) break;
-                }
-                if (kl[o] == k[e]) break;
+                const uint32_t o = atomicCAS(&tab[sx], kEmpty32, i);
+                if (o == kEmpty32 || kl[o] == k[e]) break;
                 sx = (sx + 1) & smask;
             }
             sl[e] = sx;
@@ -2489,14 +2487,12 @@ __global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint
         const uint32_t i = w * 64 * E + e * 64 + lane;
         sl[e] = 0;
         if (i < m) {
-            uint32_t sidx = fib_slot(user_hash<MODE>(k[e]), lg);
+            // one compare-and-swap claims the slot or returns its owner;
+            // Fibonacci hashing of the folded key (as in k_base)
+            uint32_t sidx = fib_slot(k[e], lg);
             while (true) {
-                uint32_t o = tab[sidx];
-                if (o == kEmpty32) {
-                    o = atomicCAS(&tab[sidx], kEmpty32, i);
-                    if (o == kEmpty32) break;
-                }
-                if (kl[o] == k[e]) break;
+                const uint32_t o = atomicCAS(&tab[sidx], kEmpty32, i);
+                if (o == kEmpty32 || kl[o] == k[e]) break;
                 sidx = (sidx + 1) & smask;
             }
             sl[e] = sidx;
