@@ -216,3 +216,23 @@ def test_autotuner_returns_a_grid_point_and_a_correct_result():
     for i in range(48):
         a, b = int(offs[i]), int(offs[i + 1])
         assert_semisort_equal(k[a:b], v[a:b], ko[a:b], vo[a:b], ctx=f"tuned instance {i}")
+
+
+@pytest.mark.parametrize("t0,td", [(8192, 8192), (65536, 65536), (16384, 65536)])
+def test_subarray_limits_do_not_change_the_result(t0, td):
+    """The output of semisort_= depends only on the buckets and the input
+    order, not on how levels are cut into subarrays: every setting of the
+    per-level subarray limits gives the default's bytes."""
+    ctx = S.context(0)
+    try:
+        for name, n in [("zipf1.2_hashed", 1_200_001), ("uniform1e9", 1_500_007)]:
+            k, v = I.np_workload(name, n, 21)
+            ref = run_equal(k, v)
+            ctx.set_option(ctx.OPT_TILE0, t0)
+            ctx.set_option(ctx.OPT_TILE_DEEP, td)
+            _say(f"case: tiles {t0}/{td} {name} n={n}")
+            ko, vo = run_equal(k, v)
+            assert np.array_equal(ko, ref[0]) and np.array_equal(vo, ref[1]), f"{name} tiles {t0}/{td}"
+    finally:
+        ctx.set_option(ctx.OPT_TILE0, 0)
+        ctx.set_option(ctx.OPT_TILE_DEEP, 0)

@@ -98,3 +98,23 @@ def test_batch_and_in_place():
         a, b = int(offs[i]), int(offs[i + 1])
         rk, rv = O.semisort_less(k[a:b], v[a:b])
         assert np.array_equal(ko[a:b], rk) and np.array_equal(vo[a:b], rv), f"instance {i}"
+
+
+def test_boundary_table_cells():
+    """The counting pass finds a key's bucket through a table of logarithmic
+    cells of the key's offset from the smallest boundary: keys spread over
+    all 64 octaves, keys in one narrow range, and two clusters 2^62 apart
+    (most boundaries in a handful of cells, long searches inside a cell)."""
+    rng = np.random.default_rng(9)
+    n = 600_000
+    cases = {
+        "log-uniform": np.floor(2.0 ** (rng.random(n) * 63.99)).astype(np.uint64),
+        "narrow": np.uint64(1 << 50) + rng.integers(0, 1_000_000, n, dtype=np.int64).astype(np.uint64),
+        "two clusters": np.where(rng.random(n) < 0.5,
+                                 rng.integers(0, 100_000, n, dtype=np.int64).astype(np.uint64),
+                                 np.uint64(1 << 62) + rng.integers(0, 100_000, n, dtype=np.int64).astype(np.uint64)),
+    }
+    v = np.arange(n, dtype=np.uint64)
+    for name, k in cases.items():
+        _say(f"case: less cells {name}")
+        check_less(k, v, ctx=name)
