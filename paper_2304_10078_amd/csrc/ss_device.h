@@ -1924,7 +1924,7 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
 // Values never touch LDS; results are written straight from registers.
 
 template <int MODE, typename V, int W>
-__global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, uint32_t njobs, const uint64_t* src_keys,
+__global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
                                                  const V* src_vals, uint64_t* out_keys, V* out_vals,
                                                  uint64_t* sink, LevelInfo* info)
 {
@@ -1967,8 +1967,10 @@ __global__ __launch_bounds__(W * 64) void k_base(const Job* jobs, uint32_t njobs
             k[e] = kn[e];
             v[e] = vn[e];
         }
-        // the next job (the last one re-reads itself)
-        const uint32_t nx = jb + gridDim.x < njobs ? jb + gridDim.x : jb;
+        // the next job (the last one re-reads itself); a wave-uniform index
+        // makes the descriptor a scalar load, whose wait does not drain the
+        // vector memory counter (stores and the prefetch)
+        const uint32_t nx = __builtin_amdgcn_readfirstlane(jb + gridDim.x < njobs ? jb + gridDim.x : jb);
         jn = jobs[nx];
         fetch(jn);
 
