@@ -66,7 +66,8 @@ typedef struct {
                               |S| <= min(n'/8, 16384) */
     uint32_t tile_min;     /* smallest subarray size l in records (power of two, 8192..65536) */
     uint32_t tile_max;     /* largest subarray size l (power of two, tile_min..65536; default 0: for
-                              semisort_= 32768 on the first level and 16384 below, else 65536) */
+                              semisort_= 32768 on the first level and 16384 below, for semisort_<
+                              32768 on the first level and 65536 below, else 65536) */
     uint32_t hash_mode;    /* ss_hash_mode */
     uint32_t heavy_min;    /* tau: a key sampled at least tau times is heavy (default 3; 0 = ceil(ln n'),
                               the paper's rule).  At most 512 keys per subproblem are heavy: if more

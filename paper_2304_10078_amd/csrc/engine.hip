@@ -233,17 +233,19 @@ ss_status resolve_params(ss_ctx* c, const ss_params* in, Params* p)
     return SS_OK;
 }
 
-// semisort_= without an explicit tile_max: subarrays of at most 32768 records
-// at the first level and 16384 below.  Shorter subarrays let neighbouring
-// ones, distributed at the same time on one XCD, complete each other's
-// partially written output lines in L2 (measured on 10^9 records: Zipf-1.2
-// 3% and uniform keys 6% faster than 65536 throughout); the reduction forms
-// and semisort_< keep 65536, where the larger counting matrix costs more.
-void equal_tiles(const ss_ctx* c, const ss_params* in, Params* p)
+// Subarray limits when the call leaves tile_max at 0: semisort_= uses at most
+// 32768 records on the first level and 16384 below, semisort_< 32768 on the
+// first level and 65536 below.  Shorter subarrays let neighbouring ones,
+// distributed at the same time on one XCD, complete each other's partially
+// written output lines in L2 (measured on 10^9 records against 65536
+// throughout: semisort_= Zipf-1.2 3% and uniform keys 6% faster, semisort_<
+// 2%); the reduction forms keep 65536, where heavy sums are added once per
+// subarray and more subarrays cost more.
+void default_tiles(const ss_ctx* c, const ss_params* in, Params* p, uint32_t first, uint32_t deeper)
 {
     if (in && in->tile_max) return;
-    if (!c->tile0) p->tmax0 = std::max(p->tmin, std::min(p->tmax, 32768u));
-    if (!c->tile_deep) p->tmaxd = std::max(p->tmin, std::min(p->tmax, 16384u));
+    if (!c->tile0) p->tmax0 = std::max(p->tmin, std::min(p->tmax, first));
+    if (!c->tile_deep) p->tmaxd = std::max(p->tmin, std::min(p->tmax, deeper));
 }
 
 bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
@@ -1088,7 +1090,7 @@ ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, u
     if (s != SS_OK || n == 0) return s;
     Params p;
     if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
-    equal_tiles(c, params, &p);
+    default_tiles(c, params, &p, 32768u, 16384u);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     const uint64_t offs[2] = {0, n};
     return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
@@ -1202,6 +1204,7 @@ ss_status ss_semisort_less(ss_ctx* c, const uint64_t* keys, const void* vals, ui
     Params p;
     if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
     p.mode = 2;
+    default_tiles(c, params, &p, 32768u, 65536u);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     const uint64_t offs[2] = {0, n};
     return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
