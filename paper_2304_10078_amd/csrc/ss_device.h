@@ -87,6 +87,8 @@ struct LevelInfo {
     unsigned long long records;      // records in the next level's subproblems
     unsigned long long job_records;  // records covered by this level's jobs
     unsigned long long fill_records; // records whose keys this level's fill jobs write
+    uint32_t smp_total;              // sample size of subproblem 0 of the last sampled level
+    uint32_t smp_heavy;              // of those, samples of heavy keys
 };
 
 struct LevelArgs {
@@ -807,6 +809,10 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
         a.segs[sid].hlog2 = (uint16_t)hfield;
         a.segs[sid].nl_bits = (uint8_t)sh_nl;
         a.segs[sid].nbk = (uint16_t)(nL + nh);
+        if (sid == 0) {
+            a.info->smp_total = s;
+            a.info->smp_heavy = sh_hs;
+        }
     }
 }
 
