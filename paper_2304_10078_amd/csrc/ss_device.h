@@ -1597,7 +1597,6 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     __shared__ uint32_t gbase[kNbStride];      // bit 31: bucket goes to fin_*
     __shared__ uint32_t ptot[kNbStride];       // previous sub-tile's bucket totals
     __shared__ uint16_t wc[2][W * kNbStride];
-    __shared__ uint32_t tmp[20];
 
     const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
@@ -1609,7 +1608,6 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(WPE))) v
     const uint64_t send = (uint64_t)sg.start + sg.len;
     const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
     const uint64_t rlast = r1 - 1;
-    const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = sg.nbk;
     const uint32_t nbits = 32 - __clz(nb - 1);
     const bool split = a.fin_keys != a.dst_keys;
