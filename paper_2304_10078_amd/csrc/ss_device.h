@@ -1417,21 +1417,30 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     V* sink_v = (V*)(a.sink + lane);
     const uint64_t kdiff = (uint64_t)a.fin_keys - (uint64_t)a.dst_keys;
     const uint64_t vdiff = (uint64_t)fin_vals - (uint64_t)dst_vals;
+    // Keys are not needed for records of one-key buckets whose keys k_fill
+    // writes, nor for the heavy records of the reduction forms (they stay):
+    // their key loads read a sink line (an L2 hit) instead of the input, so
+    // key loads wait for the bucket ids, which are loaded first.
+    auto skip_key = [&](uint32_t b) -> bool {
+        if constexpr (RED != 0) return finl[b] != 0;
+        else return fillk && finl[b] != 0;
+    };
     uint64_t kn[E];
     uint16_t bn[E];
     {
-        const uint64_t* ks = a.src_keys + r0;
         const uint16_t* bs = a.bids + r0;
         const uint32_t lim = (uint32_t)(rlast - r0 < SUB ? rlast - r0 : SUB);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const uint32_t o = min(lofs + e * 64u, lim);
-            kn[e] = ks[o];
-            bn[e] = bs[o];
-        }
+        for (int e = 0; e < E; ++e) bn[e] = bs[min(lofs + e * 64u, lim)];
     }
     if (tid == 0) sh_bad = 0;
     __syncthreads();
+    {
+        const uint64_t* ks = a.src_keys + r0;
+        const uint32_t lim = (uint32_t)(rlast - r0 < SUB ? rlast - r0 : SUB);
+#pragma unroll
+        for (int e = 0; e < E; ++e) kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + e * 64u, lim));
+    }
 
     bool out_of_range = false;
     for (uint64_t sub = r0; sub < r1; sub += SUB) {
@@ -1454,15 +1463,11 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             bk[e] = bn[e];
         }
         {
-            // next sub-tile (the last iteration re-reads its own, clamped)
-            const uint64_t* ks = a.src_keys + sub;
+            // bucket ids of the next sub-tile (the last iteration re-reads its
+            // own, clamped); its keys are loaded once these have arrived
             const uint16_t* bs = a.bids + sub;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const uint32_t o = min(lofs + SUB + e * 64u, left - 1);
-                kn[e] = ks[o];
-                bn[e] = bs[o];
-            }
+            for (int e = 0; e < E; ++e) bn[e] = bs[min(lofs + SUB + e * 64u, left - 1)];
         }
         uint16_t* wcw = wc + w * nb;
         bool mv[E];  // this record moves (heavy records of collect-reduce stay)
@@ -1477,6 +1482,12 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
             }
         }
         wave_rank_all<E>(bk, mv, nbits, wcw, pos);
+        {
+            const uint64_t* ks = a.src_keys + sub;
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + SUB + e * 64u, left - 1));
+        }
         __syncthreads();
 
         // per bucket: exclusive prefix over waves, sub-tile total, and the
