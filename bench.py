@@ -63,13 +63,15 @@ def other_configs(args, S, I, torch):
     and Zipf-1.2 (u64 keys and values), semisort_< and histogram on
     exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values).  Whole-job
     HBM fraction from the algorithmic bytes per record: semisort K + 2R +
-    2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; histogram 2K + 2K f_L +
-    16 m/n, with f_H the records whose key occurs more than 500 ln n times."""
+    2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; ordered histogram 2K +
+    2K f_L + 16 m/n + 32 m/n (the m pairs read and written once more to order
+    them), with f_H the records whose key occurs more than 500 ln n times."""
     n = 10 ** 9
     res = {}
     cases = [("uniform1e9", ("semisort_=", "collect_reduce")), ("uniform1e3", ("semisort_=", "collect_reduce")),
              ("zipf1.2_hashed", ("collect_reduce",)),
-             ("exp1e-5_u32idx", ("semisort_<", "histogram")), ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram"))]
+             ("exp1e-5_u32idx", ("semisort_<", "histogram_ordered")),
+             ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram_ordered"))]
     for wl, ops in cases:
         keys, vals = I.t_workload(wl, n, 4, "cuda")
         _, counts = torch.unique(keys, return_counts=True)
@@ -90,8 +92,9 @@ def other_configs(args, S, I, torch):
                 fn = lambda: S.collect_reduce(keys, v64)  # noqa: E731
                 b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
             else:
-                fn = lambda: S.histogram(keys)  # noqa: E731
-                b = 16 + 16 * (1 - f_h) + 16.0 * m / n
+                # these workloads need groups in ascending key order
+                fn = lambda: S.histogram(keys, ordered=True)  # noqa: E731
+                b = 16 + 16 * (1 - f_h) + 16.0 * m / n + 32.0 * m / n
             fn()
             S.sync()
             t0 = time.perf_counter()

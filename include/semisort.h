@@ -220,6 +220,19 @@ ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* v
 ss_status ss_histogram(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
                        uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
 
+/* Ordered forms: the same m pairs as ss_collect_reduce / ss_histogram, in
+ * ascending key order (the order that semisort_< gives the groups, Section 3.4;
+ * the sorted output of a group-by).  The unordered call runs first, then its
+ * m pairs are sorted in place by the semisort_< path, so the extra work is
+ * proportional to m, not n; params apply to both parts (hash_mode to the
+ * first only).  Same arguments, conventions and errors as the unordered
+ * calls; the call waits for its stream before returning. */
+ss_status ss_collect_reduce_ordered(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals,
+                                    uint64_t n, uint64_t* out_keys, uint64_t* out_sums,
+                                    uint64_t* m_out, const ss_params* params);
+ss_status ss_histogram_ordered(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
+                               uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
+
 /* ---- serving (continuous batching of group-by requests) ----------------
  *
  * A server owns `lanes` worker threads, each driving its own context on its

@@ -964,6 +964,26 @@ ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t v
     return SS_OK;
 }
 
+// Puts the m (key, result) pairs of a reduction into ascending key order: a
+// semisort_< of the pairs in place (the keys are distinct, so its stable
+// order is the sorted order), then a wait so the call keeps the reductions'
+// convention of returning with its results ready.
+ss_status order_results(ss_ctx* c, uint64_t* ok, uint64_t* ov, uint64_t m, const ss_params* params)
+{
+    if (m < 2) return SS_OK;
+    Params p;
+    ss_status s = resolve_params(c, params, &p);
+    if (s != SS_OK) return s;
+    p.mode = 2;
+    default_tiles(c, params, &p, 32768u, 65536u);
+    const uint64_t offs[2] = {0, m};
+    if ((s = run_semisort<uint64_t>(c, ok, ov, offs, 1, ok, ov, p)) != SS_OK) return s;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->info_host->status) return status_failure(c, c->info_host->status, "in ordering the results");
+    return SS_OK;
+}
+
 }  // namespace
 
 // ==================================================================== C-ABI
@@ -1343,6 +1363,22 @@ ss_status ss_histogram(ss_ctx* c, const uint64_t* keys, uint64_t n, uint64_t* ou
     if (n == 0) return SS_OK;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     return run_reduce<2>(c, keys, nullptr, n, out_keys, out_counts, m_out, p);
+}
+
+ss_status ss_collect_reduce_ordered(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                                    uint64_t* out_keys, uint64_t* out_sums, uint64_t* m_out, const ss_params* params)
+{
+    ss_status s = ss_collect_reduce(c, keys, vals, n, out_keys, out_sums, m_out, params);
+    if (s != SS_OK) return s;
+    return order_results(c, out_keys, out_sums, *m_out, params);
+}
+
+ss_status ss_histogram_ordered(ss_ctx* c, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
+                               uint64_t* out_counts, uint64_t* m_out, const ss_params* params)
+{
+    ss_status s = ss_histogram(c, keys, n, out_keys, out_counts, m_out, params);
+    if (s != SS_OK) return s;
+    return order_results(c, out_keys, out_counts, *m_out, params);
 }
 
 }  // extern "C"

@@ -80,6 +80,8 @@ def lib():
         L.ss_autotune_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, u32, P,
                                               ctypes.POINTER(ctypes.c_double)]
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
+        L.ss_collect_reduce_ordered.argtypes = L.ss_collect_reduce.argtypes
+        L.ss_histogram_ordered.argtypes = L.ss_histogram.argtypes
         for name in declared_symbols():
             if name != "ss_last_error":
                 getattr(L, name).restype = ctypes.c_int
@@ -285,8 +287,9 @@ def _check_keys(keys, name="keys"):
         raise ValueError(f"{name} must be a contiguous 1-D int64 device tensor (uint64 bits)")
 
 
-def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None):
-    """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values).
+def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False):
+    """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values);
+    ss_collect_reduce_ordered with ordered=True (keys ascending as uint64).
 
     Returns views of length m of the two output tensors (capacity n each)."""
     import torch
@@ -301,13 +304,15 @@ def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=No
     if out_sums is None:
         out_sums = torch.empty_like(keys)
     m = ctypes.c_uint64()
-    ctx.check(lib().ss_collect_reduce(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(out_keys), _ptr(out_sums),
-                                      ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    fn = lib().ss_collect_reduce_ordered if ordered else lib().ss_collect_reduce
+    ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(out_keys), _ptr(out_sums),
+                 ctypes.byref(m), ctypes.byref(params) if params is not None else None))
     return out_keys[:m.value], out_sums[:m.value]
 
 
-def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None):
-    """ss_histogram: (unique keys, occurrence counts) as views of length m."""
+def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None, ordered=False):
+    """ss_histogram: (unique keys, occurrence counts) as views of length m;
+    ss_histogram_ordered with ordered=True (keys ascending as uint64)."""
     import torch
     _check_keys(keys)
     ctx = ctx or context(keys.device.index or 0)
@@ -317,8 +322,9 @@ def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None):
     if out_counts is None:
         out_counts = torch.empty_like(keys)
     m = ctypes.c_uint64()
-    ctx.check(lib().ss_histogram(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
-                                 ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    fn = lib().ss_histogram_ordered if ordered else lib().ss_histogram
+    ctx.check(fn(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
+                 ctypes.byref(m), ctypes.byref(params) if params is not None else None))
     return out_keys[:m.value], out_counts[:m.value]
 
 

@@ -19,6 +19,7 @@ def test_header_declares_the_boundary():
     names = S.declared_symbols()
     for want in ["ss_create", "ss_destroy", "ss_semisort_equal", "ss_semisort_equal_batch",
                  "ss_semisort_less", "ss_semisort_less_batch", "ss_collect_reduce", "ss_histogram",
+                 "ss_collect_reduce_ordered", "ss_histogram_ordered",
                  "ss_autotune_equal_batch", "ss_server_create", "ss_server_submit", "ss_server_poll",
                  "ss_server_drain", "ss_server_stats", "ss_server_destroy", "ss_server_now",
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync"]:
@@ -45,6 +46,8 @@ def test_null_context_is_rejected():
     m = ctypes.c_uint64(7)
     assert L.ss_collect_reduce(None, None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_histogram(None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
+    assert L.ss_collect_reduce_ordered(None, None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
+    assert L.ss_histogram_ordered(None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_destroy(None) == S.SS_EINVAL
     assert L.ss_sync(None) == S.SS_EINVAL
     assert L.ss_last_error(None) == b"null context"

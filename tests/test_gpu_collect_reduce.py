@@ -1,7 +1,8 @@
 """GPU parity for collect-reduce and histogram (Section 3.5): the HIP path
-(through the C-ABI) against the CPU oracle.  The GPU returns the m pairs in
-an unspecified order, so both sides are compared after sorting by key; keys
-are unique on both sides, so the sorted pairs must match exactly."""
+(through the C-ABI) against the CPU oracle.  The unordered calls return the
+m pairs in an unspecified order, so both sides are compared after sorting by
+key; keys are unique on both sides, so the sorted pairs must match exactly.
+The ordered calls must match the oracle's ascending pairs as they stand."""
 import sys
 
 import numpy as np
@@ -154,3 +155,55 @@ def test_histogram_after_semisort_on_one_context_reuses_workspace():
         ko, vo = S.semisort_equal(to_dev(k), to_dev(v), ctx=ctx)
         check_hist(k, ctx="mixed hist")
         check_cr(k, v, ctx="mixed CR")
+
+
+def check_ordered(keys, vals=None, params=None, ctx=""):
+    """The ordered forms against the oracle, element by element (the oracle
+    emits keys ascending as uint64; the pairs are unique)."""
+    if vals is None:
+        gk, gv = S.histogram(to_dev(keys), params=params, ordered=True)
+        rk, rv = O.histogram(keys)
+    else:
+        gk, gv = S.collect_reduce(to_dev(keys), to_dev(vals), params=params, ordered=True)
+        rk, rv = O.collect_reduce(keys, vals)
+    S.sync()
+    gk, gv = to_host(gk, np.uint64), to_host(gv, np.uint64)
+    assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"
+    if not np.array_equal(gk, rk):
+        i = int(np.nonzero(gk != rk)[0][0])
+        raise AssertionError(f"{ctx}: key {i} is {gk[i]}, oracle {rk[i]}")
+    assert np.array_equal(gv, rv), f"{ctx}: results differ"
+
+
+@pytest.mark.parametrize("name,n", [("exp1e-5_u32idx", 1_500_000), ("zipf0.8_1e8_u32idx", 1_200_000),
+                                    ("zipf1.2_hashed", 700_001), ("uniform1e9", 900_000)])
+def test_ordered_results_paper_distributions(name, n):
+    k, v = I.np_workload(name, n, 23)
+    v = v.astype(np.uint64)
+    _say(f"case: ordered hist/CR {name} n={n}")
+    check_ordered(k, ctx=f"ordered hist {name}")
+    check_ordered(k, v, ctx=f"ordered CR {name}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 4097, 65537, 300001])
+def test_ordered_results_ragged_and_unsigned_order(n):
+    rng = np.random.default_rng(n + 7)
+    # keys over the whole uint64 range: the order must be unsigned
+    k = rng.integers(0, max(2, n // 3), n, dtype=np.int64).astype(np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    v = rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64)
+    _say(f"case: ordered hist/CR ragged n={n}")
+    check_ordered(k, ctx=f"ordered hist n={n}")
+    check_ordered(k, v, ctx=f"ordered CR n={n}")
+    same = np.full(n, 5, dtype=np.uint64)
+    check_ordered(same, v, ctx=f"ordered CR one key n={n}")
+
+
+def test_ordered_results_empty_and_small_parameters():
+    e = torch.empty(0, dtype=torch.int64, device="cuda")
+    gk, gc = S.histogram(e, ordered=True)
+    assert gk.numel() == 0 and gc.numel() == 0
+    rng = np.random.default_rng(11)
+    k = rng.integers(0, 30_000, 120_000, dtype=np.int64).astype(np.uint64)
+    p = S.default_params(n_light_log2=2, base_case=256, sample_mult=20, tile_min=8192, tile_max=8192)
+    _say("case: ordered histogram, small parameters")
+    check_ordered(k, params=p, ctx="ordered hist small params")

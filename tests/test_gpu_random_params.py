@@ -93,3 +93,8 @@ def test_random_shapes_and_parameters(case):
     o = np.argsort(gk, kind="stable")
     rk, rc = O.histogram(k)
     assert np.array_equal(gk[o], rk) and np.array_equal(gc[o], rc), f"case {case} histogram"
+
+    gk, gc = S.histogram(to_dev(k), params=p, ordered=True)
+    S.sync()
+    assert np.array_equal(to_host(gk, np.uint64), rk), f"case {case} ordered histogram keys"
+    assert np.array_equal(to_host(gc, np.uint64), rc), f"case {case} ordered histogram counts"
