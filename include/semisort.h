@@ -154,6 +154,41 @@ ss_status ss_semisort_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void*
                                   uint64_t nseg, uint64_t* keys_out, void* vals_out,
                                   const ss_params* params);
 
+/* Batched semisort_= sized entirely on the device, for callers that record
+ * the call into a HIP graph (stream capture) and replay it.  Same result as
+ * ss_semisort_equal_batch (each instance's result is the one
+ * ss_semisort_equal gives for it alone), but:
+ * - seg_offsets is a DEVICE array of nseg+1 uint64 (non-decreasing,
+ *   seg_offsets[0] = 0, seg_offsets[nseg] = n) and n is passed by the caller;
+ *   offsets that break this raise a device condition (SS_EDEVICE at ss_sync).
+ * - The host never waits: the first level is planned by a kernel from the
+ *   offsets, and every later level's kernels run as resident grids that read
+ *   the level's subproblem, subarray and job counts from device memory, where
+ *   the previous level's planning put them (the per-level syncs of the other
+ *   entry points size launches instead).  Exactly max_levels levels of
+ *   launches are enqueued (1..64); subproblems still left after them raise a
+ *   device condition, reported by ss_sync.  Levels with no work cost a few
+ *   microseconds each.
+ * - Buffers are sized for the worst case of n records and the parameters:
+ *   about (8 + val_bytes + 14) bytes per record plus 51 KB per possible
+ *   subproblem (n / base_case of them).  A call that needs more workspace
+ *   than the context holds allocates it, and therefore must not be under
+ *   stream capture (SS_EINVAL if it is): make one uncaptured call with the
+ *   same n, nseg, val_bytes and params first.  A captured graph keeps the
+ *   workspace addresses of that moment; the context must not grow its
+ *   workspace (a larger call of any kind) while the graph is replayed, and
+ *   calls on the context must not overlap the replays.
+ * - One-key buckets move their keys with the distribution (no key-fill
+ *   stream), and the subarray size follows tile_min/tile_max only.
+ * Supports hash_mode, base_case, n_light_log2, sample_mult, heavy_min, tile_*
+ * and seed like the other calls; in place (keys_out == keys, vals_out ==
+ * vals) is allowed. */
+ss_status ss_semisort_equal_batch_capturable(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                             uint32_t val_bytes, const uint64_t* seg_offsets,
+                                             uint64_t nseg, uint64_t n, uint64_t* keys_out,
+                                             void* vals_out, uint32_t max_levels,
+                                             const ss_params* params);
+
 /* Autotuner for batched semisort_=: runs the batch with every parameter set
  * of a fixed grid around the defaults (sample_mult in {500, 800}, heavy_min in
  * {0, 3}, n_light_log2 in {8, 10}, base_case in {2048, 4096}, tile_max in

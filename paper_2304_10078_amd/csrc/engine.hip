@@ -49,6 +49,7 @@ struct ss_ctx {
     hipEvent_t fill_done[2] = {nullptr, nullptr};
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
+    DevBuf ds_jobs, ds_info;         // device-sized batches: job lists, per-level counts
     std::vector<Seg> host_segs;
     std::vector<Job> host_jobs[kJobClasses];
     uint32_t job_cap = 0;  // entries per class list
@@ -439,6 +440,8 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.res_keys = nullptr;
     a.res_vals = nullptr;
     a.rflag = nullptr;
+    a.dims = nullptr;
+    a.seg_cap = 0;
     return a;
 }
 
@@ -499,7 +502,12 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         pa.next = (Seg*)c->segs[cur ^ 1].p;
         pa.next_cap = *seg_cap;
         pa.jobs = (Job*)c->jobs.p;
-        pa.job_cap = c->job_cap;
+        for (int k = 0; k < kJobClasses; ++k) {
+            pa.job_base[k] = (uint64_t)k * c->job_cap;
+            pa.job_capc[k] = c->job_cap;
+        }
+        pa.dims = nullptr;
+        pa.cur_cap = 0;
         pa.info = (LevelInfo*)c->info.p;
         pa.alpha = p.alpha;
         pa.finals_in_out = finals_in_out;
@@ -752,6 +760,224 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     for (int b = 0; b < 2; ++b)
         if (fill_used[b]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[b], 0));
     guard.armed = false;
+    return SS_OK;
+}
+
+// ---------------------------------------------------------------- device-sized batches
+
+// Resident grid of a device-sized kernel: as many blocks as fit on the device
+// at once (occupancy queried once per kernel), at most `bound`.
+template <auto K>
+uint32_t ds_grid(const ss_ctx* c, int threads, uint64_t bound)
+{
+    static const int per = [threads] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, K, threads, 0) != hipSuccess || b < 1) b = 1;
+        return b;
+    }();
+    const uint64_t g = std::min<uint64_t>(bound, (uint64_t)per * (uint64_t)c->ncu);
+    return (uint32_t)std::max<uint64_t>(g, 1);
+}
+
+// Grows a buffer outside stream capture only: a captured call must find its
+// workspace already sized by an earlier uncaptured call.
+ss_status ensure_ds(ss_ctx* c, DevBuf& b, size_t bytes, bool capturing)
+{
+    if (bytes <= b.cap) return SS_OK;
+    if (capturing)
+        return fail(c, SS_EINVAL, "the workspace must grow, which stream capture does not allow: make one "
+                                  "uncaptured call with the same sizes first");
+    return ensure(c, b, bytes);
+}
+
+// Upper bounds of one device-sized level over n records: subproblems hold at
+// least alpha records (the first level's at most one per instance), so
+// nsegs <= n / alpha; a level of R <= n records in nsegs subproblems has at
+// most R / tile + nsegs subarrays; a job of class c holds at least
+// 2, 513, 1025, 2049 records, and copy jobs at least one.
+struct DsBounds {
+    uint64_t segs, tiles, chunks;
+    uint64_t jobs[kJobClasses];
+};
+
+DsBounds ds_bounds(uint64_t n, uint64_t nseg, const Params& p)
+{
+    DsBounds b;
+    b.segs = std::max<uint64_t>(std::min<uint64_t>(nseg, n / p.alpha), n / p.alpha) + 1;
+    b.tiles = n / p.tmin + b.segs;
+    b.chunks = b.tiles / kChunk + b.segs;
+    b.jobs[0] = n / 2 + 1;
+    b.jobs[1] = n / 513 + 1;
+    b.jobs[2] = n / 1025 + 1;
+    b.jobs[3] = n / 2049 + 1;
+    b.jobs[kCopyClass] = n + n / kCopyChunk + 1;
+    return b;
+}
+
+template <int MODE, typename V>
+void launch_jobs_ds(ss_ctx* c, const JobLists& jl, const LevelInfo* dims, const uint64_t* sk, const void* sv,
+                    uint64_t* ok, void* ov, LevelInfo* info)
+{
+    const V* svv = (const V*)sv;
+    V* ovv = (V*)ov;
+    uint64_t* sink = (uint64_t*)c->sink.p;
+    const uint32_t* cnt = dims->njobs;
+    hipLaunchKernelGGL((k_base_ds<MODE, V, 1>), dim3(ds_grid<k_base_ds<MODE, V, 1>>(c, 64, jl.cap[0])), dim3(64), 0,
+                       c->stream, jl.jobs + jl.base[0], cnt + 0, jl.cap[0], sk, svv, ok, ovv, sink, info);
+    hipLaunchKernelGGL((k_base_ds<MODE, V, 2>), dim3(ds_grid<k_base_ds<MODE, V, 2>>(c, 128, jl.cap[1])), dim3(128), 0,
+                       c->stream, jl.jobs + jl.base[1], cnt + 1, jl.cap[1], sk, svv, ok, ovv, sink, info);
+    hipLaunchKernelGGL((k_base_ds<MODE, V, 4>), dim3(ds_grid<k_base_ds<MODE, V, 4>>(c, 256, jl.cap[2])), dim3(256), 0,
+                       c->stream, jl.jobs + jl.base[2], cnt + 2, jl.cap[2], sk, svv, ok, ovv, sink, info);
+    hipLaunchKernelGGL((k_base_2pass_ds<MODE, V>), dim3(ds_grid<k_base_2pass_ds<MODE, V>>(c, 512, jl.cap[3])),
+                       dim3(512), 0, c->stream, jl.jobs + jl.base[3], cnt + 3, jl.cap[3], sk, svv, ok, ovv, info);
+    hipLaunchKernelGGL((k_copy_ds<V>), dim3(ds_grid<k_copy_ds<V>>(c, 256, jl.cap[kCopyClass])), dim3(256), 0,
+                       c->stream, jl.jobs + jl.base[kCopyClass], cnt + kCopyClass, jl.cap[kCopyClass], sk, svv, ok,
+                       ovv);
+}
+
+template <int MODE, typename V>
+void launch_level_ds(ss_ctx* c, const LevelArgs& a, const DsBounds& b)
+{
+    hipLaunchKernelGGL((k_sample_heavy_ds<MODE>), dim3(ds_grid<k_sample_heavy_ds<MODE>>(c, 1024, b.segs)), dim3(1024),
+                       0, c->stream, a);
+    hipLaunchKernelGGL((k_count_ds<MODE>), dim3(ds_grid<k_count_ds<MODE>>(c, 1024, b.tiles)), dim3(1024), 0,
+                       c->stream, a);
+    hipLaunchKernelGGL(k_scan_chunks_ds, dim3(ds_grid<k_scan_chunks_ds>(c, 256, b.chunks)), dim3(256), 0, c->stream,
+                       a);
+    hipLaunchKernelGGL(k_scan_buckets_ds, dim3(ds_grid<k_scan_buckets_ds>(c, 1024, b.segs * kBucketGroups)),
+                       dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan_offsets_ds, dim3(ds_grid<k_scan_offsets_ds>(c, 1024, b.segs)), dim3(1024), 0,
+                       c->stream, a);
+    hipLaunchKernelGGL(k_scan_fill_ds, dim3(ds_grid<k_scan_fill_ds>(c, 256, b.chunks)), dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_distribute_ds<V, 16, 8, 0>), dim3(ds_grid<k_distribute_ds<V, 16, 8, 0>>(c, 1024, b.tiles)),
+                       dim3(1024), 0, c->stream, a);
+}
+
+// The batch with every level sized on the device: no host synchronization
+// and, once the workspace is sized, no allocation, so the whole call can be
+// captured into a graph.  `offs` is a device array of ninst + 1 offsets.
+template <int MODE, typename V>
+ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs, uint64_t ninst,
+                          uint64_t n, uint64_t* keys_out, void* vals_out, const Params& p, uint32_t levels)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OR_FAIL(c, hipStreamIsCapturing(c->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    const bool inplace = keys_out == keys;
+    const DsBounds b = ds_bounds(n, ninst, p);
+    if (b.segs >= (1ull << 31) || b.tiles >= (1ull << 31) || b.jobs[kCopyClass] >= (1ull << 32))
+        return fail(c, SS_EINVAL, "batch too large for the device-sized form");
+    ss_status s;
+    uint64_t jtot = 0;
+    JobLists jl;
+    for (int k = 0; k < kJobClasses; ++k) {
+        jl.base[k] = jtot;
+        jl.cap[k] = (uint32_t)b.jobs[k];
+        jtot += b.jobs[k];
+    }
+    if ((s = ensure_ds(c, c->t_keys, n * 8, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->t_vals, n * sizeof(V), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->bids, n * 2, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->sink, 512, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->info, sizeof(LevelInfo), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->ds_info, (size_t)(levels + 1) * sizeof(LevelInfo), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->ds_jobs, jtot * sizeof(Job), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->segs[0], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->segs[1], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->C, b.tiles * kNbStride * 4, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->P, b.chunks * kNbStride * 4, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->tot, b.segs * kNbStride * 4, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->bstart, b.segs * (kNbStride + 1) * 4, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->heavy_list, b.segs * kHeavyMax * 8, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->tab_h, b.segs * 2 * kHeavySlotsMax * 8, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->tab_id, b.segs * 2 * kHeavySlotsMax * 2, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->bfin, b.segs * kNbStride, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->bkey, b.segs * kNbStride * 8, capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->top, b.segs * 4, capturing)) != SS_OK) return s;
+    jl.jobs = (Job*)c->ds_jobs.p;
+    const uint32_t seg_cap = (uint32_t)b.segs;
+    LevelInfo* infos = (LevelInfo*)c->ds_info.p;
+
+    // counts of every level start at zero; so does the call's status word
+    const uint32_t iw = (uint32_t)((levels + 1) * sizeof(LevelInfo) / 4);
+    hipLaunchKernelGGL(k_ds_clear, dim3((iw + 255) / 256), dim3(256), 0, c->stream, (uint32_t*)infos, iw);
+    hipLaunchKernelGGL(k_ds_clear, dim3(1), dim3(256), 0, c->stream, (uint32_t*)c->info.p,
+                       (uint32_t)(sizeof(LevelInfo) / 4));
+    hipLaunchKernelGGL(k_ds_check_offsets, dim3((uint32_t)std::min<uint64_t>((ninst + 255) / 256, 4096)),
+                       dim3(256), 0, c->stream, offs, (uint32_t)ninst, n, infos);
+    hipLaunchKernelGGL(k_ds_plan_instances, dim3((uint32_t)std::min<uint64_t>((ninst + 255) / 256, 4096)), dim3(256),
+                       0, c->stream, offs, (uint32_t)ninst, n, p.alpha, p.nl0, (uint32_t)inplace,
+                       (Seg*)c->segs[0].p, seg_cap, jl, infos);
+    hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[0].p, seg_cap, infos, p.tmin,
+                       p.tmax0);
+    launch_jobs_ds<MODE, V>(c, jl, infos, keys, vals, keys_out, vals_out, infos);
+    HIP_OR_FAIL(c, hipGetLastError());
+
+    const uint64_t* loc_k = keys;
+    const void* loc_v = vals;
+    uint64_t* T_k = (uint64_t*)c->t_keys.p;
+    void* T_v = c->t_vals.p;
+    int cur = 0;
+    for (uint32_t level = 0; level < levels; ++level) {
+        // buffers as in the host-sized engine (the sequence does not depend on the data)
+        uint64_t* dst_k;
+        void* dst_v;
+        uint64_t* fin_k;
+        void* fin_v;
+        if (loc_k == keys_out) {
+            dst_k = fin_k = T_k;
+            dst_v = fin_v = T_v;
+        } else if (loc_k == T_k) {
+            dst_k = fin_k = keys_out;
+            dst_v = fin_v = vals_out;
+        } else {
+            dst_k = T_k;
+            dst_v = T_v;
+            fin_k = keys_out;
+            fin_v = vals_out;
+        }
+        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, 0, 0, loc_k, loc_v, dst_k, dst_v, fin_k, fin_v);
+        a.dims = infos + level;
+        a.seg_cap = seg_cap;
+        a.info = infos + level + 1;
+        a.fill_heavy = 0;  // one-key buckets move their keys too (no fill lists)
+        launch_level_ds<MODE, V>(c, a, b);
+
+        PlanArgs pa;
+        pa.segs = (const Seg*)c->segs[cur].p;
+        pa.nsegs = 0;
+        pa.bstart = (const uint32_t*)c->bstart.p;
+        pa.next = (Seg*)c->segs[cur ^ 1].p;
+        pa.next_cap = seg_cap;
+        pa.jobs = jl.jobs;
+        for (int k = 0; k < kJobClasses; ++k) {
+            pa.job_base[k] = jl.base[k];
+            pa.job_capc[k] = jl.cap[k];
+        }
+        pa.info = infos + level + 1;
+        pa.alpha = p.alpha;
+        pa.finals_in_out = fin_k == keys_out;
+        pa.ordered = 0;
+        pa.bfin = (const uint8_t*)c->bfin.p;
+        pa.reduce = 0;
+        pa.fill = 0;
+        pa.bkey = (const uint64_t*)c->bkey.p;
+        pa.fills = nullptr;
+        pa.fill_cap = 0;
+        pa.dims = infos + level;
+        pa.cur_cap = seg_cap;
+        hipLaunchKernelGGL(k_plan_ds, dim3(ds_grid<k_plan_ds>(c, 256, b.segs)), dim3(256), 0, c->stream, pa);
+        hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, seg_cap,
+                           infos + level + 1, p.tmin, p.tmaxd);
+        launch_jobs_ds<MODE, V>(c, jl, infos + level + 1, dst_k, dst_v, keys_out, vals_out, infos + level + 1);
+        HIP_OR_FAIL(c, hipGetLastError());
+        loc_k = dst_k;
+        loc_v = dst_v;
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_ds_finish, dim3(1), dim3(64), 0, c->stream, (const LevelInfo*)infos, levels, seg_cap, jl,
+                       (LevelInfo*)c->info.p);
+    HIP_OR_FAIL(c, hipGetLastError());
     return SS_OK;
 }
 
@@ -1040,7 +1266,8 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1]};
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
+                      &c->ds_jobs, &c->ds_info};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1138,7 +1365,8 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     if (!c || !bytes) return SS_EINVAL;
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1]};
+                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
+                      &c->ds_jobs, &c->ds_info};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -1177,6 +1405,29 @@ ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* v
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p)
                    : run_semisort<uint32_t>(c, keys, vals, offs, nseg, keys_out, vals_out, p);
+}
+
+ss_status ss_semisort_equal_batch_capturable(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                             const uint64_t* seg_offsets, uint64_t nseg, uint64_t n,
+                                             uint64_t* keys_out, void* vals_out, uint32_t max_levels,
+                                             const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (nseg == 0) return SS_OK;
+    if (!seg_offsets) return fail(c, SS_EINVAL, "null seg_offsets");
+    if (nseg >= (1ull << 31)) return fail(c, SS_EINVAL, "too many instances");
+    if (max_levels < 1 || max_levels > 64) return fail(c, SS_EINVAL, "max_levels must be in 1..64");
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    default_tiles(c, params, &p, 32768u, 16384u);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (p.mode == 1)
+        return vb == 8 ? run_semisort_ds<1, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                       : run_semisort_ds<1, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
+    return vb == 8 ? run_semisort_ds<0, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                   : run_semisort_ds<0, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
 }
 
 ss_status ss_autotune_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,

@@ -37,6 +37,9 @@ constexpr uint32_t kStatusSizeMismatch = 1u;   // bucket sizes do not add up to 
 constexpr uint32_t kStatusScatterRange = 2u;   // a distribution target fell outside its subproblem
 constexpr uint32_t kStatusBaseIndex = 4u;      // a base-case permutation entry out of range
 constexpr uint32_t kStatusHeavyTable = 8u;     // the heavy table could not be built
+constexpr uint32_t kStatusBadOffsets = 16u;    // instance offsets not non-decreasing from 0 to n
+constexpr uint32_t kStatusTooDeep = 32u;       // subproblems left after the last device-sized level
+constexpr uint32_t kStatusCapacity = 64u;      // a device-sized level outgrew a reserved list
 
 struct Seg {
     uint32_t start;    // absolute first record
@@ -130,6 +133,11 @@ struct LevelArgs {
     uint64_t* res_keys;             // results at position coordinates (n entries)
     uint64_t* res_vals;
     uint8_t* rflag;                 // 1 where a result sits
+    // device-sized levels (the *_ds kernels): the level's subproblem, tile and
+    // chunk counts and subarray size are read from dims, written there by the
+    // previous level's planning; seg_cap bounds the subproblem list
+    const LevelInfo* dims;
+    uint32_t seg_cap;
 };
 
 // ---------------------------------------------------------------- hashing
@@ -681,7 +689,7 @@ __device__ void sample_sort_keys(const LevelArgs& a, const Seg& sg, uint32_t s, 
 }
 
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
+__device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t sid)
 {
     constexpr int BS = 1024;
     __shared__ uint64_t smp[kSampleMax];
@@ -692,7 +700,6 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     __shared__ uint32_t sh_s, sh_tau, sh_te, sh_hs, sh_nl, sh_fail;
     __shared__ unsigned long long sh_top[2];
 
-    const uint32_t sid = blockIdx.x;
     const uint32_t tid = threadIdx.x;
     const Seg sg = a.segs[sid];
     if (tid < 2) sh_top[tid] = 0;
@@ -816,13 +823,36 @@ __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
     }
 }
 
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
+{
+    sample_heavy_item<MODE>(a, blockIdx.x);
+}
+
+// Device-sized levels: a resident grid walks the subproblems counted in dims.
+__device__ __forceinline__ uint32_t ds_nsegs(const LevelArgs& a)
+{
+    const uint32_t n = a.dims->nsegs;
+    return n < a.seg_cap ? n : a.seg_cap;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_sample_heavy_ds(LevelArgs a)
+{
+    const uint32_t n = ds_nsegs(a);
+    for (uint32_t sid = blockIdx.x; sid < n; sid += gridDim.x) {
+        sample_heavy_item<MODE>(a, sid);
+        __syncthreads();
+    }
+}
+
 // ================================================================ Step 2a
 // Counting pass (Section 3.2): per subarray, sequential over its records in
 // the paper; here one block per subarray with LDS counters.  Counting is
 // order-free, so plain LDS atomics suffice.
 
 template <int MODE>
-__global__ __launch_bounds__(1024) void k_count(LevelArgs a)
+__device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint32_t nsegs, uint32_t tile)
 {
     constexpr int BS = 1024;
     __shared__ uint32_t cnt[kNbStride];
@@ -830,14 +860,13 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     __shared__ uint64_t th[2 * kHeavySlotsMax];
     __shared__ uint16_t tidh[2 * kHeavySlotsMax];
 
-    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
-    const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
+    const uint32_t sid = find_by_tile(a.segs, nsegs, t);
     const Seg sg = a.segs[sid];
     const uint32_t lt = t - sg.tile0;
-    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * a.tile;
+    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * tile;
     const uint64_t send = (uint64_t)sg.start + sg.len;
-    const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
+    const uint64_t r1 = r0 + tile < send ? r0 + tile : send;
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = sg.nbk;
     const uint32_t hlog2 = sg.hlog2;  // slot bits and salt
@@ -907,6 +936,22 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     // keeps one slot (in the subproblem's first subarray) for its result
     uint32_t* row = a.C + (size_t)t * kNbStride;
     for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b] + ((finl[b] && lt == 0) ? 1u : 0u);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_count(LevelArgs a)
+{
+    count_item<MODE>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_count_ds(LevelArgs a)
+{
+    const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
+    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+        count_item<MODE>(a, t, ns, tile);
+        __syncthreads();
+    }
 }
 
 // ================================================================ semisort_<
@@ -1238,10 +1283,9 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
 // subarrays.  Four passes over the rows: chunk sums, a scan over chunks per
 // bucket, bucket starts per subproblem, and the fill of X.
 
-__global__ __launch_bounds__(256) void k_scan_chunks(LevelArgs a)
+__device__ __forceinline__ void scan_chunks_item(const LevelArgs& a, uint32_t ch, uint32_t nsegs)
 {
-    const uint32_t ch = blockIdx.x;
-    const uint32_t sid = find_by_chunk(a.segs, a.nsegs, ch);
+    const uint32_t sid = find_by_chunk(a.segs, nsegs, ch);
     const Seg sg = a.segs[sid];
     const uint32_t lc = ch - sg.chunk0;
     const uint32_t t0 = sg.tile0 + lc * kChunk;
@@ -1255,11 +1299,22 @@ __global__ __launch_bounds__(256) void k_scan_chunks(LevelArgs a)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_buckets(LevelArgs a)
+__global__ __launch_bounds__(256) void k_scan_chunks(LevelArgs a)
+{
+    scan_chunks_item(a, blockIdx.x, a.nsegs);
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks_ds(LevelArgs a)
+{
+    const uint32_t ns = ds_nsegs(a), n = a.dims->chunks;
+    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) scan_chunks_item(a, ch, ns);
+}
+
+__device__ __forceinline__ void scan_buckets_item(const LevelArgs& a, uint32_t blk)
 {
     __shared__ uint32_t part[16][64];
-    const uint32_t sid = blockIdx.x / kBucketGroups;
-    const uint32_t bg = blockIdx.x % kBucketGroups;
+    const uint32_t sid = blk / kBucketGroups;
+    const uint32_t bg = blk % kBucketGroups;
     const Seg sg = a.segs[sid];
     const uint32_t nb = sg.nbk;
     if (bg * 64 >= nb) return;  // uniform over the block
@@ -1287,10 +1342,23 @@ __global__ __launch_bounds__(1024) void k_scan_buckets(LevelArgs a)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_scan_offsets(LevelArgs a)
+__global__ __launch_bounds__(1024) void k_scan_buckets(LevelArgs a)
+{
+    scan_buckets_item(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_buckets_ds(LevelArgs a)
+{
+    const uint32_t n = ds_nsegs(a) * kBucketGroups;
+    for (uint32_t blk = blockIdx.x; blk < n; blk += gridDim.x) {
+        scan_buckets_item(a, blk);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void scan_offsets_item(const LevelArgs& a, uint32_t sid)
 {
     __shared__ uint32_t tmp[20];
-    const uint32_t sid = blockIdx.x;
     const Seg sg = a.segs[sid];
     const uint32_t nb = sg.nbk;
     const uint32_t b0 = 2 * threadIdx.x, b1 = b0 + 1;
@@ -1308,10 +1376,23 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(LevelArgs a)
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
+__global__ __launch_bounds__(1024) void k_scan_offsets(LevelArgs a)
 {
-    const uint32_t ch = blockIdx.x;
-    const uint32_t sid = find_by_chunk(a.segs, a.nsegs, ch);
+    scan_offsets_item(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_offsets_ds(LevelArgs a)
+{
+    const uint32_t n = ds_nsegs(a);
+    for (uint32_t sid = blockIdx.x; sid < n; sid += gridDim.x) {
+        scan_offsets_item(a, sid);
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ void scan_fill_item(const LevelArgs& a, uint32_t ch, uint32_t nsegs)
+{
+    const uint32_t sid = find_by_chunk(a.segs, nsegs, ch);
     const Seg sg = a.segs[sid];
     const uint32_t lc = ch - sg.chunk0;
     const uint32_t t0 = sg.tile0 + lc * kChunk;
@@ -1328,6 +1409,17 @@ __global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
             x += c;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_scan_fill(LevelArgs a)
+{
+    scan_fill_item(a, blockIdx.x, a.nsegs);
+}
+
+__global__ __launch_bounds__(256) void k_scan_fill_ds(LevelArgs a)
+{
+    const uint32_t ns = ds_nsegs(a), n = a.dims->chunks;
+    for (uint32_t ch = blockIdx.x; ch < n; ch += gridDim.x) scan_fill_item(a, ch, ns);
 }
 
 // ================================================================ Step 2c
@@ -1352,7 +1444,7 @@ __device__ __forceinline__ bool bucket_is_final(bool one_key_bucket, uint32_t sz
 // LDS and added to the subproblem's heavy sums, light records move); RED = 2:
 // histogram (as 1 with every value 1 and no value array).
 template <typename V, int W, int E, int RED>
-__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
+__device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, uint32_t nsegs, uint32_t tile)
 {
     // Every global load and store in the sub-tile loop is issued
     // unconditionally (clamped 32-bit load offsets from the sub-tile's start,
@@ -1376,15 +1468,14 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ unsigned long long hs[RED ? kNbStride : 1];
     __shared__ uint8_t finl[kNbStride];
 
-    const uint32_t t = xcd_remap(blockIdx.x, gridDim.x);
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u, w = tid >> 6;
-    const uint32_t sid = find_by_tile(a.segs, a.nsegs, t);
+    const uint32_t sid = find_by_tile(a.segs, nsegs, t);
     const Seg sg = a.segs[sid];
     const uint32_t lt = t - sg.tile0;
-    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * a.tile;
+    const uint64_t r0 = (uint64_t)sg.start + (uint64_t)lt * tile;
     const uint64_t send = (uint64_t)sg.start + sg.len;
-    const uint64_t r1 = r0 + a.tile < send ? r0 + a.tile : send;
+    const uint64_t r1 = r0 + tile < send ? r0 + tile : send;
     const uint64_t rlast = r1 - 1;
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = sg.nbk;
@@ -1593,6 +1684,22 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
 }
 
+template <typename V, int W, int E, int RED>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
+{
+    distribute_item<V, W, E, RED>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
+}
+
+template <typename V, int W, int E, int RED>
+__global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute_ds(LevelArgs a)
+{
+    const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
+    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+        distribute_item<V, W, E, RED>(a, t, ns, tile);
+        __syncthreads();
+    }
+}
+
 // Direct form of the distribution: the same stable ranking, but every record
 // is written straight from registers to its destination, without staging
 // the sub-tile in LDS.  Lanes of a wave that share a bucket in a round hold
@@ -1740,8 +1847,9 @@ struct PlanArgs {
     const uint32_t* bstart;
     Seg* next;
     uint32_t next_cap;
-    Job* jobs;          // kJobClasses lists of job_cap entries
-    uint32_t job_cap;
+    Job* jobs;          // kJobClasses lists: list c holds job_capc[c] entries from job_base[c]
+    uint64_t job_base[kJobClasses];
+    uint32_t job_capc[kJobClasses];
     LevelInfo* info;
     uint32_t alpha;
     uint32_t finals_in_out;  // final buckets were written to the output by the distribution
@@ -1752,6 +1860,10 @@ struct PlanArgs {
     const uint64_t* bkey;    // [nsegs][kNbStride] keys of one-key buckets
     FillJob* fills;
     uint32_t fill_cap;
+    // device-sized levels: the current level's subproblem count is read from
+    // dims (bounded by cur_cap) instead of nsegs
+    const LevelInfo* dims;
+    uint32_t cur_cap;
 };
 
 struct PlanCount {
@@ -1781,7 +1893,7 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
         if (p.bfin[(size_t)sidx * kNbStride + b]) return;
         if (sz == 1 || all_bits_used) {
             if (emit) {
-                if (job_at[kCopyClass] < p.job_cap) p.jobs[(size_t)kCopyClass * p.job_cap + job_at[kCopyClass]] = Job{st, sz};
+                if (job_at[kCopyClass] < p.job_capc[kCopyClass]) p.jobs[p.job_base[kCopyClass] + job_at[kCopyClass]] = Job{st, sz};
                 ++job_at[kCopyClass];
             }
             ++cnt.job[kCopyClass];
@@ -1806,8 +1918,8 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
         }
         for (uint32_t o = 0; o < sz; o += kCopyChunk) {
             const uint32_t l = sz - o < kCopyChunk ? sz - o : kCopyChunk;
-            if (emit && job_at[kCopyClass] < p.job_cap)
-                p.jobs[(size_t)kCopyClass * p.job_cap + job_at[kCopyClass]] = Job{st + o, l};
+            if (emit && job_at[kCopyClass] < p.job_capc[kCopyClass])
+                p.jobs[p.job_base[kCopyClass] + job_at[kCopyClass]] = Job{st + o, l};
             if (emit) ++job_at[kCopyClass];
             ++cnt.job[kCopyClass];
         }
@@ -1836,18 +1948,17 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
     }
     const int c = base_class(sz);
     if (emit) {
-        if (job_at[c] < p.job_cap) p.jobs[(size_t)c * p.job_cap + job_at[c]] = Job{st, sz};
+        if (job_at[c] < p.job_capc[c]) p.jobs[p.job_base[c] + job_at[c]] = Job{st, sz};
         ++job_at[c];
     }
     ++cnt.job[c];
     cnt.rec += sz;
 }
 
-__global__ __launch_bounds__(256) void k_plan(PlanArgs p)
+__device__ __forceinline__ void plan_item(const PlanArgs& p, uint32_t sidx)
 {
     __shared__ uint32_t tmp[20];
     __shared__ uint32_t sh_base[kJobClasses + 2];
-    const uint32_t sidx = blockIdx.x;
     const Seg sg = p.segs[sidx];
     const uint32_t nL = 1u << sg.nl_bits;
     const uint32_t nb = sg.nbk;
@@ -1879,6 +1990,20 @@ __global__ __launch_bounds__(256) void k_plan(PlanArgs p)
     PlanCount again{};
     for (uint32_t b = threadIdx.x; b < nb; b += 256)
         plan_bucket(p, sidx, sg, b, nL, again, true, &seg_at, job_at, &fill_at);
+}
+
+__global__ __launch_bounds__(256) void k_plan(PlanArgs p)
+{
+    plan_item(p, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_plan_ds(PlanArgs p)
+{
+    const uint32_t c = p.dims->nsegs, n = c < p.cur_cap ? c : p.cur_cap;
+    for (uint32_t sidx = blockIdx.x; sidx < n; sidx += gridDim.x) {
+        plan_item(p, sidx);
+        __syncthreads();
+    }
 }
 
 // Prefix over the next level's subproblems: subarray size for the level,
@@ -1923,6 +2048,90 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
     }
 }
 
+// ---------------------------------------------------------------- device-sized levels
+// A batch whose level sizes never travel to the host: the first level is
+// planned here from the instance offsets, every later level by k_plan_ds, and
+// each kernel of a level reads its counts from that level's LevelInfo.
+
+// Zeroes `words` 32-bit words (a kernel, so the call can be captured).
+__global__ __launch_bounds__(256) void k_ds_clear(uint32_t* p, uint32_t words)
+{
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < words; i += gridDim.x * 256) p[i] = 0;
+}
+
+struct JobLists {
+    Job* jobs;
+    uint64_t base[kJobClasses];
+    uint32_t cap[kJobClasses];
+};
+
+// Offsets must rise from 0 to n; otherwise no instance is planned at all
+// (instances would overlap), and the status says why.
+__global__ __launch_bounds__(256) void k_ds_check_offsets(const uint64_t* offs, uint32_t ninst, uint64_t n,
+                                                          LevelInfo* info)
+{
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < ninst; i += gridDim.x * 256) {
+        const uint64_t o0 = offs[i], o1 = offs[i + 1];
+        if (o1 < o0 || o1 > n || (i == 0 && o0 != 0) || (i + 1 == ninst && o1 != n))
+            atomicOr(&info->status, kStatusBadOffsets);
+    }
+}
+
+// First level of a batch: instance i is [offs[i], offs[i+1]).  Instances of
+// at least alpha records become subproblems, smaller ones base-case jobs by
+// capacity class, single records copy jobs (none in place).  The order of the
+// lists depends on scheduling; results do not (each entry names its records).
+__global__ __launch_bounds__(256) void k_ds_plan_instances(const uint64_t* offs, uint32_t ninst, uint64_t n,
+                                                           uint32_t alpha, uint32_t nl0, uint32_t inplace,
+                                                           Seg* segs, uint32_t seg_cap, JobLists jl,
+                                                           LevelInfo* info)
+{
+    if (info->status & kStatusBadOffsets) return;  // checked by k_ds_check_offsets
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < ninst; i += gridDim.x * 256) {
+        const uint64_t o0 = offs[i], o1 = offs[i + 1];
+        const uint32_t len = (uint32_t)(o1 - o0);
+        if (len >= alpha) {
+            const uint32_t at = atomicAdd(&info->nsegs, 1u);
+            if (at < seg_cap) {
+                Seg sg;
+                sg.start = (uint32_t)o0;
+                sg.len = len;
+                sg.ibase = (uint32_t)o0;
+                sg.tile0 = sg.chunk0 = sg.ntiles = 0;
+                const uint32_t nl = choose_nl(len, alpha, kLightBitsMax, 0);
+                sg.nl_bits = (uint8_t)(nl < nl0 ? nl : nl0);
+                sg.shift = 0;
+                sg.nbk = 0;
+                sg.nheavy = 0;
+                sg.hlog2 = 0;
+                segs[at] = sg;
+            }
+        } else if (len >= 2 || (len == 1 && !inplace)) {
+            const int c = len == 1 ? kCopyClass : base_class(len);
+            const uint32_t at = atomicAdd(&info->njobs[c], 1u);
+            if (at < jl.cap[c]) jl.jobs[jl.base[c] + at] = Job{(uint32_t)o0, len};
+        }
+    }
+}
+
+// After the last device-sized level: folds every level's status into *out,
+// and flags subproblems left unfinished or lists that outgrew their room.
+__global__ void k_ds_finish(const LevelInfo* infos, uint32_t levels, uint32_t seg_cap, JobLists jl,
+                            LevelInfo* out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    uint32_t st = 0;
+    for (uint32_t l = 0; l <= levels; ++l) {
+        const LevelInfo& li = infos[l];
+        st |= li.status;
+        if (li.nsegs > seg_cap) st |= kStatusCapacity;
+        for (int c = 0; c < kJobClasses; ++c)
+            if (li.njobs[c] > jl.cap[c]) st |= kStatusCapacity;
+    }
+    if (infos[levels].nsegs) st |= kStatusTooDeep;
+    if (st) atomicOr(&out->status, st);
+}
+
 // ================================================================ Step 3
 // Local refining base case for semisort_= (Section 3.3).  The paper packs a
 // sequential chained hash table in table order.  Here one block per bucket of
@@ -1939,9 +2148,9 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
 // Values never touch LDS; results are written straight from registers.
 
 template <int MODE, typename V, int W>
-__global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
-                                                 const V* src_vals, uint64_t* out_keys, V* out_vals,
-                                                 uint64_t* sink, LevelInfo* info)
+__device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
+                                         const V* src_vals, uint64_t* out_keys, V* out_vals, uint64_t* sink,
+                                         LevelInfo* info)
 {
     // Persistent: the grid holds as many blocks as fit on the device, each
     // takes every gridDim.x-th job, and the next job's records are loaded
@@ -2089,14 +2298,32 @@ __global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, u
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
 }
 
+template <int MODE, typename V, int W>
+__global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
+                                                 const V* src_vals, uint64_t* out_keys, V* out_vals,
+                                                 uint64_t* sink, LevelInfo* info)
+{
+    base_run<MODE, V, W>(jobs, njobs, src_keys, src_vals, out_keys, out_vals, sink, info);
+}
+
+// Device-counted: the class's job count is read from *count (bounded by cap).
+template <int MODE, typename V, int W>
+__global__ __launch_bounds__(W * 64) void k_base_ds(const Job* __restrict__ jobs, const uint32_t* count, uint32_t cap,
+                                                    const uint64_t* src_keys, const V* src_vals, uint64_t* out_keys,
+                                                    V* out_vals, uint64_t* sink, LevelInfo* info)
+{
+    const uint32_t n = *count < cap ? *count : cap;
+    base_run<MODE, V, W>(jobs, n, src_keys, src_vals, out_keys, out_vals, sink, info);
+}
+
 // The same base case for buckets of up to 4096 records, with the stable
 // multisplit on f(i) done as two 6-bit passes (small per-wave counters) so two
 // blocks fit on a CU.  Values are gathered from the source by index after the
 // sort (the bucket was just read, so the gather hits in L2); all reads finish
 // before the first write, so the output may be the source.
 template <int MODE, typename V>
-__global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                                    uint64_t* out_keys, V* out_vals, LevelInfo* info)
+__device__ __forceinline__ void base_2pass_item(const Job j, const uint64_t* src_keys, const V* src_vals,
+                                                uint64_t* out_keys, V* out_vals, LevelInfo* info)
 {
     constexpr int W = 8, BS = 512, E = 8, CAP = 4096;
     __shared__ uint64_t kl[CAP];
@@ -2105,7 +2332,6 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
     __shared__ uint32_t dst_[64];
     __shared__ uint32_t tmp[20];
 
-    const Job j = jobs[blockIdx.x];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
     const uint32_t m = j.len;  // 2 .. CAP
     const uint64_t start = j.start;
@@ -2226,6 +2452,25 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
         }
     }
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
+}
+
+template <int MODE, typename V>
+__global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                                    uint64_t* out_keys, V* out_vals, LevelInfo* info)
+{
+    base_2pass_item<MODE, V>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals, info);
+}
+
+template <int MODE, typename V>
+__global__ __launch_bounds__(512) void k_base_2pass_ds(const Job* jobs, const uint32_t* count, uint32_t cap,
+                                                       const uint64_t* src_keys, const V* src_vals, uint64_t* out_keys,
+                                                       V* out_vals, LevelInfo* info)
+{
+    const uint32_t n = *count < cap ? *count : cap;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        base_2pass_item<MODE, V>(jobs[i], src_keys, src_vals, out_keys, out_vals, info);
+        __syncthreads();
+    }
 }
 
 // Base case of semisort_< (Section 3.3: a stable comparison sort of a small
@@ -2360,15 +2605,30 @@ __global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uin
 
 // Copy jobs: buckets that are final but sit in T (Section 3.4).
 template <typename V>
-__global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                              uint64_t* out_keys, V* out_vals)
+__device__ __forceinline__ void copy_item(const Job j, const uint64_t* src_keys, const V* src_vals,
+                                          uint64_t* out_keys, V* out_vals)
 {
-    const Job j = jobs[blockIdx.x];
     const uint64_t st = j.start;
     for (uint32_t i = threadIdx.x; i < j.len; i += 256) {
         out_keys[st + i] = src_keys[st + i];
         out_vals[st + i] = src_vals[st + i];
     }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
+                                              uint64_t* out_keys, V* out_vals)
+{
+    copy_item<V>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_copy_ds(const Job* jobs, const uint32_t* count, uint32_t cap,
+                                                 const uint64_t* src_keys, const V* src_vals, uint64_t* out_keys,
+                                                 V* out_vals)
+{
+    const uint32_t n = *count < cap ? *count : cap;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) copy_item<V>(jobs[i], src_keys, src_vals, out_keys, out_vals);
 }
 
 // Key-fill jobs: the keys of a one-key bucket are one value repeated.

@@ -80,6 +80,7 @@ def lib():
         L.ss_autotune_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, u32, P,
                                               ctypes.POINTER(ctypes.c_double)]
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
+        L.ss_semisort_equal_batch_capturable.argtypes = [vp, vp, vp, u32, vp, u64, u64, vp, vp, u32, P]
         L.ss_collect_reduce_ordered.argtypes = L.ss_collect_reduce.argtypes
         L.ss_histogram_ordered.argtypes = L.ss_histogram.argtypes
         for name in declared_symbols():
@@ -258,6 +259,30 @@ def semisort_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, 
     ctx.check(lib().ss_semisort_equal_batch(ctx.h, _ptr(keys), _ptr(vals), vb,
                                             ctypes.c_void_p(offs.ctypes.data), offs.size - 1, _ptr(keys_out),
                                             _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def semisort_equal_batch_capturable(keys, vals, seg_offsets, keys_out=None, vals_out=None, max_levels=6,
+                                    params=None, ctx=None):
+    """ss_semisort_equal_batch_capturable: the batch sized on the device, so
+    the call can be recorded into a graph (torch.cuda.graph) and replayed.
+    seg_offsets: int64 DEVICE tensor of nseg+1 boundaries, the last = len(keys).
+    Under capture, pass keys_out / vals_out (allocated before capture) and make
+    one uncaptured call with the same sizes first, so the workspace is sized."""
+    import torch
+    vb = _check_kv(keys, vals)
+    _check_keys(seg_offsets, "seg_offsets")
+    if seg_offsets.numel() < 1:
+        raise ValueError("seg_offsets needs nseg + 1 entries")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    ctx.check(lib().ss_semisort_equal_batch_capturable(
+        ctx.h, _ptr(keys), _ptr(vals), vb, _ptr(seg_offsets), seg_offsets.numel() - 1, keys.numel(),
+        _ptr(keys_out), _ptr(vals_out), max_levels, ctypes.byref(params) if params is not None else None))
     return keys_out, vals_out
 
 
