@@ -117,7 +117,8 @@ def batched(args, S, I, torch):
     scaled to a total of at most 5e8 records, per-instance key distribution
     uniform[0, n/10), Zipf 0.8 / 1.2 hashed or uniform[0, 100); u64 keys,
     u64 values): autotuned batched launch chain against one call per
-    instance with the same parameters."""
+    instance with the same parameters, and the device-sized form of the
+    batch, eager and replayed from a captured graph."""
     log(f"batched: generating {args.batch_count} instances, total <= {args.batch_total:.0f}")
     keys, vals, offs, d = I.t_batch_workload(args.batch_count, 1e3, 1e7, args.batch_total, 7, "cuda")
     n = keys.numel()
@@ -146,11 +147,49 @@ def batched(args, S, I, torch):
     l_ms = (time.perf_counter() - t0) * 1e3
     log(f"batched: {b_ms:.2f} ms ({n / b_ms / 1e6:.2f} Grec/s) vs per-instance loop {l_ms:.2f} ms "
         f"({n / l_ms / 1e6:.2f} Grec/s)")
+    # The device-sized form (no host synchronization), eager and recorded
+    # once into a graph, on a context of its own; results checked against
+    # the host-sized batch (ko, vo) bit for bit.
+    import numpy as np
+    gctx = S.Context(0)
+    od = torch.from_numpy(np.asarray(offs, dtype=np.uint64).view(np.int64)).to(keys.device)
+    ko2, vo2 = torch.empty_like(keys), torch.empty_like(vals)
+    S.semisort_equal_batch_capturable(keys, vals, od, ko2, vo2, params=best, ctx=gctx)
+    gctx.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        S.semisort_equal_batch_capturable(keys, vals, od, ko2, vo2, params=best, ctx=gctx)
+    gctx.sync()
+    d_ms = (time.perf_counter() - t0) * 1e3 / reps
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.semisort_equal_batch_capturable(keys, vals, od, ko2, vo2, params=best, ctx=gctx)
+    ko2.fill_(-1)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    g_ms = (time.perf_counter() - t0) * 1e3 / reps
+    gctx.sync()
+    same = bool(torch.equal(ko, ko2) and torch.equal(vo, vo2))
+    del g
+    torch.cuda.synchronize()
+    gctx.close()
+    del ko2, vo2, od
+    log(f"batched: device-sized {d_ms:.2f} ms, graph replay {g_ms:.2f} ms ({n / g_ms / 1e6:.2f} Grec/s), "
+        f"same result as the host-sized batch: {same}")
+    if not same:
+        raise RuntimeError("device-sized batch differs from the host-sized batch")
     res = {"workload": f"semisort_= batch of {len(o) - 1} instances, n={n} (u64 key, u64 value)",
            "instances": len(o) - 1, "n": n, "batched_ms": round(b_ms, 3),
            "batched_grecs": round(n / b_ms / 1e6, 3), "per_instance_ms": round(l_ms, 3),
            "per_instance_grecs": round(n / l_ms / 1e6, 3), "speedup": round(l_ms / b_ms, 2),
            "autotune_s": round(tune_s, 2),
+           "device_sized_ms": round(d_ms, 3), "graph_replay_ms": round(g_ms, 3),
+           "graph_replay_grecs": round(n / g_ms / 1e6, 3),
            "tuned": {"sample_mult": best.sample_mult, "heavy_min": best.heavy_min,
                      "n_light_log2": best.n_light_log2, "base_case": best.base_case, "tile_max": best.tile_max}}
     del keys, vals, ko, vo

@@ -165,21 +165,26 @@ ss_status ss_semisort_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void*
  *   offsets, and every later level's kernels run as resident grids that read
  *   the level's subproblem, subarray and job counts from device memory, where
  *   the previous level's planning put them (the per-level syncs of the other
- *   entry points size launches instead).  Exactly max_levels levels of
- *   launches are enqueued (1..64); subproblems still left after them raise a
- *   device condition, reported by ss_sync.  Levels with no work cost a few
- *   microseconds each.
+ *   entry points size launches instead).  Work is taken from device-side
+ *   queues: subarrays by per-XCD counters, base-case jobs by a counter.
+ *   Exactly max_levels levels of launches are enqueued (1..64); subproblems
+ *   still left after them raise a device condition, reported by ss_sync.
+ *   With the default n_light_log2, inputs below 2^31 records need two levels
+ *   (three when keys escape the sample); a level with no work costs about
+ *   0.1 ms (fifteen launches that find nothing to do).
  * - Buffers are sized for the worst case of n records and the parameters:
- *   about (8 + val_bytes + 14) bytes per record plus 51 KB per possible
- *   subproblem (n / base_case of them).  A call that needs more workspace
+ *   up to (8 + val_bytes + 46) bytes per record (temporary array, bucket
+ *   ids, job and key-fill lists) plus about 63 KB per possible subproblem
+ *   (n / base_case + 1 of them).  A call that needs more workspace
  *   than the context holds allocates it, and therefore must not be under
  *   stream capture (SS_EINVAL if it is): make one uncaptured call with the
  *   same n, nseg, val_bytes and params first.  A captured graph keeps the
  *   workspace addresses of that moment; the context must not grow its
  *   workspace (a larger call of any kind) while the graph is replayed, and
  *   calls on the context must not overlap the replays.
- * - One-key buckets move their keys with the distribution (no key-fill
- *   stream), and the subarray size follows tile_min/tile_max only.
+ * - Keys of one-key buckets are filled on the context's second stream, forked
+ *   from and joined back to the call's stream with events (so a capture
+ *   records both); the subarray size follows tile_min/tile_max only.
  * Supports hash_mode, base_case, n_light_log2, sample_mult, heavy_min, tile_*
  * and seed like the other calls; in place (keys_out == keys, vals_out ==
  * vals) is allowed. */

@@ -47,9 +47,10 @@ struct ss_ctx {
     uint32_t fill_cap[2] = {0, 0};
     hipStream_t aux = nullptr;       // second stream: key fills overlap the next level
     hipEvent_t fill_done[2] = {nullptr, nullptr};
+    hipEvent_t fill_fork[2] = {nullptr, nullptr};  // device-sized levels: fills start after the planning
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
-    DevBuf ds_jobs, ds_info;         // device-sized batches: job lists, per-level counts
+    DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
     std::vector<Seg> host_segs;
     std::vector<Job> host_jobs[kJobClasses];
     uint32_t job_cap = 0;  // entries per class list
@@ -442,6 +443,7 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.rflag = nullptr;
     a.dims = nullptr;
     a.seg_cap = 0;
+    a.q = nullptr;
     return a;
 }
 
@@ -466,9 +468,11 @@ void host_prefix(std::vector<Seg>& segs, const Params& p, uint32_t* tiles, uint3
 // The second stream and its events, created on first use (default priority).
 ss_status ensure_aux(ss_ctx* c)
 {
-    if (c->aux) return SS_OK;
-    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-    for (hipEvent_t& e : c->fill_done) HIP_OR_FAIL(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    if (!c->aux) HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+    for (hipEvent_t& e : c->fill_done)
+        if (!e) HIP_OR_FAIL(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (hipEvent_t& e : c->fill_fork)
+        if (!e) HIP_OR_FAIL(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return SS_OK;
 }
 
@@ -779,6 +783,13 @@ uint32_t ds_grid(const ss_ctx* c, int threads, uint64_t bound)
     return (uint32_t)std::max<uint64_t>(g, 1);
 }
 
+// The same for kernels with per-XCD work queues: a multiple of 8 blocks.
+template <auto K>
+uint32_t ds_grid_xcd(const ss_ctx* c, int threads)
+{
+    return (ds_grid<K>(c, threads, ~0ull) + 7u) & ~7u;
+}
+
 // Grows a buffer outside stream capture only: a captured call must find its
 // workspace already sized by an earlier uncaptured call.
 ss_status ensure_ds(ss_ctx* c, DevBuf& b, size_t bytes, bool capturing)
@@ -789,6 +800,10 @@ ss_status ensure_ds(ss_ctx* c, DevBuf& b, size_t bytes, bool capturing)
                                   "uncaptured call with the same sizes first");
     return ensure(c, b, bytes);
 }
+
+// Work-queue counters per device-sized level: [0, 8) counting and [8, 16)
+// distribution (per XCD), 16 the two-pass base cases of the level's jobs.
+constexpr uint32_t kQueueWords = 32;
 
 // Upper bounds of one device-sized level over n records: subproblems hold at
 // least alpha records (the first level's at most one per instance), so
@@ -815,8 +830,8 @@ DsBounds ds_bounds(uint64_t n, uint64_t nseg, const Params& p)
 }
 
 template <int MODE, typename V>
-void launch_jobs_ds(ss_ctx* c, const JobLists& jl, const LevelInfo* dims, const uint64_t* sk, const void* sv,
-                    uint64_t* ok, void* ov, LevelInfo* info)
+void launch_jobs_ds(ss_ctx* c, const JobLists& jl, const LevelInfo* dims, uint32_t* q, const uint64_t* sk,
+                    const void* sv, uint64_t* ok, void* ov, LevelInfo* info)
 {
     const V* svv = (const V*)sv;
     V* ovv = (V*)ov;
@@ -829,7 +844,8 @@ void launch_jobs_ds(ss_ctx* c, const JobLists& jl, const LevelInfo* dims, const 
     hipLaunchKernelGGL((k_base_ds<MODE, V, 4>), dim3(ds_grid<k_base_ds<MODE, V, 4>>(c, 256, jl.cap[2])), dim3(256), 0,
                        c->stream, jl.jobs + jl.base[2], cnt + 2, jl.cap[2], sk, svv, ok, ovv, sink, info);
     hipLaunchKernelGGL((k_base_2pass_ds<MODE, V>), dim3(ds_grid<k_base_2pass_ds<MODE, V>>(c, 512, jl.cap[3])),
-                       dim3(512), 0, c->stream, jl.jobs + jl.base[3], cnt + 3, jl.cap[3], sk, svv, ok, ovv, info);
+                       dim3(512), 0, c->stream, jl.jobs + jl.base[3], cnt + 3, jl.cap[3], q + 16, sk, svv, ok, ovv,
+                       info);
     hipLaunchKernelGGL((k_copy_ds<V>), dim3(ds_grid<k_copy_ds<V>>(c, 256, jl.cap[kCopyClass])), dim3(256), 0,
                        c->stream, jl.jobs + jl.base[kCopyClass], cnt + kCopyClass, jl.cap[kCopyClass], sk, svv, ok,
                        ovv);
@@ -840,8 +856,8 @@ void launch_level_ds(ss_ctx* c, const LevelArgs& a, const DsBounds& b)
 {
     hipLaunchKernelGGL((k_sample_heavy_ds<MODE>), dim3(ds_grid<k_sample_heavy_ds<MODE>>(c, 1024, b.segs)), dim3(1024),
                        0, c->stream, a);
-    hipLaunchKernelGGL((k_count_ds<MODE>), dim3(ds_grid<k_count_ds<MODE>>(c, 1024, b.tiles)), dim3(1024), 0,
-                       c->stream, a);
+    hipLaunchKernelGGL((k_count_ds<MODE>), dim3(ds_grid_xcd<k_count_ds<MODE>>(c, 1024)), dim3(1024), 0, c->stream,
+                       a);
     hipLaunchKernelGGL(k_scan_chunks_ds, dim3(ds_grid<k_scan_chunks_ds>(c, 256, b.chunks)), dim3(256), 0, c->stream,
                        a);
     hipLaunchKernelGGL(k_scan_buckets_ds, dim3(ds_grid<k_scan_buckets_ds>(c, 1024, b.segs * kBucketGroups)),
@@ -849,7 +865,7 @@ void launch_level_ds(ss_ctx* c, const LevelArgs& a, const DsBounds& b)
     hipLaunchKernelGGL(k_scan_offsets_ds, dim3(ds_grid<k_scan_offsets_ds>(c, 1024, b.segs)), dim3(1024), 0,
                        c->stream, a);
     hipLaunchKernelGGL(k_scan_fill_ds, dim3(ds_grid<k_scan_fill_ds>(c, 256, b.chunks)), dim3(256), 0, c->stream, a);
-    hipLaunchKernelGGL((k_distribute_ds<V, 16, 8, 0>), dim3(ds_grid<k_distribute_ds<V, 16, 8, 0>>(c, 1024, b.tiles)),
+    hipLaunchKernelGGL((k_distribute_ds<V, 16, 8, 0>), dim3(ds_grid_xcd<k_distribute_ds<V, 16, 8, 0>>(c, 1024)),
                        dim3(1024), 0, c->stream, a);
 }
 
@@ -882,6 +898,7 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
     if ((s = ensure_ds(c, c->info, sizeof(LevelInfo), capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->ds_info, (size_t)(levels + 1) * sizeof(LevelInfo), capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->ds_jobs, jtot * sizeof(Job), capturing)) != SS_OK) return s;
+    if ((s = ensure_ds(c, c->ds_q, (size_t)(levels + 1) * kQueueWords * 4, capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->segs[0], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->segs[1], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->C, b.tiles * kNbStride * 4, capturing)) != SS_OK) return s;
@@ -894,6 +911,18 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
     if ((s = ensure_ds(c, c->bfin, b.segs * kNbStride, capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->bkey, b.segs * kNbStride * 8, capturing)) != SS_OK) return s;
     if ((s = ensure_ds(c, c->top, b.segs * 4, capturing)) != SS_OK) return s;
+    // key-fill lists of one-key buckets (alternating levels), run on the
+    // second stream as in the host-sized engine: at most one job per
+    // non-empty heavy bucket plus one per kFillChunk records
+    const uint64_t fcap = std::min<uint64_t>(b.segs * kHeavyMax, n) + n / kFillChunk + 1;
+    for (int k = 0; k < 2; ++k) {
+        if ((s = ensure_ds(c, c->fills[k], fcap * sizeof(FillJob), capturing)) != SS_OK) return s;
+        c->fill_cap[k] = (uint32_t)std::min<uint64_t>(c->fills[k].cap / sizeof(FillJob), 0xFFFFFFFFu);
+    }
+    if (!c->aux && capturing)
+        return fail(c, SS_EINVAL, "the second stream must be created by an uncaptured call first");
+    if ((s = ensure_aux(c)) != SS_OK) return s;
+    bool fill_used[2] = {false, false};
     jl.jobs = (Job*)c->ds_jobs.p;
     const uint32_t seg_cap = (uint32_t)b.segs;
     LevelInfo* infos = (LevelInfo*)c->ds_info.p;
@@ -901,6 +930,9 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
     // counts of every level start at zero; so does the call's status word
     const uint32_t iw = (uint32_t)((levels + 1) * sizeof(LevelInfo) / 4);
     hipLaunchKernelGGL(k_ds_clear, dim3((iw + 255) / 256), dim3(256), 0, c->stream, (uint32_t*)infos, iw);
+    uint32_t* qs = (uint32_t*)c->ds_q.p;  // per level: kQueueWords counters
+    hipLaunchKernelGGL(k_ds_clear, dim3(((levels + 1) * kQueueWords + 255) / 256), dim3(256), 0, c->stream, qs,
+                       (levels + 1) * kQueueWords);
     hipLaunchKernelGGL(k_ds_clear, dim3(1), dim3(256), 0, c->stream, (uint32_t*)c->info.p,
                        (uint32_t)(sizeof(LevelInfo) / 4));
     hipLaunchKernelGGL(k_ds_check_offsets, dim3((uint32_t)std::min<uint64_t>((ninst + 255) / 256, 4096)),
@@ -910,7 +942,7 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
                        (Seg*)c->segs[0].p, seg_cap, jl, infos);
     hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[0].p, seg_cap, infos, p.tmin,
                        p.tmax0);
-    launch_jobs_ds<MODE, V>(c, jl, infos, keys, vals, keys_out, vals_out, infos);
+    launch_jobs_ds<MODE, V>(c, jl, infos, qs, keys, vals, keys_out, vals_out, infos);
     HIP_OR_FAIL(c, hipGetLastError());
 
     const uint64_t* loc_k = keys;
@@ -940,8 +972,14 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
         a.dims = infos + level;
         a.seg_cap = seg_cap;
         a.info = infos + level + 1;
-        a.fill_heavy = 0;  // one-key buckets move their keys too (no fill lists)
+        // one-key buckets bound for keys_out move only their values; their
+        // keys are filled on the second stream while the next level runs
+        const bool fill = fin_k == keys_out;
+        const int fb = level & 1;
+        a.fill_heavy = fill;
+        a.q = qs + (size_t)(level + 1) * kQueueWords;
         launch_level_ds<MODE, V>(c, a, b);
+        if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         PlanArgs pa;
         pa.segs = (const Seg*)c->segs[cur].p;
@@ -960,23 +998,37 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
         pa.ordered = 0;
         pa.bfin = (const uint8_t*)c->bfin.p;
         pa.reduce = 0;
-        pa.fill = 0;
+        pa.fill = fill;
         pa.bkey = (const uint64_t*)c->bkey.p;
-        pa.fills = nullptr;
-        pa.fill_cap = 0;
+        pa.fills = (FillJob*)c->fills[fb].p;
+        pa.fill_cap = c->fill_cap[fb];
         pa.dims = infos + level;
         pa.cur_cap = seg_cap;
         hipLaunchKernelGGL(k_plan_ds, dim3(ds_grid<k_plan_ds>(c, 256, b.segs)), dim3(256), 0, c->stream, pa);
         hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, seg_cap,
                            infos + level + 1, p.tmin, p.tmaxd);
-        launch_jobs_ds<MODE, V>(c, jl, infos + level + 1, dst_k, dst_v, keys_out, vals_out, infos + level + 1);
+        if (fill) {
+            HIP_OR_FAIL(c, hipEventRecord(c->fill_fork[fb], c->stream));
+            HIP_OR_FAIL(c, hipStreamWaitEvent(c->aux, c->fill_fork[fb], 0));
+            // one block per CU: the fill is bound by HBM writes and leaves
+            // room for the base cases running beside it
+            hipLaunchKernelGGL(k_fill_ds, dim3((uint32_t)std::min<uint64_t>(fcap, (uint64_t)c->ncu)), dim3(1024), 0,
+                               c->aux,
+                               (const FillJob*)c->fills[fb].p, &infos[level + 1].nfills, c->fill_cap[fb], keys_out);
+            HIP_OR_FAIL(c, hipEventRecord(c->fill_done[fb], c->aux));
+            fill_used[fb] = true;
+        }
+        launch_jobs_ds<MODE, V>(c, jl, infos + level + 1, qs + (size_t)(level + 1) * kQueueWords, dst_k, dst_v,
+                                keys_out, vals_out, infos + level + 1);
         HIP_OR_FAIL(c, hipGetLastError());
         loc_k = dst_k;
         loc_v = dst_v;
         cur ^= 1;
     }
+    for (int k = 0; k < 2; ++k)  // joins the second stream (also ends its part of a capture)
+        if (fill_used[k]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[k], 0));
     hipLaunchKernelGGL(k_ds_finish, dim3(1), dim3(64), 0, c->stream, (const LevelInfo*)infos, levels, seg_cap, jl,
-                       (LevelInfo*)c->info.p);
+                       c->fill_cap[0] < c->fill_cap[1] ? c->fill_cap[0] : c->fill_cap[1], (LevelInfo*)c->info.p);
     HIP_OR_FAIL(c, hipGetLastError());
     return SS_OK;
 }
@@ -1267,7 +1319,7 @@ ss_status ss_destroy(ss_ctx* c)
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
-                      &c->ds_jobs, &c->ds_info};
+                      &c->ds_jobs, &c->ds_info, &c->ds_q};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1277,6 +1329,8 @@ ss_status ss_destroy(ss_ctx* c)
     }
     for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->fill_done)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->fill_fork)
         if (e) (void)hipEventDestroy(e);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->info_host) (void)hipHostFree(c->info_host);
@@ -1366,7 +1420,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                             &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
-                      &c->ds_jobs, &c->ds_info};
+                      &c->ds_jobs, &c->ds_info, &c->ds_q};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;

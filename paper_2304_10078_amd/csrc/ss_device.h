@@ -138,6 +138,7 @@ struct LevelArgs {
     // previous level's planning; seg_cap bounds the subproblem list
     const LevelInfo* dims;
     uint32_t seg_cap;
+    uint32_t* q;  // the level's work-queue counters, zero at the start: [0, 8) counting, [8, 16) distribution
 };
 
 // ---------------------------------------------------------------- hashing
@@ -944,14 +945,31 @@ __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
     count_item<MODE>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
 }
 
+// Work queue of a resident grid: the n items are split into eight contiguous
+// ranges, one per XCD (block b runs on XCD b mod 8 when the grid is first
+// dispatched), and the blocks of an XCD take the items of its range in order
+// from a counter.  Neighbouring items then run at the same time on one XCD
+// and share its L2, as with one block per item.  Every range has blocks
+// (the grid is a multiple of 8), so every item is taken whatever the
+// placement.  Returns the next item, or n when the block's range is done.
+__device__ __forceinline__ uint32_t xcd_queue_next(uint32_t* ctr8, uint32_t n, uint32_t* sh)
+{
+    const uint32_t x = blockIdx.x & 7u;
+    const uint32_t lo = (uint32_t)((uint64_t)n * x / 8), hi = (uint32_t)((uint64_t)n * (x + 1) / 8);
+    __syncthreads();  // the previous item's readers of *sh are done
+    if (threadIdx.x == 0) *sh = lo + atomicAdd(ctr8 + x, 1u);
+    __syncthreads();
+    const uint32_t t = *sh;
+    return t < hi ? t : n;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_count_ds(LevelArgs a)
 {
+    __shared__ uint32_t sh_t;
     const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
-    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+    for (uint32_t t = xcd_queue_next(a.q, n, &sh_t); t < n; t = xcd_queue_next(a.q, n, &sh_t))
         count_item<MODE>(a, t, ns, tile);
-        __syncthreads();
-    }
 }
 
 // ================================================================ semisort_<
@@ -1693,11 +1711,10 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
 template <typename V, int W, int E, int RED>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute_ds(LevelArgs a)
 {
+    __shared__ uint32_t sh_t;
     const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
-    for (uint32_t t = blockIdx.x; t < n; t += gridDim.x) {
+    for (uint32_t t = xcd_queue_next(a.q + 8, n, &sh_t); t < n; t = xcd_queue_next(a.q + 8, n, &sh_t))
         distribute_item<V, W, E, RED>(a, t, ns, tile);
-        __syncthreads();
-    }
 }
 
 // Direct form of the distribution: the same stable ranking, but every record
@@ -2117,7 +2134,7 @@ __global__ __launch_bounds__(256) void k_ds_plan_instances(const uint64_t* offs,
 // After the last device-sized level: folds every level's status into *out,
 // and flags subproblems left unfinished or lists that outgrew their room.
 __global__ void k_ds_finish(const LevelInfo* infos, uint32_t levels, uint32_t seg_cap, JobLists jl,
-                            LevelInfo* out)
+                            uint32_t fill_cap, LevelInfo* out)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     uint32_t st = 0;
@@ -2127,6 +2144,7 @@ __global__ void k_ds_finish(const LevelInfo* infos, uint32_t levels, uint32_t se
         if (li.nsegs > seg_cap) st |= kStatusCapacity;
         for (int c = 0; c < kJobClasses; ++c)
             if (li.njobs[c] > jl.cap[c]) st |= kStatusCapacity;
+        if (li.nfills > fill_cap) st |= kStatusCapacity;
     }
     if (infos[levels].nsegs) st |= kStatusTooDeep;
     if (st) atomicOr(&out->status, st);
@@ -2462,14 +2480,41 @@ __global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint6
 }
 
 template <int MODE, typename V>
-__global__ __launch_bounds__(512) void k_base_2pass_ds(const Job* jobs, const uint32_t* count, uint32_t cap,
-                                                       const uint64_t* src_keys, const V* src_vals, uint64_t* out_keys,
-                                                       V* out_vals, LevelInfo* info)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_base_2pass_ds(
+    const Job* jobs, const uint32_t* count, uint32_t cap, uint32_t* ctr, const uint64_t* src_keys, const V* src_vals,
+    uint64_t* out_keys, V* out_vals, LevelInfo* info)
 {
+    // Jobs differ in size: blocks take the next one from a counter, asking
+    // for it (and loading its descriptor) while the current one runs.  Two
+    // blocks per CU, as with one block per job (the register cap keeps the
+    // loop's extra state from costing occupancy).
+    __shared__ uint32_t sh_i;
+    __shared__ Job sh_j;
     const uint32_t n = *count < cap ? *count : cap;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        base_2pass_item<MODE, V>(jobs[i], src_keys, src_vals, out_keys, out_vals, info);
+    if (threadIdx.x == 0) {
+        const uint32_t i = atomicAdd(ctr, 1u);
+        sh_i = i;
+        if (i < n) sh_j = jobs[i];
+    }
+    __syncthreads();
+    for (uint32_t i = __builtin_amdgcn_readfirstlane(sh_i); i < n;) {
+        // block-uniform: scalar registers, as a descriptor loaded by block index
+        const Job j{(uint32_t)__builtin_amdgcn_readfirstlane(sh_j.start),
+                    (uint32_t)__builtin_amdgcn_readfirstlane(sh_j.len)};
+        uint32_t nx = 0;
+        Job jn{0u, 0u};
+        __syncthreads();  // every thread has read sh_i and sh_j
+        if (threadIdx.x == 0) {
+            nx = atomicAdd(ctr, 1u);
+            if (nx < n) jn = jobs[nx];
+        }
+        base_2pass_item<MODE, V>(j, src_keys, src_vals, out_keys, out_vals, info);
+        if (threadIdx.x == 0) {
+            sh_i = nx;
+            sh_j = jn;
+        }
         __syncthreads();
+        i = __builtin_amdgcn_readfirstlane(sh_i);
     }
 }
 
@@ -2633,9 +2678,8 @@ __global__ __launch_bounds__(256) void k_copy_ds(const Job* jobs, const uint32_t
 
 // Key-fill jobs: the keys of a one-key bucket are one value repeated.
 // 16-byte stores after an odd first element, if any.
-__global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, uint64_t* out_keys)
+__device__ __forceinline__ void fill_item(const FillJob j, uint64_t* out_keys)
 {
-    const FillJob j = jobs[blockIdx.x];
     uint64_t* o = out_keys + j.start;
     const uint32_t head = (((uintptr_t)o & 8u) && j.len) ? 1u : 0u;  // keys are 8-byte aligned
     const uint32_t n2 = (j.len - head) / 2;
@@ -2646,6 +2690,19 @@ __global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, uint64_t* ou
     ulonglong2* o2 = (ulonglong2*)(o + head);
     const ulonglong2 kk = make_ulonglong2(j.key, j.key);
     for (uint32_t i = threadIdx.x; i < n2; i += 1024) o2[i] = kk;
+}
+
+__global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, uint64_t* out_keys)
+{
+    fill_item(jobs[blockIdx.x], out_keys);
+}
+
+// Device-counted: the level's fill-job count is read from *count (bounded by cap).
+__global__ __launch_bounds__(1024) void k_fill_ds(const FillJob* jobs, const uint32_t* count, uint32_t cap,
+                                                  uint64_t* out_keys)
+{
+    const uint32_t n = *count < cap ? *count : cap;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) fill_item(jobs[i], out_keys);
 }
 
 // Offsets and heavy list of a single-subproblem level, for inspection.

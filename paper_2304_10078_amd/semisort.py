@@ -262,13 +262,16 @@ def semisort_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, 
     return keys_out, vals_out
 
 
-def semisort_equal_batch_capturable(keys, vals, seg_offsets, keys_out=None, vals_out=None, max_levels=6,
+def semisort_equal_batch_capturable(keys, vals, seg_offsets, keys_out=None, vals_out=None, max_levels=4,
                                     params=None, ctx=None):
     """ss_semisort_equal_batch_capturable: the batch sized on the device, so
     the call can be recorded into a graph (torch.cuda.graph) and replayed.
     seg_offsets: int64 DEVICE tensor of nseg+1 boundaries, the last = len(keys).
     Under capture, pass keys_out / vals_out (allocated before capture) and make
-    one uncaptured call with the same sizes first, so the workspace is sized."""
+    one uncaptured call with the same sizes first, so the workspace is sized.
+    max_levels=4: with the default n_light_log2 every input below 2^31 records
+    needs at most two levels plus the rare third for keys that escape the
+    sample; more levels left unfinished raise SemisortError at sync."""
     import torch
     vb = _check_kv(keys, vals)
     _check_keys(seg_offsets, "seg_offsets")
