@@ -36,6 +36,8 @@ def lib():
         L.orc_histogram.argtypes = [vp, u64, vp, vp]
         L.orc_collect_reduce.restype = i64
         L.orc_collect_reduce.argtypes = [vp, vp, u64, vp, vp]
+        L.orc_collect_reduce_monoid.restype = i64
+        L.orc_collect_reduce_monoid.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
         L.orc_canonicalize_equal.restype = i64
         L.orc_canonicalize_equal.argtypes = [vp, vp, u32, u64, i32, vp, vp]
         L.orc_stats.restype = i32
@@ -117,12 +119,19 @@ def histogram(keys):
     return ok[:m].copy(), oc[:m].copy()
 
 
-def collect_reduce(keys, vals):
+MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3}
+
+
+def collect_reduce(keys, vals, op="sum"):
+    """(unique keys ascending, fold of their values); op one of MONOIDS."""
     keys = _u64(keys)
     vals = _u64(vals)
     ok = np.empty_like(keys)
     os_ = np.empty_like(keys)
-    m = lib().orc_collect_reduce(_p(keys), _p(vals), keys.size, _p(ok), _p(os_))
+    if op == "sum":
+        m = lib().orc_collect_reduce(_p(keys), _p(vals), keys.size, _p(ok), _p(os_))
+    else:
+        m = lib().orc_collect_reduce_monoid(_p(keys), _p(vals), keys.size, MONOIDS[op], _p(ok), _p(os_))
     if m < 0:
         raise MemoryError("oracle collect_reduce")
     return ok[:m].copy(), os_[:m].copy()

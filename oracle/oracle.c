@@ -186,6 +186,56 @@ int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t 
     return m;
 }
 
+/* The monoids of collect-reduce on uint64 values (Section 3.5 allows any
+ * monoid (+, I)): 0 = (+ mod 2^64, 0), 1 = (min, 2^64 - 1), 2 = (max, 0),
+ * 3 = (xor, 0).  All four are associative and commutative. */
+static uint64_t monoid_identity(int op)
+{
+    return op == 1 ? ~0ULL : 0ULL;
+}
+
+static uint64_t monoid_combine(int op, uint64_t x, uint64_t y)
+{
+    switch (op) {
+    case 0: return x + y;
+    case 1: return x < y ? x : y;
+    case 2: return x > y ? x : y;
+    default: return x ^ y;
+    }
+}
+
+int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                  uint64_t* out_keys, uint64_t* out_vals)
+{
+    /* R = { (k, fold of the monoid over M(r), r in S_k) } with M(r) =
+     * value(r); ascending keys. */
+    if (op < 0 || op > 3) return -2;
+    if (n == 0) return 0;
+    kv_t* s = (kv_t*)malloc(n * sizeof(kv_t));
+    if (!s) return -1;
+    for (uint64_t i = 0; i < n; i++) {
+        s[i].k = keys[i];
+        s[i].v = vals[i];
+    }
+    qsort(s, n, sizeof(kv_t), cmp_kv_key);
+    int64_t m = 0;
+    uint64_t p = 0;
+    while (p < n) {
+        uint64_t acc = monoid_identity(op);
+        uint64_t q = p;
+        while (q < n && s[q].k == s[p].k) {
+            acc = monoid_combine(op, acc, s[q].v);
+            q++;
+        }
+        out_keys[m] = s[p].k;
+        out_vals[m] = acc;
+        m++;
+        p = q;
+    }
+    free(s);
+    return m;
+}
+
 typedef struct { uint64_t h, k, start, len; } run_t;
 
 static int cmp_run(const void* a, const void* b)

@@ -55,6 +55,13 @@ int64_t orc_histogram(const uint64_t* keys, uint64_t n, uint64_t* out_keys,
 int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t n,
                            uint64_t* out_keys, uint64_t* out_sums);
 
+/* collect-reduce with map = value and the monoid `op` (Section 3.5): 0 = (+ mod
+ * 2^64, 0), 1 = (min, 2^64 - 1), 2 = (max, 0), 3 = (xor, 0) on uint64; (unique
+ * key, fold of its values), ascending keys.  Returns m, -1 when out of
+ * memory, -2 for an unknown op. */
+int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                  uint64_t* out_keys, uint64_t* out_vals);
+
 /* Canonical form of a candidate semisort_= output: split it into maximal runs
  * of equal keys and order the runs by ascending (h(k), k).  Because a stable
  * semisort is unique up to the order of its groups, a correct output has the

@@ -125,6 +125,57 @@ def test_histogram_and_collect_reduce_brute_force():
         assert int(hc.sum()) == n
 
 
+def test_collect_reduce_monoids_brute_force():
+    # every key sequence of length <= 5 over 3 keys; per key the fold of its
+    # values by Python's own min / max / ^ (the monoids' definitions)
+    rng = np.random.default_rng(17)
+    ops = {"min": min, "max": max, "xor": lambda a, b: a ^ b}
+    for keys in _all_sequences(5):
+        n = len(keys)
+        vals = [int(x) for x in rng.integers(0, 2 ** 63, n, dtype=np.int64)]
+        vals = [(MOD - 1 - v) if i % 3 == 1 else v for i, v in enumerate(vals)]  # top bit set too
+        k = np.array(keys, dtype=np.uint64)
+        v = np.array(vals, dtype=np.uint64)
+        uniq = sorted(set(keys))
+        for name, f in ops.items():
+            ck, cv = O.collect_reduce(k, v, op=name)
+            assert [int(x) for x in ck] == uniq
+            for j, u in enumerate(uniq):
+                group = [vals[i] for i in range(n) if keys[i] == u]
+                acc = group[0]
+                for x in group[1:]:
+                    acc = f(acc, x)
+                assert int(cv[j]) == acc, (name, keys, u)
+
+
+def test_collect_reduce_monoids_match_numpy_segment_reductions():
+    # the same folds by numpy's ufunc.reduceat over the key-sorted values
+    rng = np.random.default_rng(29)
+    for n, M in [(1, 1), (2000, 7), (30000, 5000)]:
+        k = rng.integers(0, M, n, dtype=np.int64).astype(np.uint64)
+        v = rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64) * np.uint64(3)
+        o = np.argsort(k, kind="stable")
+        ks, vs = k[o], v[o]
+        starts = np.flatnonzero(np.concatenate([[True], ks[1:] != ks[:-1]]))
+        for name, uf in (("min", np.minimum), ("max", np.maximum), ("xor", np.bitwise_xor)):
+            ck, cv = O.collect_reduce(k, v, op=name)
+            assert np.array_equal(ck, ks[starts])
+            assert np.array_equal(cv, uf.reduceat(vs, starts)), name
+        ck, cs = O.collect_reduce(k, v, op="sum")
+        assert np.array_equal(cs, np.add.reduceat(vs, starts))  # uint64 adds wrap
+
+
+def test_collect_reduce_monoid_identities():
+    k = np.array([4, 9, 4, 9], dtype=np.uint64)
+    v = np.array([MOD - 1, 0, MOD - 1, 0], dtype=np.uint64)
+    # a value xor-ed with itself vanishes; min / max of equal values is that value
+    assert [int(x) for x in O.collect_reduce(k, v, op="xor")[1]] == [0, 0]
+    assert [int(x) for x in O.collect_reduce(k, v, op="min")[1]] == [MOD - 1, 0]
+    assert [int(x) for x in O.collect_reduce(k, v, op="max")[1]] == [MOD - 1, 0]
+    with pytest.raises(KeyError):
+        O.collect_reduce(k, v, op="product")
+
+
 def test_collect_reduce_wraps_mod_2_64():
     k = np.array([5, 5, 5], dtype=np.uint64)
     v = np.array([MOD - 1, MOD - 1, 3], dtype=np.uint64)
