@@ -60,7 +60,8 @@ def cpu_baseline(keys_dev, vals_dev, m):
 def other_configs(args, S, I, torch):
     """The remaining 10^9-record configurations, one timed call each after a
     warm-up: semisort_= and collect-reduce on uniform[0, 1e9), uniform[0, 1e3)
-    and Zipf-1.2 (u64 keys and values), semisort_< and histogram on
+    and Zipf-1.2 (u64 keys and values; also the min monoid on uniform[0, 1e9)
+    and the max monoid on Zipf-1.2), semisort_< and histogram on
     exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values).  Whole-job
     HBM fraction from the algorithmic bytes per record: semisort K + 2R +
     2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; ordered histogram 2K +
@@ -68,8 +69,9 @@ def other_configs(args, S, I, torch):
     them), with f_H the records whose key occurs more than 500 ln n times."""
     n = 10 ** 9
     res = {}
-    cases = [("uniform1e9", ("semisort_=", "collect_reduce")), ("uniform1e3", ("semisort_=", "collect_reduce")),
-             ("zipf1.2_hashed", ("collect_reduce",)),
+    cases = [("uniform1e9", ("semisort_=", "collect_reduce", "collect_reduce_min")),
+             ("uniform1e3", ("semisort_=", "collect_reduce")),
+             ("zipf1.2_hashed", ("collect_reduce", "collect_reduce_max")),
              ("exp1e-5_u32idx", ("semisort_<", "histogram_ordered")),
              ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram_ordered"))]
     for wl, ops in cases:
@@ -87,9 +89,10 @@ def other_configs(args, S, I, torch):
             elif op == "semisort_<":
                 fn = lambda: S.semisort_less(keys, vals)  # noqa: E731
                 b = 8 + 2 * R + 2 * R * (1 - f_h)
-            elif op == "collect_reduce":
+            elif op.startswith("collect_reduce"):
                 v64 = vals if vals.element_size() == 8 else vals.to(torch.int64)
-                fn = lambda: S.collect_reduce(keys, v64)  # noqa: E731
+                mono = op.split("_")[-1] if op != "collect_reduce" else "sum"  # monoid: sum, min, max
+                fn = lambda mono=mono: S.collect_reduce(keys, v64, op=mono)  # noqa: E731
                 b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
             else:
                 # these workloads need groups in ascending key order

@@ -254,6 +254,22 @@ ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* v
                             uint64_t n, uint64_t* out_keys, uint64_t* out_sums,
                             uint64_t* m_out, const ss_params* params);
 
+/* collect-reduce with another monoid (Section 3.5 defines collect-reduce for
+ * any monoid (+, I)): op selects it on uint64 values.  ordered = 0 gives the
+ * pairs in an unspecified order (as ss_collect_reduce), 1 in ascending key
+ * order (as ss_collect_reduce_ordered).  SS_MONOID_SUM is ss_collect_reduce
+ * itself.  An op outside the enum: SS_EINVAL.  Otherwise the arguments,
+ * conventions and errors of ss_collect_reduce. */
+typedef enum {
+    SS_MONOID_SUM = 0, /* (+ mod 2^64, 0) */
+    SS_MONOID_MIN = 1, /* (min, 2^64 - 1) */
+    SS_MONOID_MAX = 2, /* (max, 0) */
+    SS_MONOID_XOR = 3  /* (xor, 0) */
+} ss_monoid;
+ss_status ss_collect_reduce_monoid(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals,
+                                   uint64_t n, int op, int ordered, uint64_t* out_keys,
+                                   uint64_t* out_vals, uint64_t* m_out, const ss_params* params);
+
 /* histogram (Section 3.5): collect-reduce with every value 1, so no value
  * array is read or moved.  out_counts[i] is the number of records with key
  * out_keys[i].  Same conventions as ss_collect_reduce. */

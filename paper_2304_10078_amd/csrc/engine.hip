@@ -441,6 +441,7 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.res_keys = nullptr;
     a.res_vals = nullptr;
     a.rflag = nullptr;
+    a.rop = 0;
     a.dims = nullptr;
     a.seg_cap = 0;
     a.q = nullptr;
@@ -1038,30 +1039,33 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
 // Reduce-mode jobs of a level: base cases in LDS, sum jobs in the copy class.
 template <int MODE, int ONES>
 void launch_red_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const uint64_t* sv,
-                       uint64_t* rk, uint64_t* rv, uint8_t* rf)
+                       uint64_t* rk, uint64_t* rv, uint8_t* rf, uint32_t op)
 {
     const Job* jobs = (const Job*)c->jobs.p;
-    if (njobs[0]) hipLaunchKernelGGL((k_base_red<MODE, 1, ONES>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, sv, rk, rv, rf);
+    if (njobs[0])
+        hipLaunchKernelGGL((k_base_red<MODE, 1, ONES>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, sv, rk, rv, rf,
+                           op);
     if (njobs[1])
-        hipLaunchKernelGGL((k_base_red<MODE, 2, ONES>), dim3(njobs[1]), dim3(128), 0, c->stream, jobs + cap, sk, sv, rk, rv, rf);
+        hipLaunchKernelGGL((k_base_red<MODE, 2, ONES>), dim3(njobs[1]), dim3(128), 0, c->stream, jobs + cap, sk, sv, rk,
+                           rv, rf, op);
     if (njobs[2])
-        hipLaunchKernelGGL((k_base_red<MODE, 4, ONES>), dim3(njobs[2]), dim3(256), 0, c->stream, jobs + 2 * (size_t)cap, sk, sv,
-                           rk, rv, rf);
+        hipLaunchKernelGGL((k_base_red<MODE, 4, ONES>), dim3(njobs[2]), dim3(256), 0, c->stream, jobs + 2 * (size_t)cap,
+                           sk, sv, rk, rv, rf, op);
     if (njobs[3])
-        hipLaunchKernelGGL((k_base_red<MODE, 8, ONES>), dim3(njobs[3]), dim3(512), 0, c->stream, jobs + 3 * (size_t)cap, sk, sv,
-                           rk, rv, rf);
+        hipLaunchKernelGGL((k_base_red<MODE, 8, ONES>), dim3(njobs[3]), dim3(512), 0, c->stream, jobs + 3 * (size_t)cap,
+                           sk, sv, rk, rv, rf, op);
     if (njobs[kCopyClass])
         hipLaunchKernelGGL((k_sum_job<ONES>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
-                           jobs + (size_t)kCopyClass * cap, sk, sv, rk, rv, rf);
+                           jobs + (size_t)kCopyClass * cap, sk, sv, rk, rv, rf, op);
 }
 
 template <int RED>
 void launch_red_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, const uint64_t* sk,
-                     const uint64_t* sv, uint64_t* rk, uint64_t* rv, uint8_t* rf, uint64_t records)
+                     const uint64_t* sv, uint64_t* rk, uint64_t* rv, uint8_t* rf, uint64_t records, uint32_t op)
 {
     ProfScope ps(c, SS_PROF_FINISH, records);
-    if (mode == 1) launch_red_jobs_m<1, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf);
-    else launch_red_jobs_m<0, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf);
+    if (mode == 1) launch_red_jobs_m<1, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf, op);
+    else launch_red_jobs_m<0, RED == 2>(c, njobs, cap, sk, sv, rk, rv, rf, op);
 }
 
 template <int MODE, int RED>
@@ -1099,7 +1103,7 @@ void launch_red_level_m(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t 
 // inside the ranges of unfinished buckets), then compacted into the output.
 template <int RED>
 ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
-                     uint64_t* out_vals, uint64_t* m_out, const Params& p)
+                     uint64_t* out_vals, uint64_t* m_out, const Params& p, uint32_t op = 0)
 {
     c->call_tmaxd = 0;
     ss_status s;
@@ -1133,7 +1137,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
         *c->job_stage = j;
         HIP_OR_FAIL(c, hipMemcpyAsync((Job*)c->jobs.p + (size_t)cls * c->job_cap, c->job_stage, sizeof(Job),
                                       hipMemcpyHostToDevice, c->stream));
-        launch_red_jobs<RED>(c, p.mode, nj, c->job_cap, keys, vals, T_k, T_v, rf, n);
+        launch_red_jobs<RED>(c, p.mode, nj, c->job_cap, keys, vals, T_k, T_v, rf, n, op);
         HIP_OR_FAIL(c, hipGetLastError());
     } else {
         if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
@@ -1167,12 +1171,13 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
             a.res_keys = T_k;
             a.res_vals = T_v;
             a.rflag = rf;
+            a.rop = op;
             if (p.mode == 1) launch_red_level_m<1, RED>(c, a, tiles, chunks, records);
             else launch_red_level_m<0, RED>(c, a, tiles, chunks, records);
             HIP_OR_FAIL(c, hipGetLastError());
             LevelInfo li;
             if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, false, true, false, &li)) != SS_OK) return s;
-            launch_red_jobs<RED>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, T_k, T_v, rf, li.job_records);
+            launch_red_jobs<RED>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, T_k, T_v, rf, li.job_records, op);
             HIP_OR_FAIL(c, hipGetLastError());
             nsegs = li.nsegs;
             records = li.records;
@@ -1668,6 +1673,22 @@ ss_status ss_histogram(ss_ctx* c, const uint64_t* keys, uint64_t n, uint64_t* ou
     if (n == 0) return SS_OK;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     return run_reduce<2>(c, keys, nullptr, n, out_keys, out_counts, m_out, p);
+}
+
+ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                   int ordered, uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out,
+                                   const ss_params* params)
+{
+    Params p;
+    ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, m_out, params, &p);
+    if (s != SS_OK) return s;
+    if (op < SS_MONOID_SUM || op > SS_MONOID_XOR) return fail(c, SS_EINVAL, "unknown monoid");
+    *m_out = 0;
+    if (n == 0) return SS_OK;
+    if (!vals) return fail(c, SS_EINVAL, "null vals");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if ((s = run_reduce<1>(c, keys, vals, n, out_keys, out_vals, m_out, p, (uint32_t)op)) != SS_OK) return s;
+    return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
 }
 
 ss_status ss_collect_reduce_ordered(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n,

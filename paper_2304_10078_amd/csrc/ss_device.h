@@ -62,6 +62,30 @@ struct Job {
     uint32_t len;
 };
 
+// Monoids of collect-reduce on uint64 values (Section 3.5 allows any monoid):
+// 0 = (+ mod 2^64, 0), 1 = (min, 2^64 - 1), 2 = (max, 0), 3 = (xor, 0).  All
+// are commutative, so partial results may be combined in any order (LDS and
+// global atomics).  op is uniform across a launch.
+__device__ __forceinline__ unsigned long long red_identity(uint32_t op)
+{
+    return op == 1 ? ~0ull : 0ull;
+}
+
+__device__ __forceinline__ unsigned long long red_combine(uint32_t op, unsigned long long x, unsigned long long y)
+{
+    return op == 0 ? x + y : op == 1 ? (x < y ? x : y) : op == 2 ? (x > y ? x : y) : x ^ y;
+}
+
+__device__ __forceinline__ void red_atomic(uint32_t op, unsigned long long* p, unsigned long long v)
+{
+    switch (op) {
+    case 0: atomicAdd(p, v); break;
+    case 1: atomicMin(p, v); break;
+    case 2: atomicMax(p, v); break;
+    default: atomicXor(p, v); break;
+    }
+}
+
 // Keys of a one-key final bucket, written as a constant run instead of being
 // moved record by record.
 struct FillJob {
@@ -133,6 +157,7 @@ struct LevelArgs {
     uint64_t* res_keys;             // results at position coordinates (n entries)
     uint64_t* res_vals;
     uint8_t* rflag;                 // 1 where a result sits
+    uint32_t rop;                   // collect-reduce monoid (red_* below); histogram: 0
     // device-sized levels (the *_ds kernels): the level's subproblem, tile and
     // chunk counts and subarray size are read from dims, written there by the
     // previous level's planning; seg_cap bounds the subproblem list
@@ -807,7 +832,7 @@ __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t s
     for (uint32_t b = tid; b < nL + nh; b += BS) a.bfin[(size_t)sid * kNbStride + b] = b >= nL ? 1 : 0;
     for (uint32_t h = tid; h < nh; h += BS) a.bkey[(size_t)sid * kNbStride + nL + h] = key_of_hash<MODE>(hv[h]);
     if (a.reduce)
-        for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = 0;
+        for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = red_identity(a.rop);
     if (tid == 0) {
         // heavy ids of the two most sampled keys, for the counting pass
         const uint32_t t0 = sh_top[0] ? nL + (uint32_t)(sh_top[0] & 0xFFFFu) : 0xFFFFu;
@@ -1515,7 +1540,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
         if (split && bucket_is_final(fin[b] != 0, bsz[b + 1] - bsz[b], all_bits)) g |= 0x80000000u;
         gbase[b] = g;
         finl[b] = fin[b];
-        if constexpr (RED != 0) hs[b] = 0;
+        if constexpr (RED != 0) hs[b] = RED == 1 ? red_identity(a.rop) : 0ull;
     }
     for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
 
@@ -1585,7 +1610,8 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
             mv[e] = lofs + e * 64u < left;
             if constexpr (RED != 0) {
                 if (mv[e] && finl[bk[e]]) {
-                    atomicAdd(&hs[bk[e]], (unsigned long long)v[e]);
+                    if constexpr (RED == 1) red_atomic(a.rop, &hs[bk[e]], (unsigned long long)v[e]);
+                    else atomicAdd(&hs[bk[e]], (unsigned long long)v[e]);
                     mv[e] = false;
                 }
             }
@@ -1697,7 +1723,8 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     if constexpr (RED != 0) {
         __syncthreads();
         for (uint32_t b = tid; b < nb; b += BS)
-            if (finl[b] && hs[b]) atomicAdd(&a.hsum[(size_t)sid * kHeavyMax + (b - nL)], hs[b]);
+            if (finl[b] && hs[b] != (RED == 1 ? red_identity(a.rop) : 0ull))  // the identity changes nothing
+                red_atomic(RED == 1 ? a.rop : 0u, &a.hsum[(size_t)sid * kHeavyMax + (b - nL)], hs[b]);
     }
     if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
 }
@@ -2748,24 +2775,26 @@ __global__ __launch_bounds__(256) void k_heavy_results(LevelArgs a)
     if (bad) atomicOr(&a.info->status, kStatusSizeMismatch);
 }
 
-// Sum jobs: a bucket whose records all share one key.  One block per job;
-// all reads finish (block reduction) before the single write.
+// Sum jobs: a bucket whose records all share one key, folded with the
+// monoid op.  One block per job; all reads finish (block reduction) before
+// the single write.
 template <int ONES>
 __global__ __launch_bounds__(256) void k_sum_job(const Job* jobs, const uint64_t* src_keys, const uint64_t* src_vals,
-                                                 uint64_t* res_keys, uint64_t* res_vals, uint8_t* rflag)
+                                                 uint64_t* res_keys, uint64_t* res_vals, uint8_t* rflag, uint32_t op)
 {
     __shared__ unsigned long long acc;
     const Job j = jobs[blockIdx.x];
-    if (threadIdx.x == 0) acc = 0;
+    const unsigned long long id = red_identity(op);
+    if (threadIdx.x == 0) acc = id;
     __syncthreads();
-    unsigned long long s = 0;
+    unsigned long long s = id;
     if constexpr (ONES) {
         s = threadIdx.x == 0 ? j.len : 0u;
     } else {
-        for (uint32_t i = threadIdx.x; i < j.len; i += 256) s += src_vals[(uint64_t)j.start + i];
+        for (uint32_t i = threadIdx.x; i < j.len; i += 256) s = red_combine(op, s, src_vals[(uint64_t)j.start + i]);
     }
     const uint64_t k = src_keys[j.start];
-    if (s) atomicAdd(&acc, s);
+    if (s != id) red_atomic(op, &acc, s);
     __syncthreads();
     if (threadIdx.x == 0) {
         res_keys[j.start] = k;
@@ -2776,14 +2805,14 @@ __global__ __launch_bounds__(256) void k_sum_job(const Job* jobs, const uint64_t
 
 // Base case of collect-reduce for a bucket of at most CAP = W*512 records:
 // an LDS hash table (slot claimed by CAS, keys compared through the owner's
-// index) accumulates each key's sum with LDS atomics and the smallest index
+// index) folds each key's values with LDS atomics of the monoid and the smallest index
 // of the key, f; the record at f writes (key, sum) at start + f.  Positions
 // and sums do not depend on scheduling.  All reads precede all writes, so
 // the results may go to the source array.
 template <int MODE, int W, int ONES>
 __global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint64_t* src_keys,
                                                      const uint64_t* src_vals, uint64_t* res_keys,
-                                                     uint64_t* res_vals, uint8_t* rflag)
+                                                     uint64_t* res_vals, uint8_t* rflag, uint32_t op)
 {
     constexpr int BS = W * 64, E = 8, CAP = BS * E;
     __shared__ uint64_t kl[CAP];
@@ -2812,7 +2841,7 @@ __global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint
     }
     for (uint32_t i = tid; i < slots; i += BS) {
         tab[i] = kEmpty32;
-        ssum[i] = 0;
+        ssum[i] = red_identity(op);
     }
     __syncthreads();
     uint32_t sl[E];
@@ -2838,7 +2867,7 @@ __global__ __launch_bounds__(W * 64) void k_base_red(const Job* jobs, const uint
         const uint32_t i = w * 64 * E + e * 64 + lane;
         if (i < m) {
             atomicMin(&tab[sl[e]], i);
-            atomicAdd(&ssum[sl[e]], (unsigned long long)v[e]);
+            red_atomic(op, &ssum[sl[e]], (unsigned long long)v[e]);
         }
     }
     __syncthreads();

@@ -81,6 +81,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_double)]
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
         L.ss_semisort_equal_batch_capturable.argtypes = [vp, vp, vp, u32, vp, u64, u64, vp, vp, u32, P]
+        L.ss_collect_reduce_monoid.argtypes = [vp, vp, vp, u64, i32, i32, vp, vp, ctypes.POINTER(u64), P]
         L.ss_collect_reduce_ordered.argtypes = L.ss_collect_reduce.argtypes
         L.ss_histogram_ordered.argtypes = L.ss_histogram.argtypes
         for name in declared_symbols():
@@ -315,9 +316,13 @@ def _check_keys(keys, name="keys"):
         raise ValueError(f"{name} must be a contiguous 1-D int64 device tensor (uint64 bits)")
 
 
-def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False):
+MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3}
+
+
+def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False, op="sum"):
     """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values);
-    ss_collect_reduce_ordered with ordered=True (keys ascending as uint64).
+    ss_collect_reduce_ordered with ordered=True (keys ascending as uint64);
+    ss_collect_reduce_monoid for op in "min", "max", "xor" (uint64 values).
 
     Returns views of length m of the two output tensors (capacity n each)."""
     import torch
@@ -332,9 +337,15 @@ def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=No
     if out_sums is None:
         out_sums = torch.empty_like(keys)
     m = ctypes.c_uint64()
-    fn = lib().ss_collect_reduce_ordered if ordered else lib().ss_collect_reduce
-    ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(out_keys), _ptr(out_sums),
-                 ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    pp = ctypes.byref(params) if params is not None else None
+    if op != "sum":
+        ctx.check(lib().ss_collect_reduce_monoid(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), MONOIDS[op],
+                                                 int(bool(ordered)), _ptr(out_keys), _ptr(out_sums),
+                                                 ctypes.byref(m), pp))
+    else:
+        fn = lib().ss_collect_reduce_ordered if ordered else lib().ss_collect_reduce
+        ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), _ptr(out_keys), _ptr(out_sums),
+                     ctypes.byref(m), pp))
     return out_keys[:m.value], out_sums[:m.value]
 
 

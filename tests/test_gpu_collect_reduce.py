@@ -207,3 +207,66 @@ def test_ordered_results_empty_and_small_parameters():
     p = S.default_params(n_light_log2=2, base_case=256, sample_mult=20, tile_min=8192, tile_max=8192)
     _say("case: ordered histogram, small parameters")
     check_ordered(k, params=p, ctx="ordered hist small params")
+
+
+def check_monoid(keys, vals, op, ordered=False, params=None, ctx=""):
+    """collect-reduce with the min / max / xor monoids against the oracle."""
+    gk, gv = S.collect_reduce(to_dev(keys), to_dev(vals), params=params, ordered=ordered, op=op)
+    S.sync()
+    gk, gv = to_host(gk, np.uint64), to_host(gv, np.uint64)
+    if not ordered:
+        gk, gv = _sorted_pairs(gk, gv)
+    rk, rv = O.collect_reduce(keys, vals, op=op)
+    assert gk.size == rk.size, f"{ctx}: {gk.size} groups, oracle {rk.size}"
+    assert np.array_equal(gk, rk), f"{ctx}: keys differ"
+    if not np.array_equal(gv, rv):
+        i = int(np.nonzero(gv != rv)[0][0])
+        raise AssertionError(f"{ctx}: {op} of key {rk[i]} is {gv[i]}, oracle {rv[i]}")
+
+
+def _wide_values(n, seed):
+    # uint64 values over the whole range (the top bit decides unsigned min / max)
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(seed & 1)
+
+
+@pytest.mark.parametrize("op", ["min", "max", "xor"])
+@pytest.mark.parametrize("name,n", [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 1_000_000),
+                                    ("uniform1e3", 700_000), ("exp1e-5_u32idx", 900_000)])
+def test_monoids_paper_distributions(op, name, n):
+    k, _ = I.np_workload(name, n, 31)
+    v = _wide_values(n, 5)
+    _say(f"case: CR {op} {name} n={n}")
+    check_monoid(k, v, op, ctx=f"CR {op} {name}")
+
+
+@pytest.mark.parametrize("op", ["min", "max", "xor"])
+def test_monoids_ragged_ordered_and_deep(op):
+    for n in [1, 2, 3, 64, 4097, 65537, 200_003]:
+        rng = np.random.default_rng(n)
+        k = rng.integers(0, max(2, n // 6), n, dtype=np.int64).astype(np.uint64)
+        v = _wide_values(n, n)
+        _say(f"case: CR {op} ragged n={n}")
+        check_monoid(k, v, op, ctx=f"CR {op} n={n}")
+        check_monoid(k, v, op, ordered=True, ctx=f"CR {op} ordered n={n}")
+    rng = np.random.default_rng(9)
+    n = 150_000
+    k = rng.integers(0, 40_000, n, dtype=np.int64).astype(np.uint64)
+    v = _wide_values(n, 3)
+    p = S.default_params(n_light_log2=1, base_case=64, sample_mult=20)
+    _say(f"case: CR {op} deep recursion")
+    check_monoid(k, v, op, params=p, ctx=f"CR {op} deep")
+    k = np.full(n, 77, dtype=np.uint64)  # one key: a single heavy bucket
+    check_monoid(k, v, op, ctx=f"CR {op} one key")
+
+
+def test_monoid_rejects_an_unknown_op():
+    import ctypes
+    k = torch.zeros(100, dtype=torch.int64, device="cuda")
+    v = torch.zeros(100, dtype=torch.int64, device="cuda")
+    ok, ov = torch.empty_like(k), torch.empty_like(k)
+    m = ctypes.c_uint64()
+    ctx = S.context(0)
+    st = S.lib().ss_collect_reduce_monoid(ctx.h, S._ptr(k), S._ptr(v), 100, 7, 0, S._ptr(ok), S._ptr(ov),
+                                          ctypes.byref(m), None)
+    assert st == S.SS_EINVAL

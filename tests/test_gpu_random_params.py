@@ -94,6 +94,14 @@ def test_random_shapes_and_parameters(case):
     rk, rc = O.histogram(k)
     assert np.array_equal(gk[o], rk) and np.array_equal(gc[o], rc), f"case {case} histogram"
 
+    op = ("min", "max", "xor")[case % 3]
+    gk, gs = S.collect_reduce(to_dev(k), to_dev(vals), params=p, op=op)
+    S.sync()
+    gk, gs = to_host(gk, np.uint64), to_host(gs, np.uint64)
+    o = np.argsort(gk, kind="stable")
+    mk, ms = O.collect_reduce(k, vals, op=op)
+    assert np.array_equal(gk[o], mk) and np.array_equal(gs[o], ms), f"case {case} collect-reduce {op}"
+
     gk, gc = S.histogram(to_dev(k), params=p, ordered=True)
     S.sync()
     assert np.array_equal(to_host(gk, np.uint64), rk), f"case {case} ordered histogram keys"
