@@ -36,6 +36,8 @@ def lib():
         L.orc_histogram.argtypes = [vp, u64, vp, vp]
         L.orc_collect_reduce.restype = i64
         L.orc_collect_reduce.argtypes = [vp, vp, u64, vp, vp]
+        L.orc_transpose_csr.restype = ctypes.c_int
+        L.orc_transpose_csr.argtypes = [u64, u64, vp, vp, vp, vp]
         L.orc_collect_reduce_monoid.restype = i64
         L.orc_collect_reduce_monoid.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
         L.orc_canonicalize_equal.restype = i64
@@ -135,6 +137,22 @@ def collect_reduce(keys, vals, op="sum"):
     if m < 0:
         raise MemoryError("oracle collect_reduce")
     return ok[:m].copy(), os_[:m].copy()
+
+
+def transpose_csr(offs, cols):
+    """Transposed CSR (offsets uint64[nv + 1], cols uint32[ne]) of the graph
+    with offsets `offs` (nv + 1 entries) and targets `cols` (uint32)."""
+    offs = np.ascontiguousarray(offs, dtype=np.uint64)
+    cols = np.ascontiguousarray(cols, dtype=np.uint32)
+    nv, ne = offs.size - 1, cols.size
+    oo = np.empty(nv + 1, dtype=np.uint64)
+    oc = np.empty(max(ne, 1), dtype=np.uint32)
+    r = lib().orc_transpose_csr(nv, ne, _p(offs), _p(cols), _p(oo), _p(oc))
+    if r == -2:
+        raise ValueError("invalid CSR")
+    if r != 0:
+        raise MemoryError("oracle transpose_csr")
+    return oo, oc[:ne].copy()
 
 
 def canonicalize_equal(keys, vals, hash_mode=HASH_MIX64):

@@ -236,6 +236,30 @@ int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, ui
     return m;
 }
 
+int orc_transpose_csr(uint64_t nv, uint64_t ne, const uint64_t* offs, const uint32_t* cols,
+                      uint64_t* out_offs, uint32_t* out_cols)
+{
+    /* E^T = { (u, v) : (v, u) in E } (Section 5, graph transposing), in CSR:
+     * out_offs[v] = number of edges whose other endpoint is below v, and the
+     * edges into v listed in input order (first endpoints ascending for a
+     * row-ordered input), i.e. a stable counting sort of the edges by their
+     * other endpoint. */
+    if (offs[0] != 0 || offs[nv] != ne) return -2;
+    for (uint64_t u = 0; u < nv; u++)
+        if (offs[u + 1] < offs[u]) return -2;
+    for (uint64_t e = 0; e < ne; e++)
+        if (cols[e] >= nv) return -2;
+    uint64_t* next = (uint64_t*)calloc(nv + 1, sizeof(uint64_t));
+    if (!next) return -1;
+    for (uint64_t e = 0; e < ne; e++) next[cols[e] + 1]++;
+    for (uint64_t v = 0; v < nv; v++) next[v + 1] += next[v];
+    memcpy(out_offs, next, (nv + 1) * sizeof(uint64_t));
+    for (uint64_t u = 0; u < nv; u++)
+        for (uint64_t e = offs[u]; e < offs[u + 1]; e++) out_cols[next[cols[e]]++] = (uint32_t)u;
+    free(next);
+    return 0;
+}
+
 typedef struct { uint64_t h, k, start, len; } run_t;
 
 static int cmp_run(const void* a, const void* b)

@@ -62,6 +62,13 @@ int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t 
 int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                   uint64_t* out_keys, uint64_t* out_vals);
 
+/* Transpose of a directed graph in CSR (Section 5, graph transposing):
+ * nv vertices, ne edges, offs[nv + 1], cols[ne] < nv.  out_offs[nv + 1] and
+ * out_cols[ne] receive the transposed CSR, each vertex's in-neighbours in
+ * input order.  Returns 0, -1 when out of memory, -2 for an invalid CSR. */
+int orc_transpose_csr(uint64_t nv, uint64_t ne, const uint64_t* offs, const uint32_t* cols,
+                      uint64_t* out_offs, uint32_t* out_cols);
+
 /* Canonical form of a candidate semisort_= output: split it into maximal runs
  * of equal keys and order the runs by ascending (h(k), k).  Because a stable
  * semisort is unique up to the order of its groups, a correct output has the

@@ -352,3 +352,54 @@ def test_count_prefix_distribute_against_definitions():
     for h in range(heavy.size):
         a, b = int(off[(1 << nl_bits) + h]), int(off[(1 << nl_bits) + h + 1])
         assert np.all(tk[a:b] == heavy[h])
+
+
+def _random_csr(rng, nv, ne, sort_rows=False, unique=False):
+    if unique:
+        pairs = rng.choice(nv * nv, size=min(ne, nv * nv), replace=False)
+        src, dst = pairs // nv, pairs % nv
+    else:
+        src = rng.integers(0, nv, ne)
+        dst = rng.integers(0, nv, ne)
+    o = np.lexsort((dst, src)) if sort_rows else np.argsort(src, kind="stable")
+    src, dst = src[o], dst[o]
+    offs = np.zeros(nv + 1, dtype=np.uint64)
+    np.add.at(offs, src + 1, 1)
+    return np.cumsum(offs).astype(np.uint64), dst.astype(np.uint32)
+
+
+def test_transpose_csr_brute_force():
+    # E^T lists, for every vertex v, the first endpoints u of the edges (u, v)
+    # in input order
+    rng = np.random.default_rng(41)
+    for nv, ne in [(1, 0), (1, 3), (2, 5), (5, 0), (5, 12), (7, 40), (30, 200)]:
+        offs, cols = _random_csr(rng, nv, ne)
+        oo, oc = O.transpose_csr(offs, cols)
+        lists = [[] for _ in range(nv)]
+        for u in range(nv):
+            for e in range(int(offs[u]), int(offs[u + 1])):
+                lists[int(cols[e])].append(u)
+        assert [int(x) for x in oo] == [0] + list(np.cumsum([len(x) for x in lists]))
+        assert [int(x) for x in oc] == [u for x in lists for u in x]
+
+
+def test_transpose_csr_matches_scipy_and_is_an_involution():
+    sp = pytest.importorskip("scipy.sparse")
+    rng = np.random.default_rng(43)
+    for nv, ne in [(50, 300), (1000, 20000), (3000, 3000)]:
+        offs, cols = _random_csr(rng, nv, ne, sort_rows=True, unique=True)
+        oo, oc = O.transpose_csr(offs, cols)
+        a = sp.csr_matrix((np.ones(cols.size), cols.astype(np.int64), offs.astype(np.int64)), shape=(nv, nv))
+        t = a.T.tocsr()
+        t.sort_indices()
+        assert np.array_equal(oo, t.indptr.astype(np.uint64))
+        assert np.array_equal(oc, t.indices.astype(np.uint32))
+        bo, bc = O.transpose_csr(oo, oc)
+        assert np.array_equal(bo, offs) and np.array_equal(bc, cols)
+
+
+def test_transpose_csr_rejects_an_invalid_graph():
+    with pytest.raises(ValueError):
+        O.transpose_csr(np.array([0, 2], dtype=np.uint64), np.array([0, 1], dtype=np.uint32))  # target >= nv
+    with pytest.raises(ValueError):
+        O.transpose_csr(np.array([0, 3, 2], dtype=np.uint64), np.array([0, 1], dtype=np.uint32))
