@@ -289,6 +289,24 @@ ss_status ss_collect_reduce_ordered(ss_ctx* ctx, const uint64_t* keys, const uin
 ss_status ss_histogram_ordered(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
                                uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
 
+/* Transpose of a directed graph in CSR (Section 5, graph transposing): the
+ * transpose holds (u, v) for every edge (v, u), which for a CSR input is a
+ * semisort of the edges by their other endpoint; a stable one keeps every
+ * vertex's new neighbours in input order (ascending for a row-ordered CSR).
+ * nv vertices (below 2^32), ne edges (below 2^31); offsets[nv + 1] (uint64,
+ * non-decreasing from 0 to ne) and cols[ne] (uint32 targets below nv) are
+ * device arrays of the input; out_offsets[nv + 1] and out_cols[ne] receive the
+ * transpose.  The edges are expanded to (target, source) records, sorted by
+ * the semisort_< path (stable), and the new offsets are the first position of
+ * every target (vertices without edges take the next one).  Workspace: 20
+ * bytes per edge besides semisort_<'s own.  SS_EINVAL for bad sizes,
+ * overlapping arrays or offsets that do not start at 0 and end at ne (read
+ * once from the device); SS_EDEVICE when an offset decreases or a target is
+ * not below nv.  The call waits for its stream before returning. */
+ss_status ss_transpose_csr(ss_ctx* ctx, uint64_t nv, uint64_t ne, const uint64_t* offsets,
+                           const uint32_t* cols, uint64_t* out_offsets, uint32_t* out_cols,
+                           const ss_params* params);
+
 /* ---- serving (continuous batching of group-by requests) ----------------
  *
  * A server owns `lanes` worker threads, each driving its own context on its

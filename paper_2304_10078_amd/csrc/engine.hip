@@ -51,6 +51,7 @@ struct ss_ctx {
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
+    DevBuf tr_keys, tr_vals, tr_sorted, tr_min;  // graph transpose: records, sorted endpoints, chunk minima
     std::vector<Seg> host_segs;
     std::vector<Job> host_jobs[kJobClasses];
     uint32_t job_cap = 0;  // entries per class list
@@ -1324,7 +1325,8 @@ ss_status ss_destroy(ss_ctx* c)
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
-                      &c->ds_jobs, &c->ds_info, &c->ds_q};
+                      &c->ds_jobs, &c->ds_info, &c->ds_q,
+                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1425,7 +1427,8 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
     const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                             &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
-                      &c->ds_jobs, &c->ds_info, &c->ds_q};
+                      &c->ds_jobs, &c->ds_info, &c->ds_q,
+                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -1673,6 +1676,67 @@ ss_status ss_histogram(ss_ctx* c, const uint64_t* keys, uint64_t n, uint64_t* ou
     if (n == 0) return SS_OK;
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     return run_reduce<2>(c, keys, nullptr, n, out_keys, out_counts, m_out, p);
+}
+
+ss_status ss_transpose_csr(ss_ctx* c, uint64_t nv, uint64_t ne, const uint64_t* offs, const uint32_t* cols,
+                           uint64_t* out_offs, uint32_t* out_cols, const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (nv >= (1ull << 32)) return fail(c, SS_EINVAL, "vertex ids must fit in 32 bits");
+    if (ne >= (1ull << 31)) return fail(c, SS_EINVAL, "ne must be below 2^31");
+    if (!offs || !out_offs || (ne && (!cols || !out_cols))) return fail(c, SS_EINVAL, "null array pointer");
+    if (ne && nv == 0) return fail(c, SS_EINVAL, "edges without vertices");
+    if (ne && (overlaps(out_cols, ne * 4, cols, ne * 4) || overlaps(out_offs, (nv + 1) * 8, offs, (nv + 1) * 8) ||
+               overlaps(out_offs, (nv + 1) * 8, out_cols, ne * 4)))
+        return fail(c, SS_EINVAL, "outputs overlap inputs or each other");
+    Params p;
+    ss_status s = resolve_params(c, params, &p);
+    if (s != SS_OK) return s;
+    p.mode = 2;
+    default_tiles(c, params, &p, 32768u, 65536u);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
+    if ((s = reset_counters(c)) != SS_OK) return s;
+    // the CSR's ends, read once: offs[0] = 0 and offs[nv] = ne
+    uint64_t ends[2] = {1, 0};
+    HIP_OR_FAIL(c, hipMemcpyAsync(&ends[0], offs, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(&ends[1], offs + nv, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (ends[0] != 0 || ends[1] != ne) return fail(c, SS_EINVAL, "offsets must start at 0 and end at ne");
+    uint64_t* out = out_offs;
+    const uint64_t n = nv + 1;
+    const uint64_t nb = (n + kMinChunk - 1) / kMinChunk;
+    if ((s = ensure(c, c->tr_min, nb * 8)) != SS_OK) return s;
+    LevelInfo* info = (LevelInfo*)c->info.p;
+    uint64_t* sk = nullptr;
+    if (ne) {
+        if ((s = ensure(c, c->tr_keys, ne * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->tr_vals, ne * 4)) != SS_OK) return s;
+        if ((s = ensure(c, c->tr_sorted, ne * 8)) != SS_OK) return s;
+        uint64_t* tk = (uint64_t*)c->tr_keys.p;
+        uint32_t* tv = (uint32_t*)c->tr_vals.p;
+        sk = (uint64_t*)c->tr_sorted.p;
+        hipLaunchKernelGGL(k_csr_check, dim3((uint32_t)std::min<uint64_t>((nv + 255) / 256, 65536)), dim3(256), 0,
+                           c->stream, offs, (uint32_t)nv, info);
+        hipLaunchKernelGGL(k_csr_expand, dim3((uint32_t)((ne + kExpandEdges - 1) / kExpandEdges)), dim3(256), 0,
+                           c->stream, offs, cols, (uint32_t)nv, ne, tk, tv, info);
+        HIP_OR_FAIL(c, hipGetLastError());
+        // the transpose proper: a stable semisort_< by the other endpoint
+        const uint64_t so[2] = {0, ne};
+        if ((s = run_semisort<uint32_t>(c, tk, tv, so, 1, sk, out_cols, p)) != SS_OK) return s;
+    }
+    hipLaunchKernelGGL(k_csr_init, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                       c->stream, out, (uint32_t)nv, ne);
+    if (ne)
+        hipLaunchKernelGGL(k_csr_starts, dim3((uint32_t)std::min<uint64_t>((ne + 255) / 256, 65536)), dim3(256), 0,
+                           c->stream, (const uint64_t*)sk, ne, (uint32_t)nv, out, info);
+    hipLaunchKernelGGL(k_min_chunks, dim3((uint32_t)nb), dim3(256), 0, c->stream, (const uint64_t*)out, n,
+                       (uint64_t*)c->tr_min.p);
+    hipLaunchKernelGGL(k_min_carry, dim3(1), dim3(1024), 0, c->stream, (uint64_t*)c->tr_min.p, (uint32_t)nb);
+    hipLaunchKernelGGL(k_min_fill, dim3((uint32_t)nb), dim3(256), 0, c->stream, out, n,
+                       (const uint64_t*)c->tr_min.p);
+    HIP_OR_FAIL(c, hipGetLastError());
+    return ss_sync(c);
 }
 
 ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,

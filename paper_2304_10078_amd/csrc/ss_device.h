@@ -40,6 +40,7 @@ constexpr uint32_t kStatusHeavyTable = 8u;     // the heavy table could not be b
 constexpr uint32_t kStatusBadOffsets = 16u;    // instance offsets not non-decreasing from 0 to n
 constexpr uint32_t kStatusTooDeep = 32u;       // subproblems left after the last device-sized level
 constexpr uint32_t kStatusCapacity = 64u;      // a device-sized level outgrew a reserved list
+constexpr uint32_t kStatusBadGraph = 128u;     // CSR offsets not non-decreasing, or a target >= the vertex count
 
 struct Seg {
     uint32_t start;    // absolute first record
@@ -2089,6 +2090,174 @@ __global__ __launch_bounds__(1024) void k_seg_prefix(Seg* segs, uint32_t cap, Le
         info->chunks = run_c;
         info->tile = tile;
         info->records = sh_total;
+    }
+}
+
+// ---------------------------------------------------------------- graph transpose
+// Section 5 (graph transposing): for a CSR graph the transpose is a stable
+// semisort of the edges by their other endpoint.  These kernels turn the CSR
+// into (other endpoint, first endpoint) records and the sorted endpoints back
+// into row offsets; the sort in between is semisort_<.
+
+constexpr uint32_t kExpandEdges = 4096;  // edges per block of k_csr_expand
+
+// Last row r in [lo, hi] with offs[r] <= e (offs non-decreasing over the range).
+__device__ __forceinline__ uint32_t csr_row_of(const uint64_t* offs, uint32_t lo, uint32_t hi, uint64_t e)
+{
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (offs[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Offsets must not decrease (the ends are checked on the host).
+__global__ __launch_bounds__(256) void k_csr_check(const uint64_t* offs, uint32_t nv, LevelInfo* info)
+{
+    bool bad = false;
+    for (uint64_t u = (uint64_t)blockIdx.x * 256 + threadIdx.x; u < nv; u += (uint64_t)gridDim.x * 256)
+        bad |= offs[u + 1] < offs[u];
+    if (bad) atomicOr(&info->status, kStatusBadGraph);
+}
+
+// Edge e of row u becomes the record (key cols[e], value u).  A block takes
+// kExpandEdges consecutive edges; its first and last rows are found once over
+// all rows, each edge's row then inside that range.
+__global__ __launch_bounds__(256) void k_csr_expand(const uint64_t* offs, const uint32_t* cols, uint32_t nv,
+                                                    uint64_t ne, uint64_t* keys, uint32_t* vals, LevelInfo* info)
+{
+    __shared__ uint32_t sh_r[2];
+    const uint64_t s = (uint64_t)blockIdx.x * kExpandEdges;
+    const uint64_t t = s + kExpandEdges < ne ? s + kExpandEdges : ne;
+    if (threadIdx.x < 2) sh_r[threadIdx.x] = csr_row_of(offs, 0, nv - 1, threadIdx.x ? t - 1 : s);
+    __syncthreads();
+    const uint32_t r0 = sh_r[0], r1 = sh_r[1] < r0 ? r0 : sh_r[1];
+    bool bad = false;
+    for (uint64_t e = s + threadIdx.x; e < t; e += 256) {
+        const uint32_t v = cols[e];
+        const uint32_t u = csr_row_of(offs, r0, r1, e);
+        bad |= v >= nv || offs[u] > e || offs[u + 1] <= e;
+        keys[e] = v;
+        vals[e] = u;
+    }
+    if (bad) atomicOr(&info->status, kStatusBadGraph);
+}
+
+// Row offsets of the transpose from the sorted endpoints: the first position
+// of every endpoint value v goes to out[v] (out[] starts at ~0, out[nv] = ne),
+// then a suffix minimum gives the vertices without edges the next start.
+__global__ __launch_bounds__(256) void k_csr_starts(const uint64_t* skeys, uint64_t ne, uint32_t nv, uint64_t* out,
+                                                    LevelInfo* info)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < ne; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t k = skeys[i];
+        if (k >= nv) {
+            atomicOr(&info->status, kStatusBadGraph);
+            continue;
+        }
+        if (i == 0 || skeys[i - 1] != k) out[k] = i;
+    }
+}
+
+// out[v] = ~0 for v < nv (no start yet), out[nv] = ne.
+__global__ __launch_bounds__(256) void k_csr_init(uint64_t* out, uint32_t nv, uint64_t ne)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i <= nv; i += (uint64_t)gridDim.x * 256)
+        out[i] = i == nv ? ne : ~0ull;
+}
+
+constexpr uint32_t kMinChunk = 4096;  // entries per block of the suffix-minimum passes
+
+__device__ __forceinline__ unsigned long long block_min_u64(unsigned long long x, unsigned long long* tmp)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        const unsigned long long y = __shfl_xor(x, o, 64);
+        x = y < x ? y : x;
+    }
+    const uint32_t w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) tmp[w] = x;
+    __syncthreads();
+    unsigned long long m = tmp[0];
+    for (uint32_t i = 1; i < nw; ++i) m = tmp[i] < m ? tmp[i] : m;
+    return m;
+}
+
+// Pass 1: the minimum of every chunk of out[0 .. n).
+__global__ __launch_bounds__(256) void k_min_chunks(const uint64_t* out, uint64_t n, uint64_t* cmin)
+{
+    __shared__ unsigned long long tmp[4];
+    const uint64_t s = (uint64_t)blockIdx.x * kMinChunk;
+    unsigned long long m = ~0ull;
+    for (uint64_t i = s + threadIdx.x; i < s + kMinChunk && i < n; i += 256) m = out[i] < m ? out[i] : m;
+    m = block_min_u64(m, tmp);
+    if (threadIdx.x == 0) cmin[blockIdx.x] = m;
+}
+
+// Pass 2 (one block): cmin[b] becomes the minimum over the chunks after b.
+__global__ __launch_bounds__(1024) void k_min_carry(uint64_t* cmin, uint32_t nb)
+{
+    __shared__ unsigned long long buf[1024];
+    __shared__ unsigned long long sh_carry;
+    if (threadIdx.x == 0) sh_carry = ~0ull;
+    __syncthreads();
+    // walk the chunk minima from the end, 1024 at a time
+    for (int64_t base = (int64_t)nb - 1024; base > -1024; base -= 1024) {
+        const int64_t i = base + (int64_t)threadIdx.x;
+        const unsigned long long v = i >= 0 ? cmin[i] : ~0ull;
+        // inclusive suffix minimum over the threads of this round (Hillis-Steele in LDS)
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (uint32_t o = 1; o < 1024; o <<= 1) {
+            const unsigned long long y = threadIdx.x + o < 1024 ? buf[threadIdx.x + o] : ~0ull;
+            __syncthreads();
+            if (y < buf[threadIdx.x]) buf[threadIdx.x] = y;
+            __syncthreads();
+        }
+        const unsigned long long carry = sh_carry;
+        const unsigned long long after = threadIdx.x + 1 < 1024 ? buf[threadIdx.x + 1] : ~0ull;
+        if (i >= 0) cmin[i] = after < carry ? after : carry;
+        __syncthreads();
+        if (threadIdx.x == 0) sh_carry = buf[0] < carry ? buf[0] : carry;
+        __syncthreads();
+    }
+}
+
+// Pass 3: out[i] = min(out[i .. end of chunk], cmin[chunk]) -- each chunk's
+// suffix minimum from the end, sequential per thread over 16 entries.
+__global__ __launch_bounds__(256) void k_min_fill(uint64_t* out, uint64_t n, const uint64_t* cmin)
+{
+    __shared__ unsigned long long buf[256];
+    const uint64_t s = (uint64_t)blockIdx.x * kMinChunk;
+    constexpr uint32_t per = kMinChunk / 256;
+    const uint64_t p0 = s + (uint64_t)threadIdx.x * per;
+    unsigned long long loc[per];
+    unsigned long long m = ~0ull;
+#pragma unroll
+    for (int j = per - 1; j >= 0; --j) {
+        const uint64_t i = p0 + j;
+        const unsigned long long x = i < n ? out[i] : ~0ull;
+        m = x < m ? x : m;
+        loc[j] = m;
+    }
+    // suffix minimum of the threads' minima (thread t needs threads > t)
+    buf[threadIdx.x] = m;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        const unsigned long long y = threadIdx.x + o < 256 ? buf[threadIdx.x + o] : ~0ull;
+        __syncthreads();
+        if (y < buf[threadIdx.x]) buf[threadIdx.x] = y;
+        __syncthreads();
+    }
+    unsigned long long c = threadIdx.x + 1 < 256 ? buf[threadIdx.x + 1] : ~0ull;
+    const unsigned long long cc = cmin[blockIdx.x];
+    c = cc < c ? cc : c;
+#pragma unroll
+    for (int j = 0; j < (int)per; ++j) {
+        const uint64_t i = p0 + j;
+        if (i < n) out[i] = loc[j] < c ? loc[j] : c;
     }
 }
 

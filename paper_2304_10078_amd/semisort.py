@@ -82,6 +82,7 @@ def lib():
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
         L.ss_semisort_equal_batch_capturable.argtypes = [vp, vp, vp, u32, vp, u64, u64, vp, vp, u32, P]
         L.ss_collect_reduce_monoid.argtypes = [vp, vp, vp, u64, i32, i32, vp, vp, ctypes.POINTER(u64), P]
+        L.ss_transpose_csr.argtypes = [vp, u64, u64, vp, vp, vp, vp, P]
         L.ss_collect_reduce_ordered.argtypes = L.ss_collect_reduce.argtypes
         L.ss_histogram_ordered.argtypes = L.ss_histogram.argtypes
         for name in declared_symbols():
@@ -365,6 +366,26 @@ def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None, order
     ctx.check(fn(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
                  ctypes.byref(m), ctypes.byref(params) if params is not None else None))
     return out_keys[:m.value], out_counts[:m.value]
+
+
+def transpose_csr(offsets, cols, params=None, ctx=None, out_offsets=None, out_cols=None):
+    """ss_transpose_csr: the transpose of a CSR graph.  offsets: int64 device
+    tensor of nv + 1 entries; cols: int32 device tensor of targets (uint32
+    bits).  Returns (out_offsets, out_cols) of the same shapes."""
+    import torch
+    _check_keys(offsets, "offsets")
+    if not cols.is_cuda or cols.dtype != torch.int32 or cols.dim() != 1 or not cols.is_contiguous():
+        raise ValueError("cols must be a contiguous 1-D int32 device tensor (uint32 bits)")
+    ctx = ctx or context(offsets.device.index or 0)
+    ctx._bind_stream()
+    if out_offsets is None:
+        out_offsets = torch.empty_like(offsets)
+    if out_cols is None:
+        out_cols = torch.empty_like(cols)
+    ctx.check(lib().ss_transpose_csr(ctx.h, offsets.numel() - 1, cols.numel(), _ptr(offsets), _ptr(cols),
+                                     _ptr(out_offsets), _ptr(out_cols),
+                                     ctypes.byref(params) if params is not None else None))
+    return out_offsets, out_cols
 
 
 def autotune_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, reps=2, ctx=None):

@@ -19,7 +19,8 @@ def test_header_declares_the_boundary():
     names = S.declared_symbols()
     for want in ["ss_create", "ss_destroy", "ss_semisort_equal", "ss_semisort_equal_batch",
                  "ss_semisort_less", "ss_semisort_less_batch", "ss_collect_reduce", "ss_histogram",
-                 "ss_collect_reduce_ordered", "ss_histogram_ordered",
+                 "ss_collect_reduce_ordered", "ss_histogram_ordered", "ss_collect_reduce_monoid",
+                 "ss_transpose_csr", "ss_semisort_equal_batch_capturable",
                  "ss_autotune_equal_batch", "ss_server_create", "ss_server_submit", "ss_server_poll",
                  "ss_server_drain", "ss_server_stats", "ss_server_destroy", "ss_server_now",
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync"]:

@@ -125,3 +125,19 @@ def test_batch_workload_numpy_and_torch_agree():
             assert k[a:b].max() < max(1, (b - a) // 10)
         if d[i] == 3:
             assert k[a:b].max() < 100
+
+
+def test_graph_generators_are_valid_csr_and_agree_across_back_ends():
+    torch = pytest.importorskip("torch")
+    for kind in I.GRAPH_KINDS:
+        for nv, ne in [(1, 5), (97, 1000), (1000, 30000)]:
+            offs, cols = I.np_graph(kind, nv, ne, 11)
+            assert offs.size == nv + 1 and int(offs[0]) == 0 and int(offs[-1]) == ne
+            assert np.all(np.diff(offs.astype(np.int64)) >= 0)
+            assert cols.size == ne and (ne == 0 or int(cols.max()) < nv)
+            to, tc = I.t_graph(kind, nv, ne, 11, "cpu")
+            assert np.array_equal(offs.view(np.int64), to.numpy()) and np.array_equal(cols.view(np.int32), tc.numpy())
+    offs, cols = I.np_graph("knn", 1000, 30000, 11)
+    rows = np.repeat(np.arange(1000), np.diff(offs.astype(np.int64)))
+    d = (cols.astype(np.int64) - rows) % 1000
+    assert np.all((d <= I.KNN_WIDTH) | (d >= 1000 - I.KNN_WIDTH))
