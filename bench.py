@@ -115,6 +115,37 @@ def other_configs(args, S, I, torch):
     return res
 
 
+def transposes(args, S, I, torch):
+    """Graph transposing (the paper's first application): CSR transpose of
+    synthetic 1e9-edge graphs over 5e7 vertices, power-law and k-NN-like (u32
+    vertex ids), one timed call after a warm-up.  Whole-job HBM model per
+    edge: expand 16 B (read the target, write an 8-byte key and 4-byte
+    source), semisort_< of those records K + 2R + 2R f_L with K = 8, R = 12,
+    offsets 8 B (read the sorted key) plus 8 B per vertex."""
+    nv, ne = 50_000_000, 1_000_000_000
+    res = {}
+    for kind in I.GRAPH_KINDS:
+        offs, cols = I.t_graph(kind, nv, ne, 5, "cuda")
+        deg = torch.bincount(cols.to(torch.int64), minlength=nv)
+        f_h = float(deg[deg > 500.0 * math.log(ne)].sum().item()) / ne
+        del deg
+        oo, oc = torch.empty_like(offs), torch.empty_like(cols)
+        S.transpose_csr(offs, cols, out_offsets=oo, out_cols=oc)
+        S.sync()
+        t0 = time.perf_counter()
+        S.transpose_csr(offs, cols, out_offsets=oo, out_cols=oc)
+        S.sync()
+        ms = (time.perf_counter() - t0) * 1e3
+        b = 16 + (8 + 24 + 24 * (1 - f_h)) + 8 + 8.0 * nv / ne
+        key = f"transpose {kind} nv={nv} ne={ne}"
+        res[key] = {"ms": round(ms, 3), "gedges": round(ne / ms / 1e6, 2), "f_H": round(f_h, 4),
+                    "B_alg_per_edge": round(b, 2), "pct_hbm_roofline": round(100 * b * ne / (ms * 1e-3) / 8e12, 1)}
+        log(f"applications: {key}: {res[key]}")
+        del offs, cols, oo, oc
+        torch.cuda.empty_cache()
+    return res
+
+
 def batched(args, S, I, torch):
     """4096 independent semisort_= instances (sizes log-uniform in [1e3, 1e7]
     scaled to a total of at most 5e8 records, per-instance key distribution
@@ -451,6 +482,7 @@ def main():
         torch.cuda.empty_cache()
         if not args.no_configs:
             out["configs"] = other_configs(args, S, I, torch)
+            out["applications"] = transposes(args, S, I, torch)
         if not args.no_batch:
             out["batched"] = batched(args, S, I, torch)
         if not args.no_serve:
