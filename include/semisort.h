@@ -98,9 +98,10 @@ ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
  *         16 waves / 4, 4 waves with 16 records per lane / 6)
  * Every variant gives the same result.  Values outside 0..5: SS_EINVAL. */
 /* SS_OPT_DEEP_SAMPLE_DIV (1..64, default 1): below level 0 the sample size is
- * ceil((c / div) ln n').  SS_OPT_NL_TARGET (10..100, default 50): the number of
+ * ceil((c / div) ln n').  SS_OPT_NL_TARGET (0 or 10..100, default 0): the number of
  * light buckets of a subproblem is chosen so that light buckets hold about
- * base_case * target / 100 records. */
+ * base_case * target / 100 records; 0 takes 50 for hash buckets and 35 for
+ * the splitter buckets of semisort_< (their sizes vary more). */
 /* SS_OPT_TILE0 / SS_OPT_TILE_DEEP (0 or a power of two in [8192, 65536],
  * default 0): the largest subarray of the first level / of the deeper levels,
  * overriding tile_max of the call's parameters (0: tile_max applies). */

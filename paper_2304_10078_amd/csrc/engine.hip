@@ -61,7 +61,7 @@ struct ss_ctx {
     size_t job_stage_cap = 0;
     int dist_variant = 0;  // distribution kernel shape (ss_set_option)
     uint32_t deep_div = 1;    // sample multiplier divisor below level 0 (ss_set_option)
-    uint32_t nl_target = 50;  // adaptive light-bucket target, percent of alpha (ss_set_option)
+    uint32_t nl_target = 0;   // adaptive light-bucket target, percent of alpha; 0: per bucketing (ss_set_option)
     uint32_t tile0 = 0, tile_deep = 0;  // tile limits of the first / deeper levels, 0 = tile_max (ss_set_option)
     uint32_t call_tmaxd = 0;            // deeper-level tile limit chosen by the current call (0: Params)
     // kernel timing with HIP events on the context's stream (ss_profile_*)
@@ -204,6 +204,10 @@ ss_status status_failure(ss_ctx* c, uint32_t status, const std::string& where)
     (void)hipMemsetAsync((char*)c->info.p + offsetof(LevelInfo, status), 0, sizeof(uint32_t), c->stream);
     return fail(c, SS_EDEVICE, "device status " + std::to_string(status) + " " + where);
 }
+
+// Default light-bucket targets (percent of alpha) for hash and splitter buckets.
+constexpr uint32_t kNlTargetHash = 50;
+constexpr uint32_t kNlTargetLess = 35;
 
 struct Params {
     uint32_t nl0, alpha, c, tmin, tmax, mode, tau;
@@ -429,7 +433,10 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.sample_mult = p.c;
     a.heavy_min = p.tau;
     a.deep_div = c->deep_div;
-    a.nl_target = c->nl_target;
+    // Splitter buckets vary more in size than hash buckets (each splitter
+    // interval holds a sampled share), so a smaller target keeps fewer of
+    // them above alpha, where they would need one more level.
+    a.nl_target = c->nl_target ? c->nl_target : (p.mode == 2 ? kNlTargetLess : kNlTargetHash);
     a.alpha = p.alpha;
     a.adaptive_nl = 1;
     a.ordered = p.mode == 2;
@@ -1388,7 +1395,8 @@ ss_status ss_set_option(ss_ctx* c, int option, int64_t value)
         return SS_OK;
     }
     case SS_OPT_NL_TARGET:
-        if (value < 10 || value > 100) return fail(c, SS_EINVAL, "light-bucket target must be 10..100 percent");
+        if (value != 0 && (value < 10 || value > 100))
+            return fail(c, SS_EINVAL, "light-bucket target must be 0 or 10..100 percent");
         c->nl_target = (uint32_t)value;
         return SS_OK;
     default:
