@@ -204,12 +204,54 @@ static uint64_t monoid_combine(int op, uint64_t x, uint64_t y)
     }
 }
 
+typedef struct { uint64_t k, i; } ki_t;
+
+static int cmp_ki(const void* a, const void* b)
+{
+    const ki_t* x = (const ki_t*)a;
+    const ki_t* y = (const ki_t*)b;
+    if (x->k != y->k) return x->k < y->k ? -1 : 1;
+    return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);
+}
+
+/* Non-commutative monoids (Section 3.5: a stable algorithm folds any
+ * associative operation): 4 = first (x (+) y = x), 5 = last (x (+) y = y),
+ * folded over each key's records in input order. */
+static int64_t collect_reduce_in_order(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                       uint64_t* out_keys, uint64_t* out_vals)
+{
+    ki_t* s = (ki_t*)malloc(n * sizeof(ki_t));
+    if (!s) return -1;
+    for (uint64_t i = 0; i < n; i++) {
+        s[i].k = keys[i];
+        s[i].i = i;
+    }
+    qsort(s, n, sizeof(ki_t), cmp_ki); /* by (key, input position): each key's records in input order */
+    int64_t m = 0;
+    uint64_t p = 0;
+    while (p < n) {
+        uint64_t acc = vals[s[p].i];
+        uint64_t q = p + 1;
+        while (q < n && s[q].k == s[p].k) {
+            acc = op == 4 ? acc : vals[s[q].i];
+            q++;
+        }
+        out_keys[m] = s[p].k;
+        out_vals[m] = acc;
+        m++;
+        p = q;
+    }
+    free(s);
+    return m;
+}
+
 int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                   uint64_t* out_keys, uint64_t* out_vals)
 {
     /* R = { (k, fold of the monoid over M(r), r in S_k) } with M(r) =
      * value(r); ascending keys. */
-    if (op < 0 || op > 3) return -2;
+    if (op < 0 || op > 5) return -2;
+    if (op >= 4) return n ? collect_reduce_in_order(keys, vals, n, op, out_keys, out_vals) : 0;
     if (n == 0) return 0;
     kv_t* s = (kv_t*)malloc(n * sizeof(kv_t));
     if (!s) return -1;

@@ -165,6 +165,33 @@ def test_collect_reduce_monoids_match_numpy_segment_reductions():
         assert np.array_equal(cs, np.add.reduceat(vs, starts))  # uint64 adds wrap
 
 
+def test_collect_reduce_first_and_last_in_input_order():
+    # brute force: the value of each key's first / last record; and numpy's
+    # np.unique first-occurrence index (on the array and on its reverse)
+    rng = np.random.default_rng(53)
+    for keys in _all_sequences(5):
+        n = len(keys)
+        vals = [int(x) for x in rng.integers(0, 2 ** 63, n, dtype=np.int64)]
+        k = np.array(keys, dtype=np.uint64)
+        v = np.array(vals, dtype=np.uint64)
+        uniq = sorted(set(keys))
+        fk, fv = O.collect_reduce(k, v, op="first")
+        lk, lv = O.collect_reduce(k, v, op="last")
+        assert [int(x) for x in fk] == uniq and [int(x) for x in lk] == uniq
+        for j, u in enumerate(uniq):
+            idx = [i for i in range(n) if keys[i] == u]
+            assert int(fv[j]) == vals[idx[0]] and int(lv[j]) == vals[idx[-1]]
+    for n, M in [(1, 1), (5000, 40), (50000, 20000)]:
+        k = rng.integers(0, M, n, dtype=np.int64).astype(np.uint64)
+        v = rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64)
+        u, first = np.unique(k, return_index=True)
+        _, rfirst = np.unique(k[::-1], return_index=True)
+        fk, fv = O.collect_reduce(k, v, op="first")
+        lk, lv = O.collect_reduce(k, v, op="last")
+        assert np.array_equal(fk, u) and np.array_equal(fv, v[first])
+        assert np.array_equal(lk, u) and np.array_equal(lv, v[::-1][rfirst])
+
+
 def test_collect_reduce_monoid_identities():
     k = np.array([4, 9, 4, 9], dtype=np.uint64)
     v = np.array([MOD - 1, 0, MOD - 1, 0], dtype=np.uint64)
