@@ -256,7 +256,11 @@ ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* v
                             uint64_t* m_out, const ss_params* params);
 
 /* collect-reduce with another monoid (Section 3.5 defines collect-reduce for
- * any monoid (+, I)): op selects it on uint64 values.  ordered = 0 gives the
+ * any monoid (+, I), and notes that a stable algorithm needs no
+ * commutativity): op selects it on uint64 values.  SS_MONOID_FIRST / _LAST
+ * are non-commutative: each key's value is that of its first / last record
+ * in input order (the positions are reduced with min / max and the values
+ * fetched; n more uint64 of workspace).  ordered = 0 gives the
  * pairs in an unspecified order (as ss_collect_reduce), 1 in ascending key
  * order (as ss_collect_reduce_ordered).  SS_MONOID_SUM is ss_collect_reduce
  * itself.  An op outside the enum: SS_EINVAL.  Otherwise the arguments,
@@ -265,7 +269,9 @@ typedef enum {
     SS_MONOID_SUM = 0, /* (+ mod 2^64, 0) */
     SS_MONOID_MIN = 1, /* (min, 2^64 - 1) */
     SS_MONOID_MAX = 2, /* (max, 0) */
-    SS_MONOID_XOR = 3  /* (xor, 0) */
+    SS_MONOID_XOR = 3, /* (xor, 0) */
+    SS_MONOID_FIRST = 4, /* x (+) y = x, in input order */
+    SS_MONOID_LAST = 5   /* x (+) y = y, in input order */
 } ss_monoid;
 ss_status ss_collect_reduce_monoid(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals,
                                    uint64_t n, int op, int ordered, uint64_t* out_keys,

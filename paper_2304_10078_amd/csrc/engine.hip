@@ -52,6 +52,7 @@ struct ss_ctx {
     LevelInfo* info_host = nullptr;  // pinned
     DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
     DevBuf tr_keys, tr_vals, tr_sorted, tr_min;  // graph transpose: records, sorted endpoints, chunk minima
+    DevBuf pos;                      // record positions (first / last collect-reduce)
     std::vector<Seg> host_segs;
     std::vector<Job> host_jobs[kJobClasses];
     uint32_t job_cap = 0;  // entries per class list
@@ -1333,7 +1334,7 @@ ss_status ss_destroy(ss_ctx* c)
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
-                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min};
+                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1436,7 +1437,7 @@ ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
                             &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                             &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
-                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min};
+                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos};
     size_t t = 0;
     for (const DevBuf* b : bufs) t += b->cap;
     *bytes = t;
@@ -1754,11 +1755,29 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
     Params p;
     ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, m_out, params, &p);
     if (s != SS_OK) return s;
-    if (op < SS_MONOID_SUM || op > SS_MONOID_XOR) return fail(c, SS_EINVAL, "unknown monoid");
+    if (op < SS_MONOID_SUM || op > SS_MONOID_LAST) return fail(c, SS_EINVAL, "unknown monoid");
     *m_out = 0;
     if (n == 0) return SS_OK;
     if (!vals) return fail(c, SS_EINVAL, "null vals");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (op == SS_MONOID_FIRST || op == SS_MONOID_LAST) {
+        // the first / last record of a key is the one at the smallest /
+        // largest position: reduce the positions, then fetch the values
+        if ((s = ensure(c, c->pos, n * 8)) != SS_OK) return s;
+        const uint32_t g = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
+        hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, c->stream, (uint64_t*)c->pos.p, n);
+        HIP_OR_FAIL(c, hipGetLastError());
+        const uint32_t pop = op == SS_MONOID_FIRST ? SS_MONOID_MIN : SS_MONOID_MAX;
+        if ((s = run_reduce<1>(c, keys, (const uint64_t*)c->pos.p, n, out_keys, out_vals, m_out, p, pop)) != SS_OK)
+            return s;
+        if (*m_out) {
+            hipLaunchKernelGGL(k_gather_at, dim3((uint32_t)std::min<uint64_t>((*m_out + 255) / 256, 65536)), dim3(256),
+                               0, c->stream, out_vals, *m_out, vals, n, (LevelInfo*)c->info.p);
+            HIP_OR_FAIL(c, hipGetLastError());
+        }
+        if (ordered) return order_results(c, out_keys, out_vals, *m_out, params);
+        return ss_sync(c);
+    }
     if ((s = run_reduce<1>(c, keys, vals, n, out_keys, out_vals, m_out, p, (uint32_t)op)) != SS_OK) return s;
     return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
 }

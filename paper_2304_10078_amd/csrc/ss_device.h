@@ -2944,6 +2944,27 @@ __global__ __launch_bounds__(256) void k_heavy_results(LevelArgs a)
     if (bad) atomicOr(&a.info->status, kStatusSizeMismatch);
 }
 
+// First / last value per key (non-commutative monoids, exact through a stable
+// order): the record positions are reduced with min / max, then each result
+// position is replaced by the value at it.
+__global__ __launch_bounds__(256) void k_iota(uint64_t* p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = i;
+}
+
+__global__ __launch_bounds__(256) void k_gather_at(uint64_t* out, uint64_t m, const uint64_t* vals, uint64_t n,
+                                                   LevelInfo* info)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t p = out[i];
+        if (p >= n) {
+            atomicOr(&info->status, kStatusSizeMismatch);
+            continue;
+        }
+        out[i] = vals[p];
+    }
+}
+
 // Sum jobs: a bucket whose records all share one key, folded with the
 // monoid op.  One block per job; all reads finish (block reduction) before
 // the single write.

@@ -317,13 +317,14 @@ def _check_keys(keys, name="keys"):
         raise ValueError(f"{name} must be a contiguous 1-D int64 device tensor (uint64 bits)")
 
 
-MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3}
+MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5}
 
 
 def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False, op="sum"):
     """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values);
     ss_collect_reduce_ordered with ordered=True (keys ascending as uint64);
-    ss_collect_reduce_monoid for op in "min", "max", "xor" (uint64 values).
+    ss_collect_reduce_monoid for op in "min", "max", "xor", "first", "last"
+    (uint64 values; first / last: the key's first / last record in input order).
 
     Returns views of length m of the two output tensors (capacity n each)."""
     import torch
