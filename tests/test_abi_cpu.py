@@ -49,6 +49,9 @@ def test_null_context_is_rejected():
     assert L.ss_histogram(None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_collect_reduce_ordered(None, None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_histogram_ordered(None, None, 10, None, None, ctypes.byref(m), None) == S.SS_EINVAL
+    assert L.ss_collect_reduce_monoid(None, None, None, 10, 1, 0, None, None, ctypes.byref(m), None) == S.SS_EINVAL
+    assert L.ss_transpose_csr(None, 4, 10, None, None, None, None, None) == S.SS_EINVAL
+    assert L.ss_semisort_equal_batch_capturable(None, None, None, 8, None, 1, 10, None, None, 4, None) == S.SS_EINVAL
     assert L.ss_destroy(None) == S.SS_EINVAL
     assert L.ss_sync(None) == S.SS_EINVAL
     assert L.ss_last_error(None) == b"null context"
