@@ -364,8 +364,9 @@ def main():
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "sharding of the path is described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): sharding the path over "
+              "several GPUs (an all-to-all of the buckets after a shared sample) is designed, not built.",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
