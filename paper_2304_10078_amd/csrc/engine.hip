@@ -1,10 +1,11 @@
 // Host driver and C-ABI of libsemisort_hip.so (declared in include/semisort.h).
 //
-// The driver runs Algorithm 1 level by level over a list of subproblems: all
+// The host engine runs Algorithm 1 level by level over a list of subproblems: all
 // subproblems of one recursion level are processed by the same kernel
 // launches (sampling, counting, scan, distribution), then a planning kernel
 // turns every bucket into a next-level subproblem, a base-case job or a copy
-// job.  One host synchronization per level reads the sizes of the next level.
+// job.  One host synchronization per level reads the sizes of the next level
+// (run_semisort_ds instead keeps them on the device for graph capture).
 // Buffers alternate between the output and the temporary array T as in the
 // in-place optimization of Section 3.4.
 #include <hip/hip_runtime.h>
