@@ -121,3 +121,27 @@ def test_full_size_histogram_zipf08():
     uk, uc = torch.unique(keys, return_counts=True)
     assert gk.numel() == uk.numel()
     assert torch.equal(gk, uk) and torch.equal(gc, uc), "ordered histogram differs from the sorted distinct-key counts"
+
+
+@pytest.mark.parametrize("kind", I.GRAPH_KINDS)
+def test_full_size_graph_transpose(kind):
+    # the benchmark's graphs: 1e9 edges over 5e7 vertices
+    nv, ne = 50_000_000, N
+    offs, cols = I.t_graph(kind, nv, ne, 5, "cuda")
+    _say(f"case: transpose {kind} nv={nv} ne={ne}")
+    oo, oc = S.transpose_csr(offs, cols)
+    S.sync()
+    # offsets: in-degree counts, accumulated
+    deg = torch.bincount(cols.to(torch.int64), minlength=nv)
+    assert int(oo[0]) == 0 and bool(torch.equal(oo[1:] - oo[:-1], deg)), "offsets differ from the in-degrees"
+    del deg
+    # sampled vertices: their in-neighbours are the sources of the edges into
+    # them, in input order (the edge positions ascend, and so do their rows)
+    g = torch.Generator(device="cpu").manual_seed(7)
+    picks = torch.randint(0, ne, (8,), generator=g).tolist()
+    for e in picks:
+        v = int(cols[e]) & 0xFFFFFFFF
+        pos = torch.nonzero(cols == v).flatten()
+        src = torch.searchsorted(offs, pos, right=True) - 1
+        got = oc[int(oo[v]):int(oo[v + 1])].to(torch.int64) & 0xFFFFFFFF
+        assert torch.equal(got, src), f"in-neighbours of vertex {v} differ"
