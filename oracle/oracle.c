@@ -214,9 +214,20 @@ static int cmp_ki(const void* a, const void* b)
     return x->i < y->i ? -1 : (x->i > y->i ? 1 : 0);
 }
 
+/* 6: composition of affine maps on 32-bit integers.  A value holds (a, b) =
+ * (high, low 32 bits) for t -> a t + b mod 2^32; x (+) y applies x, then y:
+ * (a_y a_x, a_y b_x + b_y) mod 2^32, identity (1, 0). */
+static uint64_t affine_then(uint64_t x, uint64_t y)
+{
+    const uint32_t ax = (uint32_t)(x >> 32), bx = (uint32_t)x;
+    const uint32_t ay = (uint32_t)(y >> 32), by = (uint32_t)y;
+    const uint32_t a = ay * ax, b = ay * bx + by;
+    return ((uint64_t)a << 32) | b;
+}
+
 /* Non-commutative monoids (Section 3.5: a stable algorithm folds any
  * associative operation): 4 = first (x (+) y = x), 5 = last (x (+) y = y),
- * folded over each key's records in input order. */
+ * 6 = affine composition, folded over each key's records in input order. */
 static int64_t collect_reduce_in_order(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                        uint64_t* out_keys, uint64_t* out_vals)
 {
@@ -233,7 +244,7 @@ static int64_t collect_reduce_in_order(const uint64_t* keys, const uint64_t* val
         uint64_t acc = vals[s[p].i];
         uint64_t q = p + 1;
         while (q < n && s[q].k == s[p].k) {
-            acc = op == 4 ? acc : vals[s[q].i];
+            acc = op == 4 ? acc : op == 5 ? vals[s[q].i] : affine_then(acc, vals[s[q].i]);
             q++;
         }
         out_keys[m] = s[p].k;
@@ -250,7 +261,7 @@ int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, ui
 {
     /* R = { (k, fold of the monoid over M(r), r in S_k) } with M(r) =
      * value(r); ascending keys. */
-    if (op < 0 || op > 5) return -2;
+    if (op < 0 || op > 6) return -2;
     if (op >= 4) return n ? collect_reduce_in_order(keys, vals, n, op, out_keys, out_vals) : 0;
     if (n == 0) return 0;
     kv_t* s = (kv_t*)malloc(n * sizeof(kv_t));

@@ -58,8 +58,10 @@ int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t 
 /* collect-reduce with map = value and the monoid `op` (Section 3.5): 0 = (+ mod
  * 2^64, 0), 1 = (min, 2^64 - 1), 2 = (max, 0), 3 = (xor, 0) on uint64; (unique
  * key, fold of its values), ascending keys; 4 = first and 5 = last (the
- * value of the key's first / last record in input order: non-commutative,
- * folded in input order).  Returns m, -1 when out of memory, -2 for an
+ * value of the key's first / last record in input order) and 6 = affine
+ * (a value (a, b) = (high, low 32 bits) is t -> a t + b mod 2^32; the fold
+ * applies the maps in input order) are non-commutative, folded in input
+ * order.  Returns m, -1 when out of memory, -2 for an
  * unknown op. */
 int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                   uint64_t* out_keys, uint64_t* out_vals);

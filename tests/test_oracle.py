@@ -192,6 +192,34 @@ def test_collect_reduce_first_and_last_in_input_order():
         assert np.array_equal(lk, u) and np.array_equal(lv, v[::-1][rfirst])
 
 
+def test_collect_reduce_affine_maps_compose_in_input_order():
+    # each value is the map t -> a t + b mod 2^32 (a, b its high and low
+    # halves); the result must act on any t as applying the key's maps one
+    # after the other in input order
+    rng = np.random.default_rng(61)
+    M32 = 1 << 32
+    for n, M in [(1, 1), (6, 2), (200, 5), (3000, 40)]:
+        k = rng.integers(0, M, n, dtype=np.int64).astype(np.uint64)
+        a = rng.integers(0, M32, n, dtype=np.uint64)
+        b = rng.integers(0, M32, n, dtype=np.uint64)
+        v = (a << np.uint64(32)) | b
+        ck, cv = O.collect_reduce(k, v, op="affine")
+        assert [int(x) for x in ck] == sorted(set(int(x) for x in k))
+        for j, u in enumerate(ck):
+            idx = [i for i in range(n) if k[i] == u]
+            for t in (0, 1, 12345, M32 - 1):
+                x = t
+                for i in idx:
+                    x = (int(a[i]) * x + int(b[i])) % M32
+                r = int(cv[j])
+                assert ((r >> 32) * t + (r & (M32 - 1))) % M32 == x
+    # order matters: two maps of one key in either order give different folds
+    k = np.array([3, 3], dtype=np.uint64)
+    f, g = (2 << 32) | 1, (1 << 32) | 5
+    assert int(O.collect_reduce(k, np.array([f, g], dtype=np.uint64), op="affine")[1][0]) != \
+        int(O.collect_reduce(k, np.array([g, f], dtype=np.uint64), op="affine")[1][0])
+
+
 def test_collect_reduce_monoid_identities():
     k = np.array([4, 9, 4, 9], dtype=np.uint64)
     v = np.array([MOD - 1, 0, MOD - 1, 0], dtype=np.uint64)
