@@ -61,7 +61,7 @@ def other_configs(args, S, I, torch):
     """The remaining 10^9-record configurations, one timed call each after a
     warm-up: semisort_= and collect-reduce on uniform[0, 1e9), uniform[0, 1e3)
     and Zipf-1.2 (u64 keys and values; also the min monoid on uniform[0, 1e9)
-    and the max monoid on Zipf-1.2), semisort_< and histogram on
+    and the max and affine monoids on Zipf-1.2), semisort_< and histogram on
     exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values).  Whole-job
     HBM fraction from the algorithmic bytes per record: semisort K + 2R +
     2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; ordered histogram 2K +
@@ -71,7 +71,7 @@ def other_configs(args, S, I, torch):
     res = {}
     cases = [("uniform1e9", ("semisort_=", "collect_reduce", "collect_reduce_min")),
              ("uniform1e3", ("semisort_=", "collect_reduce")),
-             ("zipf1.2_hashed", ("collect_reduce", "collect_reduce_max")),
+             ("zipf1.2_hashed", ("collect_reduce", "collect_reduce_max", "collect_reduce_affine")),
              ("exp1e-5_u32idx", ("semisort_<", "histogram_ordered")),
              ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram_ordered"))]
     for wl, ops in cases:
@@ -94,6 +94,8 @@ def other_configs(args, S, I, torch):
                 mono = op.split("_")[-1] if op != "collect_reduce" else "sum"  # monoid: sum, min, max
                 fn = lambda mono=mono: S.collect_reduce(keys, v64, op=mono)  # noqa: E731
                 b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
+                if mono == "affine":  # semisort_=, two reads of the grouped records, flags, results
+                    b = 8 + 32 + 32 * (1 - f_h) + 32 + 2 + 32.0 * m / n
             else:
                 # these workloads need groups in ascending key order
                 fn = lambda: S.histogram(keys, ordered=True)  # noqa: E731

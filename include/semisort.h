@@ -260,7 +260,9 @@ ss_status ss_collect_reduce(ss_ctx* ctx, const uint64_t* keys, const uint64_t* v
  * commutativity): op selects it on uint64 values.  SS_MONOID_FIRST / _LAST
  * are non-commutative: each key's value is that of its first / last record
  * in input order (the positions are reduced with min / max and the values
- * fetched; n more uint64 of workspace).  ordered = 0 gives the
+ * fetched; n more uint64 of workspace).  SS_MONOID_AFFINE is a general
+ * non-commutative fold: a stable semisort_= groups the records in input
+ * order and a segmented scan folds each group (2n uint64 of workspace).  ordered = 0 gives the
  * pairs in an unspecified order (as ss_collect_reduce), 1 in ascending key
  * order (as ss_collect_reduce_ordered).  SS_MONOID_SUM is ss_collect_reduce
  * itself.  An op outside the enum: SS_EINVAL.  Otherwise the arguments,
@@ -271,7 +273,9 @@ typedef enum {
     SS_MONOID_MAX = 2, /* (max, 0) */
     SS_MONOID_XOR = 3, /* (xor, 0) */
     SS_MONOID_FIRST = 4, /* x (+) y = x, in input order */
-    SS_MONOID_LAST = 5   /* x (+) y = y, in input order */
+    SS_MONOID_LAST = 5,  /* x (+) y = y, in input order */
+    SS_MONOID_AFFINE = 6 /* composition of t -> a t + b mod 2^32, (a, b) the value's high and low
+                            halves, applied in input order; identity (1, 0) */
 } ss_monoid;
 ss_status ss_collect_reduce_monoid(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals,
                                    uint64_t n, int op, int ordered, uint64_t* out_keys,

@@ -1111,6 +1111,33 @@ void launch_red_level_m(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t 
 // arrays; results are written to T at positions flagged in rflag (positions
 // of finished work are never touched again by later levels, which only work
 // inside the ranges of unfinished buckets), then compacted into the output.
+// Packs the results flagged in rf (position order) from (T_k, T_v) into the
+// outputs and reads their number back (the buffers were sized by the caller:
+// rf padded to whole flag blocks, bcnt and mdev as in run_reduce).
+ss_status compact_results(ss_ctx* c, uint64_t n, const uint64_t* T_k, const uint64_t* T_v, const uint8_t* rf,
+                          uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out)
+{
+    const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
+    const uint64_t nchunk = nblk * (kFlagBlock / kFlagChunk);
+    {
+        ProfScope ps(c, SS_PROF_COMPACT, n);
+        uint32_t* ccnt = (uint32_t*)c->bcnt.p;  // per chunk, then per block
+        uint32_t* btot = ccnt + nchunk;
+        hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, rf, ccnt, btot);
+        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, btot, (uint32_t)nblk,
+                           (unsigned long long*)c->mdev.p);
+        hipLaunchKernelGGL(k_flag_scatter, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, rf, (const uint32_t*)ccnt,
+                           (const uint32_t*)btot, n, T_k, T_v, out_keys, out_vals);
+    }
+    HIP_OR_FAIL(c, hipGetLastError());
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, c->mdev.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    if (c->info_host->status) return status_failure(c, c->info_host->status, "in collect-reduce");
+    *m_out = c->info_host->records;
+    return SS_OK;
+}
+
 template <int RED>
 ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
                      uint64_t* out_vals, uint64_t* m_out, const Params& p, uint32_t op = 0)
@@ -1199,25 +1226,7 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
             cur ^= 1;
         }
     }
-    {
-        ProfScope ps(c, SS_PROF_COMPACT, n);
-        uint32_t* ccnt = (uint32_t*)c->bcnt.p;  // per chunk, then per block
-        uint32_t* btot = ccnt + nchunk;
-        hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf, ccnt,
-                           btot);
-        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, btot, (uint32_t)nblk,
-                           (unsigned long long*)c->mdev.p);
-        hipLaunchKernelGGL(k_flag_scatter, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, (const uint8_t*)rf,
-                           (const uint32_t*)ccnt, (const uint32_t*)btot, n, (const uint64_t*)T_k, (const uint64_t*)T_v,
-                           out_keys, out_vals);
-    }
-    HIP_OR_FAIL(c, hipGetLastError());
-    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, c->mdev.p, 8, hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-    if (c->info_host->status) return status_failure(c, c->info_host->status, "in collect-reduce");
-    *m_out = c->info_host->records;
-    return SS_OK;
+    return compact_results(c, n, T_k, T_v, rf, out_keys, out_vals, m_out);
 }
 
 ss_status check_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, const uint64_t* ok,
@@ -1756,11 +1765,47 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
     Params p;
     ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, m_out, params, &p);
     if (s != SS_OK) return s;
-    if (op < SS_MONOID_SUM || op > SS_MONOID_LAST) return fail(c, SS_EINVAL, "unknown monoid");
+    if (op < SS_MONOID_SUM || op > SS_MONOID_AFFINE) return fail(c, SS_EINVAL, "unknown monoid");
     *m_out = 0;
     if (n == 0) return SS_OK;
     if (!vals) return fail(c, SS_EINVAL, "null vals");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (op == SS_MONOID_AFFINE) {
+        // in input order: a stable semisort_= makes every key's records
+        // contiguous and ordered, then a segmented scan folds each group
+        Params q = p;
+        default_tiles(c, params, &q, 32768u, 16384u);
+        if ((s = ensure(c, c->tr_keys, n * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->tr_sorted, n * 8)) != SS_OK) return s;
+        uint64_t* sk = (uint64_t*)c->tr_keys.p;
+        uint64_t* sv = (uint64_t*)c->tr_sorted.p;
+        const uint64_t so[2] = {0, n};
+        if ((s = run_semisort<uint64_t>(c, keys, vals, so, 1, sk, sv, q)) != SS_OK) return s;
+        const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
+        const uint64_t nch = (n + kFoldChunk - 1) / kFoldChunk;
+        if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->t_vals, n * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->rflag, nblk * kFlagBlock)) != SS_OK) return s;
+        if ((s = ensure(c, c->bcnt, (nblk * (kFlagBlock / kFlagChunk) + nblk) * 4)) != SS_OK) return s;
+        if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->pos, nch * 12)) != SS_OK) return s;
+        uint64_t* aggv = (uint64_t*)c->pos.p;
+        uint32_t* aggf = (uint32_t*)(aggv + nch);
+        uint8_t* rf = (uint8_t*)c->rflag.p;
+        HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
+        hipLaunchKernelGGL(k_sfold_aggr, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const uint64_t*)sk,
+                           (const uint64_t*)sv, n, aggv, aggf);
+        hipLaunchKernelGGL(k_sfold_carry, dim3(1), dim3(256), 0, c->stream, aggv, (const uint32_t*)aggf,
+                           (uint32_t)nch);
+        hipLaunchKernelGGL(k_sfold_apply, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const uint64_t*)sk,
+                           (const uint64_t*)sv, n, (const uint64_t*)aggv, (uint64_t*)c->t_keys.p,
+                           (uint64_t*)c->t_vals.p, rf);
+        HIP_OR_FAIL(c, hipGetLastError());
+        if ((s = compact_results(c, n, (const uint64_t*)c->t_keys.p, (const uint64_t*)c->t_vals.p, rf, out_keys,
+                                 out_vals, m_out)) != SS_OK)
+            return s;
+        return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
+    }
     if (op == SS_MONOID_FIRST || op == SS_MONOID_LAST) {
         // the first / last record of a key is the one at the smallest /
         // largest position: reduce the positions, then fetch the values

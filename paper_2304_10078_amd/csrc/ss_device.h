@@ -2965,6 +2965,139 @@ __global__ __launch_bounds__(256) void k_gather_at(uint64_t* out, uint64_t m, co
     }
 }
 
+// ---------------------------------------------------------------- in-order folds
+// Section 3.5: a stable algorithm reduces with any associative operation,
+// commutative or not.  After a stable semisort_= each key's records are
+// contiguous and in input order, so a segmented scan in position order folds
+// every group.  The operation here composes affine maps on 32-bit integers:
+// a value holds (a, b) = (high, low 32 bits) for t -> a t + b mod 2^32, and
+// x then y = (a_y a_x, a_y b_x + b_y) mod 2^32, identity (1, 0).
+
+constexpr uint64_t kAffineId = 1ull << 32;
+constexpr uint32_t kFoldChunk = 4096;  // positions per block (256 threads x 16)
+
+__device__ __forceinline__ uint64_t affine_then(uint64_t x, uint64_t y)
+{
+    const uint32_t ax = (uint32_t)(x >> 32), bx = (uint32_t)x;
+    const uint32_t ay = (uint32_t)(y >> 32), by = (uint32_t)y;
+    return ((uint64_t)(ay * ax) << 32) | (uint32_t)(ay * bx + by);
+}
+
+// Segmented pairs (fold, a group starts inside): (v, f) then (w, g) is
+// (g ? w : v then w, f or g); associative because the fold is.
+struct SegPair {
+    uint64_t v;
+    uint32_t f;
+};
+
+__device__ __forceinline__ SegPair seg_then(SegPair l, SegPair r)
+{
+    return SegPair{r.f ? r.v : affine_then(l.v, r.v), l.f | r.f};
+}
+
+// Block-wide inclusive scan of one pair per thread, in thread order.
+__device__ __forceinline__ SegPair seg_block_scan(SegPair x, uint64_t* bv, uint32_t* bf)
+{
+    const uint32_t t = threadIdx.x;
+    bv[t] = x.v;
+    bf[t] = x.f;
+    __syncthreads();
+    for (uint32_t o = 1; o < 256; o <<= 1) {
+        SegPair y = x;
+        if (t >= o) y = seg_then(SegPair{bv[t - o], bf[t - o]}, x);
+        __syncthreads();
+        bv[t] = y.v;
+        bf[t] = y.f;
+        x = y;
+        __syncthreads();
+    }
+    return x;
+}
+
+__device__ __forceinline__ SegPair fold_thread_range(const uint64_t* sk, const uint64_t* sv, uint64_t n, uint64_t p0)
+{
+    SegPair acc{kAffineId, 0u};
+    for (uint32_t j = 0; j < kFoldChunk / 256; ++j) {
+        const uint64_t i = p0 + j;
+        if (i >= n) break;
+        const uint32_t st = i == 0 || sk[i] != sk[i - 1];
+        acc = seg_then(acc, SegPair{sv[i], st});
+    }
+    return acc;
+}
+
+// Pass 1: the segmented fold of every chunk of positions.
+__global__ __launch_bounds__(256) void k_sfold_aggr(const uint64_t* sk, const uint64_t* sv, uint64_t n,
+                                                    uint64_t* aggv, uint32_t* aggf)
+{
+    __shared__ uint64_t bv[256];
+    __shared__ uint32_t bf[256];
+    const uint64_t p0 = (uint64_t)blockIdx.x * kFoldChunk + (uint64_t)threadIdx.x * (kFoldChunk / 256);
+    const SegPair x = seg_block_scan(fold_thread_range(sk, sv, n, p0), bv, bf);
+    if (threadIdx.x == 255) {
+        aggv[blockIdx.x] = x.v;
+        aggf[blockIdx.x] = x.f;
+    }
+}
+
+// Pass 2 (one block): aggv[c] becomes the fold of the group open at the
+// start of chunk c (an exclusive segmented scan over the chunks).
+__global__ __launch_bounds__(256) void k_sfold_carry(uint64_t* aggv, const uint32_t* aggf, uint32_t nch)
+{
+    __shared__ uint64_t bv[256];
+    __shared__ uint32_t bf[256];
+    __shared__ uint64_t sh_cv;
+    __shared__ uint32_t sh_cf;
+    if (threadIdx.x == 0) {
+        sh_cv = kAffineId;
+        sh_cf = 0;
+    }
+    __syncthreads();
+    for (uint32_t base = 0; base < nch; base += 256) {
+        const uint32_t c = base + threadIdx.x;
+        const SegPair mine = c < nch ? SegPair{aggv[c], aggf[c]} : SegPair{kAffineId, 0u};
+        const SegPair inc = seg_block_scan(mine, bv, bf);
+        const SegPair carry{sh_cv, sh_cf};
+        // exclusive: the round's carry, then the threads before this one
+        const SegPair before = threadIdx.x ? seg_then(carry, SegPair{bv[threadIdx.x - 1], bf[threadIdx.x - 1]}) : carry;
+        __syncthreads();
+        if (c < nch) aggv[c] = before.v;
+        if (threadIdx.x == 255) {
+            const SegPair next = seg_then(carry, inc);
+            sh_cv = next.v;
+            sh_cf = next.f;
+        }
+        __syncthreads();
+    }
+}
+
+// Pass 3: each group's fold, written at its last position (the position
+// order of the flagged results is the group order of the semisort).
+__global__ __launch_bounds__(256) void k_sfold_apply(const uint64_t* sk, const uint64_t* sv, uint64_t n,
+                                                     const uint64_t* carryv, uint64_t* res_keys, uint64_t* res_vals,
+                                                     uint8_t* rflag)
+{
+    __shared__ uint64_t bv[256];
+    __shared__ uint32_t bf[256];
+    const uint64_t p0 = (uint64_t)blockIdx.x * kFoldChunk + (uint64_t)threadIdx.x * (kFoldChunk / 256);
+    const SegPair mine = fold_thread_range(sk, sv, n, p0);
+    seg_block_scan(mine, bv, bf);
+    const SegPair chunk_in{carryv[blockIdx.x], 0u};
+    SegPair acc = threadIdx.x ? seg_then(chunk_in, SegPair{bv[threadIdx.x - 1], bf[threadIdx.x - 1]}) : chunk_in;
+    for (uint32_t j = 0; j < kFoldChunk / 256; ++j) {
+        const uint64_t i = p0 + j;
+        if (i >= n) break;
+        const uint64_t k = sk[i];
+        const uint32_t st = i == 0 || k != sk[i - 1];
+        acc = seg_then(acc, SegPair{sv[i], st});
+        if (i + 1 == n || sk[i + 1] != k) {
+            res_keys[i] = k;
+            res_vals[i] = acc.v;
+            rflag[i] = 1;
+        }
+    }
+}
+
 // Sum jobs: a bucket whose records all share one key, folded with the
 // monoid op.  One block per job; all reads finish (block reduction) before
 // the single write.

@@ -317,7 +317,7 @@ def _check_keys(keys, name="keys"):
         raise ValueError(f"{name} must be a contiguous 1-D int64 device tensor (uint64 bits)")
 
 
-MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5}
+MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5, "affine": 6}
 
 
 def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False, op="sum"):

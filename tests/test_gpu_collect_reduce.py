@@ -210,9 +210,10 @@ def test_ordered_results_empty_and_small_parameters():
 
 
 def check_monoid(keys, vals, op, ordered=False, params=None, ctx=""):
-    """collect-reduce with the min / max / xor / first / last monoids against
-    the oracle (first / last: the value of the key's first / last record in
-    input order)."""
+    """collect-reduce with the min / max / xor / first / last / affine monoids
+    against the oracle (first / last: the value of the key's first / last
+    record in input order; affine: the composition of the key's maps in input
+    order)."""
     gk, gv = S.collect_reduce(to_dev(keys), to_dev(vals), params=params, ordered=ordered, op=op)
     S.sync()
     gk, gv = to_host(gk, np.uint64), to_host(gv, np.uint64)
@@ -232,7 +233,7 @@ def _wide_values(n, seed):
     return rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(seed & 1)
 
 
-@pytest.mark.parametrize("op", ["min", "max", "xor", "first", "last"])
+@pytest.mark.parametrize("op", ["min", "max", "xor", "first", "last", "affine"])
 @pytest.mark.parametrize("name,n", [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 1_000_000),
                                     ("uniform1e3", 700_000), ("exp1e-5_u32idx", 900_000)])
 def test_monoids_paper_distributions(op, name, n):
@@ -242,7 +243,7 @@ def test_monoids_paper_distributions(op, name, n):
     check_monoid(k, v, op, ctx=f"CR {op} {name}")
 
 
-@pytest.mark.parametrize("op", ["min", "max", "xor", "first", "last"])
+@pytest.mark.parametrize("op", ["min", "max", "xor", "first", "last", "affine"])
 def test_monoids_ragged_ordered_and_deep(op):
     for n in [1, 2, 3, 64, 4097, 65537, 200_003]:
         rng = np.random.default_rng(n)

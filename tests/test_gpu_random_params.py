@@ -94,7 +94,7 @@ def test_random_shapes_and_parameters(case):
     rk, rc = O.histogram(k)
     assert np.array_equal(gk[o], rk) and np.array_equal(gc[o], rc), f"case {case} histogram"
 
-    op = ("min", "max", "xor", "first", "last")[case % 5]
+    op = ("min", "max", "xor", "first", "last", "affine")[case % 6]
     gk, gs = S.collect_reduce(to_dev(k), to_dev(vals), params=p, op=op)
     S.sync()
     gk, gs = to_host(gk, np.uint64), to_host(gs, np.uint64)
