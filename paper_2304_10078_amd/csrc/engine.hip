@@ -1788,18 +1788,22 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
         if ((s = ensure(c, c->rflag, nblk * kFlagBlock)) != SS_OK) return s;
         if ((s = ensure(c, c->bcnt, (nblk * (kFlagBlock / kFlagChunk) + nblk) * 4)) != SS_OK) return s;
         if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
-        if ((s = ensure(c, c->pos, nch * 12)) != SS_OK) return s;
+        const uint64_t ncb = (nch + 255) / 256;  // blocks of the first carry level (<= 2048 for n < 2^31)
+        if ((s = ensure(c, c->pos, (nch + ncb) * 12)) != SS_OK) return s;
         uint64_t* aggv = (uint64_t*)c->pos.p;
-        uint32_t* aggf = (uint32_t*)(aggv + nch);
+        uint64_t* totv = aggv + nch;
+        uint32_t* aggf = (uint32_t*)(totv + ncb);
+        uint32_t* totf = aggf + nch;
         uint8_t* rf = (uint8_t*)c->rflag.p;
         HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
         hipLaunchKernelGGL(k_sfold_aggr, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const uint64_t*)sk,
                            (const uint64_t*)sv, n, aggv, aggf);
-        hipLaunchKernelGGL(k_sfold_carry, dim3(1), dim3(256), 0, c->stream, aggv, (const uint32_t*)aggf,
-                           (uint32_t)nch);
+        hipLaunchKernelGGL(k_sfold_carry_blocks, dim3((uint32_t)ncb), dim3(256), 0, c->stream, aggv, aggf,
+                           (uint32_t)nch, totv, totf);
+        hipLaunchKernelGGL(k_sfold_carry_top, dim3(1), dim3(1024), 0, c->stream, totv, totf, (uint32_t)ncb);
         hipLaunchKernelGGL(k_sfold_apply, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const uint64_t*)sk,
-                           (const uint64_t*)sv, n, (const uint64_t*)aggv, (uint64_t*)c->t_keys.p,
-                           (uint64_t*)c->t_vals.p, rf);
+                           (const uint64_t*)sv, n, (const uint64_t*)aggv, (const uint32_t*)aggf,
+                           (const uint64_t*)totv, (uint64_t*)c->t_keys.p, (uint64_t*)c->t_vals.p, rf);
         HIP_OR_FAIL(c, hipGetLastError());
         if ((s = compact_results(c, n, (const uint64_t*)c->t_keys.p, (const uint64_t*)c->t_vals.p, rf, out_keys,
                                  out_vals, m_out)) != SS_OK)

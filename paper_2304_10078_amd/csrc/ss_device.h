@@ -3014,14 +3014,47 @@ __device__ __forceinline__ SegPair seg_block_scan(SegPair x, uint64_t* bv, uint3
     return x;
 }
 
-__device__ __forceinline__ SegPair fold_thread_range(const uint64_t* sk, const uint64_t* sv, uint64_t n, uint64_t p0)
+// A chunk of grouped records staged in LDS with coalesced loads; thread t's
+// 16 consecutive positions sit at t * 17 .. t * 17 + 15 (one slot of padding
+// per thread keeps the per-thread walks off shared banks).  Also the keys
+// just before and just after the chunk (for the group boundaries).
+constexpr uint32_t kFoldPer = kFoldChunk / 256;
+constexpr uint32_t kFoldSlots = 256 * (kFoldPer + 1);
+
+__device__ __forceinline__ void stage_chunk(const uint64_t* sk, const uint64_t* sv, uint64_t n, uint64_t base,
+                                            uint64_t* lk, uint64_t* lv, uint64_t* prev_next)
+{
+    for (uint32_t j = threadIdx.x; j < kFoldChunk; j += 256) {
+        const uint64_t i = base + j;
+        const uint32_t slot = (j / kFoldPer) * (kFoldPer + 1) + j % kFoldPer;
+        lk[slot] = i < n ? sk[i] : 0ull;
+        lv[slot] = i < n ? sv[i] : 0ull;
+    }
+    if (threadIdx.x == 0) prev_next[0] = base ? sk[base - 1] : 0ull;
+    if (threadIdx.x == 1) prev_next[1] = base + kFoldChunk < n ? sk[base + kFoldChunk] : 0ull;
+    __syncthreads();
+}
+
+// Key of in-chunk position j from the staged chunk (j = -1 and kFoldChunk
+// give the neighbours).
+__device__ __forceinline__ uint64_t staged_key(const uint64_t* lk, const uint64_t* prev_next, int32_t j)
+{
+    if (j < 0) return prev_next[0];
+    if (j >= (int32_t)kFoldChunk) return prev_next[1];
+    return lk[(j / kFoldPer) * (kFoldPer + 1) + j % kFoldPer];
+}
+
+__device__ __forceinline__ SegPair fold_thread_range(const uint64_t* lk, const uint64_t* lv, const uint64_t* pn,
+                                                     uint64_t n, uint64_t base)
 {
     SegPair acc{kAffineId, 0u};
-    for (uint32_t j = 0; j < kFoldChunk / 256; ++j) {
-        const uint64_t i = p0 + j;
-        if (i >= n) break;
-        const uint32_t st = i == 0 || sk[i] != sk[i - 1];
-        acc = seg_then(acc, SegPair{sv[i], st});
+    const uint32_t t = threadIdx.x;
+    for (uint32_t j = 0; j < kFoldPer; ++j) {
+        const uint32_t q = t * kFoldPer + j;
+        if (base + q >= n) break;
+        const uint64_t k = lk[t * (kFoldPer + 1) + j];
+        const uint32_t st = base + q == 0 || k != staged_key(lk, pn, (int32_t)q - 1);
+        acc = seg_then(acc, SegPair{lv[t * (kFoldPer + 1) + j], st});
     }
     return acc;
 }
@@ -3030,40 +3063,80 @@ __device__ __forceinline__ SegPair fold_thread_range(const uint64_t* sk, const u
 __global__ __launch_bounds__(256) void k_sfold_aggr(const uint64_t* sk, const uint64_t* sv, uint64_t n,
                                                     uint64_t* aggv, uint32_t* aggf)
 {
+    __shared__ uint64_t lk[kFoldSlots];
+    __shared__ uint64_t lv[kFoldSlots];
+    __shared__ uint64_t pn[2];
     __shared__ uint64_t bv[256];
     __shared__ uint32_t bf[256];
-    const uint64_t p0 = (uint64_t)blockIdx.x * kFoldChunk + (uint64_t)threadIdx.x * (kFoldChunk / 256);
-    const SegPair x = seg_block_scan(fold_thread_range(sk, sv, n, p0), bv, bf);
+    const uint64_t base = (uint64_t)blockIdx.x * kFoldChunk;
+    stage_chunk(sk, sv, n, base, lk, lv, pn);
+    const SegPair x = seg_block_scan(fold_thread_range(lk, lv, pn, n, base), bv, bf);
     if (threadIdx.x == 255) {
         aggv[blockIdx.x] = x.v;
         aggf[blockIdx.x] = x.f;
     }
 }
 
-// Pass 2 (one block): aggv[c] becomes the fold of the group open at the
-// start of chunk c (an exclusive segmented scan over the chunks).
-__global__ __launch_bounds__(256) void k_sfold_carry(uint64_t* aggv, const uint32_t* aggf, uint32_t nch)
+// Pass 2, in two levels.  2a: each block scans 256 chunk folds in place
+// (exclusive, flags kept) and writes their total; 2b (one block of 1024):
+// the block totals become exclusive carries.  The fold open at the start of
+// chunk c is then carry[c / 256] then the in-block prefix of c.
+__global__ __launch_bounds__(256) void k_sfold_carry_blocks(uint64_t* aggv, uint32_t* aggf, uint32_t nch,
+                                                            uint64_t* totv, uint32_t* totf)
 {
     __shared__ uint64_t bv[256];
     __shared__ uint32_t bf[256];
+    const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+    const SegPair mine = c < nch ? SegPair{aggv[c], aggf[c]} : SegPair{kAffineId, 0u};
+    const SegPair inc = seg_block_scan(mine, bv, bf);
+    const SegPair excl = threadIdx.x ? SegPair{bv[threadIdx.x - 1], bf[threadIdx.x - 1]} : SegPair{kAffineId, 0u};
+    if (c < nch) {
+        aggv[c] = excl.v;
+        aggf[c] = excl.f;
+    }
+    if (threadIdx.x == 255) {
+        totv[blockIdx.x] = inc.v;
+        totf[blockIdx.x] = inc.f;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sfold_carry_top(uint64_t* totv, uint32_t* totf, uint32_t nb)
+{
+    // nb <= 2048: two rounds of 1024, Hillis-Steele in LDS
+    __shared__ uint64_t bv[1024];
+    __shared__ uint32_t bf[1024];
     __shared__ uint64_t sh_cv;
     __shared__ uint32_t sh_cf;
-    if (threadIdx.x == 0) {
+    const uint32_t t = threadIdx.x;
+    if (t == 0) {
         sh_cv = kAffineId;
         sh_cf = 0;
     }
     __syncthreads();
-    for (uint32_t base = 0; base < nch; base += 256) {
-        const uint32_t c = base + threadIdx.x;
-        const SegPair mine = c < nch ? SegPair{aggv[c], aggf[c]} : SegPair{kAffineId, 0u};
-        const SegPair inc = seg_block_scan(mine, bv, bf);
-        const SegPair carry{sh_cv, sh_cf};
-        // exclusive: the round's carry, then the threads before this one
-        const SegPair before = threadIdx.x ? seg_then(carry, SegPair{bv[threadIdx.x - 1], bf[threadIdx.x - 1]}) : carry;
+    for (uint32_t base = 0; base < nb; base += 1024) {
+        const uint32_t i = base + t;
+        SegPair x = i < nb ? SegPair{totv[i], totf[i]} : SegPair{kAffineId, 0u};
+        bv[t] = x.v;
+        bf[t] = x.f;
         __syncthreads();
-        if (c < nch) aggv[c] = before.v;
-        if (threadIdx.x == 255) {
-            const SegPair next = seg_then(carry, inc);
+        for (uint32_t o = 1; o < 1024; o <<= 1) {
+            SegPair y = x;
+            if (t >= o) y = seg_then(SegPair{bv[t - o], bf[t - o]}, x);
+            __syncthreads();
+            bv[t] = y.v;
+            bf[t] = y.f;
+            x = y;
+            __syncthreads();
+        }
+        const SegPair carry{sh_cv, sh_cf};
+        const SegPair before = t ? seg_then(carry, SegPair{bv[t - 1], bf[t - 1]}) : carry;
+        __syncthreads();
+        if (i < nb) {
+            totv[i] = before.v;
+            totf[i] = before.f;
+        }
+        if (t == 1023) {
+            const SegPair next = seg_then(carry, x);
             sh_cv = next.v;
             sh_cf = next.f;
         }
@@ -3074,23 +3147,30 @@ __global__ __launch_bounds__(256) void k_sfold_carry(uint64_t* aggv, const uint3
 // Pass 3: each group's fold, written at its last position (the position
 // order of the flagged results is the group order of the semisort).
 __global__ __launch_bounds__(256) void k_sfold_apply(const uint64_t* sk, const uint64_t* sv, uint64_t n,
-                                                     const uint64_t* carryv, uint64_t* res_keys, uint64_t* res_vals,
-                                                     uint8_t* rflag)
+                                                     const uint64_t* aggv, const uint32_t* aggf, const uint64_t* totv,
+                                                     uint64_t* res_keys, uint64_t* res_vals, uint8_t* rflag)
 {
+    __shared__ uint64_t lk[kFoldSlots];
+    __shared__ uint64_t lv[kFoldSlots];
+    __shared__ uint64_t pn[2];
     __shared__ uint64_t bv[256];
     __shared__ uint32_t bf[256];
-    const uint64_t p0 = (uint64_t)blockIdx.x * kFoldChunk + (uint64_t)threadIdx.x * (kFoldChunk / 256);
-    const SegPair mine = fold_thread_range(sk, sv, n, p0);
-    seg_block_scan(mine, bv, bf);
-    const SegPair chunk_in{carryv[blockIdx.x], 0u};
-    SegPair acc = threadIdx.x ? seg_then(chunk_in, SegPair{bv[threadIdx.x - 1], bf[threadIdx.x - 1]}) : chunk_in;
-    for (uint32_t j = 0; j < kFoldChunk / 256; ++j) {
-        const uint64_t i = p0 + j;
+    const uint64_t base = (uint64_t)blockIdx.x * kFoldChunk;
+    stage_chunk(sk, sv, n, base, lk, lv, pn);
+    seg_block_scan(fold_thread_range(lk, lv, pn, n, base), bv, bf);
+    // the fold open at this chunk's start: its block's carry, then the
+    // chunks before it in that block
+    const SegPair chunk_in = seg_then(SegPair{totv[blockIdx.x / 256], 0u}, SegPair{aggv[blockIdx.x], aggf[blockIdx.x]});
+    const uint32_t t = threadIdx.x;
+    SegPair acc = t ? seg_then(chunk_in, SegPair{bv[t - 1], bf[t - 1]}) : chunk_in;
+    for (uint32_t j = 0; j < kFoldPer; ++j) {
+        const uint32_t q = t * kFoldPer + j;
+        const uint64_t i = base + q;
         if (i >= n) break;
-        const uint64_t k = sk[i];
-        const uint32_t st = i == 0 || k != sk[i - 1];
-        acc = seg_then(acc, SegPair{sv[i], st});
-        if (i + 1 == n || sk[i + 1] != k) {
+        const uint64_t k = lk[t * (kFoldPer + 1) + j];
+        const uint32_t st = i == 0 || k != staged_key(lk, pn, (int32_t)q - 1);
+        acc = seg_then(acc, SegPair{lv[t * (kFoldPer + 1) + j], st});
+        if (i + 1 == n || staged_key(lk, pn, (int32_t)q + 1) != k) {
             res_keys[i] = k;
             res_vals[i] = acc.v;
             rflag[i] = 1;
