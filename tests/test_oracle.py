@@ -318,6 +318,54 @@ def test_canonicalizer_rejects_each_mutation():
     assert not verdict(cv)
 
 
+# ------------------------------------------------- Table 3 input statistics
+
+
+def _stats_by_numpy(keys, thr):
+    u, c = np.unique(keys, return_counts=True)
+    return int(u.size), int(c.max()) if c.size else 0, int(c[c > thr].sum())
+
+
+def test_stats_match_numpy_unique_counts_at_every_threshold():
+    # Table 3 defines "Heavy Freq." as the share of records whose key occurs
+    # MORE than 500 ln n times: a key whose count equals the threshold is
+    # light.  Keys are built with known counts so that several of them sit
+    # exactly at each threshold tried; a >= slip, a dropped run or a
+    # miscounted last run changes the result.
+    rng = np.random.default_rng(21)
+    counts = {np.uint64(7): 5, np.uint64(1 << 63): 5, np.uint64(2): 4, np.uint64((1 << 64) - 1): 6,
+              np.uint64(0): 1, np.uint64(99): 3, np.uint64(12345): 5}
+    keys = np.concatenate([np.full(c, k, dtype=np.uint64) for k, c in counts.items()])
+    keys = keys[rng.permutation(keys.size)]
+    for thr in (0, 0.5, 1, 3, 4, 4.5, 5, 5.5, 6, 7):
+        got = O.stats(keys, thr)
+        assert got == _stats_by_numpy(keys, thr), thr
+    # exactly at the threshold: the keys with count 5 are not heavy
+    assert O.stats(keys, 5)[2] == 6
+    assert O.stats(keys, 4.999)[2] == 5 * 3 + 6
+    # the last run of the sorted keys (2^64 - 1) is counted
+    assert O.stats(keys, 5)[1] == 6
+    # empty and single-record inputs
+    assert O.stats(np.zeros(0, dtype=np.uint64), 1) == (0, 0, 0)
+    assert O.stats(np.array([5], dtype=np.uint64), 0) == (1, 1, 1)
+    assert O.stats(np.array([5], dtype=np.uint64), 1) == (1, 1, 0)
+
+
+def test_stats_on_random_skewed_keys_match_numpy():
+    rng = np.random.default_rng(22)
+    for trial in range(20):
+        n = int(rng.integers(1, 5000))
+        pool = rng.integers(0, 2 ** 63, int(rng.integers(1, 300)), dtype=np.int64).astype(np.uint64)
+        pool[0] = np.uint64((1 << 64) - 1)
+        keys = rng.choice(pool, n, p=rng.dirichlet(np.ones(pool.size) * 0.3))
+        for thr in (0, 1, 10, 500 * math.log(max(n, 2)) / 100):
+            assert O.stats(keys, thr) == _stats_by_numpy(keys, thr), (trial, thr)
+        # thresholds equal to a count that occurs
+        _, c = np.unique(keys, return_counts=True)
+        for thr in np.unique(c)[:5]:
+            assert O.stats(keys, float(thr)) == _stats_by_numpy(keys, float(thr)), (trial, thr)
+
+
 # -------------------------------------------------- stage model of one level
 
 
