@@ -105,7 +105,13 @@ ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
 /* SS_OPT_TILE0 / SS_OPT_TILE_DEEP (0 or a power of two in [8192, 65536],
  * default 0): the largest subarray of the first level / of the deeper levels,
  * overriding tile_max of the call's parameters (0: tile_max applies). */
-enum { SS_OPT_DIST_VARIANT = 1, SS_OPT_DEEP_SAMPLE_DIV = 2, SS_OPT_NL_TARGET = 3, SS_OPT_TILE0 = 4, SS_OPT_TILE_DEEP = 5 };
+/* SS_OPT_FOLD_ROUND (a power of two in [1, 1024], default 1024): the in-order
+ * fold of SS_MONOID_AFFINE carries across 4096-record chunks in two levels,
+ * 256 chunks per block and then the block totals in rounds of this many; a
+ * smaller round exercises the cross-round carry on small inputs.  Every
+ * value gives the same result. */
+enum { SS_OPT_DIST_VARIANT = 1, SS_OPT_DEEP_SAMPLE_DIV = 2, SS_OPT_NL_TARGET = 3, SS_OPT_TILE0 = 4, SS_OPT_TILE_DEEP = 5,
+       SS_OPT_FOLD_ROUND = 6 };
 ss_status ss_set_option(ss_ctx* ctx, int option, int64_t value);
 
 /* Kernel timing.  While enabled, every kernel launch of the engine is

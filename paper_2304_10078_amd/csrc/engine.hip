@@ -66,6 +66,7 @@ struct ss_ctx {
     uint32_t nl_target = 0;   // adaptive light-bucket target, percent of alpha; 0: per bucketing (ss_set_option)
     uint32_t tile0 = 0, tile_deep = 0;  // tile limits of the first / deeper levels, 0 = tile_max (ss_set_option)
     uint32_t call_tmaxd = 0;            // deeper-level tile limit chosen by the current call (0: Params)
+    uint32_t fold_round = 1024;         // block totals per round of the in-order fold's top carry (ss_set_option)
     // kernel timing with HIP events on the context's stream (ss_profile_*)
     bool prof_on = false;
     struct Pending {
@@ -1405,6 +1406,11 @@ ss_status ss_set_option(ss_ctx* c, int option, int64_t value)
         (option == SS_OPT_TILE0 ? c->tile0 : c->tile_deep) = (uint32_t)value;
         return SS_OK;
     }
+    case SS_OPT_FOLD_ROUND:
+        if (value < 1 || value > 1024 || (value & (value - 1)) != 0)
+            return fail(c, SS_EINVAL, "fold round must be a power of two in [1, 1024]");
+        c->fold_round = (uint32_t)value;
+        return SS_OK;
     case SS_OPT_NL_TARGET:
         if (value != 0 && (value < 10 || value > 100))
             return fail(c, SS_EINVAL, "light-bucket target must be 0 or 10..100 percent");
@@ -1800,7 +1806,8 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
                            (const uint64_t*)sv, n, aggv, aggf);
         hipLaunchKernelGGL(k_sfold_carry_blocks, dim3((uint32_t)ncb), dim3(256), 0, c->stream, aggv, aggf,
                            (uint32_t)nch, totv, totf);
-        hipLaunchKernelGGL(k_sfold_carry_top, dim3(1), dim3(1024), 0, c->stream, totv, totf, (uint32_t)ncb);
+        hipLaunchKernelGGL(k_sfold_carry_top, dim3(1), dim3(1024), 0, c->stream, totv, totf, (uint32_t)ncb,
+                           c->fold_round);
         hipLaunchKernelGGL(k_sfold_apply, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const uint64_t*)sk,
                            (const uint64_t*)sv, n, (const uint64_t*)aggv, (const uint32_t*)aggf,
                            (const uint64_t*)totv, (uint64_t*)c->t_keys.p, (uint64_t*)c->t_vals.p, rf);

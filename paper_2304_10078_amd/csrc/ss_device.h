@@ -3100,9 +3100,10 @@ __global__ __launch_bounds__(256) void k_sfold_carry_blocks(uint64_t* aggv, uint
     }
 }
 
-__global__ __launch_bounds__(1024) void k_sfold_carry_top(uint64_t* totv, uint32_t* totf, uint32_t nb)
+__global__ __launch_bounds__(1024) void k_sfold_carry_top(uint64_t* totv, uint32_t* totf, uint32_t nb, uint32_t rb)
 {
-    // nb <= 2048: two rounds of 1024, Hillis-Steele in LDS
+    // rounds of rb <= 1024 block totals (a power of two), Hillis-Steele in
+    // LDS; the fold of every earlier round is carried into the next
     __shared__ uint64_t bv[1024];
     __shared__ uint32_t bf[1024];
     __shared__ uint64_t sh_cv;
@@ -3113,9 +3114,10 @@ __global__ __launch_bounds__(1024) void k_sfold_carry_top(uint64_t* totv, uint32
         sh_cf = 0;
     }
     __syncthreads();
-    for (uint32_t base = 0; base < nb; base += 1024) {
+    for (uint32_t base = 0; base < nb; base += rb) {
         const uint32_t i = base + t;
-        SegPair x = i < nb ? SegPair{totv[i], totf[i]} : SegPair{kAffineId, 0u};
+        const bool mine = t < rb && i < nb;
+        SegPair x = mine ? SegPair{totv[i], totf[i]} : SegPair{kAffineId, 0u};
         bv[t] = x.v;
         bf[t] = x.f;
         __syncthreads();
@@ -3131,11 +3133,11 @@ __global__ __launch_bounds__(1024) void k_sfold_carry_top(uint64_t* totv, uint32
         const SegPair carry{sh_cv, sh_cf};
         const SegPair before = t ? seg_then(carry, SegPair{bv[t - 1], bf[t - 1]}) : carry;
         __syncthreads();
-        if (i < nb) {
+        if (mine) {
             totv[i] = before.v;
             totf[i] = before.f;
         }
-        if (t == 1023) {
+        if (t == rb - 1) {
             const SegPair next = seg_then(carry, x);
             sh_cv = next.v;
             sh_cf = next.f;

@@ -139,6 +139,7 @@ class Context:
     OPT_NL_TARGET = 3
     OPT_TILE0 = 4
     OPT_TILE_DEEP = 5
+    OPT_FOLD_ROUND = 6
 
     def sync(self):
         """Wait for the context's stream; raises SemisortError for a device

@@ -233,12 +233,24 @@ def _wide_values(n, seed):
     return rng.integers(0, 2 ** 63, n, dtype=np.int64).astype(np.uint64) * np.uint64(2) + np.uint64(seed & 1)
 
 
+def _affine_values(n, seed):
+    # maps t -> a t + b mod 2^32 with ODD a: invertible, so every record of a
+    # group changes its fold (with even multipliers the product of a few
+    # dozen of them is 0 mod 2^32 and a long group's fold would depend only
+    # on its last records, hiding a lost carry)
+    return _wide_values(n, seed) | np.uint64(1 << 32)
+
+
+def _monoid_values(op, n, seed):
+    return _affine_values(n, seed) if op == "affine" else _wide_values(n, seed)
+
+
 @pytest.mark.parametrize("op", ["min", "max", "xor", "first", "last", "affine"])
 @pytest.mark.parametrize("name,n", [("zipf1.2_hashed", 1_500_001), ("uniform1e9", 1_000_000),
                                     ("uniform1e3", 700_000), ("exp1e-5_u32idx", 900_000)])
 def test_monoids_paper_distributions(op, name, n):
     k, _ = I.np_workload(name, n, 31)
-    v = _wide_values(n, 5)
+    v = _monoid_values(op, n, 5)
     _say(f"case: CR {op} {name} n={n}")
     check_monoid(k, v, op, ctx=f"CR {op} {name}")
 
@@ -248,19 +260,49 @@ def test_monoids_ragged_ordered_and_deep(op):
     for n in [1, 2, 3, 64, 4097, 65537, 200_003]:
         rng = np.random.default_rng(n)
         k = rng.integers(0, max(2, n // 6), n, dtype=np.int64).astype(np.uint64)
-        v = _wide_values(n, n)
+        v = _monoid_values(op, n, n)
         _say(f"case: CR {op} ragged n={n}")
         check_monoid(k, v, op, ctx=f"CR {op} n={n}")
         check_monoid(k, v, op, ordered=True, ctx=f"CR {op} ordered n={n}")
     rng = np.random.default_rng(9)
     n = 150_000
     k = rng.integers(0, 40_000, n, dtype=np.int64).astype(np.uint64)
-    v = _wide_values(n, 3)
+    v = _monoid_values(op, n, 3)
     p = S.default_params(n_light_log2=1, base_case=64, sample_mult=20)
     _say(f"case: CR {op} deep recursion")
     check_monoid(k, v, op, params=p, ctx=f"CR {op} deep")
     k = np.full(n, 77, dtype=np.uint64)  # one key: a single heavy bucket
     check_monoid(k, v, op, ctx=f"CR {op} one key")
+
+
+def test_affine_fold_carries_across_chunks_blocks_and_rounds():
+    # The in-order fold carries the open fold across 4096-record chunks, then
+    # across blocks of 256 chunks (2^20 positions), then across rounds of
+    # block totals.  Groups long enough to straddle those boundaries, with
+    # invertible maps, make every carry visible; rounds of 1 and 2 block
+    # totals reach the cross-round carry at this size.
+    n = 3 * (1 << 20) + 4099
+    v = _affine_values(n, 17)
+    cases = [("one key", np.full(n, 5, dtype=np.uint64)),
+             ("seven keys", np.random.default_rng(3).integers(0, 7, n, dtype=np.int64).astype(np.uint64)),
+             ("two keys in runs", (np.arange(n, dtype=np.uint64) // np.uint64(700_001)) % np.uint64(2)),
+             ("zipf", I.np_workload("zipf1.2_hashed", n, 9)[0])]
+    ctx = S.context(0)
+    try:
+        for rb in (1024, 2, 1):
+            ctx.set_option(S.Context.OPT_FOLD_ROUND, rb)
+            for name, k in cases:
+                _say(f"case: CR affine {name} n={n} fold round {rb}")
+                check_monoid(k, v, "affine", ctx=f"affine {name} round {rb}")
+    finally:
+        ctx.set_option(S.Context.OPT_FOLD_ROUND, 1024)
+
+
+def test_affine_fold_rejects_a_bad_round():
+    ctx = S.context(0)
+    for bad in (0, 3, 2048):
+        with pytest.raises(S.SemisortError):
+            ctx.set_option(S.Context.OPT_FOLD_ROUND, bad)
 
 
 def test_monoid_rejects_an_unknown_op():

@@ -1,15 +1,26 @@
 """Parity at the full 10^9-record sizes, in the launch configuration the
 benchmark times (default parameters, one call on the whole device-resident
 input).  The oracle cannot process 10^9 records inside a test, so these check
-properties that hold at any size -- the output is a permutation of the input,
-equal keys are contiguous, records of a key keep their input order -- plus
-sampled groups computed one by one by brute force (the input positions of one
-key, in order, are exactly that group of a stable semisort)."""
+complete properties that hold at any size and pin the result exactly:
+- semisort: the output is a permutation of the input (values are record
+  indices), every record kept its key, equal keys are contiguous, records of
+  a key keep their input order (with ascending keys for semisort_<); a stable
+  grouping is unique up to the order of its groups, so this is the whole
+  definition (Section 2.1, stability as in Section 2.2);
+- histogram and collect-reduce: EVERY group against a segment reduction of
+  the input by key computed with library operations (unique + scatter),
+  independent of the HIP path (Section 2.1, collect-reduce with the monoid);
+- the in-order affine fold: every group against the oracle at 10^8 records,
+  and sampled groups at 10^9 folded by the oracle one group at a time;
+- the batch of 4096 instances: every instance by the same complete
+  properties, and a sample of instances against the oracle;
+plus sampled groups computed one by one by brute force."""
 import sys
 
 import numpy as np
 import pytest
 
+import oracle as O
 from paper_2304_10078_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -92,24 +103,166 @@ def test_full_size_semisort_less_exponential_u32_values():
     _check_grouping(keys, ko, vo, ordered=True, seed=2)
 
 
-def test_full_size_collect_reduce_zipf12():
-    keys, vals = I.t_workload("zipf1.2_hashed", N, 4, "cuda")
-    _say("case: collect-reduce zipf1.2_hashed n=1e9")
-    gk, gs = S.collect_reduce(keys, vals)
+_SIGN = torch.iinfo(torch.int64).min
+
+
+def _segment_reduce(keys, vals, op):
+    """(distinct keys ascending as int64, per-key reduction): unique + scatter.
+    Sums wrap mod 2^64 like int64 addition; min / max compare unsigned (the
+    sign bit flipped maps unsigned order onto signed order)."""
+    uk, inv = torch.unique(keys, return_inverse=True)
+    m = uk.numel()
+    if op == "count":
+        r = torch.bincount(inv, minlength=m).to(torch.int64)
+    elif op == "sum":
+        r = torch.zeros(m, dtype=torch.int64, device=keys.device).index_add_(0, inv, vals)
+    elif op in ("min", "max"):
+        f = vals ^ _SIGN
+        r = torch.empty(m, dtype=torch.int64, device=keys.device)
+        r.scatter_reduce_(0, inv, f, "amin" if op == "min" else "amax", include_self=False)
+        r ^= _SIGN
+    else:
+        raise ValueError(op)
+    del inv
+    return uk, r
+
+
+def _check_reduce_complete(keys, vals, gk, gv, op, ordered=False):
+    uk, want = _segment_reduce(keys, vals, op)
+    assert gk.numel() == uk.numel(), f"{gk.numel()} groups, {uk.numel()} distinct keys"
+    if ordered:
+        # ascending as unsigned 64-bit words
+        a, b = gk[:-1] ^ _SIGN, gk[1:] ^ _SIGN
+        assert bool((a < b).all()), "ordered result keys are not strictly ascending"
+    o = torch.argsort(gk)
+    gk, gv = gk[o], gv[o]
+    assert torch.equal(gk, uk), "group keys differ from the distinct keys"
+    bad = torch.nonzero(gv != want).flatten()
+    assert bad.numel() == 0, f"{op} of key {int(gk[bad[0]])} is {int(gv[bad[0]])}, expected {int(want[bad[0]])}"
+
+
+@pytest.mark.parametrize("name,seed,op", [("zipf1.2_hashed", 4, "sum"), ("uniform1e9", 2, "sum"),
+                                          ("uniform1e3", 3, "sum"), ("uniform1e9", 2, "min"),
+                                          ("zipf1.2_hashed", 4, "max")])
+def test_full_size_collect_reduce_every_group(name, seed, op):
+    keys, vals = I.t_workload(name, N, seed, "cuda")
+    _say(f"case: collect-reduce {op} {name} n=1e9")
+    gk, gv = S.collect_reduce(keys, vals, op=op)
     S.sync()
-    uk = torch.unique(keys)
-    assert gk.numel() == uk.numel(), "number of groups differs from the distinct keys"
-    assert torch.equal(torch.sort(gk).values, uk), "group keys differ from the distinct keys"
-    # wrapping sums: the total is preserved mod 2^64 (int64 addition wraps the same way)
-    assert int(gs.sum()) == int(vals.sum()), "sum of the group sums differs from the sum of the values"
-    g = torch.Generator(device="cpu").manual_seed(3)
-    for p in torch.randint(0, gk.numel(), (16,), generator=g).tolist():
-        k = gk[p]
-        assert int(gs[p]) == int(vals[keys == k].sum()), f"sum of key {int(k)} differs"
-    # the heaviest key too
-    top = uk[torch.argmax(torch.bincount(torch.searchsorted(uk, keys)))]
-    p = int(torch.nonzero(gk == top).flatten()[0])
-    assert int(gs[p]) == int(vals[keys == top].sum())
+    _check_reduce_complete(keys, vals, gk, gv, op)
+
+
+def test_full_size_affine_fold_every_group_at_1e8():
+    # every group against the oracle (the in-order fold needs the input
+    # order, so no library reduction stands in for it)
+    n = 10 ** 8
+    keys, vals = I.t_workload("zipf1.2_hashed", n, 4, "cuda")
+    vals = vals | (1 << 32)  # odd multipliers: invertible maps
+    _say("case: collect-reduce affine zipf1.2_hashed n=1e8, every group against the oracle")
+    gk, gv = S.collect_reduce(keys, vals, op="affine")
+    S.sync()
+    hk = keys.cpu().numpy().view(np.uint64)
+    hv = vals.cpu().numpy().view(np.uint64)
+    rk, rv = O.collect_reduce(hk, hv, op="affine")
+    gk = gk.cpu().numpy().view(np.uint64)
+    gv = gv.cpu().numpy().view(np.uint64)
+    o = np.argsort(gk, kind="stable")
+    assert np.array_equal(gk[o], rk), "group keys differ from the oracle"
+    bad = np.nonzero(gv[o] != rv)[0]
+    assert bad.size == 0, f"fold of key {rk[bad[0]]} differs from the oracle"
+
+
+def test_full_size_affine_fold_sampled_groups():
+    keys, vals = I.t_workload("zipf1.2_hashed", N, 4, "cuda")
+    vals = vals | (1 << 32)
+    _say("case: collect-reduce affine zipf1.2_hashed n=1e9, sampled groups")
+    gk, gv = S.collect_reduce(keys, vals, op="affine")
+    S.sync()
+    assert gk.numel() == torch.unique(keys).numel()
+    g = torch.Generator(device="cpu").manual_seed(5)
+    picks = torch.randint(0, gk.numel(), (12,), generator=g).tolist()
+    # and groups met at random record positions (heavier keys), below 5e6 records
+    for p in torch.randint(0, N, (24,), generator=g).tolist():
+        q = int(torch.nonzero(gk == keys[p]).flatten()[0])
+        if len(picks) < 24 and int((keys == keys[p]).sum()) < 5_000_000:
+            picks.append(q)
+    for q in picks:
+        k = gk[q]
+        sel = torch.nonzero(keys == k).flatten()  # the group's records in input order
+        gvk = vals[sel].cpu().numpy().view(np.uint64)
+        rk, rv = O.collect_reduce(np.full(gvk.size, int(k) & (2 ** 64 - 1), dtype=np.uint64), gvk, op="affine")
+        assert rk.size == 1 and int(rv[0]) == int(gv[q]) & (2 ** 64 - 1), f"fold of key {int(k)} differs"
+
+
+def test_full_size_semisort_equal_uniform_1e3():
+    keys, vals = _indexed("uniform1e3", 3)
+    _say("case: semisort_= uniform[0,1e3) n=1e9")
+    ko, vo = S.semisort_equal(keys, vals)
+    S.sync()
+    _check_grouping(keys, ko, vo, ordered=False, seed=4)
+
+
+def test_full_size_semisort_less_zipf08_u32_values():
+    keys, vals = _indexed("zipf0.8_1e8_u32idx", 6)
+    _say("case: semisort_< zipf0.8 over [1,1e8] n=1e9, u32 values")
+    ko, vo = S.semisort_less(keys, vals)
+    S.sync()
+    _check_grouping(keys, ko, vo, ordered=True, seed=5)
+
+
+def test_full_size_histogram_exponential():
+    keys, _ = I.t_workload("exp1e-5_u32idx", N, 5, "cuda")
+    _say("case: ordered histogram exp(1e-5) n=1e9")
+    gk, gc = S.histogram(keys, ordered=True)
+    S.sync()
+    _check_reduce_complete(keys, None, gk, gc, "count", ordered=True)
+    # keys are non-negative, so the signed ascending order is the unsigned one
+    assert torch.equal(gk, torch.unique(keys))
+
+
+def test_full_size_batch_every_instance():
+    # the benchmark's batch: 4096 instances, 5e8 records, autotuned
+    # parameters; values are the global record index
+    keys, vals, offs, _ = I.t_batch_workload(4096, 1e3, 1e7, 5e8, 7, "cuda")
+    n = keys.numel()
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    best, _ = S.autotune_equal_batch(keys, vals, offs, ko, vo, reps=1)
+    _say(f"case: batch of 4096 instances n={n}, tuned c={best.sample_mult} tau={best.heavy_min} "
+         f"nl={best.n_light_log2} alpha={best.base_case} tmax={best.tile_max}")
+    S.semisort_equal_batch(keys, vals, offs, ko, vo, params=best)
+    S.sync()
+    od = torch.from_numpy(np.asarray(offs, dtype=np.int64)).cuda()
+    inst = torch.searchsorted(od, torch.arange(n, device="cuda"), right=True) - 1  # instance of each position
+    # every record stays in its instance, once, with its key
+    mark = torch.zeros(n, dtype=torch.bool, device="cuda")
+    mark[vo] = True
+    assert bool(mark.all()), "output is not a permutation of the input"
+    del mark
+    assert bool(torch.equal(inst[vo], inst)), "a record left its instance"
+    assert bool(torch.equal(ko, keys[vo])), "a record lost its key"
+    # contiguity per instance: (instance, key) starts one run only
+    same = (ko[1:] == ko[:-1]) & (inst[1:] == inst[:-1])
+    starts = torch.ones(n, dtype=torch.bool, device="cuda")
+    starts[1:] = ~same
+    rk, ri = ko[starts], inst[starts]
+    o1 = torch.argsort(rk, stable=True)
+    o = o1[torch.argsort(ri[o1], stable=True)]  # runs ordered by (instance, key)
+    rk, ri = rk[o], ri[o]
+    dup = (rk[1:] == rk[:-1]) & (ri[1:] == ri[:-1])
+    assert not bool(dup.any()), "a key occurs in two runs of one instance"
+    del rk, ri, o, o1, dup, starts
+    assert bool(((vo[1:] > vo[:-1]) | ~same).all()), "records of a key lost their input order"
+    # a sample of instances against the oracle, bit-exact after canonicalization
+    o = [int(x) for x in offs]
+    g = np.random.default_rng(12)
+    for i in sorted(set(g.integers(0, 4096, 48).tolist())):
+        a, b = o[i], o[i + 1]
+        k = keys[a:b].cpu().numpy().view(np.uint64)
+        v = vals[a:b].cpu().numpy().view(np.uint64)
+        rk, rv = O.semisort_equal(k, v, best.hash_mode)
+        bad, ck, cv = O.canonicalize_equal(ko[a:b].cpu().numpy().view(np.uint64),
+                                           vo[a:b].cpu().numpy().view(np.uint64), best.hash_mode)
+        assert bad == -1 and np.array_equal(ck, rk) and np.array_equal(cv, rv), f"instance {i} differs from the oracle"
 
 
 def test_full_size_histogram_zipf08():
@@ -117,10 +270,9 @@ def test_full_size_histogram_zipf08():
     _say("case: ordered histogram zipf0.8 over [1,1e8] n=1e9")
     gk, gc = S.histogram(keys, ordered=True)
     S.sync()
+    _check_reduce_complete(keys, None, gk, gc, "count", ordered=True)
     # keys are positive, so torch's signed ascending order is the unsigned one
-    uk, uc = torch.unique(keys, return_counts=True)
-    assert gk.numel() == uk.numel()
-    assert torch.equal(gk, uk) and torch.equal(gc, uc), "ordered histogram differs from the sorted distinct-key counts"
+    assert torch.equal(gk, torch.unique(keys))
 
 
 @pytest.mark.parametrize("kind", I.GRAPH_KINDS)

@@ -95,6 +95,8 @@ def test_random_shapes_and_parameters(case):
     assert np.array_equal(gk[o], rk) and np.array_equal(gc[o], rc), f"case {case} histogram"
 
     op = ("min", "max", "xor", "first", "last", "affine")[case % 6]
+    if op == "affine":
+        vals = vals | np.uint64(1 << 32)  # odd multipliers: every record changes its group's fold
     gk, gs = S.collect_reduce(to_dev(k), to_dev(vals), params=p, op=op)
     S.sync()
     gk, gs = to_host(gk, np.uint64), to_host(gs, np.uint64)

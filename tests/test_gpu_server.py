@@ -143,3 +143,92 @@ def test_rejects_bad_requests_and_tickets():
         assert srv.poll(t)[0]
     finally:
         srv.close()
+
+
+def _digest(t, w1, w2):
+    """Order-dependent 128-bit digest of an int64 tensor: two sums of the
+    entries times fixed odd per-position weights, wrapping mod 2^64."""
+    n = t.numel()
+    return int((t * w1[:n]).sum()), int((t * w2[:n]).sum())
+
+
+def test_full_trace_every_served_result_equals_its_alone_run():
+    # The benchmark's served configuration: 20,000 requests of a Poisson
+    # stream at 2000/s, sizes log-uniform in [1e4, 1e8], semisort_= /
+    # histogram / collect-reduce over a device-resident pool, 200 GB budget,
+    # four lanes.  Each output's digest is taken when the request completes
+    # and compared with the digest of the same request run alone.
+    import time
+    R, P = 20_000, 10 ** 8
+    tr = I.serving_trace(R, P, seed=8)
+    pool = I.t_serving_pool(P, 8, "cuda")
+    g = torch.Generator(device="cuda").manual_seed(99)
+    w1 = torch.randint(-2 ** 62, 2 ** 62, (P,), device="cuda", generator=g) * 2 + 1
+    w2 = torch.randint(-2 ** 62, 2 ** 62, (P,), device="cuda", generator=g) * 2 + 1
+    torch.cuda.synchronize()
+    opcode = {0: S.OP_SEMISORT_EQUAL, 1: S.OP_HISTOGRAM, 2: S.OP_COLLECT_REDUCE}
+
+    def req(i):
+        k, v = pool[int(tr["dists"][i])]
+        a, n = int(tr["offs"][i]), int(tr["sizes"][i])
+        return opcode[int(tr["ops"][i])], k[a:a + n], v[a:a + n]
+
+    served = [None] * R
+    srv = S.Server(lanes=4, hbm_budget=200 << 30)
+    try:
+        pending = {}
+        out_bytes, cap = 0, 48 << 30
+
+        def reap():
+            nonlocal out_bytes
+            for i in list(pending):
+                t, oa, ob, nb = pending[i]
+                done, st, _, m = srv.poll(t)
+                if done:
+                    assert st == 0, f"request {i} failed with {st}"
+                    op = opcode[int(tr["ops"][i])]
+                    if op != S.OP_SEMISORT_EQUAL:
+                        oa, ob = oa[:m], ob[:m]
+                    served[i] = (m, _digest(oa, w1, w2), _digest(ob, w1, w2))
+                    out_bytes -= nb
+                    del pending[i]
+
+        base = srv.now()
+        for i in range(R):
+            op, k, v = req(i)
+            nb = k.numel() * 16
+            while out_bytes + nb > cap and pending:
+                reap()
+                time.sleep(0.0002)
+            while srv.now() - base < tr["arrival"][i]:
+                reap()
+            oa, ob = torch.empty_like(k), torch.empty_like(k)
+            t = srv.submit(op, k, v if op != S.OP_HISTOGRAM else None, oa, ob, arrival=base + tr["arrival"][i])
+            pending[i] = (t, oa, ob, nb)
+            out_bytes += nb
+            if i % 2000 == 0:
+                _say(f"served trace: {i} of {R} submitted")
+        srv.drain()
+        reap()
+        assert not pending
+        st = srv.stats()
+        _say(f"served trace: {st['completed']} completed, {st['calls']} calls, {st['packed']} packed")
+    finally:
+        srv.close()
+    ctx = S.context(0)
+    for i in range(R):
+        op, k, v = req(i)
+        if op == S.OP_SEMISORT_EQUAL:
+            oa, ob = S.semisort_equal(k, v, ctx=ctx)
+            m = 0
+        elif op == S.OP_HISTOGRAM:
+            oa, ob = S.histogram(k, ctx=ctx)
+            m = oa.numel()
+        else:
+            oa, ob = S.collect_reduce(k, v, ctx=ctx)
+            m = oa.numel()
+        ctx.sync()
+        alone = (m, _digest(oa, w1, w2), _digest(ob, w1, w2))
+        assert served[i] == alone, f"request {i} (op {op}, n {k.numel()}) differs from its alone run"
+        if i % 2000 == 0:
+            _say(f"alone runs: {i} of {R} match")
