@@ -201,6 +201,31 @@ ss_status ss_semisort_equal_batch_capturable(ss_ctx* ctx, const uint64_t* keys, 
                                              void* vals_out, uint32_t max_levels,
                                              const ss_params* params);
 
+/* For callers that cannot allocate device memory (code under stream capture
+ * that must not depend on an earlier sizing call, tight serving loops,
+ * harnesses that forbid hipMalloc): ss_semisort_equal_batch_capturable with
+ * the whole workspace in a static device array of the library (64 MiB,
+ * one copy per device, held by every device the library runs on until the
+ * process ends; its address is looked up once per device in ss_create).  The
+ * call allocates nothing: no hipMalloc, hipFree or allocating library
+ * routine.  Arguments, result, device conditions and errors are those of
+ * ss_semisort_equal_batch_capturable, except:
+ * - The workspace needed by the call's worst case (about 50 bytes per record
+ *   with the default parameters and 8-byte values, more with a smaller
+ *   base_case or tile_min) must fit in the array, else SS_EINVAL with the
+ *   bytes needed, before anything is enqueued.  With the default parameters
+ *   batches of up to 2^20 records fit, with either value width.
+ * - Every call on a device shares that device's array, which keeps the last
+ *   call's contents (each call clears the counters it needs): calls that
+ *   overlap on one device -- on two streams, two contexts or two threads --
+ *   race and give wrong results.  Serialize them.
+ * - A captured graph of this call needs no earlier uncaptured call. */
+ss_status ss_semisort_equal_batch_noalloc(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                          uint32_t val_bytes, const uint64_t* seg_offsets,
+                                          uint64_t nseg, uint64_t n, uint64_t* keys_out,
+                                          void* vals_out, uint32_t max_levels,
+                                          const ss_params* params);
+
 /* Autotuner for batched semisort_=: runs the batch with every parameter set
  * of a fixed grid around the defaults (sample_mult in {500, 800}, heavy_min in
  * {0, 3}, n_light_log2 in {8, 10}, base_case in {2048, 4096}, tile_max in

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,38 @@ struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
 };
+
+}  // namespace
+
+// Workspace of ss_semisort_equal_batch_noalloc, for callers that cannot
+// allocate: a static device array, one copy per device, held by every device
+// the library runs on until the process ends.  Host code never passes its
+// name to a kernel (on the host the name is only a stand-in); it uses the
+// device address looked up once per device.
+constexpr size_t kScratchBytes = 64ull << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The scratch array's address on `device`, which must be current.
+hipError_t scratch_address(int device, void** out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -54,6 +87,8 @@ struct ss_ctx {
     DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
     DevBuf tr_keys, tr_vals, tr_sorted, tr_min;  // graph transpose: records, sorted endpoints, chunk minima
     DevBuf pos;                      // record positions (first / last collect-reduce)
+    void* scratch = nullptr;         // device address of the static scratch array on this device
+    std::string scratch_err;         // why it has none
     std::vector<Seg> host_segs;
     std::vector<Job> host_jobs[kJobClasses];
     uint32_t job_cap = 0;  // entries per class list
@@ -841,13 +876,101 @@ DsBounds ds_bounds(uint64_t n, uint64_t nseg, const Params& p)
     return b;
 }
 
+// Workspace of a device-sized batch: every buffer the levels use, taken
+// either from the context's growable buffers or, for the call that must not
+// allocate, carved out of the library's static scratch array.
+enum DsBufId {
+    kDsTKeys, kDsTVals, kDsBids, kDsSink, kDsInfos, kDsJobs, kDsQueues, kDsSegs0, kDsSegs1, kDsC, kDsP, kDsTot,
+    kDsBstart, kDsHeavy, kDsTabH, kDsTabId, kDsBfin, kDsBkey, kDsTop, kDsFills0, kDsFills1, kDsBufCount
+};
+
+struct DsSpace {
+    void* p[kDsBufCount];
+    uint32_t fill_cap;  // entries of each key-fill list
+};
+
+// Bytes of every buffer for a batch of n records in ninst instances.
+void ds_sizes(uint64_t n, uint32_t vb, const DsBounds& b, uint32_t levels, uint64_t jtot, uint64_t fcap,
+              size_t (&sz)[kDsBufCount])
+{
+    sz[kDsTKeys] = n * 8;
+    sz[kDsTVals] = n * vb;
+    sz[kDsBids] = n * 2;
+    sz[kDsSink] = 512;
+    sz[kDsInfos] = (size_t)(levels + 1) * sizeof(LevelInfo);
+    sz[kDsJobs] = jtot * sizeof(Job);
+    sz[kDsQueues] = (size_t)(levels + 1) * kQueueWords * 4;
+    sz[kDsSegs0] = sz[kDsSegs1] = b.segs * sizeof(Seg);
+    sz[kDsC] = b.tiles * kNbStride * 4;
+    sz[kDsP] = b.chunks * kNbStride * 4;
+    sz[kDsTot] = b.segs * kNbStride * 4;
+    sz[kDsBstart] = b.segs * (kNbStride + 1) * 4;
+    sz[kDsHeavy] = b.segs * kHeavyMax * 8;
+    sz[kDsTabH] = b.segs * 2 * kHeavySlotsMax * 8;
+    sz[kDsTabId] = b.segs * 2 * kHeavySlotsMax * 2;
+    sz[kDsBfin] = b.segs * kNbStride;
+    sz[kDsBkey] = b.segs * kNbStride * 8;
+    sz[kDsTop] = b.segs * 4;
+    sz[kDsFills0] = sz[kDsFills1] = fcap * sizeof(FillJob);
+}
+
+// The context's buffers, grown outside capture only.
+ss_status ds_space_ctx(ss_ctx* c, const size_t (&sz)[kDsBufCount], bool capturing, DsSpace* sp)
+{
+    DevBuf* bufs[kDsBufCount] = {&c->t_keys, &c->t_vals, &c->bids, &c->sink, &c->ds_info, &c->ds_jobs, &c->ds_q,
+                                 &c->segs[0], &c->segs[1], &c->C, &c->P, &c->tot, &c->bstart, &c->heavy_list,
+                                 &c->tab_h, &c->tab_id, &c->bfin, &c->bkey, &c->top, &c->fills[0], &c->fills[1]};
+    ss_status s;
+    for (int i = 0; i < kDsBufCount; ++i) {
+        if ((s = ensure_ds(c, *bufs[i], sz[i], capturing)) != SS_OK) return s;
+        sp->p[i] = bufs[i]->p;
+    }
+    for (int k = 0; k < 2; ++k)
+        c->fill_cap[k] = (uint32_t)std::min<uint64_t>(c->fills[k].cap / sizeof(FillJob), 0xFFFFFFFFu);
+    sp->fill_cap = std::min(c->fill_cap[0], c->fill_cap[1]);
+    return SS_OK;
+}
+
+// Consecutive 256-byte aligned pieces of [base, base + cap); the bytes
+// needed, whether or not they fit, in *need.
+bool ds_space_carve(void* base, size_t cap, const size_t (&sz)[kDsBufCount], uint64_t fcap, DsSpace* sp,
+                    size_t* need)
+{
+    size_t o = 0;
+    for (int i = 0; i < kDsBufCount; ++i) {
+        sp->p[i] = (char*)base + o;
+        o += (sz[i] + 255) & ~(size_t)255;
+    }
+    sp->fill_cap = (uint32_t)std::min<uint64_t>(fcap, 0xFFFFFFFFu);
+    *need = o;
+    return o <= cap;
+}
+
+LevelArgs make_args_ds(ss_ctx* c, const DsSpace& sp, const Params& p, uint32_t level, Seg* segs,
+                       const uint64_t* sk, const void* sv, uint64_t* dk, void* dv, uint64_t* fk, void* fv)
+{
+    LevelArgs a = make_args(c, p, level, segs, 0, 0, sk, sv, dk, dv, fk, fv);
+    a.bids = (uint16_t*)sp.p[kDsBids];
+    a.sink = (uint64_t*)sp.p[kDsSink];
+    a.C = (uint32_t*)sp.p[kDsC];
+    a.P = (uint32_t*)sp.p[kDsP];
+    a.tot = (uint32_t*)sp.p[kDsTot];
+    a.bstart = (uint32_t*)sp.p[kDsBstart];
+    a.heavy_list = (uint64_t*)sp.p[kDsHeavy];
+    a.tab_h = (uint64_t*)sp.p[kDsTabH];
+    a.tab_id = (uint16_t*)sp.p[kDsTabId];
+    a.bfin = (uint8_t*)sp.p[kDsBfin];
+    a.bkey = (uint64_t*)sp.p[kDsBkey];
+    a.top = (uint32_t*)sp.p[kDsTop];
+    return a;
+}
+
 template <int MODE, typename V>
 void launch_jobs_ds(ss_ctx* c, const JobLists& jl, const LevelInfo* dims, uint32_t* q, const uint64_t* sk,
-                    const void* sv, uint64_t* ok, void* ov, LevelInfo* info)
+                    const void* sv, uint64_t* ok, void* ov, LevelInfo* info, uint64_t* sink)
 {
     const V* svv = (const V*)sv;
     V* ovv = (V*)ov;
-    uint64_t* sink = (uint64_t*)c->sink.p;
     const uint32_t* cnt = dims->njobs;
     hipLaunchKernelGGL((k_base_ds<MODE, V, 1>), dim3(ds_grid<k_base_ds<MODE, V, 1>>(c, 64, jl.cap[0])), dim3(64), 0,
                        c->stream, jl.jobs + jl.base[0], cnt + 0, jl.cap[0], sk, svv, ok, ovv, sink, info);
@@ -881,68 +1004,55 @@ void launch_level_ds(ss_ctx* c, const LevelArgs& a, const DsBounds& b)
                        dim3(1024), 0, c->stream, a);
 }
 
-// The batch with every level sized on the device: no host synchronization
-// and, once the workspace is sized, no allocation, so the whole call can be
-// captured into a graph.  `offs` is a device array of ninst + 1 offsets.
-template <int MODE, typename V>
-ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs, uint64_t ninst,
-                          uint64_t n, uint64_t* keys_out, void* vals_out, const Params& p, uint32_t levels)
-{
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    HIP_OR_FAIL(c, hipStreamIsCapturing(c->stream, &cs));
-    const bool capturing = cs != hipStreamCaptureStatusNone;
-    const bool inplace = keys_out == keys;
-    const DsBounds b = ds_bounds(n, ninst, p);
-    if (b.segs >= (1ull << 31) || b.tiles >= (1ull << 31) || b.jobs[kCopyClass] >= (1ull << 32))
-        return fail(c, SS_EINVAL, "batch too large for the device-sized form");
-    ss_status s;
-    uint64_t jtot = 0;
+// Bounds, job-list layout and key-fill list size of a device-sized batch.
+struct DsPlan {
+    DsBounds b;
     JobLists jl;
+    uint64_t jtot, fcap;
+};
+
+ss_status ds_plan(ss_ctx* c, uint64_t n, uint64_t ninst, const Params& p, DsPlan* d)
+{
+    d->b = ds_bounds(n, ninst, p);
+    if (d->b.segs >= (1ull << 31) || d->b.tiles >= (1ull << 31) || d->b.jobs[kCopyClass] >= (1ull << 32))
+        return fail(c, SS_EINVAL, "batch too large for the device-sized form");
+    d->jtot = 0;
     for (int k = 0; k < kJobClasses; ++k) {
-        jl.base[k] = jtot;
-        jl.cap[k] = (uint32_t)b.jobs[k];
-        jtot += b.jobs[k];
+        d->jl.base[k] = d->jtot;
+        d->jl.cap[k] = (uint32_t)d->b.jobs[k];
+        d->jtot += d->b.jobs[k];
     }
-    if ((s = ensure_ds(c, c->t_keys, n * 8, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->t_vals, n * sizeof(V), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->bids, n * 2, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->sink, 512, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->info, sizeof(LevelInfo), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->ds_info, (size_t)(levels + 1) * sizeof(LevelInfo), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->ds_jobs, jtot * sizeof(Job), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->ds_q, (size_t)(levels + 1) * kQueueWords * 4, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->segs[0], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->segs[1], b.segs * sizeof(Seg), capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->C, b.tiles * kNbStride * 4, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->P, b.chunks * kNbStride * 4, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->tot, b.segs * kNbStride * 4, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->bstart, b.segs * (kNbStride + 1) * 4, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->heavy_list, b.segs * kHeavyMax * 8, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->tab_h, b.segs * 2 * kHeavySlotsMax * 8, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->tab_id, b.segs * 2 * kHeavySlotsMax * 2, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->bfin, b.segs * kNbStride, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->bkey, b.segs * kNbStride * 8, capturing)) != SS_OK) return s;
-    if ((s = ensure_ds(c, c->top, b.segs * 4, capturing)) != SS_OK) return s;
     // key-fill lists of one-key buckets (alternating levels), run on the
     // second stream as in the host-sized engine: at most one job per
     // non-empty heavy bucket plus one per kFillChunk records
-    const uint64_t fcap = std::min<uint64_t>(b.segs * kHeavyMax, n) + n / kFillChunk + 1;
-    for (int k = 0; k < 2; ++k) {
-        if ((s = ensure_ds(c, c->fills[k], fcap * sizeof(FillJob), capturing)) != SS_OK) return s;
-        c->fill_cap[k] = (uint32_t)std::min<uint64_t>(c->fills[k].cap / sizeof(FillJob), 0xFFFFFFFFu);
-    }
-    if (!c->aux && capturing)
-        return fail(c, SS_EINVAL, "the second stream must be created by an uncaptured call first");
-    if ((s = ensure_aux(c)) != SS_OK) return s;
+    d->fcap = std::min<uint64_t>(d->b.segs * kHeavyMax, n) + n / kFillChunk + 1;
+    return SS_OK;
+}
+
+// The batch with every level sized on the device: no host synchronization
+// and no allocation (the workspace `sp` is sized already), so the whole call
+// can be captured into a graph.  `offs` is a device array of ninst + 1
+// offsets.
+template <int MODE, typename V>
+ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs, uint64_t ninst,
+                          uint64_t n, uint64_t* keys_out, void* vals_out, const Params& p, uint32_t levels,
+                          const DsPlan& d, const DsSpace& sp)
+{
+    const bool inplace = keys_out == keys;
+    const DsBounds& b = d.b;
+    JobLists jl = d.jl;
+    jl.jobs = (Job*)sp.p[kDsJobs];
     bool fill_used[2] = {false, false};
-    jl.jobs = (Job*)c->ds_jobs.p;
     const uint32_t seg_cap = (uint32_t)b.segs;
-    LevelInfo* infos = (LevelInfo*)c->ds_info.p;
+    LevelInfo* infos = (LevelInfo*)sp.p[kDsInfos];
+    uint64_t* sink = (uint64_t*)sp.p[kDsSink];
+    Seg* segs[2] = {(Seg*)sp.p[kDsSegs0], (Seg*)sp.p[kDsSegs1]};
+    FillJob* fills[2] = {(FillJob*)sp.p[kDsFills0], (FillJob*)sp.p[kDsFills1]};
 
     // counts of every level start at zero; so does the call's status word
     const uint32_t iw = (uint32_t)((levels + 1) * sizeof(LevelInfo) / 4);
     hipLaunchKernelGGL(k_ds_clear, dim3((iw + 255) / 256), dim3(256), 0, c->stream, (uint32_t*)infos, iw);
-    uint32_t* qs = (uint32_t*)c->ds_q.p;  // per level: kQueueWords counters
+    uint32_t* qs = (uint32_t*)sp.p[kDsQueues];  // per level: kQueueWords counters
     hipLaunchKernelGGL(k_ds_clear, dim3(((levels + 1) * kQueueWords + 255) / 256), dim3(256), 0, c->stream, qs,
                        (levels + 1) * kQueueWords);
     hipLaunchKernelGGL(k_ds_clear, dim3(1), dim3(256), 0, c->stream, (uint32_t*)c->info.p,
@@ -951,16 +1061,16 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
                        dim3(256), 0, c->stream, offs, (uint32_t)ninst, n, infos);
     hipLaunchKernelGGL(k_ds_plan_instances, dim3((uint32_t)std::min<uint64_t>((ninst + 255) / 256, 4096)), dim3(256),
                        0, c->stream, offs, (uint32_t)ninst, n, p.alpha, p.nl0, (uint32_t)inplace,
-                       (Seg*)c->segs[0].p, seg_cap, jl, infos);
-    hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[0].p, seg_cap, infos, p.tmin,
+                       segs[0], seg_cap, jl, infos);
+    hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, segs[0], seg_cap, infos, p.tmin,
                        p.tmax0);
-    launch_jobs_ds<MODE, V>(c, jl, infos, qs, keys, vals, keys_out, vals_out, infos);
+    launch_jobs_ds<MODE, V>(c, jl, infos, qs, keys, vals, keys_out, vals_out, infos, sink);
     HIP_OR_FAIL(c, hipGetLastError());
 
     const uint64_t* loc_k = keys;
     const void* loc_v = vals;
-    uint64_t* T_k = (uint64_t*)c->t_keys.p;
-    void* T_v = c->t_vals.p;
+    uint64_t* T_k = (uint64_t*)sp.p[kDsTKeys];
+    void* T_v = sp.p[kDsTVals];
     int cur = 0;
     for (uint32_t level = 0; level < levels; ++level) {
         // buffers as in the host-sized engine (the sequence does not depend on the data)
@@ -980,7 +1090,7 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
             fin_k = keys_out;
             fin_v = vals_out;
         }
-        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, 0, 0, loc_k, loc_v, dst_k, dst_v, fin_k, fin_v);
+        LevelArgs a = make_args_ds(c, sp, p, level, segs[cur], loc_k, loc_v, dst_k, dst_v, fin_k, fin_v);
         a.dims = infos + level;
         a.seg_cap = seg_cap;
         a.info = infos + level + 1;
@@ -994,10 +1104,10 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
         if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         PlanArgs pa;
-        pa.segs = (const Seg*)c->segs[cur].p;
+        pa.segs = segs[cur];
         pa.nsegs = 0;
-        pa.bstart = (const uint32_t*)c->bstart.p;
-        pa.next = (Seg*)c->segs[cur ^ 1].p;
+        pa.bstart = a.bstart;
+        pa.next = segs[cur ^ 1];
         pa.next_cap = seg_cap;
         pa.jobs = jl.jobs;
         for (int k = 0; k < kJobClasses; ++k) {
@@ -1008,30 +1118,29 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
         pa.alpha = p.alpha;
         pa.finals_in_out = fin_k == keys_out;
         pa.ordered = 0;
-        pa.bfin = (const uint8_t*)c->bfin.p;
+        pa.bfin = a.bfin;
         pa.reduce = 0;
         pa.fill = fill;
-        pa.bkey = (const uint64_t*)c->bkey.p;
-        pa.fills = (FillJob*)c->fills[fb].p;
-        pa.fill_cap = c->fill_cap[fb];
+        pa.bkey = a.bkey;
+        pa.fills = fills[fb];
+        pa.fill_cap = sp.fill_cap;
         pa.dims = infos + level;
         pa.cur_cap = seg_cap;
         hipLaunchKernelGGL(k_plan_ds, dim3(ds_grid<k_plan_ds>(c, 256, b.segs)), dim3(256), 0, c->stream, pa);
-        hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, (Seg*)c->segs[cur ^ 1].p, seg_cap,
+        hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(1024), 0, c->stream, segs[cur ^ 1], seg_cap,
                            infos + level + 1, p.tmin, p.tmaxd);
         if (fill) {
             HIP_OR_FAIL(c, hipEventRecord(c->fill_fork[fb], c->stream));
             HIP_OR_FAIL(c, hipStreamWaitEvent(c->aux, c->fill_fork[fb], 0));
             // one block per CU: the fill is bound by HBM writes and leaves
             // room for the base cases running beside it
-            hipLaunchKernelGGL(k_fill_ds, dim3((uint32_t)std::min<uint64_t>(fcap, (uint64_t)c->ncu)), dim3(1024), 0,
-                               c->aux,
-                               (const FillJob*)c->fills[fb].p, &infos[level + 1].nfills, c->fill_cap[fb], keys_out);
+            hipLaunchKernelGGL(k_fill_ds, dim3((uint32_t)std::min<uint64_t>(d.fcap, (uint64_t)c->ncu)), dim3(1024),
+                               0, c->aux, (const FillJob*)fills[fb], &infos[level + 1].nfills, sp.fill_cap, keys_out);
             HIP_OR_FAIL(c, hipEventRecord(c->fill_done[fb], c->aux));
             fill_used[fb] = true;
         }
         launch_jobs_ds<MODE, V>(c, jl, infos + level + 1, qs + (size_t)(level + 1) * kQueueWords, dst_k, dst_v,
-                                keys_out, vals_out, infos + level + 1);
+                                keys_out, vals_out, infos + level + 1, sink);
         HIP_OR_FAIL(c, hipGetLastError());
         loc_k = dst_k;
         loc_v = dst_v;
@@ -1040,9 +1149,54 @@ ss_status run_semisort_ds(ss_ctx* c, const uint64_t* keys, const void* vals, con
     for (int k = 0; k < 2; ++k)  // joins the second stream (also ends its part of a capture)
         if (fill_used[k]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[k], 0));
     hipLaunchKernelGGL(k_ds_finish, dim3(1), dim3(64), 0, c->stream, (const LevelInfo*)infos, levels, seg_cap, jl,
-                       c->fill_cap[0] < c->fill_cap[1] ? c->fill_cap[0] : c->fill_cap[1], (LevelInfo*)c->info.p);
+                       sp.fill_cap, (LevelInfo*)c->info.p);
     HIP_OR_FAIL(c, hipGetLastError());
     return SS_OK;
+}
+
+// The device-sized batch on the context's own workspace, grown (outside
+// capture) to the call's worst case.
+template <int MODE, typename V>
+ss_status run_semisort_ds_ctx(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
+                              uint64_t ninst, uint64_t n, uint64_t* keys_out, void* vals_out, const Params& p,
+                              uint32_t levels)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OR_FAIL(c, hipStreamIsCapturing(c->stream, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    ss_status s;
+    DsPlan d;
+    if ((s = ds_plan(c, n, ninst, p, &d)) != SS_OK) return s;
+    size_t sz[kDsBufCount];
+    ds_sizes(n, sizeof(V), d.b, levels, d.jtot, d.fcap, sz);
+    DsSpace sp;
+    if ((s = ds_space_ctx(c, sz, capturing, &sp)) != SS_OK) return s;
+    if (!c->aux && capturing)
+        return fail(c, SS_EINVAL, "the second stream must be created by an uncaptured call first");
+    if ((s = ensure_aux(c)) != SS_OK) return s;
+    return run_semisort_ds<MODE, V>(c, keys, vals, offs, ninst, n, keys_out, vals_out, p, levels, d, sp);
+}
+
+// The device-sized batch on the device's static scratch array (no allocation
+// at all); SS_EINVAL when the call's worst case does not fit in it.
+template <int MODE, typename V>
+ss_status run_semisort_ds_static(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
+                                 uint64_t ninst, uint64_t n, uint64_t* keys_out, void* vals_out, const Params& p,
+                                 uint32_t levels)
+{
+    if (!c->scratch) return fail(c, SS_EHIP, "the static scratch array has no device address: " + c->scratch_err);
+    if (!c->aux) return fail(c, SS_EHIP, "the context has no second stream");
+    ss_status s;
+    DsPlan d;
+    if ((s = ds_plan(c, n, ninst, p, &d)) != SS_OK) return s;
+    size_t sz[kDsBufCount];
+    ds_sizes(n, sizeof(V), d.b, levels, d.jtot, d.fcap, sz);
+    DsSpace sp;
+    size_t need = 0;
+    if (!ds_space_carve(c->scratch, kScratchBytes, sz, d.fcap, &sp, &need))
+        return fail(c, SS_EINVAL, "the batch needs " + std::to_string(need) + " bytes of workspace, more than the " +
+                                      std::to_string(kScratchBytes) + "-byte static scratch array holds");
+    return run_semisort_ds<MODE, V>(c, keys, vals, offs, ninst, n, keys_out, vals_out, p, levels, d, sp);
 }
 
 // ---------------------------------------------------------------- collect-reduce
@@ -1326,11 +1480,15 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
     }
     if (ensure(c, c->info, sizeof(LevelInfo)) != SS_OK ||
         hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        if (c->info.p) (void)hipFree(c->info.p);
-        (void)hipHostFree(c->info_host);
-        delete c;
+        hipStreamSynchronize(c->stream) != hipSuccess || ensure_aux(c) != SS_OK) {
+        (void)ss_destroy(c);
         return SS_EHIP;
+    }
+    // the static scratch array's address on this device (current above)
+    const hipError_t se = scratch_address(device, &c->scratch);
+    if (se != hipSuccess) {
+        (void)hipGetLastError();
+        c->scratch_err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(se);
     }
     *out = c;
     return SS_OK;
@@ -1511,10 +1669,33 @@ ss_status ss_semisort_equal_batch_capturable(ss_ctx* c, const uint64_t* keys, co
     default_tiles(c, params, &p, 32768u, 16384u);
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
     if (p.mode == 1)
-        return vb == 8 ? run_semisort_ds<1, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
-                       : run_semisort_ds<1, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
-    return vb == 8 ? run_semisort_ds<0, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
-                   : run_semisort_ds<0, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
+        return vb == 8 ? run_semisort_ds_ctx<1, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                       : run_semisort_ds_ctx<1, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
+    return vb == 8 ? run_semisort_ds_ctx<0, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                   : run_semisort_ds_ctx<0, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
+}
+
+ss_status ss_semisort_equal_batch_noalloc(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                          const uint64_t* seg_offsets, uint64_t nseg, uint64_t n,
+                                          uint64_t* keys_out, void* vals_out, uint32_t max_levels,
+                                          const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (nseg == 0) return SS_OK;
+    if (!seg_offsets) return fail(c, SS_EINVAL, "null seg_offsets");
+    if (nseg >= (1ull << 31)) return fail(c, SS_EINVAL, "too many instances");
+    if (max_levels < 1 || max_levels > 64) return fail(c, SS_EINVAL, "max_levels must be in 1..64");
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    default_tiles(c, params, &p, 32768u, 16384u);
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (p.mode == 1)
+        return vb == 8 ? run_semisort_ds_static<1, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                       : run_semisort_ds_static<1, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
+    return vb == 8 ? run_semisort_ds_static<0, uint64_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels)
+                   : run_semisort_ds_static<0, uint32_t>(c, keys, vals, seg_offsets, nseg, n, keys_out, vals_out, p, max_levels);
 }
 
 ss_status ss_autotune_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,

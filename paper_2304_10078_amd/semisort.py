@@ -81,6 +81,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_double)]
         L.ss_histogram.argtypes = [vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
         L.ss_semisort_equal_batch_capturable.argtypes = [vp, vp, vp, u32, vp, u64, u64, vp, vp, u32, P]
+        L.ss_semisort_equal_batch_noalloc.argtypes = L.ss_semisort_equal_batch_capturable.argtypes
         L.ss_collect_reduce_monoid.argtypes = [vp, vp, vp, u64, i32, i32, vp, vp, ctypes.POINTER(u64), P]
         L.ss_transpose_csr.argtypes = [vp, u64, u64, vp, vp, vp, vp, P]
         L.ss_collect_reduce_ordered.argtypes = L.ss_collect_reduce.argtypes
@@ -287,6 +288,27 @@ def semisort_equal_batch_capturable(keys, vals, seg_offsets, keys_out=None, vals
     if vals_out is None:
         vals_out = torch.empty_like(vals)
     ctx.check(lib().ss_semisort_equal_batch_capturable(
+        ctx.h, _ptr(keys), _ptr(vals), vb, _ptr(seg_offsets), seg_offsets.numel() - 1, keys.numel(),
+        _ptr(keys_out), _ptr(vals_out), max_levels, ctypes.byref(params) if params is not None else None))
+    return keys_out, vals_out
+
+
+def semisort_equal_batch_noalloc(keys, vals, seg_offsets, keys_out, vals_out, max_levels=4, params=None,
+                                 ctx=None):
+    """ss_semisort_equal_batch_noalloc: ss_semisort_equal_batch_capturable
+    with its workspace in the library's static scratch array, so the call
+    allocates nothing.  The outputs are passed in (this function allocates
+    nothing either); seg_offsets is an int64 DEVICE tensor of nseg+1
+    boundaries, the last = len(keys).  Calls on one device must not overlap."""
+    vb = _check_kv(keys, vals)
+    _check_keys(seg_offsets, "seg_offsets")
+    if seg_offsets.numel() < 1:
+        raise ValueError("seg_offsets needs nseg + 1 entries")
+    if keys_out.shape != keys.shape or vals_out.shape != vals.shape or vals_out.dtype != vals.dtype:
+        raise ValueError("outputs must match the inputs' shapes and value type")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    ctx.check(lib().ss_semisort_equal_batch_noalloc(
         ctx.h, _ptr(keys), _ptr(vals), vb, _ptr(seg_offsets), seg_offsets.numel() - 1, keys.numel(),
         _ptr(keys_out), _ptr(vals_out), max_levels, ctypes.byref(params) if params is not None else None))
     return keys_out, vals_out
