@@ -78,17 +78,46 @@ typedef struct {
 /* Fill *p with the defaults. */
 ss_status ss_default_params(ss_params* p);
 
+/* Operations (Section 2.1): semisort_= and semisort_< reorder records;
+ * histogram and collect-reduce (Section 3.5) emit one pair per distinct key. */
+typedef enum {
+    SS_OP_SEMISORT_EQUAL = 0,
+    SS_OP_SEMISORT_LESS = 1,
+    SS_OP_HISTOGRAM = 2,
+    SS_OP_COLLECT_REDUCE = 3
+} ss_op;
+
 /* Create a context on HIP device `device` issuing work on `hip_stream`
- * (a hipStream_t; NULL = the default stream). */
-ss_status ss_create(int device, void* hip_stream, ss_ctx** out);
+ * (a hipStream_t; NULL = the default stream).  workspace_cap bounds the
+ * device memory the context's workspace may hold (bytes; 0 = no bound): a
+ * call whose workspace would grow past it fails with SS_ENOMEM before
+ * anything is enqueued or freed, and the context stays usable.  The
+ * workspace grows on demand (by half again its size when that fits under
+ * the cap) and is freed by ss_destroy.  The context also holds a small
+ * status word and a second stream (default priority) for key fills. */
+ss_status ss_create(int device, void* hip_stream, size_t workspace_cap, ss_ctx** out);
 ss_status ss_destroy(ss_ctx* ctx);
 ss_status ss_set_stream(ss_ctx* ctx, void* hip_stream);
 const char* ss_last_error(ss_ctx* ctx);
 /* Wait for the context's stream; SS_EDEVICE if a kernel of an earlier call
  * on the context raised a device condition that was not reported yet. */
 ss_status ss_sync(ss_ctx* ctx);
-/* Bytes of workspace currently held by the context. */
-ss_status ss_workspace_bytes(ss_ctx* ctx, size_t* bytes);
+/* Bytes of workspace the context holds now. */
+ss_status ss_workspace_held(ss_ctx* ctx, size_t* bytes);
+/* Planning query (no context, no device): an upper bound of the workspace
+ * one call of operation `op` on n records makes a new context hold, for
+ * val_bytes 4 or 8 (semisort; histogram and collect-reduce use 8) and the
+ * given parameters (NULL = defaults).  A context created with workspace_cap
+ * at least this value cannot fail that call with SS_ENOMEM because of the
+ * cap.  The bound assumes the worst case of every level list (every
+ * subproblem at the base-case size, one job per bucket): about 70 bytes per
+ * record with the defaults, against about 22 actually held for the paper's
+ * distributions.  It covers collect-reduce with the commutative monoids and
+ * the ordered forms; the first/last monoids add 8 bytes per record and the
+ * affine fold 16.  SS_EINVAL for an unknown op, a bad val_bytes or
+ * parameters, or n >= 2^31. */
+ss_status ss_workspace_bytes(int op, uint64_t n, uint32_t val_bytes, const ss_params* params,
+                             size_t* bytes);
 
 /* Engine options (tuning knobs that are not part of ss_params).
  * SS_OPT_DIST_VARIANT selects the shape of the semisort distribution kernel:
@@ -331,6 +360,54 @@ ss_status ss_collect_reduce_ordered(ss_ctx* ctx, const uint64_t* keys, const uin
 ss_status ss_histogram_ordered(ss_ctx* ctx, const uint64_t* keys, uint64_t n, uint64_t* out_keys,
                                uint64_t* out_counts, uint64_t* m_out, const ss_params* params);
 
+/* Forms of ss_collect_reduce_monoid and ss_histogram that leave m on the
+ * device (Section 3.5; the count of distinct keys is known only at the end):
+ * d_m is a DEVICE pointer to one uint64 that receives m, written on the
+ * context's stream, and the call does not wait for its last kernels (its
+ * levels still wait once each to size the next level's launches, as
+ * semisort does).  With ordered = 1 the call reads m back once to size the
+ * ordering of the pairs, then waits as the ordered forms do.  Arguments,
+ * results and errors otherwise as the monoid / histogram calls; n = 0
+ * writes m = 0. */
+ss_status ss_collect_reduce_async(ss_ctx* ctx, const uint64_t* keys, const uint64_t* vals, uint64_t n,
+                                  int op, int ordered, uint64_t* out_keys, uint64_t* out_vals,
+                                  uint64_t* d_m, const ss_params* params);
+ss_status ss_histogram_async(ss_ctx* ctx, const uint64_t* keys, uint64_t n, int ordered,
+                             uint64_t* out_keys, uint64_t* out_counts, uint64_t* d_m,
+                             const ss_params* params);
+
+/* A batch of independent jobs of mixed operations (Section 2.1 and 3.5 for
+ * each; thousands of small group-by instances in one call).  Every job gets
+ * the result the single call gives for it alone: semisort_= as
+ * ss_semisort_equal, semisort_< as ss_semisort_less, histogram as
+ * ss_histogram_async (unordered) and collect-reduce as ss_collect_reduce_async
+ * with the (+ mod 2^64, 0) monoid (unordered); m of a histogram or
+ * collect-reduce job goes to its d_m (device).  Jobs are grouped by
+ * operation and value width; in each group the jobs of at most
+ * SS_BATCH_PACK_MAX records are gathered into one packed array by one kernel,
+ * run as one batched call (one launch chain per level for all of them) and
+ * their results scattered back by one kernel; larger jobs run one by one on
+ * their own arrays.  Packing takes 4 x (8 + value bytes) bytes of workspace
+ * per packed record (inputs and outputs, packed) besides the group's own.
+ * Jobs may share inputs; no output may overlap another job's arrays or its
+ * own inputs (in-place is not offered here).  SS_EINVAL for a bad job (op,
+ * val_bytes, n >= 2^31, a null pointer, an overlap) before anything is
+ * enqueued.  The call returns once everything is enqueued; results are
+ * ready when the stream is (ss_sync reports device conditions).  params
+ * apply to every job (NULL = defaults). */
+enum { SS_BATCH_PACK_MAX = 1 << 22 };
+typedef struct {
+    int32_t op;          /* ss_op */
+    uint32_t val_bytes;  /* 4 or 8 for semisort; ignored otherwise (collect-reduce values are u64) */
+    uint64_t n;
+    const uint64_t* keys;
+    const void* vals;    /* unused by the histogram */
+    void* out_a;         /* keys_out / out_keys: n entries */
+    void* out_b;         /* vals_out / out_sums / out_counts: n entries */
+    uint64_t* d_m;       /* histogram / collect-reduce: device uint64 receiving m; unused by semisort */
+} ss_job;
+ss_status ss_batch(ss_ctx* ctx, const ss_job* jobs, uint64_t njobs, const ss_params* params);
+
 /* Transpose of a directed graph in CSR (Section 5, graph transposing): the
  * transpose holds (u, v) for every edge (v, u), which for a CSR input is a
  * semisort of the edges by their other endpoint; a stable one keeps every
@@ -354,23 +431,18 @@ ss_status ss_transpose_csr(ss_ctx* ctx, uint64_t nv, uint64_t ne, const uint64_t
  * A server owns `lanes` worker threads, each driving its own context on its
  * own HIP stream (default priority), so requests on different lanes overlap
  * on the device.  Requests wait in arrival order; a free lane takes the
- * oldest request whose workspace estimate fits in hbm_budget together with
- * what the other lanes hold (an idle lane first gives its own workspace back
- * if nothing fits).  semisort_= requests of at most pack_max_records records
- * that are waiting with the same value width join the lane's call: they are
- * copied into the lane's packing buffers (batch_records records each for keys
- * and values, in and out), run as one ss_semisort_equal_batch and copied out.
- * Every request gets the result it gets alone (instances of a batch do not
- * interact).  Inputs and outputs are caller-owned device arrays that must stay
- * valid until the request is done.  Completion is taken on the host once the
+ * oldest request that fits in hbm_budget together with everything else being
+ * served, and the requests of at most pack_max_records records waiting
+ * behind it -- of any operation -- join the same call, up to batch_records
+ * records and 4096 requests: the lane runs them as one ss_batch (packed
+ * into one launch chain per operation and level).  Every request gets the
+ * result it gets alone.  The budget counts the arrays of the requests being
+ * served (inputs and outputs) and each lane's workspace: what its context
+ * holds plus the planning bound (ss_workspace_bytes) of what the call may
+ * add; an idle lane gives its workspace back when nothing else fits.
+ * Inputs and outputs are caller-owned device arrays that must stay valid
+ * until the request is done.  Completion is taken on the host once the
  * lane's stream has drained; latency runs from the arrival time to then. */
-typedef enum {
-    SS_OP_SEMISORT_EQUAL = 0,
-    SS_OP_SEMISORT_LESS = 1,
-    SS_OP_HISTOGRAM = 2,
-    SS_OP_COLLECT_REDUCE = 3
-} ss_op;
-
 typedef struct {
     int32_t op;          /* ss_op */
     uint32_t val_bytes;  /* 4 or 8 for semisort; ignored otherwise (collect-reduce values are u64) */
@@ -383,26 +455,25 @@ typedef struct {
 
 typedef struct {
     uint32_t lanes;             /* 1..16 (default 4) */
-    uint32_t pack_max_records;  /* largest semisort_= request that is packed (default 2^20; 0 = never) */
-    uint64_t batch_records;     /* packing buffer size in records (default 2^24) */
-    uint64_t hbm_budget;        /* bytes of device memory the server may hold (default 200 GiB) */
+    uint32_t pack_max_records;  /* largest request that joins another's call (default 2^20; 0 = never) */
+    uint64_t batch_records;     /* most records of one packed call (default 2^24) */
+    uint64_t hbm_budget;        /* bytes of device memory the requests being served and the lanes'
+                                   workspace may hold (default 200 GiB) */
     ss_params params;           /* parameters of every call (default ss_default_params) */
 } ss_server_config;
 
 typedef struct ss_server ss_server;
 
 ss_status ss_server_default_config(ss_server_config* cfg);
-/* cfg may be NULL (defaults).  SS_EINVAL for a bad device or lane count, or
- * when the packing buffers alone exceed the budget. */
+/* cfg may be NULL (defaults).  SS_EINVAL for a bad device or lane count. */
 ss_status ss_server_create(int device, const ss_server_config* cfg, ss_server** out);
 /* Seconds since the server was created (the clock of arrival times). */
 double ss_server_now(ss_server* srv);
 /* Queue a request (does not block on the device).  arrival_s: its arrival on
  * the server clock, or <= 0 for now.  *ticket identifies it in ss_server_poll.
- * SS_EINVAL for a malformed request, SS_ENOMEM for one whose workspace
- * estimate (about (8 + value bytes + 2) bytes per record, plus 64 MiB) can
- * never fit in the budget.  Inputs must be complete on the device: the lanes
- * do not wait for other streams. */
+ * SS_EINVAL for a malformed request, SS_ENOMEM for one whose arrays and
+ * workspace bound can never fit in the budget.  Inputs must be complete on
+ * the device: the lanes do not wait for other streams. */
 ss_status ss_server_submit(ss_server* srv, const ss_request* req, double arrival_s, uint64_t* ticket);
 /* *done = 1 once the request is complete; then *result is its status,
  * *latency_s its latency and *m its group count (histogram and collect-reduce).
@@ -412,7 +483,8 @@ ss_status ss_server_poll(ss_server* srv, uint64_t ticket, int* done, ss_status* 
 /* Wait until every submitted request is complete. */
 ss_status ss_server_drain(ss_server* srv);
 /* Requests completed, device calls made, requests that were packed with
- * others, and the largest device memory the server reserved (bytes). */
+ * others, and the largest device memory the server reserved (bytes; never
+ * above the budget). */
 ss_status ss_server_stats(ss_server* srv, uint64_t* completed, uint64_t* calls, uint64_t* packed,
                           uint64_t* peak_reserved);
 /* Stop the lanes and free everything; requests still waiting are dropped

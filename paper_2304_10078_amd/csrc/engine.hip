@@ -87,6 +87,13 @@ struct ss_ctx {
     DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
     DevBuf tr_keys, tr_vals, tr_sorted, tr_min;  // graph transpose: records, sorted endpoints, chunk minima
     DevBuf pos;                      // record positions (first / last collect-reduce)
+    DevBuf pk_k, pk_v, po_k, po_v;   // ss_batch: packed inputs and outputs
+    DevBuf pack_tab, pack_rank;      // ss_batch: packed job table, first result rank of every job
+    PackJob* pack_stage = nullptr;   // pinned staging of the packed job table
+    size_t pack_stage_cap = 0;
+    hipEvent_t stage_ev = nullptr;   // last copy out of a pinned staging buffer
+    size_t ws_cap = 0;               // workspace cap (0: none), from ss_create
+    size_t ws_held = 0;              // bytes of workspace held now
     void* scratch = nullptr;         // device address of the static scratch array on this device
     std::string scratch_err;         // why it has none
     std::vector<Seg> host_segs;
@@ -131,15 +138,29 @@ ss_status fail(ss_ctx* c, ss_status s, const std::string& msg)
             return fail((ctx), SS_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
     } while (0)
 
+// Grows a workspace buffer to at least `bytes` (by half again its size when
+// that fits, so buffers that grow level by level are not reallocated each
+// time).  With a workspace cap, the context's total must stay within it:
+// growth falls back to the exact size, and past the cap the call fails with
+// SS_ENOMEM before anything is freed or allocated.
 ss_status ensure(ss_ctx* c, DevBuf& b, size_t bytes)
 {
     if (bytes <= b.cap) return SS_OK;
+    const size_t need = (bytes + 255) & ~(size_t)255;
     size_t want = std::max(bytes, b.cap + b.cap / 2);
     want = (want + 255) & ~(size_t)255;
+    const size_t others = c->ws_held - b.cap;
+    if (c->ws_cap) {
+        if (others + need > c->ws_cap)
+            return fail(c, SS_ENOMEM, "the workspace cap of " + std::to_string(c->ws_cap) + " bytes is too small: " +
+                                          std::to_string(others + need) + " bytes are needed");
+        if (others + want > c->ws_cap) want = need;
+    }
     if (b.p) {
         HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
         HIP_OR_FAIL(c, hipFree(b.p));
         b.p = nullptr;
+        c->ws_held -= b.cap;
         b.cap = 0;
     }
     hipError_t e = hipMalloc(&b.p, want);
@@ -149,6 +170,19 @@ ss_status ensure(ss_ctx* c, DevBuf& b, size_t bytes)
         return fail(c, SS_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
     }
     b.cap = want;
+    c->ws_held += want;
+    return SS_OK;
+}
+
+// Frees a workspace buffer (after the stream's work on it).
+ss_status release(ss_ctx* c, DevBuf& b)
+{
+    if (!b.p) return SS_OK;
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    HIP_OR_FAIL(c, hipFree(b.p));
+    c->ws_held -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
     return SS_OK;
 }
 
@@ -164,6 +198,20 @@ ss_status ensure_pinned(ss_ctx* c, void** p, size_t* cap, size_t bytes)
     size_t want = std::max<size_t>(bytes, 4096);
     HIP_OR_FAIL(c, hipHostMalloc(p, want, hipHostMallocDefault));
     *cap = want;
+    return SS_OK;
+}
+
+// The pinned staging buffers are rewritten by the next call: wait for the
+// last copy out of them first (stage_mark records it).
+ss_status stage_wait(ss_ctx* c)
+{
+    if (c->stage_ev) HIP_OR_FAIL(c, hipEventSynchronize(c->stage_ev));
+    return SS_OK;
+}
+
+ss_status stage_mark(ss_ctx* c)
+{
+    if (c->stage_ev) HIP_OR_FAIL(c, hipEventRecord(c->stage_ev, c->stream));
     return SS_OK;
 }
 
@@ -276,8 +324,8 @@ ss_status resolve_params(ss_ctx* c, const ss_params* in, Params* p)
         return fail(c, SS_EINVAL, "tile_min/tile_max must be powers of two with 8192 <= tile_min <= tile_max <= 65536");
     if (p->mode > 1) return fail(c, SS_EINVAL, "hash_mode must be SS_HASH_MIX64 or SS_HASH_IDENTITY");
     p->auto_tiles = false;
-    p->tmax0 = c->tile0 ? std::max(p->tmin, c->tile0) : p->tmax;
-    p->tmaxd = c->tile_deep ? std::max(p->tmin, c->tile_deep) : p->tmax;
+    p->tmax0 = c && c->tile0 ? std::max(p->tmin, c->tile0) : p->tmax;
+    p->tmaxd = c && c->tile_deep ? std::max(p->tmin, c->tile_deep) : p->tmax;
     return SS_OK;
 }
 
@@ -589,8 +637,7 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
             if ((s = ensure(c, c->segs[0], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
             if ((s = ensure(c, c->segs[1], (size_t)li.nsegs * sizeof(Seg))) != SS_OK) return s;
             HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, keep.p, (size_t)nsegs * sizeof(Seg), hipMemcpyDeviceToDevice, c->stream));
-            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
-            HIP_OR_FAIL(c, hipFree(keep.p));
+            if ((s = release(c, keep)) != SS_OK) return s;
             *seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
             again = true;
         }
@@ -620,6 +667,8 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     const uint64_t n = offs[ninst];
     const bool inplace = keys_out == keys;
     c->call_tmaxd = 0;
+    ss_status s;
+    if ((s = stage_wait(c)) != SS_OK) return s;
     // first level: classify instances on the host
     c->host_segs.clear();
     for (auto& v : c->host_jobs) v.clear();
@@ -643,7 +692,6 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
             jrec += 1;
         }
     }
-    ss_status s;
     uint32_t nsegs = (uint32_t)c->host_segs.size();
     uint32_t tiles = 0, chunks = 0, tile = p.tmin;
     uint64_t records = 0;
@@ -1269,9 +1317,13 @@ void launch_red_level_m(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t 
 // Packs the results flagged in rf (position order) from (T_k, T_v) into the
 // outputs and reads their number back (the buffers were sized by the caller:
 // rf padded to whole flag blocks, bcnt and mdev as in run_reduce).
+// m goes to d_m (device) when given, else to the context's own word; m_out
+// (host), when given, receives it after a wait.  With m_out NULL the call
+// does not wait.
 ss_status compact_results(ss_ctx* c, uint64_t n, const uint64_t* T_k, const uint64_t* T_v, const uint8_t* rf,
-                          uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out)
+                          uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out, uint64_t* d_m = nullptr)
 {
+    unsigned long long* mdst = d_m ? (unsigned long long*)d_m : (unsigned long long*)c->mdev.p;
     const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
     const uint64_t nchunk = nblk * (kFlagBlock / kFlagChunk);
     {
@@ -1279,26 +1331,36 @@ ss_status compact_results(ss_ctx* c, uint64_t n, const uint64_t* T_k, const uint
         uint32_t* ccnt = (uint32_t*)c->bcnt.p;  // per chunk, then per block
         uint32_t* btot = ccnt + nchunk;
         hipLaunchKernelGGL(k_flag_count, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, rf, ccnt, btot);
-        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, btot, (uint32_t)nblk,
-                           (unsigned long long*)c->mdev.p);
+        hipLaunchKernelGGL(k_flag_scan, dim3(1), dim3(1024), 0, c->stream, btot, (uint32_t)nblk, mdst);
         hipLaunchKernelGGL(k_flag_scatter, dim3((uint32_t)nblk), dim3(1024), 0, c->stream, rf, (const uint32_t*)ccnt,
                            (const uint32_t*)btot, n, T_k, T_v, out_keys, out_vals);
     }
     HIP_OR_FAIL(c, hipGetLastError());
+    if (!m_out) return SS_OK;
     HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
-    HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, c->mdev.p, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipMemcpyAsync(&c->info_host->records, mdst, 8, hipMemcpyDeviceToHost, c->stream));
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     if (c->info_host->status) return status_failure(c, c->info_host->status, "in collect-reduce");
     *m_out = c->info_host->records;
     return SS_OK;
 }
 
+// Collect-reduce (RED = 1, u64 values, the monoid `op`) or histogram (RED = 2,
+// no values) of `ninst` independent instances packed back to back
+// (instance i is [offs[i], offs[i+1]), host offsets).  Data moves between T
+// and the caller's output arrays; results are written to T at positions
+// flagged in rflag (positions of finished work are never touched again by
+// later levels, which only work inside the ranges of unfinished buckets),
+// then compacted into the outputs in position order, so every instance's
+// pairs are contiguous and in the order the instance gives alone.
 template <int RED>
-ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
-                     uint64_t* out_vals, uint64_t* m_out, const Params& p, uint32_t op = 0)
+ss_status run_reduce_multi(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, const uint64_t* offs,
+                           uint64_t ninst, uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out, const Params& p,
+                           uint32_t op, uint64_t* d_m)
 {
     c->call_tmaxd = 0;
     ss_status s;
+    const uint64_t n = offs[ninst];
     const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
     const uint64_t nchunk = nblk * (kFlagBlock / kFlagChunk);
     if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
@@ -1308,46 +1370,72 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
     if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
     if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
-    if ((s = ensure_jobs(c, 4096)) != SS_OK) return s;
-    uint32_t seg_cap = 1024;
+    // first level: instances of at least alpha records are subproblems, the
+    // others base-case jobs (sum jobs for single records)
+    std::vector<Seg> first;
+    for (auto& v : c->host_jobs) v.clear();
+    uint64_t jrec = 0;
+    for (uint64_t i = 0; i < ninst; ++i) {
+        const uint32_t st = (uint32_t)offs[i];
+        const uint32_t len = (uint32_t)(offs[i + 1] - offs[i]);
+        if (len >= p.alpha) {
+            Seg sg{};
+            sg.start = st;
+            sg.len = len;
+            sg.ibase = st;
+            sg.nl_bits = (uint8_t)std::min(p.nl0, choose_nl(len, p.alpha, kLightBitsMax, 0));
+            sg.shift = 0;
+            first.push_back(sg);
+        } else if (len >= 1) {
+            c->host_jobs[len == 1 ? kCopyClass : base_class(len)].push_back(Job{st, len});
+            jrec += len;
+        }
+    }
+    uint32_t nj0[kJobClasses], nj0_max = 0, nj0_tot = 0;
+    for (int k = 0; k < kJobClasses; ++k) {
+        nj0[k] = (uint32_t)c->host_jobs[k].size();
+        nj0_max = std::max(nj0_max, nj0[k]);
+        nj0_tot += nj0[k];
+    }
+    if ((s = ensure_jobs(c, std::max<uint32_t>(nj0_max, 4096))) != SS_OK) return s;
+    uint32_t seg_cap = std::max<uint32_t>((uint32_t)first.size(), 1024);
     if ((s = ensure(c, c->segs[0], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
     if ((s = ensure(c, c->segs[1], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
     seg_cap = (uint32_t)std::min(c->segs[0].cap, c->segs[1].cap) / sizeof(Seg);
+    uint32_t nsegs = (uint32_t)first.size();
+    uint32_t tiles = 0, chunks = 0, tile = p.tmin;
+    uint64_t records = 0;
+    for (const Seg& sg : first) records += sg.len;
+    if (nsegs && (s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     uint64_t* T_k = (uint64_t*)c->t_keys.p;
     uint64_t* T_v = (uint64_t*)c->t_vals.p;
     uint8_t* rf = (uint8_t*)c->rflag.p;
     HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
     if ((s = reset_counters(c)) != SS_OK) return s;
-
-    if (n < p.alpha) {
-        // one job: a sum job for a single record, else a base case
-        Job j{0u, (uint32_t)n};
-        uint32_t nj[kJobClasses] = {};
-        const int cls = n == 1 ? kCopyClass : base_class((uint32_t)n);
-        nj[cls] = 1;
-        if ((s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, sizeof(Job))) != SS_OK) return s;
-        *c->job_stage = j;
-        HIP_OR_FAIL(c, hipMemcpyAsync((Job*)c->jobs.p + (size_t)cls * c->job_cap, c->job_stage, sizeof(Job),
-                                      hipMemcpyHostToDevice, c->stream));
-        launch_red_jobs<RED>(c, p.mode, nj, c->job_cap, keys, vals, T_k, T_v, rf, n, op);
+    const size_t stage = (size_t)nj0_tot * sizeof(Job) + (size_t)nsegs * sizeof(Seg);
+    if ((s = stage_wait(c)) != SS_OK) return s;
+    if (stage && (s = ensure_pinned(c, (void**)&c->job_stage, &c->job_stage_cap, stage)) != SS_OK) return s;
+    if (nj0_tot) {
+        size_t o = 0;
+        for (int k = 0; k < kJobClasses; ++k) {
+            if (!nj0[k]) continue;
+            memcpy(c->job_stage + o, c->host_jobs[k].data(), nj0[k] * sizeof(Job));
+            HIP_OR_FAIL(c, hipMemcpyAsync((Job*)c->jobs.p + (size_t)k * c->job_cap, c->job_stage + o,
+                                          nj0[k] * sizeof(Job), hipMemcpyHostToDevice, c->stream));
+            o += nj0[k];
+        }
+        launch_red_jobs<RED>(c, p.mode, nj0, c->job_cap, keys, vals, T_k, T_v, rf, jrec, op);
         HIP_OR_FAIL(c, hipGetLastError());
-    } else {
-        if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
-        std::vector<Seg> first(1);
-        first[0] = Seg{};
-        first[0].start = 0;
-        first[0].len = (uint32_t)n;
-        first[0].ibase = 0;
-        first[0].nl_bits = (uint8_t)std::min(p.nl0, choose_nl((uint32_t)n, p.alpha, kLightBitsMax, 0));
-        first[0].shift = 0;
-        uint32_t tiles, chunks, tile;
+    }
+    if (nsegs) {
         host_prefix(first, p, &tiles, &chunks, &tile);
-        if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, sizeof(Seg))) != SS_OK) return s;
-        memcpy(c->seg_stage, first.data(), sizeof(Seg));
+        Seg* sst = (Seg*)(c->job_stage + nj0_tot);  // after the jobs in the same pinned staging
+        memcpy(sst, first.data(), nsegs * sizeof(Seg));
+        HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[0].p, sst, nsegs * sizeof(Seg), hipMemcpyHostToDevice, c->stream));
+    }
+    if ((s = stage_mark(c)) != SS_OK) return s;
+    if (nsegs) {
         int cur = 0;
-        HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
-        uint32_t nsegs = 1;
-        uint64_t records = n;
         const uint64_t* loc_k = keys;
         const uint64_t* loc_v = vals;
         for (uint32_t level = 0; nsegs; ++level) {
@@ -1381,7 +1469,15 @@ ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint
             cur ^= 1;
         }
     }
-    return compact_results(c, n, T_k, T_v, rf, out_keys, out_vals, m_out);
+    return compact_results(c, n, T_k, T_v, rf, out_keys, out_vals, m_out, d_m);
+}
+
+template <int RED>
+ss_status run_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, uint64_t* out_keys,
+                     uint64_t* out_vals, uint64_t* m_out, const Params& p, uint32_t op = 0, uint64_t* d_m = nullptr)
+{
+    const uint64_t offs[2] = {0, n};
+    return run_reduce_multi<RED>(c, keys, vals, offs, 1, out_keys, out_vals, m_out, p, op, d_m);
 }
 
 ss_status check_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, const uint64_t* ok,
@@ -1441,6 +1537,58 @@ ss_status order_results(ss_ctx* c, uint64_t* ok, uint64_t* ov, uint64_t m, const
     return SS_OK;
 }
 
+// Upper bound of the workspace that one call of `op` on n records can make a
+// new context hold: every buffer the host-sized engine grows, at its largest
+// size over all levels, with the headroom of ensure() (half again) on the
+// buffers that grow level by level.  A level has at most n / alpha + 1
+// subproblems (each holds at least alpha records), at most n / tile_min plus
+// one per subproblem subarrays, and emits at most one job per bucket plus
+// one per copy chunk.
+size_t workspace_bound(int op, uint64_t n, uint32_t vb, const Params& p)
+{
+    if (n == 0) return 0;
+    const bool reduce = op == SS_OP_HISTOGRAM || op == SS_OP_COLLECT_REDUCE;
+    size_t b = 0;
+    auto add = [&](uint64_t x) { b += (x + 255) & ~(uint64_t)255; };
+    auto grow = [&](uint64_t x) { add(x + x / 2); };
+    add(sizeof(LevelInfo));  // status word, held from ss_create
+    add(512);                // sink
+    add(n * 8);              // T: keys
+    add(n * (reduce ? 8 : vb));  // T: values
+    add(n * 2);              // bucket ids
+    const uint64_t S = n / p.alpha + 1;
+    const uint64_t tiles = n / p.tmin + S;
+    const uint64_t chunks = tiles / kChunk + S;
+    grow(tiles * kNbStride * 4);              // counting matrix
+    grow(chunks * kNbStride * 4);             // chunk sums
+    grow(S * kNbStride * 4);                  // bucket totals
+    grow(S * (kNbStride + 1) * 4);            // bucket starts
+    grow(S * kHeavyMax * 8);                  // heavy hashes
+    grow(S * 2 * kHeavySlotsMax * 8);         // heavy tables: hashes
+    grow(S * 2 * kHeavySlotsMax * 2);         // heavy tables: ids
+    grow(S * kNbStride);                      // final-bucket flags
+    grow(S * kNbStride * 8);                  // keys of one-key buckets
+    grow(S * 4);                              // most sampled heavy buckets
+    const uint64_t segs = std::max<uint64_t>(S, 1024) * sizeof(Seg);
+    grow(segs);
+    grow(segs);
+    add(S * sizeof(Seg));                     // the list kept while both lists grow
+    const uint64_t jobs = std::max<uint64_t>(4096, S * kNbStride + n / kCopyChunk + 1);
+    grow(jobs * kJobClasses * sizeof(Job));
+    if (reduce) {
+        const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
+        add(nblk * kFlagBlock);                           // result flags
+        add((nblk * (kFlagBlock / kFlagChunk) + nblk) * 4);  // flag counts
+        add(8);                                           // m
+        grow(S * kHeavyMax * 8);                          // heavy sums
+    } else {
+        const uint64_t f = std::max<uint64_t>(4096, S * kHeavyMax + n / kFillChunk + 1) * sizeof(FillJob);
+        grow(f);  // key-fill lists of two levels
+        grow(f);
+    }
+    return b;
+}
+
 }  // namespace
 
 // ==================================================================== C-ABI
@@ -1461,7 +1609,7 @@ ss_status ss_default_params(ss_params* p)
     return SS_OK;
 }
 
-ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
+ss_status ss_create(int device, void* hip_stream, size_t workspace_cap, ss_ctx** out)
 {
     if (!out) return SS_EINVAL;
     *out = nullptr;
@@ -1472,6 +1620,7 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
     if (!c) return SS_ENOMEM;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    c->ws_cap = workspace_cap;
     if (hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->ncu < 1)
         c->ncu = 1;
     if (hipHostMalloc((void**)&c->info_host, sizeof(LevelInfo), hipHostMallocDefault) != hipSuccess) {
@@ -1480,7 +1629,8 @@ ss_status ss_create(int device, void* hip_stream, ss_ctx** out)
     }
     if (ensure(c, c->info, sizeof(LevelInfo)) != SS_OK ||
         hipMemsetAsync(c->info.p, 0, sizeof(LevelInfo), c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess || ensure_aux(c) != SS_OK) {
+        hipStreamSynchronize(c->stream) != hipSuccess || ensure_aux(c) != SS_OK ||
+        hipEventCreateWithFlags(&c->stage_ev, hipEventDisableTiming) != hipSuccess) {
         (void)ss_destroy(c);
         return SS_EHIP;
     }
@@ -1503,7 +1653,8 @@ ss_status ss_destroy(ss_ctx* c)
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
-                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos};
+                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos,
+                      &c->pk_k, &c->pk_v, &c->po_k, &c->po_v, &c->pack_tab, &c->pack_rank};
     if (c->aux) (void)hipStreamSynchronize(c->aux);
     for (DevBuf* b : bufs)
         if (b->p) (void)hipFree(b->p);
@@ -1520,6 +1671,8 @@ ss_status ss_destroy(ss_ctx* c)
     if (c->info_host) (void)hipHostFree(c->info_host);
     if (c->seg_stage) (void)hipHostFree(c->seg_stage);
     if (c->job_stage) (void)hipHostFree(c->job_stage);
+    if (c->pack_stage) (void)hipHostFree(c->pack_stage);
+    if (c->stage_ev) (void)hipEventDestroy(c->stage_ev);
     delete c;
     return SS_OK;
 }
@@ -1604,17 +1757,24 @@ ss_status ss_profile_read(ss_ctx* c, int kind, double* total_ms, uint64_t* launc
     return SS_OK;
 }
 
-ss_status ss_workspace_bytes(ss_ctx* c, size_t* bytes)
+ss_status ss_workspace_held(ss_ctx* c, size_t* bytes)
 {
     if (!c || !bytes) return SS_EINVAL;
-    const DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
-                            &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                            &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
-                      &c->ds_jobs, &c->ds_info, &c->ds_q,
-                      &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos};
-    size_t t = 0;
-    for (const DevBuf* b : bufs) t += b->cap;
-    *bytes = t;
+    *bytes = c->ws_held;
+    return SS_OK;
+}
+
+ss_status ss_workspace_bytes(int op, uint64_t n, uint32_t vb, const ss_params* params, size_t* bytes)
+{
+    if (!bytes) return SS_EINVAL;
+    *bytes = 0;
+    if (op < SS_OP_SEMISORT_EQUAL || op > SS_OP_COLLECT_REDUCE) return SS_EINVAL;
+    const bool semisort = op == SS_OP_SEMISORT_EQUAL || op == SS_OP_SEMISORT_LESS;
+    if (semisort && vb != 4 && vb != 8) return SS_EINVAL;
+    if (n >= (1ull << 31)) return SS_EINVAL;
+    Params p;
+    if (resolve_params(nullptr, params, &p) != SS_OK) return SS_EINVAL;
+    *bytes = workspace_bound(op, n, semisort ? vb : 8, p);
     return SS_OK;
 }
 
@@ -1945,18 +2105,16 @@ ss_status ss_transpose_csr(ss_ctx* c, uint64_t nv, uint64_t ne, const uint64_t* 
     return ss_sync(c);
 }
 
-ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
-                                   int ordered, uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out,
-                                   const ss_params* params)
+// collect-reduce with a monoid after the argument checks (n >= 1): m goes to
+// *m_out (host, after a wait) when m_out is given, and to d_m (device) when
+// d_m is given; with m_out NULL and ordered = 0 nothing waits for the result.
+static ss_status reduce_call(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op, int ordered,
+                      uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out, uint64_t* d_m, const ss_params* params,
+                      const Params& p)
 {
-    Params p;
-    ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, m_out, params, &p);
-    if (s != SS_OK) return s;
-    if (op < SS_MONOID_SUM || op > SS_MONOID_AFFINE) return fail(c, SS_EINVAL, "unknown monoid");
-    *m_out = 0;
-    if (n == 0) return SS_OK;
-    if (!vals) return fail(c, SS_EINVAL, "null vals");
-    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    ss_status s;
+    uint64_t m_host = 0;
+    if (ordered && !m_out) m_out = &m_host;  // ordering the pairs needs m on the host
     if (op == SS_MONOID_AFFINE) {
         // in input order: a stable semisort_= makes every key's records
         // contiguous and ordered, then a segmented scan folds each group
@@ -1994,7 +2152,7 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
                            (const uint64_t*)totv, (uint64_t*)c->t_keys.p, (uint64_t*)c->t_vals.p, rf);
         HIP_OR_FAIL(c, hipGetLastError());
         if ((s = compact_results(c, n, (const uint64_t*)c->t_keys.p, (const uint64_t*)c->t_vals.p, rf, out_keys,
-                                 out_vals, m_out)) != SS_OK)
+                                 out_vals, m_out, d_m)) != SS_OK)
             return s;
         return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
     }
@@ -2006,18 +2164,265 @@ ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64
         hipLaunchKernelGGL(k_iota, dim3(g), dim3(256), 0, c->stream, (uint64_t*)c->pos.p, n);
         HIP_OR_FAIL(c, hipGetLastError());
         const uint32_t pop = op == SS_MONOID_FIRST ? SS_MONOID_MIN : SS_MONOID_MAX;
-        if ((s = run_reduce<1>(c, keys, (const uint64_t*)c->pos.p, n, out_keys, out_vals, m_out, p, pop)) != SS_OK)
+        if ((s = run_reduce<1>(c, keys, (const uint64_t*)c->pos.p, n, out_keys, out_vals, m_out, p, pop, d_m)) !=
+            SS_OK)
             return s;
-        if (*m_out) {
-            hipLaunchKernelGGL(k_gather_at, dim3((uint32_t)std::min<uint64_t>((*m_out + 255) / 256, 65536)), dim3(256),
-                               0, c->stream, out_vals, *m_out, vals, n, (LevelInfo*)c->info.p);
-            HIP_OR_FAIL(c, hipGetLastError());
+        if (m_out) {
+            if (*m_out) {
+                hipLaunchKernelGGL(k_gather_at, dim3((uint32_t)std::min<uint64_t>((*m_out + 255) / 256, 65536)),
+                                   dim3(256), 0, c->stream, out_vals, *m_out, vals, n, (LevelInfo*)c->info.p);
+                HIP_OR_FAIL(c, hipGetLastError());
+            }
+            if (ordered) return order_results(c, out_keys, out_vals, *m_out, params);
+            return ss_sync(c);
         }
-        if (ordered) return order_results(c, out_keys, out_vals, *m_out, params);
-        return ss_sync(c);
+        // m stays on the device: the gather reads it there
+        hipLaunchKernelGGL(k_gather_at_dev, dim3((uint32_t)std::min<uint64_t>((n + 255) / 256, 65536)), dim3(256), 0,
+                           c->stream, out_vals, (const uint64_t*)d_m, vals, n, (LevelInfo*)c->info.p);
+        HIP_OR_FAIL(c, hipGetLastError());
+        return SS_OK;
     }
-    if ((s = run_reduce<1>(c, keys, vals, n, out_keys, out_vals, m_out, p, (uint32_t)op)) != SS_OK) return s;
+    if ((s = run_reduce<1>(c, keys, vals, n, out_keys, out_vals, m_out, p, (uint32_t)op, d_m)) != SS_OK) return s;
     return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
+}
+
+ss_status ss_collect_reduce_monoid(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                   int ordered, uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out,
+                                   const ss_params* params)
+{
+    Params p;
+    ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, m_out, params, &p);
+    if (s != SS_OK) return s;
+    if (op < SS_MONOID_SUM || op > SS_MONOID_AFFINE) return fail(c, SS_EINVAL, "unknown monoid");
+    *m_out = 0;
+    if (n == 0) return SS_OK;
+    if (!vals) return fail(c, SS_EINVAL, "null vals");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    return reduce_call(c, keys, vals, n, op, ordered, out_keys, out_vals, m_out, nullptr, params, p);
+}
+
+ss_status ss_collect_reduce_async(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
+                                  int ordered, uint64_t* out_keys, uint64_t* out_vals, uint64_t* d_m,
+                                  const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (!d_m) return fail(c, SS_EINVAL, "null d_m");
+    Params p;
+    uint64_t unused = 0;
+    ss_status s = check_reduce(c, keys, vals, n, out_keys, out_vals, &unused, params, &p);
+    if (s != SS_OK) return s;
+    if (op < SS_MONOID_SUM || op > SS_MONOID_AFFINE) return fail(c, SS_EINVAL, "unknown monoid");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (n == 0) {
+        HIP_OR_FAIL(c, hipMemsetAsync(d_m, 0, 8, c->stream));
+        return SS_OK;
+    }
+    if (!vals) return fail(c, SS_EINVAL, "null vals");
+    return reduce_call(c, keys, vals, n, op, ordered, out_keys, out_vals, nullptr, d_m, params, p);
+}
+
+ss_status ss_histogram_async(ss_ctx* c, const uint64_t* keys, uint64_t n, int ordered, uint64_t* out_keys,
+                             uint64_t* out_counts, uint64_t* d_m, const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (!d_m) return fail(c, SS_EINVAL, "null d_m");
+    Params p;
+    uint64_t unused = 0;
+    ss_status s = check_reduce(c, keys, nullptr, n, out_keys, out_counts, &unused, params, &p);
+    if (s != SS_OK) return s;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    if (n == 0) {
+        HIP_OR_FAIL(c, hipMemsetAsync(d_m, 0, 8, c->stream));
+        return SS_OK;
+    }
+    uint64_t m_host = 0;
+    if ((s = run_reduce<2>(c, keys, nullptr, n, out_keys, out_counts, ordered ? &m_host : nullptr, p, 0, d_m)) !=
+        SS_OK)
+        return s;
+    return ordered ? order_results(c, out_keys, out_counts, m_host, params) : SS_OK;
+}
+
+ss_status ss_batch(ss_ctx* c, const ss_job* jobs, uint64_t njobs, const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (njobs == 0) return SS_OK;
+    if (!jobs) return fail(c, SS_EINVAL, "null jobs");
+    if (njobs >= (1ull << 31)) return fail(c, SS_EINVAL, "too many jobs");
+    // every job on its own, then no output may overlap any other array
+    struct Span {
+        uintptr_t a, b;
+        bool out;
+    };
+    std::vector<Span> spans;
+    spans.reserve(njobs * 5);
+    for (uint64_t i = 0; i < njobs; ++i) {
+        const ss_job& J = jobs[i];
+        const std::string at = "job " + std::to_string(i) + ": ";
+        if (J.op < SS_OP_SEMISORT_EQUAL || J.op > SS_OP_COLLECT_REDUCE) return fail(c, SS_EINVAL, at + "unknown op");
+        const bool red = J.op == SS_OP_HISTOGRAM || J.op == SS_OP_COLLECT_REDUCE;
+        if (!red && J.val_bytes != 4 && J.val_bytes != 8) return fail(c, SS_EINVAL, at + "val_bytes must be 4 or 8");
+        if (J.n >= (1ull << 31)) return fail(c, SS_EINVAL, at + "n must be below 2^31");
+        if (red && !J.d_m) return fail(c, SS_EINVAL, at + "null d_m");
+        if (red) spans.push_back({(uintptr_t)J.d_m, (uintptr_t)J.d_m + 8, true});
+        if (J.n == 0) continue;
+        if (!J.keys || !J.out_a || !J.out_b || (J.op != SS_OP_HISTOGRAM && !J.vals))
+            return fail(c, SS_EINVAL, at + "null array pointer");
+        const uint64_t vb = red ? 8 : J.val_bytes;
+        spans.push_back({(uintptr_t)J.keys, (uintptr_t)J.keys + J.n * 8, false});
+        if (J.op != SS_OP_HISTOGRAM) spans.push_back({(uintptr_t)J.vals, (uintptr_t)J.vals + J.n * vb, false});
+        spans.push_back({(uintptr_t)J.out_a, (uintptr_t)J.out_a + J.n * 8, true});
+        spans.push_back({(uintptr_t)J.out_b, (uintptr_t)J.out_b + J.n * vb, true});
+    }
+    std::sort(spans.begin(), spans.end(), [](const Span& x, const Span& y) { return x.a < y.a; });
+    uintptr_t max_end = 0, max_out_end = 0;
+    for (const Span& x : spans) {
+        if ((x.out && max_end > x.a) || (!x.out && max_out_end > x.a))
+            return fail(c, SS_EINVAL, "an output of the batch overlaps another array of the batch");
+        max_end = std::max(max_end, x.b);
+        if (x.out) max_out_end = std::max(max_out_end, x.b);
+    }
+    Params p;
+    ss_status s = resolve_params(c, params, &p);
+    if (s != SS_OK) return s;
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+
+    // groups: semisort_= and semisort_< by value width, histogram, collect-reduce
+    constexpr int kGroups = 6;
+    auto group_of = [](const ss_job& J) {
+        switch (J.op) {
+        case SS_OP_SEMISORT_EQUAL: return J.val_bytes == 8 ? 1 : 0;
+        case SS_OP_SEMISORT_LESS: return J.val_bytes == 8 ? 3 : 2;
+        case SS_OP_HISTOGRAM: return 4;
+        default: return 5;
+        }
+    };
+    std::vector<uint32_t> packed[kGroups], direct;
+    for (uint64_t i = 0; i < njobs; ++i) {
+        const ss_job& J = jobs[i];
+        if (J.n == 0) {
+            if (J.op == SS_OP_HISTOGRAM || J.op == SS_OP_COLLECT_REDUCE)
+                HIP_OR_FAIL(c, hipMemsetAsync(J.d_m, 0, 8, c->stream));
+            continue;
+        }
+        if (J.n <= SS_BATCH_PACK_MAX) packed[group_of(J)].push_back((uint32_t)i);
+        else direct.push_back((uint32_t)i);
+    }
+    // large jobs one by one on their own arrays, as the single calls run them
+    for (uint32_t i : direct) {
+        const ss_job& J = jobs[i];
+        const uint64_t offs[2] = {0, J.n};
+        Params q = p;
+        switch (J.op) {
+        case SS_OP_SEMISORT_EQUAL:
+        case SS_OP_SEMISORT_LESS:
+            if (J.op == SS_OP_SEMISORT_LESS) {
+                q.mode = 2;
+                default_tiles(c, params, &q, 32768u, 65536u);
+            } else {
+                default_tiles(c, params, &q, 32768u, 16384u);
+            }
+            s = J.val_bytes == 8
+                    ? run_semisort<uint64_t>(c, J.keys, J.vals, offs, 1, (uint64_t*)J.out_a, J.out_b, q)
+                    : run_semisort<uint32_t>(c, J.keys, J.vals, offs, 1, (uint64_t*)J.out_a, J.out_b, q);
+            break;
+        case SS_OP_HISTOGRAM:
+            s = run_reduce<2>(c, J.keys, nullptr, J.n, (uint64_t*)J.out_a, (uint64_t*)J.out_b, nullptr, p, 0, J.d_m);
+            break;
+        default:
+            s = run_reduce<1>(c, J.keys, (const uint64_t*)J.vals, J.n, (uint64_t*)J.out_a, (uint64_t*)J.out_b,
+                              nullptr, p, 0, J.d_m);
+            break;
+        }
+        if (s != SS_OK) return s;
+    }
+    // the packed job tables of every group, staged and copied at once
+    uint64_t ntab = 0;
+    for (int g = 0; g < kGroups; ++g) ntab += packed[g].size();
+    if (!ntab) return SS_OK;
+    if ((s = stage_wait(c)) != SS_OK) return s;
+    if ((s = ensure_pinned(c, (void**)&c->pack_stage, &c->pack_stage_cap, ntab * sizeof(PackJob))) != SS_OK) return s;
+    if ((s = ensure(c, c->pack_tab, ntab * sizeof(PackJob))) != SS_OK) return s;
+    uint64_t tab0[kGroups], total[kGroups];
+    std::vector<uint64_t> offs[kGroups];
+    {
+        uint64_t t = 0;
+        for (int g = 0; g < kGroups; ++g) {
+            tab0[g] = t;
+            offs[g].assign(1, 0);
+            for (uint32_t i : packed[g]) {
+                const ss_job& J = jobs[i];
+                PackJob& e = c->pack_stage[t++];
+                e.keys = J.keys;
+                e.vals = J.vals;
+                e.out_a = J.out_a;
+                e.out_b = J.out_b;
+                e.d_m = J.d_m;
+                e.off = offs[g].back();
+                e.n = J.n;
+                offs[g].push_back(e.off + J.n);
+            }
+            total[g] = offs[g].back();
+        }
+    }
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->pack_tab.p, c->pack_stage, ntab * sizeof(PackJob), hipMemcpyHostToDevice,
+                                  c->stream));
+    if ((s = stage_mark(c)) != SS_OK) return s;
+    const PackJob* dtab = (const PackJob*)c->pack_tab.p;
+    for (int g = 0; g < kGroups; ++g) {
+        const uint32_t nj = (uint32_t)packed[g].size();
+        if (!nj) continue;
+        const uint64_t tot = total[g];
+        const bool red = g >= 4;
+        const uint32_t vb = red || (g & 1) ? 8 : 4;
+        if ((s = ensure(c, c->pk_k, tot * 8)) != SS_OK) return s;
+        if (g != 4 && (s = ensure(c, c->pk_v, tot * vb)) != SS_OK) return s;
+        if ((s = ensure(c, c->po_k, tot * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->po_v, tot * vb)) != SS_OK) return s;
+        const PackJob* tab = dtab + tab0[g];
+        const uint32_t grid = (uint32_t)((tot + kPackChunk - 1) / kPackChunk);
+        uint64_t* pk = (uint64_t*)c->pk_k.p;
+        uint64_t* ok = (uint64_t*)c->po_k.p;
+        if (vb == 8)
+            hipLaunchKernelGGL((k_pack_gather<uint64_t>), dim3(grid), dim3(256), 0, c->stream, tab, nj, tot, pk,
+                               g == 4 ? nullptr : (uint64_t*)c->pk_v.p);
+        else
+            hipLaunchKernelGGL((k_pack_gather<uint32_t>), dim3(grid), dim3(256), 0, c->stream, tab, nj, tot, pk,
+                               (uint32_t*)c->pk_v.p);
+        HIP_OR_FAIL(c, hipGetLastError());
+        if (!red) {
+            Params q = p;
+            if (g >= 2) q.mode = 2;
+            s = vb == 8 ? run_semisort<uint64_t>(c, pk, c->pk_v.p, offs[g].data(), nj, ok, c->po_v.p, q)
+                        : run_semisort<uint32_t>(c, pk, c->pk_v.p, offs[g].data(), nj, ok, c->po_v.p, q);
+            if (s != SS_OK) return s;
+            if (vb == 8)
+                hipLaunchKernelGGL((k_pack_scatter<uint64_t>), dim3(grid), dim3(256), 0, c->stream, tab, nj, tot, ok,
+                                   (const uint64_t*)c->po_v.p);
+            else
+                hipLaunchKernelGGL((k_pack_scatter<uint32_t>), dim3(grid), dim3(256), 0, c->stream, tab, nj, tot, ok,
+                                   (const uint32_t*)c->po_v.p);
+        } else {
+            s = g == 4 ? run_reduce_multi<2>(c, pk, nullptr, offs[g].data(), nj, ok, (uint64_t*)c->po_v.p, nullptr, p,
+                                             0, nullptr)
+                       : run_reduce_multi<1>(c, pk, (const uint64_t*)c->pk_v.p, offs[g].data(), nj, ok,
+                                             (uint64_t*)c->po_v.p, nullptr, p, 0, nullptr);
+            if (s != SS_OK) return s;
+            // every job's pairs are a contiguous run of the packed pairs
+            if ((s = ensure(c, c->pack_rank, (size_t)(nj + 1) * 8)) != SS_OK) return s;
+            const uint64_t nblk = (tot + kFlagBlock - 1) / kFlagBlock;
+            const uint32_t* ccnt = (const uint32_t*)c->bcnt.p;
+            const uint32_t* boff = ccnt + nblk * (kFlagBlock / kFlagChunk);
+            uint64_t* rank = (uint64_t*)c->pack_rank.p;
+            hipLaunchKernelGGL(k_inst_ranks, dim3(nj + 1), dim3(256), 0, c->stream, (const uint8_t*)c->rflag.p, ccnt,
+                               boff, tab, nj, (const unsigned long long*)c->mdev.p, rank);
+            hipLaunchKernelGGL(k_inst_m, dim3((nj + 255) / 256), dim3(256), 0, c->stream, tab, nj,
+                               (const uint64_t*)rank);
+            hipLaunchKernelGGL(k_pack_scatter_red, dim3(grid), dim3(256), 0, c->stream, tab, nj,
+                               (const uint64_t*)rank, (const uint64_t*)ok, (const uint64_t*)c->po_v.p);
+        }
+        HIP_OR_FAIL(c, hipGetLastError());
+    }
+    return SS_OK;
 }
 
 ss_status ss_collect_reduce_ordered(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, uint64_t n,

@@ -3,12 +3,16 @@
 // Group-by requests (semisort_=, semisort_<, histogram, collect-reduce) are
 // queued on submission and served by `lanes` worker threads, each driving its
 // own context on its own HIP stream, so requests on different lanes run on
-// the device at the same time.  A free lane takes the oldest request whose
-// workspace fits in the HBM budget; small semisort_= requests waiting behind
-// it with the same value width are packed into the lane's buffers and run as
-// one batched call (continuous batching): every instance of a batch gives the
-// result it gives alone.  Completion is observed on the host after the lane's
-// stream drains; latency runs from arrival to that moment.
+// the device at the same time.  A free lane takes the oldest request that
+// fits in the HBM budget, and the small requests of any operation waiting
+// behind it join the same call (continuous batching): the lane runs them as
+// one ss_batch, which packs them into one launch chain per operation and
+// level, and every request gets the result it gets alone.  The budget counts
+// the arrays of the requests being served (inputs and outputs) and every
+// lane's workspace: what it holds plus an upper bound of what the call may
+// add (the planning bound of ss_workspace_bytes), so the total stays within
+// the budget.  Completion is observed on the host after the lane's stream
+// drains; latency runs from arrival to that moment.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,6 +32,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Requests one lane call takes at most (the device array of group counts).
+constexpr uint32_t kMaxBatchJobs = 4096;
+
 struct Ticket {
     ss_request req;
     double arrival = 0.0;
@@ -41,12 +48,9 @@ struct Lane {
     int index = 0;
     hipStream_t stream = nullptr;
     ss_ctx* ctx = nullptr;
-    // packing buffers: keys and values in, keys and values out
-    void* pk_in = nullptr;
-    void* pv_in = nullptr;
-    void* pk_out = nullptr;
-    void* pv_out = nullptr;
-    uint64_t reserved = 0;  // bytes this lane may hold (workspace estimate, packing buffers)
+    uint64_t* d_m = nullptr;  // device: m of every reduction of the lane's call
+    uint64_t* h_m = nullptr;  // pinned copy
+    uint64_t ws = 0;          // bytes charged for the lane's workspace
     std::thread th;
 };
 
@@ -62,101 +66,110 @@ struct ss_server {
     std::deque<uint64_t> queue;       // ticket ids in arrival order
     std::deque<Ticket> tickets;       // stable addresses; index = ticket id
     std::vector<Lane> lanes;
-    uint64_t reserved = 0;            // sum over lanes
+    uint64_t ws_charged = 0;          // sum of the lanes' workspace charges
+    uint64_t io_charged = 0;          // inputs and outputs of the requests being served
     uint64_t peak_reserved = 0;
     uint64_t in_flight = 0;
     uint64_t completed = 0, batches = 0, packed = 0;
     bool stop = false;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    uint64_t reserved() const { return ws_charged + io_charged; }
 };
 
 namespace {
 
-bool is_semisort(int op) { return op == SS_OP_SEMISORT_EQUAL || op == SS_OP_SEMISORT_LESS; }
+bool is_reduce(int op) { return op == SS_OP_HISTOGRAM || op == SS_OP_COLLECT_REDUCE; }
 
-// Device workspace a context needs for a request of n records (the
-// temporary array, bucket ids and, for collect-reduce, the result flags),
-// plus a fixed allowance for tables and work lists.
-uint64_t workspace_estimate(const ss_request& r)
+uint64_t value_bytes(const ss_request& r) { return is_reduce(r.op) ? 8 : r.val_bytes; }
+
+// Device memory of a request's own arrays: keys and values in, both outputs.
+uint64_t io_bytes(const ss_request& r)
 {
-    const uint64_t vb = r.op == SS_OP_HISTOGRAM || r.op == SS_OP_COLLECT_REDUCE ? 8 : r.val_bytes;
-    uint64_t b = r.n * (8 + vb) + 2 * r.n;
-    if (!is_semisort(r.op)) b += r.n + 4 * (r.n / 65536 + 1);
-    return b + (64ull << 20);
+    const uint64_t vb = value_bytes(r);
+    return r.n * (8 + (r.op == SS_OP_HISTOGRAM ? 0 : vb) + 8 + vb);
 }
 
-ss_status run_one(const ss_params* prm, Lane& L, Ticket& t)
+// Upper bound of the workspace one ss_batch call over `group` adds to a
+// context: the planning bound of every operation group's packed total (the
+// groups share the buffers, so the sum bounds their largest), packing
+// buffers of 2 x (8 + value bytes) per packed record twice, and the job table.
+uint64_t batch_bound(const std::vector<Ticket*>& group, const ss_params* prm)
 {
-    const ss_request& r = t.req;
-    ss_status s;
-    switch (r.op) {
-    case SS_OP_SEMISORT_EQUAL:
-        s = ss_semisort_equal(L.ctx, r.keys, r.vals, r.val_bytes, r.n, (uint64_t*)r.out_a, r.out_b, prm);
-        break;
-    case SS_OP_SEMISORT_LESS:
-        s = ss_semisort_less(L.ctx, r.keys, r.vals, r.val_bytes, r.n, (uint64_t*)r.out_a, r.out_b, prm);
-        break;
-    case SS_OP_HISTOGRAM:
-        s = ss_histogram(L.ctx, r.keys, r.n, (uint64_t*)r.out_a, (uint64_t*)r.out_b, &t.m, prm);
-        break;
-    default:
-        s = ss_collect_reduce(L.ctx, r.keys, (const uint64_t*)r.vals, r.n, (uint64_t*)r.out_a,
-                              (uint64_t*)r.out_b, &t.m, prm);
-        break;
+    uint64_t tot[6] = {}, big = 0, njobs = group.size();
+    for (const Ticket* t : group) {
+        const ss_request& r = t->req;
+        int g = r.op == SS_OP_HISTOGRAM ? 4 : r.op == SS_OP_COLLECT_REDUCE ? 5 : 2 * r.op + (r.val_bytes == 8);
+        if (r.n > SS_BATCH_PACK_MAX) {
+            size_t b = 0;
+            if (ss_workspace_bytes(r.op, r.n, (uint32_t)value_bytes(r), prm, &b) == SS_OK) big += b;
+        } else {
+            tot[g] += r.n;
+        }
     }
-    if (s != SS_OK) return s;
-    return ss_sync(L.ctx);
+    uint64_t b = big + njobs * 64 + (64ull << 10);
+    for (int g = 0; g < 6; ++g) {
+        if (!tot[g]) continue;
+        const int op = g == 4 ? SS_OP_HISTOGRAM : g == 5 ? SS_OP_COLLECT_REDUCE : g / 2;
+        const uint32_t vb = g >= 4 || (g & 1) ? 8 : 4;
+        size_t w = 0;
+        if (ss_workspace_bytes(op, tot[g], vb, prm, &w) == SS_OK) b += w;
+        b += 2 * tot[g] * (8 + vb) + 512;
+    }
+    return b;
 }
 
-// Packed semisort_= of several requests: copy in, one batched call, copy out.
-ss_status run_packed(ss_server* S, Lane& L, const std::vector<Ticket*>& group)
+// One call for the whole group: small requests are packed by ss_batch, the
+// counts of the reductions come back through the lane's device array.
+ss_status run_group(ss_server* S, Lane& L, const std::vector<Ticket*>& group)
 {
-    const uint32_t vb = group[0]->req.val_bytes;
-    std::vector<uint64_t> offs(group.size() + 1, 0);
-    for (size_t i = 0; i < group.size(); ++i) offs[i + 1] = offs[i] + group[i]->req.n;
+    std::vector<ss_job> jobs(group.size());
     for (size_t i = 0; i < group.size(); ++i) {
         const ss_request& r = group[i]->req;
-        if (hipMemcpyAsync((uint64_t*)L.pk_in + offs[i], r.keys, r.n * 8, hipMemcpyDeviceToDevice, L.stream) !=
-                hipSuccess ||
-            hipMemcpyAsync((char*)L.pv_in + offs[i] * vb, r.vals, r.n * vb, hipMemcpyDeviceToDevice, L.stream) !=
-                hipSuccess)
-            return SS_EHIP;
+        ss_job& j = jobs[i];
+        j.op = r.op;
+        j.val_bytes = r.val_bytes;
+        j.n = r.n;
+        j.keys = r.keys;
+        j.vals = r.vals;
+        j.out_a = r.out_a;
+        j.out_b = r.out_b;
+        j.d_m = is_reduce(r.op) ? L.d_m + i : nullptr;
     }
-    ss_status s = ss_semisort_equal_batch(L.ctx, (const uint64_t*)L.pk_in, L.pv_in, vb, offs.data(), group.size(),
-                                          (uint64_t*)L.pk_out, L.pv_out, &S->cfg.params);
+    ss_status s = ss_batch(L.ctx, jobs.data(), jobs.size(), &S->cfg.params);
     if (s != SS_OK) return s;
-    for (size_t i = 0; i < group.size(); ++i) {
-        const ss_request& r = group[i]->req;
-        if (hipMemcpyAsync(r.out_a, (uint64_t*)L.pk_out + offs[i], r.n * 8, hipMemcpyDeviceToDevice, L.stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(r.out_b, (char*)L.pv_out + offs[i] * vb, r.n * vb, hipMemcpyDeviceToDevice, L.stream) !=
-                hipSuccess)
-            return SS_EHIP;
-    }
-    return ss_sync(L.ctx);
+    if (hipMemcpyAsync(L.h_m, L.d_m, group.size() * 8, hipMemcpyDeviceToHost, L.stream) != hipSuccess)
+        return SS_EHIP;
+    if ((s = ss_sync(L.ctx)) != SS_OK) return s;
+    for (size_t i = 0; i < group.size(); ++i)
+        if (is_reduce(group[i]->req.op)) group[i]->m = L.h_m[i];
+    return SS_OK;
 }
 
 void worker(ss_server* S, int li)
 {
     Lane& L = S->lanes[li];
     (void)hipSetDevice(S->device);
-    const uint64_t pack_cap = S->cfg.batch_records;
+    const uint64_t budget = S->cfg.hbm_budget;
     for (;;) {
         std::vector<Ticket*> group;
+        uint64_t group_io = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
                 if (S->stop) return;
-                // the oldest request that fits in the budget with this lane's share
+                // The oldest request whose arrays and workspace fit in the
+                // budget beside everything else being served.  The lane is
+                // charged its current workspace plus the bound of what the
+                // call may add, so the total never passes the budget.
                 size_t pick = S->queue.size();
-                uint64_t need = 0;
+                uint64_t charge = 0;
                 for (size_t qi = 0; qi < S->queue.size(); ++qi) {
                     Ticket& t = S->tickets[S->queue[qi]];
-                    const uint64_t est = std::max<uint64_t>(L.reserved, workspace_estimate(t.req));
-                    if (S->reserved - L.reserved + est <= S->cfg.hbm_budget) {
+                    const uint64_t need = L.ws + batch_bound({&t}, &S->cfg.params);
+                    if (S->reserved() - L.ws + need + io_bytes(t.req) <= budget) {
                         pick = qi;
-                        need = est;
+                        charge = need;
                         break;
                     }
                 }
@@ -164,46 +177,44 @@ void worker(ss_server* S, int li)
                     Ticket* head = &S->tickets[S->queue[pick]];
                     S->queue.erase(S->queue.begin() + (long)pick);
                     group.push_back(head);
-                    S->reserved += need - L.reserved;
-                    L.reserved = need;
-                    S->peak_reserved = std::max(S->peak_reserved, S->reserved);
-                    // continuous batching: small semisort_= requests of the same
-                    // value width that are already waiting join this call
-                    const ss_request& h = head->req;
-                    if (h.op == SS_OP_SEMISORT_EQUAL && h.n <= S->cfg.pack_max_records && L.pk_in) {
-                        // (each joins only if the workspace for the whole batch fits)
-                        ss_request all = h;
-                        for (size_t qi = 0; qi < S->queue.size();) {
+                    group_io = io_bytes(head->req);
+                    // continuous batching: small requests already waiting join
+                    // this call while the batch and the budget allow
+                    uint64_t recs = head->req.n;
+                    if (head->req.n <= S->cfg.pack_max_records) {
+                        for (size_t qi = 0; qi < S->queue.size() && group.size() < kMaxBatchJobs;) {
                             Ticket& t = S->tickets[S->queue[qi]];
-                            ss_request more = all;
-                            more.n = all.n + t.req.n;
-                            const uint64_t est = std::max<uint64_t>(L.reserved, workspace_estimate(more));
-                            if (t.req.op == SS_OP_SEMISORT_EQUAL && t.req.val_bytes == h.val_bytes &&
-                                t.req.n <= S->cfg.pack_max_records && more.n <= pack_cap &&
-                                S->reserved - L.reserved + est <= S->cfg.hbm_budget) {
-                                all.n = more.n;
-                                S->reserved += est - L.reserved;
-                                L.reserved = est;
-                                S->peak_reserved = std::max(S->peak_reserved, S->reserved);
-                                group.push_back(&t);
+                            if (t.req.n > S->cfg.pack_max_records || recs + t.req.n > S->cfg.batch_records) {
+                                ++qi;
+                                continue;
+                            }
+                            group.push_back(&t);
+                            const uint64_t need = L.ws + batch_bound(group, &S->cfg.params);
+                            if (S->reserved() - L.ws + need + group_io + io_bytes(t.req) <= budget) {
+                                charge = need;
+                                group_io += io_bytes(t.req);
+                                recs += t.req.n;
                                 S->queue.erase(S->queue.begin() + (long)qi);
                             } else {
+                                group.pop_back();
                                 ++qi;
                             }
                         }
                     }
+                    S->ws_charged += charge - L.ws;
+                    L.ws = charge;
+                    S->io_charged += group_io;
+                    S->peak_reserved = std::max(S->peak_reserved, S->reserved());
                     break;
                 }
                 // nothing fits: an idle lane gives its workspace back first
-                // (it keeps its packing buffers)
-                const uint64_t pack_bytes = L.pk_in ? 4 * pack_cap * 8 : 0;
-                if (L.reserved > pack_bytes && !S->queue.empty()) {
+                if (L.ws > 0 && !S->queue.empty()) {
                     ss_ctx* fresh = nullptr;
-                    if (ss_create(S->device, L.stream, &fresh) == SS_OK) {
+                    if (ss_create(S->device, L.stream, 0, &fresh) == SS_OK) {
                         (void)ss_destroy(L.ctx);
                         L.ctx = fresh;
-                        S->reserved -= L.reserved - pack_bytes;
-                        L.reserved = pack_bytes;
+                        S->ws_charged -= L.ws;
+                        L.ws = 0;
                         S->cv.notify_all();  // other idle lanes look again (and give back too)
                         continue;
                     }
@@ -211,10 +222,10 @@ void worker(ss_server* S, int li)
                 S->cv.wait(lk);
             }
         }
-        ss_status st;
-        if (group.size() == 1) st = run_one(&S->cfg.params, L, *group[0]);
-        else st = run_packed(S, L, group);
+        const ss_status st = run_group(S, L, group);
         const double t_done = S->now();
+        size_t held = 0;
+        const bool have_held = ss_workspace_held(L.ctx, &held) == SS_OK;
         {
             std::lock_guard<std::mutex> lk(S->mu);
             for (Ticket* t : group) {
@@ -226,16 +237,12 @@ void worker(ss_server* S, int li)
             S->in_flight -= group.size();
             S->batches += 1;
             if (group.size() > 1) S->packed += group.size();
-            // what the context really holds now
-            size_t ws = 0;
-            if (ss_workspace_bytes(L.ctx, &ws) == SS_OK) {
-                const uint64_t pack_bytes = L.pk_in ? 4 * pack_cap * 8 : 0;
-                const uint64_t held = (uint64_t)ws + pack_bytes;
-                if (held > L.reserved) {
-                    S->reserved += held - L.reserved;
-                    L.reserved = held;
-                    S->peak_reserved = std::max(S->peak_reserved, S->reserved);
-                }
+            S->io_charged -= group_io;
+            // from now on the lane is charged what its context really holds
+            // (at most the charge it ran under)
+            if (have_held && held < L.ws) {
+                S->ws_charged -= L.ws - held;
+                L.ws = held;
             }
         }
         S->cv.notify_all();
@@ -282,30 +289,24 @@ ss_status ss_server_create(int device, const ss_server_config* cfg, ss_server** 
             st = SS_EHIP;
             break;
         }
-        if ((st = ss_create(device, L.stream, &L.ctx)) != SS_OK) break;
-        if (c.pack_max_records && c.batch_records) {
-            const size_t kb = c.batch_records * 8;
-            if (hipMalloc(&L.pk_in, kb) != hipSuccess || hipMalloc(&L.pv_in, kb) != hipSuccess ||
-                hipMalloc(&L.pk_out, kb) != hipSuccess || hipMalloc(&L.pv_out, kb) != hipSuccess) {
-                st = SS_ENOMEM;
-                break;
-            }
-            L.reserved = 4 * kb;
-            S->reserved += L.reserved;
+        if ((st = ss_create(device, L.stream, 0, &L.ctx)) != SS_OK) break;
+        if (hipMalloc((void**)&L.d_m, kMaxBatchJobs * 8) != hipSuccess ||
+            hipHostMalloc((void**)&L.h_m, kMaxBatchJobs * 8, hipHostMallocDefault) != hipSuccess) {
+            st = SS_ENOMEM;
+            break;
         }
     }
-    if (st == SS_OK && S->reserved > c.hbm_budget) st = SS_EINVAL;  // packing buffers alone exceed the budget
     if (st != SS_OK) {
         for (Lane& L : S->lanes) {
             if (L.ctx) ss_destroy(L.ctx);
-            for (void* p : {L.pk_in, L.pv_in, L.pk_out, L.pv_out})
-                if (p) (void)hipFree(p);
+            if (L.d_m) (void)hipFree(L.d_m);
+            if (L.h_m) (void)hipHostFree(L.h_m);
             if (L.stream) (void)hipStreamDestroy(L.stream);
         }
         delete S;
         return st;
     }
-    S->peak_reserved = S->reserved;
+    S->peak_reserved = S->reserved();
     for (uint32_t i = 0; i < c.lanes; ++i) S->lanes[i].th = std::thread(worker, S, (int)i);
     *out = S;
     return SS_OK;
@@ -320,16 +321,16 @@ ss_status ss_server_submit(ss_server* S, const ss_request* r, double arrival_s, 
 {
     if (!S || !r || !ticket) return SS_EINVAL;
     if (r->op < SS_OP_SEMISORT_EQUAL || r->op > SS_OP_COLLECT_REDUCE) return SS_EINVAL;
-    if (is_semisort(r->op) && r->val_bytes != 4 && r->val_bytes != 8) return SS_EINVAL;
+    if (!is_reduce(r->op) && r->val_bytes != 4 && r->val_bytes != 8) return SS_EINVAL;
     if (r->n >= (1ull << 31)) return SS_EINVAL;
     if (r->n && (!r->keys || !r->out_a || !r->out_b || (r->op != SS_OP_HISTOGRAM && !r->vals))) return SS_EINVAL;
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return SS_EINVAL;
     // a request that cannot fit even with every lane's workspace given back
-    uint64_t pack_total = 0;
-    for (const Lane& L : S->lanes)
-        if (L.pk_in) pack_total += 4 * S->cfg.batch_records * 8;
-    if (r->n && workspace_estimate(*r) + pack_total > S->cfg.hbm_budget) return SS_ENOMEM;
+    Ticket probe;
+    probe.req = *r;
+    if (r->n && batch_bound({&probe}, &S->cfg.params) + io_bytes(*r) > S->cfg.hbm_budget)
+        return SS_ENOMEM;
     S->tickets.emplace_back();
     Ticket& t = S->tickets.back();
     t.req = *r;
@@ -397,8 +398,8 @@ ss_status ss_server_destroy(ss_server* S)
     (void)hipSetDevice(S->device);
     for (Lane& L : S->lanes) {
         if (L.ctx) ss_destroy(L.ctx);
-        for (void* p : {L.pk_in, L.pv_in, L.pk_out, L.pv_out})
-            if (p) (void)hipFree(p);
+        if (L.d_m) (void)hipFree(L.d_m);
+        if (L.h_m) (void)hipHostFree(L.h_m);
         if (L.stream) (void)hipStreamDestroy(L.stream);
     }
     delete S;

@@ -2965,6 +2965,21 @@ __global__ __launch_bounds__(256) void k_gather_at(uint64_t* out, uint64_t m, co
     }
 }
 
+// The same with m read from device memory (m <= n; the grid covers n).
+__global__ __launch_bounds__(256) void k_gather_at_dev(uint64_t* out, const uint64_t* m, const uint64_t* vals,
+                                                       uint64_t n, LevelInfo* info)
+{
+    const uint64_t mm = *m;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < mm; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t p = out[i];
+        if (p >= n) {
+            atomicOr(&info->status, kStatusSizeMismatch);
+            continue;
+        }
+        out[i] = vals[p];
+    }
+}
+
 // ---------------------------------------------------------------- in-order folds
 // Section 3.5: a stable algorithm reduces with any associative operation,
 // commutative or not.  After a stable semisort_= each key's records are
@@ -3429,5 +3444,136 @@ __global__ __launch_bounds__(1024) void k_flag_scatter(const uint8_t* rflag, con
         }
     }
 }
+
+// ---------------------------------------------------------------- batches of jobs
+// A batch packs small jobs back to back: job j occupies [off, off + n) of
+// the packed arrays.  Gathering and scattering walk the packed array in
+// chunks; a chunk finds its first job by binary search over the offsets.
+
+struct PackJob {
+    const uint64_t* keys;
+    const void* vals;
+    void* out_a;
+    void* out_b;
+    uint64_t* d_m;
+    uint64_t off;
+    uint64_t n;
+};
+
+constexpr uint32_t kPackChunk = 4096;  // packed positions per block
+
+// Largest j < njobs with at[j] <= x (at[] non-decreasing, at[0] <= x).
+__device__ __forceinline__ uint32_t last_at_or_below(const uint64_t* at, size_t stride, uint32_t njobs, uint64_t x)
+{
+    uint32_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (at[(size_t)mid * stride] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Inputs of the packed jobs into the packed arrays (pv NULL: keys only).
+template <typename V>
+__global__ __launch_bounds__(256) void k_pack_gather(const PackJob* jobs, uint32_t njobs, uint64_t total,
+                                                     uint64_t* pk, V* pv)
+{
+    __shared__ uint32_t sj;
+    const uint64_t r0 = (uint64_t)blockIdx.x * kPackChunk;
+    if (r0 >= total) return;
+    const uint64_t r1 = r0 + kPackChunk < total ? r0 + kPackChunk : total;
+    if (threadIdx.x == 0) sj = last_at_or_below(&jobs[0].off, sizeof(PackJob) / 8, njobs, r0);
+    __syncthreads();
+    for (uint32_t j = sj; j < njobs && jobs[j].off < r1; ++j) {
+        const PackJob J = jobs[j];
+        const uint64_t a = r0 > J.off ? r0 : J.off;
+        const uint64_t b = r1 < J.off + J.n ? r1 : J.off + J.n;
+        for (uint64_t i = a + threadIdx.x; i < b; i += 256) {
+            pk[i] = J.keys[i - J.off];
+            if (pv) pv[i] = ((const V*)J.vals)[i - J.off];
+        }
+    }
+}
+
+// Packed semisort results back to every job's outputs.
+template <typename V>
+__global__ __launch_bounds__(256) void k_pack_scatter(const PackJob* jobs, uint32_t njobs, uint64_t total,
+                                                      const uint64_t* ok, const V* ov)
+{
+    __shared__ uint32_t sj;
+    const uint64_t r0 = (uint64_t)blockIdx.x * kPackChunk;
+    if (r0 >= total) return;
+    const uint64_t r1 = r0 + kPackChunk < total ? r0 + kPackChunk : total;
+    if (threadIdx.x == 0) sj = last_at_or_below(&jobs[0].off, sizeof(PackJob) / 8, njobs, r0);
+    __syncthreads();
+    for (uint32_t j = sj; j < njobs && jobs[j].off < r1; ++j) {
+        const PackJob J = jobs[j];
+        const uint64_t a = r0 > J.off ? r0 : J.off;
+        const uint64_t b = r1 < J.off + J.n ? r1 : J.off + J.n;
+        for (uint64_t i = a + threadIdx.x; i < b; i += 256) {
+            ((uint64_t*)J.out_a)[i - J.off] = ok[i];
+            ((V*)J.out_b)[i - J.off] = ov[i];
+        }
+    }
+}
+
+// Rank among all packed results of the first result of job j (j = njobs:
+// the total m): the results are packed in position order, so the rank is the
+// number of flagged positions below the job's offset -- its flag block's
+// scanned total, the counts of the block's earlier chunks and the flags of
+// its own chunk below it.  One block per boundary.
+__global__ __launch_bounds__(256) void k_inst_ranks(const uint8_t* rflag, const uint32_t* ccnt, const uint32_t* boff,
+                                                    const PackJob* jobs, uint32_t njobs,
+                                                    const unsigned long long* m_total, uint64_t* rank)
+{
+    __shared__ uint32_t ws[4];
+    const uint32_t j = blockIdx.x;
+    if (j == njobs) {
+        if (threadIdx.x == 0) rank[j] = *m_total;
+        return;
+    }
+    const uint64_t x = jobs[j].off;
+    const uint64_t blk = x / kFlagBlock, ch = x / kFlagChunk;
+    uint32_t c = 0;
+    for (uint64_t q = blk * (kFlagBlock / kFlagChunk) + threadIdx.x; q < ch; q += 256) c += ccnt[q];
+    for (uint64_t i = ch * kFlagChunk + threadIdx.x; i < x; i += 256) c += rflag[i] != 0;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
+    if ((threadIdx.x & 63u) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) rank[j] = (uint64_t)boff[blk] + ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// m of every job to its d_m.
+__global__ __launch_bounds__(256) void k_inst_m(const PackJob* jobs, uint32_t njobs, const uint64_t* rank)
+{
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    if (j < njobs) *jobs[j].d_m = rank[j + 1] - rank[j];
+}
+
+// Packed (key, result) pairs back to every job's outputs: positions
+// [rank[j], rank[j + 1]) of the packed pairs are job j's.
+__global__ __launch_bounds__(256) void k_pack_scatter_red(const PackJob* jobs, uint32_t njobs, const uint64_t* rank,
+                                                          const uint64_t* ok, const uint64_t* ov)
+{
+    __shared__ uint32_t sj;
+    const uint64_t m = rank[njobs];
+    const uint64_t r0 = (uint64_t)blockIdx.x * kPackChunk;
+    if (r0 >= m) return;
+    const uint64_t r1 = r0 + kPackChunk < m ? r0 + kPackChunk : m;
+    if (threadIdx.x == 0) sj = last_at_or_below(rank, 1, njobs, r0);
+    __syncthreads();
+    for (uint32_t j = sj; j < njobs && rank[j] < r1; ++j) {
+        const PackJob J = jobs[j];
+        const uint64_t s = rank[j], e = rank[j + 1];
+        const uint64_t a = r0 > s ? r0 : s;
+        const uint64_t b = r1 < e ? r1 : e;
+        for (uint64_t i = a + threadIdx.x; i < b; i += 256) {
+            ((uint64_t*)J.out_a)[i - s] = ok[i];
+            ((uint64_t*)J.out_b)[i - s] = ov[i];
+        }
+    }
+}
+
 
 }  // namespace ssd

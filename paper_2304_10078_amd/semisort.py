@@ -60,13 +60,17 @@ def lib():
         vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
         P = ctypes.POINTER(ss_params)
         L.ss_default_params.argtypes = [P]
-        L.ss_create.argtypes = [i32, vp, ctypes.POINTER(vp)]
+        L.ss_create.argtypes = [i32, vp, ctypes.c_size_t, ctypes.POINTER(vp)]
         L.ss_destroy.argtypes = [vp]
         L.ss_set_stream.argtypes = [vp, vp]
         L.ss_last_error.argtypes = [vp]
         L.ss_last_error.restype = ctypes.c_char_p
         L.ss_sync.argtypes = [vp]
-        L.ss_workspace_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ss_workspace_held.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        L.ss_workspace_bytes.argtypes = [i32, u64, u32, P, ctypes.POINTER(ctypes.c_size_t)]
+        L.ss_collect_reduce_async.argtypes = [vp, vp, vp, u64, i32, i32, vp, vp, vp, P]
+        L.ss_histogram_async.argtypes = [vp, vp, u64, i32, vp, vp, vp, P]
+        L.ss_batch.argtypes = [vp, vp, u64, P]
         L.ss_profile_enable.argtypes = [vp, i32]
         L.ss_set_option.argtypes = [vp, i32, ctypes.c_int64]
         L.ss_profile_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64),
@@ -106,11 +110,12 @@ def default_params(**kw):
 class Context:
     """One library context (ss_ctx) on a device; reuses its workspace across calls."""
 
-    def __init__(self, device=0):
+    def __init__(self, device=0, workspace_cap=0):
         import torch
         self.device = device
         h = ctypes.c_void_p()
-        st = lib().ss_create(device, ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream), ctypes.byref(h))
+        st = lib().ss_create(device, ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream),
+                             int(workspace_cap), ctypes.byref(h))
         if st != SS_OK:
             raise SemisortError(st, "ss_create failed")
         self.h = h
@@ -164,10 +169,22 @@ class Context:
             out[name] = (ms.value, la.value, un.value)
         return out
 
-    def workspace_bytes(self):
+    def workspace_held(self):
+        """ss_workspace_held: bytes of workspace the context holds now."""
         b = ctypes.c_size_t()
-        self.check(lib().ss_workspace_bytes(self.h, ctypes.byref(b)))
+        self.check(lib().ss_workspace_held(self.h, ctypes.byref(b)))
         return b.value
+
+
+def workspace_bound(op, n, val_bytes=8, params=None):
+    """ss_workspace_bytes: upper bound of the workspace one call of `op` on n
+    records makes a new context hold (a planning query; no device needed)."""
+    b = ctypes.c_size_t()
+    st = lib().ss_workspace_bytes(int(op), int(n), int(val_bytes),
+                                  ctypes.byref(params) if params is not None else None, ctypes.byref(b))
+    if st != SS_OK:
+        raise SemisortError(st, "ss_workspace_bytes rejected its arguments")
+    return b.value
 
 
 _ctx = {}
@@ -390,6 +407,67 @@ def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None, order
     ctx.check(fn(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
                  ctypes.byref(m), ctypes.byref(params) if params is not None else None))
     return out_keys[:m.value], out_counts[:m.value]
+
+
+def collect_reduce_async(keys, vals, d_m, out_keys, out_vals, op="sum", ordered=False, params=None, ctx=None):
+    """ss_collect_reduce_async: like collect_reduce, but m goes to d_m (an
+    int64 device tensor of one entry) and the call does not wait for it.
+    The outputs have capacity n; their first m entries hold the pairs."""
+    _check_keys(keys)
+    _check_keys(vals, "vals")
+    _check_keys(d_m, "d_m")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    ctx.check(lib().ss_collect_reduce_async(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), MONOIDS[op],
+                                            int(bool(ordered)), _ptr(out_keys), _ptr(out_vals), _ptr(d_m),
+                                            ctypes.byref(params) if params is not None else None))
+
+
+def histogram_async(keys, d_m, out_keys, out_counts, ordered=False, params=None, ctx=None):
+    """ss_histogram_async: like histogram, with m to the device tensor d_m."""
+    _check_keys(keys)
+    _check_keys(d_m, "d_m")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    ctx.check(lib().ss_histogram_async(ctx.h, _ptr(keys), keys.numel(), int(bool(ordered)), _ptr(out_keys),
+                                       _ptr(out_counts), _ptr(d_m),
+                                       ctypes.byref(params) if params is not None else None))
+
+
+class ss_job(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_int32),
+        ("val_bytes", ctypes.c_uint32),
+        ("n", ctypes.c_uint64),
+        ("keys", ctypes.c_void_p),
+        ("vals", ctypes.c_void_p),
+        ("out_a", ctypes.c_void_p),
+        ("out_b", ctypes.c_void_p),
+        ("d_m", ctypes.c_void_p),
+    ]
+
+
+def batch(jobs, params=None, ctx=None):
+    """ss_batch over a list of (op, keys, vals, out_a, out_b, d_m) tuples of
+    device tensors (vals None for the histogram, d_m None for semisort; d_m
+    is an int64 tensor whose first entry receives m).  Returns after the
+    work is enqueued."""
+    arr = (ss_job * max(1, len(jobs)))()
+    dev = 0
+    for i, (op, k, v, oa, ob, dm) in enumerate(jobs):
+        j = arr[i]
+        j.op = int(op)
+        j.val_bytes = v.element_size() if v is not None else 8
+        j.n = k.numel()
+        j.keys = k.data_ptr() if k.numel() else None
+        j.vals = v.data_ptr() if v is not None and v.numel() else None
+        j.out_a = oa.data_ptr() if oa.numel() else None
+        j.out_b = ob.data_ptr() if ob.numel() else None
+        j.d_m = dm.data_ptr() if dm is not None else None
+        dev = k.device.index or 0
+    ctx = ctx or context(dev)
+    ctx._bind_stream()
+    ctx.check(lib().ss_batch(ctx.h, arr, len(jobs), ctypes.byref(params) if params is not None else None))
 
 
 def transpose_csr(offsets, cols, params=None, ctx=None, out_offsets=None, out_cols=None):
