@@ -46,6 +46,66 @@ def load_traffic(workload, n):
     return d.get("bytes_per_launch")
 
 
+def load_pass_traffic(op, workload, n):
+    """HBM bytes per call of every pass from committed rocprofv3 counter runs
+    of `bench.py --profile-op`, only if they were taken on the current kernel
+    sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_passes_{op_file(op)}_{workload}_n{n}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    from paper_2304_10078_amd.profiling import source_digest
+    if d.get("source_digest") != source_digest() or d.get("workload") != workload or d.get("n") != n:
+        return None
+    return d["passes"]
+
+
+def op_file(op):
+    return op.replace("semisort_=", "semisort_equal").replace("semisort_<", "semisort_less")
+
+
+def run_op(S, op, keys, vals, torch, out=None):
+    """One call of a benchmarked operation on device-resident inputs."""
+    if op == "semisort_=":
+        return S.semisort_equal(keys, vals, *(out or ()))
+    if op == "semisort_<":
+        return S.semisort_less(keys, vals, *(out or ()))
+    if op.startswith("collect_reduce"):
+        v64 = vals if vals.element_size() == 8 else vals.to(torch.int64)
+        mono = op.split("_")[-1] if op != "collect_reduce" else "sum"
+        return S.collect_reduce(keys, v64, op=mono)
+    if op == "histogram_ordered":
+        return S.histogram(keys, ordered=True)
+    if op == "histogram":
+        return S.histogram(keys)
+    raise ValueError(op)
+
+
+def profile_op(args, S, I, torch):
+    """--profile-op: only `warmup + steps` calls of one operation on one
+    workload, then the calibration copy -- the program that rocprofv3 counter
+    runs of the other configurations profile."""
+    keys, vals = I.t_workload(args.workload, args.n, args.seed, "cuda")
+    torch.cuda.synchronize()
+    out = None
+    if args.profile_op in ("semisort_=", "semisort_<"):
+        out = (torch.empty_like(keys), torch.empty_like(vals))
+    for _ in range(args.warmup + args.steps):
+        r = run_op(S, args.profile_op, keys, vals, torch, out)
+        S.sync()
+        del r
+    src = torch.empty(1 << 28, dtype=torch.int64, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_op": args.profile_op, "workload": args.workload, "n": args.n,
+                      "calls": args.warmup + args.steps}), flush=True)
+
+
 def cpu_baseline(keys_dev, vals_dev, m):
     import numpy as np
 
@@ -99,22 +159,15 @@ def other_configs(args, S, I, torch):
         torch.cuda.empty_cache()
         R = 8 + vals.element_size()
         for op in ops:
-            if op == "semisort_=":
-                fn = lambda: S.semisort_equal(keys, vals)  # noqa: E731
-                b = 8 + 2 * R + 2 * R * (1 - f_h)
-            elif op == "semisort_<":
-                fn = lambda: S.semisort_less(keys, vals)  # noqa: E731
+            fn = lambda op=op: run_op(S, op, keys, vals, torch)  # noqa: E731
+            if op in ("semisort_=", "semisort_<"):
                 b = 8 + 2 * R + 2 * R * (1 - f_h)
             elif op.startswith("collect_reduce"):
-                v64 = vals if vals.element_size() == 8 else vals.to(torch.int64)
-                mono = op.split("_")[-1] if op != "collect_reduce" else "sum"  # monoid: sum, min, max
-                fn = lambda mono=mono: S.collect_reduce(keys, v64, op=mono)  # noqa: E731
                 b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
-                if mono == "affine":  # semisort_=, two reads of the grouped records, flags, results
+                if op.endswith("affine"):  # semisort_=, two reads of the grouped records, flags, results
                     b = 8 + 32 + 32 * (1 - f_h) + 32 + 2 + 32.0 * m / n
             else:
                 # these workloads need groups in ascending key order
-                fn = lambda: S.histogram(keys, ordered=True)  # noqa: E731
                 b = 16 + 16 * (1 - f_h) + 16.0 * m / n + 32.0 * m / n
             fn()
             S.sync()
@@ -130,6 +183,13 @@ def other_configs(args, S, I, torch):
             key = f"{op} {wl}"
             res[key] = {"ms": round(ms, 3), "ms_runs": [round(t, 3) for t in times], "grecs": round(n / ms / 1e6, 2), "f_H": round(f_h, 4),
                         "B_alg_per_record": round(b, 2), "pct_hbm_roofline": round(100 * b * n / (ms * 1e-3) / 8e12, 1)}
+            tp = load_pass_traffic(op, wl, n)
+            if tp:
+                # counter bytes of the whole call (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+                tot = sum(x["fetch_bytes"] + x["write_bytes"] for x in tp.values())
+                res[key]["counter_bytes_per_record"] = round(tot / n, 2)
+                res[key]["counter_gbs"] = round(tot / (ms * 1e-3) / 1e9, 1)
+                res[key]["counter_bytes_by_pass"] = {k: round(x["fetch_bytes"] + x["write_bytes"]) for k, x in tp.items()}
             log(f"configs: {key}: {res[key]}")
         del keys, vals
         torch.cuda.empty_cache()
@@ -396,6 +456,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the served-requests measurement")
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--serve-lanes", type=int, default=4)
+    ap.add_argument("--profile-op", default=None,
+                    help="only run this operation (semisort_=, semisort_<, collect_reduce, collect_reduce_min, "
+                         "histogram_ordered, histogram) warmup + steps times on --workload, then the calibration "
+                         "copy: the program of the counter runs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, copy 2^28 int64 (2 GiB) once: a plain copy of known size that "
                          "calibrates rocprofv3 FETCH_SIZE/WRITE_SIZE counters")
@@ -411,6 +475,9 @@ def main():
     from paper_2304_10078_amd import inputs as I
     from paper_2304_10078_amd import semisort as S
 
+    if args.profile_op:
+        profile_op(args, S, I, torch)
+        return
     dev = torch.device("cuda:0")
     n = args.n
     log(f"generating {args.workload} n={n} seed={args.seed} on {torch.cuda.get_device_name(0)}")
@@ -459,9 +526,17 @@ def main():
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step, {grecs:.2f} Grec/s")
 
     passes = {}
+    tp = load_pass_traffic("semisort_=", args.workload, n) or {}
     for name, (ms, launches, units) in prof.items():
         passes[name] = {"ms_per_step": round(ms / args.steps, 4), "launches_per_step": launches / args.steps,
                         "units_per_step": units / args.steps}
+        if name in tp and ms > 0:
+            # HBM bytes of the pass's kernels from the committed counter runs
+            # over its live event time: achieved GB/s against the 8 TB/s peak
+            cb = tp[name]["fetch_bytes"] + tp[name]["write_bytes"]
+            gbs = cb / (ms / args.steps * 1e-3) / 1e9
+            passes[name].update({"counter_bytes_per_step": round(cb), "counter_gbs": round(gbs, 1),
+                                 "frac_peak": round(gbs / HBM_PEAK_GBS, 3)})
         log(f"  {name:10s} {ms / args.steps:8.3f} ms/step  launches {launches / args.steps:.1f}")
     d_ms, d_launch, d_units = prof["distribute"]
     # the distribution pass reads key and value of every record and writes

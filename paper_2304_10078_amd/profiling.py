@@ -13,7 +13,11 @@ kept with the project:
       known size that bench.py --calib-copy makes;
   traffic <fetch.json> <write.json> <out.json> --calib-bytes B --workload W --n N
       HBM bytes per distribution launch: each counter (KiB per dispatch) is
-      scaled by known_bytes / counter_bytes of the calibration copy.
+      scaled by known_bytes / counter_bytes of the calibration copy;
+  passes  <fetch.json> <write.json> <out.json> --calib-bytes B --workload W --op O --n N --calls C
+      HBM bytes per call of every pass (sampling, counting, prefix,
+      distribution, planning, base cases, compaction, key fills), scaled the
+      same way.
 
 Nothing here runs on the GPU.
 """
@@ -128,6 +132,45 @@ def traffic(fetch, write, out, calib_bytes, workload, n, kernel_prefix="k_distri
     return res
 
 
+# pass of each engine kernel (the passes of ss_profile_read)
+PASS_OF = (("k_sample", "sample"), ("k_count", "count"), ("k_scan", "scan"), ("k_distribute", "distribute"),
+           ("k_plan", "plan"), ("k_seg_prefix", "plan"), ("k_heavy_results", "plan"), ("k_base", "finish"),
+           ("k_copy", "finish"), ("k_sum_job", "finish"), ("k_flag", "compact"), ("k_fill", "fill"),
+           ("k_sfold", "fold"), ("k_iota", "fold"), ("k_gather_at", "fold"), ("k_pack", "pack"),
+           ("k_inst", "pack"))
+
+
+def pass_of(kernel):
+    for prefix, name in PASS_OF:
+        if kernel.startswith(prefix):
+            return name
+    return "other"
+
+
+def passes(fetch, write, out, calib_bytes, workload, op, n, calls, commands=None):
+    """HBM bytes per call of every pass: each counter (KiB per dispatch) is
+    scaled by the calibration copy, summed over the pass's kernels and divided
+    by the number of calls in the profiled run."""
+    F = json.load(open(fetch))
+    W = json.load(open(write))
+
+    def calib(d):
+        last = max(x for lst in d["kernels"].values() for x, _ in lst)
+        return sum(v for x, v in d["copies"] if x > last) * 1024.0
+
+    res = {"workload": workload, "op": op, "n": n, "source_digest": source_digest(), "calls": calls,
+           "calib_copy_bytes": calib_bytes, "passes": {}, "commands": commands or []}
+    for key, d in (("fetch_bytes", F), ("write_bytes", W)):
+        scale = calib_bytes / calib(d)
+        res[key + "_scale"] = scale
+        for name, lst in d["kernels"].items():
+            p = res["passes"].setdefault(pass_of(name), {"fetch_bytes": 0.0, "write_bytes": 0.0})
+            p[key] += sum(v for _, v in lst) * 1024.0 * scale / calls
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    return res
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="action", required=True)
@@ -146,7 +189,21 @@ def main(argv=None):
     c.add_argument("--workload", required=True)
     c.add_argument("--n", type=int, required=True)
     c.add_argument("--command", action="append", default=[], help="profiler command of a counter run (repeat)")
+    e = sub.add_parser("passes")
+    e.add_argument("fetch")
+    e.add_argument("write")
+    e.add_argument("out")
+    e.add_argument("--calib-bytes", type=float, required=True)
+    e.add_argument("--workload", required=True)
+    e.add_argument("--op", required=True)
+    e.add_argument("--n", type=int, required=True)
+    e.add_argument("--calls", type=int, required=True)
+    e.add_argument("--command", action="append", default=[], help="profiler command of a counter run (repeat)")
     args = ap.parse_args(argv)
+    if args.action == "passes":
+        print(json.dumps(passes(args.fetch, args.write, args.out, args.calib_bytes, args.workload, args.op, args.n,
+                                args.calls, commands=args.command)))
+        return
     if args.action == "kstats":
         kstats(args.csv, args.out, args.command)
     elif args.action == "pmc":
