@@ -180,6 +180,23 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
                             uint32_t val_bytes, uint64_t n, uint64_t* keys_out,
                             void* vals_out, const ss_params* params);
 
+/* semisort_= and semisort_< (as ss_semisort_equal / ss_semisort_less) with
+ * keys of key_bytes = 4 or 8 bytes (Section 2.1 defines the problem for any
+ * key type; Section 4.1 and the key-length study of Section 5 compare key
+ * widths): keys[n] and keys_out[n] hold key_bytes-wide unsigned integers.
+ * 32-bit records move 4 bytes less per key through every pass.  A 32-bit
+ * key is hashed as its zero-extended 64-bit value, so SS_HASH_MIX64 stays a
+ * bijection and the result equals the 64-bit call's on the zero-extended
+ * keys.  SS_EINVAL for another key_bytes; otherwise the arguments,
+ * conventions and errors of the 64-bit calls (in place: keys_out == keys
+ * and vals_out == vals). */
+ss_status ss_semisort_equal_keys(ss_ctx* ctx, const void* keys, uint32_t key_bytes, const void* vals,
+                                 uint32_t val_bytes, uint64_t n, void* keys_out, void* vals_out,
+                                 const ss_params* params);
+ss_status ss_semisort_less_keys(ss_ctx* ctx, const void* keys, uint32_t key_bytes, const void* vals,
+                                uint32_t val_bytes, uint64_t n, void* keys_out, void* vals_out,
+                                const ss_params* params);
+
 /* Batched semisort_=: `nseg` independent instances packed back to back;
  * instance i occupies [seg_offsets[i], seg_offsets[i+1]) of keys/vals and of
  * the outputs.  seg_offsets is a HOST array of nseg+1 non-decreasing

@@ -361,22 +361,24 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes)
 // the mixing / identity hash; MODE 2: semisort_<.
 // Grid of a persistent base-case launch: the blocks that fit on the device
 // at once (the occupancy of the kernel is queried once), at most one per job.
-template <int MODE, typename V, int W>
+template <int MODE, typename V, int W, typename K = uint64_t>
 uint32_t base_grid(const ss_ctx* c, uint32_t njobs)
 {
     static const int per = [] {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_base<MODE, V, W>, W * 64, 0) != hipSuccess || b < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_base<MODE, V, W, K>, W * 64, 0) != hipSuccess || b < 1)
             b = 1;
         return b;
     }();
     return (uint32_t)std::min<uint64_t>(njobs, (uint64_t)per * (uint64_t)c->ncu);
 }
 
-template <int MODE, typename V>
-void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
-                   uint64_t* ok, void* ov)
+template <int MODE, typename V, typename K>
+void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_t* skw, const void* sv,
+                   uint64_t* okw, void* ov)
 {
+    const K* sk = (const K*)skw;  // keys of K bytes
+    K* ok = (K*)okw;
     const Job* jobs = (const Job*)c->jobs.p;
     LevelInfo* info = (LevelInfo*)c->info.p;
     const V* svv = (const V*)sv;
@@ -385,54 +387,54 @@ void launch_jobs_m(ss_ctx* c, const uint32_t* njobs, uint32_t cap, const uint64_
     const Job* j2 = jobs + 2 * (size_t)cap;
     const Job* j3 = jobs + 3 * (size_t)cap;
     if constexpr (MODE == 2) {
-        if (njobs[0]) hipLaunchKernelGGL((k_base_less<V, 1>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv);
-        if (njobs[1]) hipLaunchKernelGGL((k_base_less<V, 2>), dim3(njobs[1]), dim3(128), 0, c->stream, j1, sk, svv, ok, ovv);
-        if (njobs[2]) hipLaunchKernelGGL((k_base_less<V, 4>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv);
-        if (njobs[3]) hipLaunchKernelGGL((k_base_less<V, 8>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv);
+        if (njobs[0]) hipLaunchKernelGGL((k_base_less<V, 1, K>), dim3(njobs[0]), dim3(64), 0, c->stream, jobs, sk, svv, ok, ovv);
+        if (njobs[1]) hipLaunchKernelGGL((k_base_less<V, 2, K>), dim3(njobs[1]), dim3(128), 0, c->stream, j1, sk, svv, ok, ovv);
+        if (njobs[2]) hipLaunchKernelGGL((k_base_less<V, 4, K>), dim3(njobs[2]), dim3(256), 0, c->stream, j2, sk, svv, ok, ovv);
+        if (njobs[3]) hipLaunchKernelGGL((k_base_less<V, 8, K>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv);
     } else {
         uint64_t* sink = (uint64_t*)c->sink.p;
         if (njobs[0])
-            hipLaunchKernelGGL((k_base<MODE, V, 1>), dim3(base_grid<MODE, V, 1>(c, njobs[0])), dim3(64), 0, c->stream,
+            hipLaunchKernelGGL((k_base<MODE, V, 1, K>), dim3(base_grid<MODE, V, 1, K>(c, njobs[0])), dim3(64), 0, c->stream,
                                jobs, njobs[0], sk, svv, ok, ovv, sink, info);
         if (njobs[1])
-            hipLaunchKernelGGL((k_base<MODE, V, 2>), dim3(base_grid<MODE, V, 2>(c, njobs[1])), dim3(128), 0, c->stream,
+            hipLaunchKernelGGL((k_base<MODE, V, 2, K>), dim3(base_grid<MODE, V, 2, K>(c, njobs[1])), dim3(128), 0, c->stream,
                                j1, njobs[1], sk, svv, ok, ovv, sink, info);
         if (njobs[2])
-            hipLaunchKernelGGL((k_base<MODE, V, 4>), dim3(base_grid<MODE, V, 4>(c, njobs[2])), dim3(256), 0, c->stream,
+            hipLaunchKernelGGL((k_base<MODE, V, 4, K>), dim3(base_grid<MODE, V, 4, K>(c, njobs[2])), dim3(256), 0, c->stream,
                                j2, njobs[2], sk, svv, ok, ovv, sink, info);
         if (njobs[3])
-            hipLaunchKernelGGL((k_base_2pass<MODE, V>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv,
+            hipLaunchKernelGGL((k_base_2pass<MODE, V, K>), dim3(njobs[3]), dim3(512), 0, c->stream, j3, sk, svv, ok, ovv,
                                info);
     }
     if (njobs[kCopyClass])
-        hipLaunchKernelGGL((k_copy<V>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
+        hipLaunchKernelGGL((k_copy<V, K>), dim3(njobs[kCopyClass]), dim3(256), 0, c->stream,
                            jobs + (size_t)kCopyClass * cap, sk, svv, ok, ovv);
 }
 
-template <typename V>
+template <typename V, typename K = uint64_t>
 void launch_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, const uint64_t* sk, const void* sv,
                  uint64_t* ok, void* ov, uint64_t records)
 {
     ProfScope ps(c, SS_PROF_FINISH, records);
-    if (mode == 2) launch_jobs_m<2, V>(c, njobs, cap, sk, sv, ok, ov);
-    else if (mode == 1) launch_jobs_m<1, V>(c, njobs, cap, sk, sv, ok, ov);
-    else launch_jobs_m<0, V>(c, njobs, cap, sk, sv, ok, ov);
+    if (mode == 2) launch_jobs_m<2, V, K>(c, njobs, cap, sk, sv, ok, ov);
+    else if (mode == 1) launch_jobs_m<1, V, K>(c, njobs, cap, sk, sv, ok, ov);
+    else launch_jobs_m<0, V, K>(c, njobs, cap, sk, sv, ok, ov);
 }
 
 // part 0: the whole level; 1: sampling only; 2: everything after sampling.
-template <int MODE, typename V>
+template <int MODE, typename V, typename K = uint64_t>
 void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks, uint64_t records, int part)
 {
     if (part != 2) {
         ProfScope ps(c, SS_PROF_SAMPLE, a.nsegs);
-        if constexpr (MODE == 2) hipLaunchKernelGGL(k_sample_less, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_sample_heavy<MODE>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        if constexpr (MODE == 2) hipLaunchKernelGGL((k_sample_less<K>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_sample_heavy<MODE, K>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
     }
     if (part == 1) return;
     {
         ProfScope ps(c, SS_PROF_COUNT, records);
-        if constexpr (MODE == 2) hipLaunchKernelGGL(k_count_less, dim3(tiles), dim3(1024), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_count<MODE>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        if constexpr (MODE == 2) hipLaunchKernelGGL((k_count_less<K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        else hipLaunchKernelGGL((k_count<MODE, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
     }
     {
         ProfScope ps(c, SS_PROF_SCAN, tiles);
@@ -443,9 +445,9 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
     }
     {
         ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
-        switch (c->dist_variant) {
+        switch (sizeof(K) == 8 ? c->dist_variant : std::min(c->dist_variant, 1)) {
         case 1:
-            hipLaunchKernelGGL((k_distribute<V, 8, 8, 0>), dim3(tiles), dim3(512), 0, c->stream, a);
+            hipLaunchKernelGGL((k_distribute<V, 8, 8, 0, K>), dim3(tiles), dim3(512), 0, c->stream, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 4>), dim3(tiles), dim3(512), 0, c->stream, a);
@@ -460,18 +462,18 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
             hipLaunchKernelGGL((k_distribute_direct<V, 4, 16, 6>), dim3(tiles), dim3(256), 0, c->stream, a);
             break;
         default:
-            hipLaunchKernelGGL((k_distribute<V, 16, 8, 0>), dim3(tiles), dim3(1024), 0, c->stream, a);
+            hipLaunchKernelGGL((k_distribute<V, 16, 8, 0, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
         }
     }
 }
 
-template <typename V>
+template <typename V, typename K = uint64_t>
 void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks,
                     uint64_t records, int part = 0)
 {
-    if (mode == 2) launch_level<2, V>(c, a, tiles, chunks, records, part);
-    else if (mode == 1) launch_level<1, V>(c, a, tiles, chunks, records, part);
-    else launch_level<0, V>(c, a, tiles, chunks, records, part);
+    if (mode == 2) launch_level<2, V, K>(c, a, tiles, chunks, records, part);
+    else if (mode == 1) launch_level<1, V, K>(c, a, tiles, chunks, records, part);
+    else launch_level<0, V, K>(c, a, tiles, chunks, records, part);
 }
 
 // Sizes a level needs: per-subproblem tables, counting matrix rows, chunk rows.
@@ -660,7 +662,8 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
 }
 
 // The whole engine: `offs` are instance boundaries (host), total n = offs.back().
-template <typename V>
+// Keys have K bytes (the key pointers are passed as uint64_t* and read as K).
+template <typename V, typename K = uint64_t>
 ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const uint64_t* offs,
                              uint64_t ninst, uint64_t* keys_out, void* vals_out, const Params& p)
 {
@@ -698,7 +701,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     for (const Seg& sg : c->host_segs) records += sg.len;
     if (nsegs) {
         host_prefix(c->host_segs, p, &tiles, &chunks, &tile);
-        if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
+        if ((s = ensure(c, c->t_keys, n * sizeof(K))) != SS_OK) return s;
         if ((s = ensure(c, c->t_vals, n * sizeof(V))) != SS_OK) return s;
         if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     }
@@ -728,7 +731,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
                                           nj0[k] * sizeof(Job), hipMemcpyHostToDevice, c->stream));
             o += nj0[k];
         }
-        launch_jobs<V>(c, p.mode, nj0, c->job_cap, keys, vals, keys_out, vals_out, jrec);
+        launch_jobs<V, K>(c, p.mode, nj0, c->job_cap, keys, vals, keys_out, vals_out, jrec);
         HIP_OR_FAIL(c, hipGetLastError());
     }
     if (!nsegs) {
@@ -795,7 +798,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
             // neighbouring ones complete each other's partial lines in L2
             // (uniform keys at 10^9: 7% faster; heavy-dominated inputs lose
             // with them).  One synchronization reads the sample's count.
-            launch_level_v<V>(c, p.mode, a, tiles, chunks, records, 1);
+            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, 1);
             HIP_OR_FAIL(c, hipGetLastError());
             HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost,
                                           c->stream));
@@ -820,9 +823,9 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
                 a.P = (uint32_t*)c->P.p;
                 a.tile = tile;
             }
-            launch_level_v<V>(c, p.mode, a, tiles, chunks, records, 2);
+            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, 2);
         } else {
-            launch_level_v<V>(c, p.mode, a, tiles, chunks, records);
+            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records);
         }
         HIP_OR_FAIL(c, hipGetLastError());
         if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
@@ -834,14 +837,14 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
             if ((s = ensure_aux(c)) != SS_OK) return s;
             {
                 ProfScope ps(c, SS_PROF_FILL, li.fill_records, c->aux);
-                hipLaunchKernelGGL(k_fill, dim3(li.nfills), dim3(1024), 0, c->aux, (const FillJob*)c->fills[fb].p,
-                                   keys_out);
+                hipLaunchKernelGGL((k_fill<K>), dim3(li.nfills), dim3(1024), 0, c->aux, (const FillJob*)c->fills[fb].p,
+                                   (K*)keys_out);
             }
             HIP_OR_FAIL(c, hipEventRecord(c->fill_done[fb], c->aux));
             fill_used[fb] = true;
             guard.armed = true;
         }
-        launch_jobs<V>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
+        launch_jobs<V, K>(c, p.mode, li.njobs, c->job_cap, dst_k, dst_v, keys_out, vals_out, li.job_records);
         HIP_OR_FAIL(c, hipGetLastError());
         nsegs = li.nsegs;
         records = li.records;
@@ -1498,10 +1501,11 @@ ss_status check_reduce(ss_ctx* c, const uint64_t* keys, const uint64_t* vals, ui
 }
 
 ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t vb, uint64_t n,
-                       const void* ko, const void* vo, bool allow_inplace)
+                       const void* ko, const void* vo, bool allow_inplace, uint32_t kb = 8)
 {
     if (!c) return SS_EINVAL;
     if (vb != 4 && vb != 8) return fail(c, SS_EINVAL, "val_bytes must be 4 or 8");
+    if (kb != 4 && kb != 8) return fail(c, SS_EINVAL, "key_bytes must be 4 or 8");
     if (n >= (1ull << 31)) return fail(c, SS_EINVAL, "n must be below 2^31");
     if (n == 0) return SS_OK;
     if (!keys || !vals || !ko || !vo) return fail(c, SS_EINVAL, "null array pointer");
@@ -1509,11 +1513,11 @@ ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t v
     if (inplace && !allow_inplace) return fail(c, SS_EINVAL, "in-place is not allowed here");
     if (!inplace) {
         if (ko == keys || vo == vals) return fail(c, SS_EINVAL, "in-place needs keys_out == keys and vals_out == vals");
-        if (overlaps(ko, n * 8, keys, n * 8) || overlaps(ko, n * 8, vals, n * vb) ||
-            overlaps(vo, n * vb, keys, n * 8) || overlaps(vo, n * vb, vals, n * vb))
+        if (overlaps(ko, n * kb, keys, n * kb) || overlaps(ko, n * kb, vals, n * vb) ||
+            overlaps(vo, n * vb, keys, n * kb) || overlaps(vo, n * vb, vals, n * vb))
             return fail(c, SS_EINVAL, "outputs overlap inputs");
     }
-    if (overlaps(ko, n * 8, vo, n * vb)) return fail(c, SS_EINVAL, "keys_out overlaps vals_out");
+    if (overlaps(ko, n * kb, vo, n * vb)) return fail(c, SS_EINVAL, "keys_out overlaps vals_out");
     return SS_OK;
 }
 
@@ -1790,6 +1794,43 @@ ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, u
     const uint64_t offs[2] = {0, n};
     return vb == 8 ? run_semisort<uint64_t>(c, keys, vals, offs, 1, keys_out, vals_out, p)
                    : run_semisort<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
+}
+
+// semisort_= / semisort_< with keys of key_bytes (4 or 8) bytes.
+static ss_status semisort_keys(ss_ctx* c, bool less, const void* keys, uint32_t kb, const void* vals, uint32_t vb,
+                               uint64_t n, void* keys_out, void* vals_out, const ss_params* params)
+{
+    ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true, kb);
+    if (s != SS_OK || n == 0) return s;
+    Params p;
+    if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    if (less) {
+        p.mode = 2;
+        default_tiles(c, params, &p, 32768u, 65536u);
+    } else {
+        default_tiles(c, params, &p, 32768u, 16384u);
+    }
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    const uint64_t offs[2] = {0, n};
+    const uint64_t* k = (const uint64_t*)keys;
+    uint64_t* ko = (uint64_t*)keys_out;
+    if (kb == 4)
+        return vb == 8 ? run_semisort<uint64_t, uint32_t>(c, k, vals, offs, 1, ko, vals_out, p)
+                       : run_semisort<uint32_t, uint32_t>(c, k, vals, offs, 1, ko, vals_out, p);
+    return vb == 8 ? run_semisort<uint64_t>(c, k, vals, offs, 1, ko, vals_out, p)
+                   : run_semisort<uint32_t>(c, k, vals, offs, 1, ko, vals_out, p);
+}
+
+ss_status ss_semisort_equal_keys(ss_ctx* c, const void* keys, uint32_t key_bytes, const void* vals, uint32_t vb,
+                                 uint64_t n, void* keys_out, void* vals_out, const ss_params* params)
+{
+    return semisort_keys(c, false, keys, key_bytes, vals, vb, n, keys_out, vals_out, params);
+}
+
+ss_status ss_semisort_less_keys(ss_ctx* c, const void* keys, uint32_t key_bytes, const void* vals, uint32_t vb,
+                                uint64_t n, void* keys_out, void* vals_out, const ss_params* params)
+{
+    return semisort_keys(c, true, keys, key_bytes, vals, vb, n, keys_out, vals_out, params);
 }
 
 ss_status ss_semisort_equal_batch(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,

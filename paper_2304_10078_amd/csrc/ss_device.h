@@ -531,7 +531,7 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&e)[C], uint32_t base, ui
 // t*C .. t*C + C - 1 (h(key) when hashed, else the key); positions past s are
 // padded with ~0.  Positions are drawn with replacement from the
 // counter-based generator; all loads of a thread are issued before use.
-template <int MODE, int C>
+template <int MODE, int C, typename K>
 __device__ __forceinline__ void gather_regs(const LevelArgs& a, const Seg& sg, uint32_t s, bool hashed,
                                             uint64_t (&e)[C])
 {
@@ -545,7 +545,7 @@ __device__ __forceinline__ void gather_regs(const LevelArgs& a, const Seg& sg, u
         e[q] = ~0ull;
         if (i < s) {
             const uint64_t x = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
-            e[q] = a.src_keys[(uint64_t)sg.start + __umul64hi(x, (uint64_t)sg.len)];
+            e[q] = ((const K*)a.src_keys)[(uint64_t)sg.start + __umul64hi(x, (uint64_t)sg.len)];
         }
     }
     if (hashed) {
@@ -694,28 +694,28 @@ __device__ uint32_t select_heavy_runs(const uint64_t (&e)[C], const uint64_t* sm
 
 // Gather, sort and heavy selection for one sample size class (P = C * BS,
 // or P <= BS with C = 1).  Returns n_H.
-template <int MODE, int BS, int C>
+template <int MODE, int BS, int C, typename K>
 __device__ uint32_t sample_select(const LevelArgs& a, const Seg& sg, uint32_t sid, uint32_t s, uint32_t tau,
                                   uint32_t P, uint64_t* smp, uint32_t* rh, uint32_t* tmp, uint32_t* sh_te,
                                   uint32_t* sh_hs, uint64_t* hv, unsigned long long* top2)
 {
     uint64_t e[C];
-    gather_regs<MODE, C>(a, sg, s, true, e);
+    gather_regs<MODE, C, K>(a, sg, s, true, e);
     bitonic_sort_block<BS, C>(e, smp, P);
     return select_heavy_runs<BS, C>(e, smp, s, tau, rh, tmp, sh_te, sh_hs, hv,
                                     a.heavy_list + (size_t)sid * kHeavyMax, top2);
 }
 
 // Gather and sort of raw keys (semisort_<): smp holds the sorted sample.
-template <int BS, int C>
+template <int BS, int C, typename K>
 __device__ void sample_sort_keys(const LevelArgs& a, const Seg& sg, uint32_t s, uint32_t P, uint64_t* smp)
 {
     uint64_t e[C];
-    gather_regs<0, C>(a, sg, s, false, e);
+    gather_regs<0, C, K>(a, sg, s, false, e);
     bitonic_sort_block<BS, C>(e, smp, P);
 }
 
-template <int MODE>
+template <int MODE, typename K>
 __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t sid)
 {
     constexpr int BS = 1024;
@@ -749,11 +749,11 @@ __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t s
     uint32_t P = 2;
     while (P < s) P <<= 1;
     uint32_t nh;
-    if (P == 16 * BS) nh = sample_select<MODE, BS, 16>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
-    else if (P == 8 * BS) nh = sample_select<MODE, BS, 8>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
-    else if (P == 4 * BS) nh = sample_select<MODE, BS, 4>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
-    else if (P == 2 * BS) nh = sample_select<MODE, BS, 2>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
-    else nh = sample_select<MODE, BS, 1>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    if (P == 16 * BS) nh = sample_select<MODE, BS, 16, K>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 8 * BS) nh = sample_select<MODE, BS, 8, K>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 4 * BS) nh = sample_select<MODE, BS, 4, K>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else if (P == 2 * BS) nh = sample_select<MODE, BS, 2, K>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
+    else nh = sample_select<MODE, BS, 1, K>(a, sg, sid, s, tau, P, smp, rh, tmp, &sh_te, &sh_hs, hv, sh_top);
 
     // Light bucket count.  With adaptive_nl, n_L is the smallest power of two
     // that lets the light records finish in the fewest levels: one level if
@@ -850,10 +850,10 @@ __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t s
     }
 }
 
-template <int MODE>
+template <int MODE, typename K = uint64_t>
 __global__ __launch_bounds__(1024) void k_sample_heavy(LevelArgs a)
 {
-    sample_heavy_item<MODE>(a, blockIdx.x);
+    sample_heavy_item<MODE, K>(a, blockIdx.x);
 }
 
 // Device-sized levels: a resident grid walks the subproblems counted in dims.
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy_ds(LevelArgs a)
 {
     const uint32_t n = ds_nsegs(a);
     for (uint32_t sid = blockIdx.x; sid < n; sid += gridDim.x) {
-        sample_heavy_item<MODE>(a, sid);
+        sample_heavy_item<MODE, uint64_t>(a, sid);
         __syncthreads();
     }
 }
@@ -878,7 +878,7 @@ __global__ __launch_bounds__(1024) void k_sample_heavy_ds(LevelArgs a)
 // the paper; here one block per subarray with LDS counters.  Counting is
 // order-free, so plain LDS atomics suffice.
 
-template <int MODE>
+template <int MODE, typename K>
 __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint32_t nsegs, uint32_t tile)
 {
     constexpr int BS = 1024;
@@ -912,7 +912,7 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
 
     const uint32_t shift = sg.shift;
     const uint32_t lmask = nL - 1;
-    const uint64_t* keys = a.src_keys;
+    const K* keys = (const K*)a.src_keys;
     uint16_t* bids = a.bids;
     // The two most frequent heavy buckets are counted per wave by ballot
     // (one LDS update per wave instead of one per record); the others by
@@ -932,11 +932,11 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
     };
     constexpr int U = 8;  // loads in flight per thread
     // 32-bit offsets from the subarray's start (uniform base pointers)
-    const uint64_t* kt = keys + r0;
+    const K* kt = keys + r0;
     uint16_t* bt = bids + r0;
     const uint32_t len = (uint32_t)(r1 - r0);
     auto pass = [&](auto kind) {
-        constexpr int K = decltype(kind)::value;
+        constexpr int TK = decltype(kind)::value;  // heavy table kind
         uint32_t o = tid;
         for (; o + (U - 1) * BS < len; o += U * BS) {
             uint64_t kk[U];
@@ -944,13 +944,13 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
             for (int u = 0; u < U; ++u) kk[u] = kt[o + u * BS];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t b = bucket_of<K>(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
+                const uint32_t b = bucket_of<TK>(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
                 bt[o + u * BS] = (uint16_t)b;
                 tally(b);
             }
         }
         for (; o < len; o += BS) {
-            const uint32_t b = bucket_of<K>(user_hash<MODE>(kt[o]), th, tidh, hlog2, shift, lmask);
+            const uint32_t b = bucket_of<TK>(user_hash<MODE>(kt[o]), th, tidh, hlog2, shift, lmask);
             bt[o] = (uint16_t)b;
             tally(b);
         }
@@ -965,10 +965,10 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
     for (uint32_t b = tid; b < nb; b += BS) row[b] = cnt[b] + ((finl[b] && lt == 0) ? 1u : 0u);
 }
 
-template <int MODE>
+template <int MODE, typename K = uint64_t>
 __global__ __launch_bounds__(1024) void k_count(LevelArgs a)
 {
-    count_item<MODE>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
+    count_item<MODE, K>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
 }
 
 // Work queue of a resident grid: the n items are split into eight contiguous
@@ -995,7 +995,7 @@ __global__ __launch_bounds__(1024) void k_count_ds(LevelArgs a)
     __shared__ uint32_t sh_t;
     const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
     for (uint32_t t = xcd_queue_next(a.q, n, &sh_t); t < n; t = xcd_queue_next(a.q, n, &sh_t))
-        count_item<MODE>(a, t, ns, tile);
+        count_item<MODE, uint64_t>(a, t, ns, tile);
 }
 
 // ================================================================ semisort_<
@@ -1078,6 +1078,7 @@ __device__ __forceinline__ uint32_t less_bucket_lut(uint64_t k, const uint64_t* 
     return rid[j] & 0x7FFFu;
 }
 
+template <typename K = uint64_t>
 __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
 {
     constexpr int BS = 1024;
@@ -1105,11 +1106,11 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
     const uint32_t s = sh_s, tau = sh_tau;
     uint32_t P = 2;
     while (P < s) P <<= 1;
-    if (P == 16 * BS) sample_sort_keys<BS, 16>(a, sg, s, P, smp);
-    else if (P == 8 * BS) sample_sort_keys<BS, 8>(a, sg, s, P, smp);
-    else if (P == 4 * BS) sample_sort_keys<BS, 4>(a, sg, s, P, smp);
-    else if (P == 2 * BS) sample_sort_keys<BS, 2>(a, sg, s, P, smp);
-    else sample_sort_keys<BS, 1>(a, sg, s, P, smp);
+    if (P == 16 * BS) sample_sort_keys<BS, 16, K>(a, sg, s, P, smp);
+    else if (P == 8 * BS) sample_sort_keys<BS, 8, K>(a, sg, s, P, smp);
+    else if (P == 4 * BS) sample_sort_keys<BS, 4, K>(a, sg, s, P, smp);
+    else if (P == 2 * BS) sample_sort_keys<BS, 2, K>(a, sg, s, P, smp);
+    else sample_sort_keys<BS, 1, K>(a, sg, s, P, smp);
     // heavy keys in ascending key order; per sample: heavy or not, and the
     // rank of the non-heavy ones
     const uint32_t per = (s + BS - 1) / BS;
@@ -1257,6 +1258,7 @@ __global__ __launch_bounds__(1024) void k_sample_less(LevelArgs a)
 }
 
 // Counting pass for splitter buckets: binary search over the boundaries in LDS.
+template <typename K = uint64_t>
 __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
 {
     constexpr int BS = 1024;
@@ -1294,7 +1296,7 @@ __global__ __launch_bounds__(1024) void k_count_less(LevelArgs a)
     }
     __syncthreads();
     constexpr int U = 8;
-    const uint64_t* kt = a.src_keys + r0;
+    const K* kt = (const K*)a.src_keys + r0;
     uint16_t* bt = a.bids + r0;
     const uint32_t len = (uint32_t)(r1 - r0);
     uint32_t o = tid;
@@ -1487,7 +1489,7 @@ __device__ __forceinline__ bool bucket_is_final(bool one_key_bucket, uint32_t sz
 // RED = 0: semisort; RED = 1: collect-reduce (heavy records are summed in
 // LDS and added to the subproblem's heavy sums, light records move); RED = 2:
 // histogram (as 1 with every value 1 and no value array).
-template <typename V, int W, int E, int RED>
+template <typename V, int W, int E, int RED, typename K>
 __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, uint32_t nsegs, uint32_t tile)
 {
     // Every global load and store in the sub-tile loop is issued
@@ -1548,7 +1550,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     // keys and bucket ids are loaded one sub-tile ahead; values at the top of
     // their own iteration (needed only after the ranking)
     const uint32_t lofs = w * 64 * E + lane;  // this lane's first offset in a sub-tile
-    uint64_t* sink_k = a.sink + lane;
+    K* sink_k = (K*)(a.sink + lane);
     V* sink_v = (V*)(a.sink + lane);
     const uint64_t kdiff = (uint64_t)a.fin_keys - (uint64_t)a.dst_keys;
     const uint64_t vdiff = (uint64_t)fin_vals - (uint64_t)dst_vals;
@@ -1571,7 +1573,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     if (tid == 0) sh_bad = 0;
     __syncthreads();
     {
-        const uint64_t* ks = a.src_keys + r0;
+        const K* ks = (const K*)a.src_keys + r0;
         const uint32_t lim = (uint32_t)(rlast - r0 < SUB ? rlast - r0 : SUB);
 #pragma unroll
         for (int e = 0; e < E; ++e) kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + e * 64u, lim));
@@ -1619,7 +1621,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
         }
         wave_rank_all<E>(bk, mv, nbits, wcw, pos);
         {
-            const uint64_t* ks = a.src_keys + sub;
+            const K* ks = (const K*)a.src_keys + sub;
 #pragma unroll
             for (int e = 0; e < E; ++e)
                 kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + SUB + e * 64u, left - 1));
@@ -1693,9 +1695,9 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
             uint32_t msk = (uint32_t)((int32_t)x >> 31);
             __asm__("" : "+v"(msk));
             const uint64_t sel = ((uint64_t)msk << 32) | msk;
-            uint64_t* out = (uint64_t*)((char*)a.dst_keys + (kdiff & sel)) + d;
+            K* out = (K*)((char*)a.dst_keys + (kdiff & sel)) + d;
             // bit 15: the key is not stored (one-key bucket, filled later)
-            *(j < m && !(sb >> 15) ? out : sink_k) = stage[jj];
+            *(j < m && !(sb >> 15) ? out : sink_k) = (K)stage[jj];
         }
         for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
         __syncthreads();
@@ -1730,10 +1732,10 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     if (out_of_range) atomicOr(&a.info->status, kStatusScatterRange);
 }
 
-template <typename V, int W, int E, int RED>
+template <typename V, int W, int E, int RED, typename K = uint64_t>
 __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) void k_distribute(LevelArgs a)
 {
-    distribute_item<V, W, E, RED>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
+    distribute_item<V, W, E, RED, K>(a, xcd_remap(blockIdx.x, gridDim.x), a.nsegs, a.tile);
 }
 
 template <typename V, int W, int E, int RED>
@@ -1742,7 +1744,7 @@ __global__ __launch_bounds__(W * 64) __attribute__((amdgpu_waves_per_eu(4))) voi
     __shared__ uint32_t sh_t;
     const uint32_t ns = ds_nsegs(a), n = a.dims->tiles, tile = a.dims->tile;
     for (uint32_t t = xcd_queue_next(a.q + 8, n, &sh_t); t < n; t = xcd_queue_next(a.q + 8, n, &sh_t))
-        distribute_item<V, W, E, RED>(a, t, ns, tile);
+        distribute_item<V, W, E, RED, uint64_t>(a, t, ns, tile);
 }
 
 // Direct form of the distribution: the same stable ranking, but every record
@@ -2361,9 +2363,9 @@ __global__ void k_ds_finish(const LevelInfo* infos, uint32_t levels, uint32_t se
 //      occurrence, input order inside a group (stable).
 // Values never touch LDS; results are written straight from registers.
 
-template <int MODE, typename V, int W>
-__device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
-                                         const V* src_vals, uint64_t* out_keys, V* out_vals, uint64_t* sink,
+template <int MODE, typename V, int W, typename K = uint64_t>
+__device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t njobs, const K* src_keys,
+                                         const V* src_vals, K* out_keys, V* out_vals, uint64_t* sink,
                                          LevelInfo* info)
 {
     // Persistent: the grid holds as many blocks as fit on the device, each
@@ -2379,7 +2381,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
     const uint32_t lofs = w * 64 * E + lane;
-    uint64_t* sink_k = sink + lane;
+    K* sink_k = (K*)(sink + lane);
     V* sink_v = (V*)(sink + lane);
     uint32_t jb = blockIdx.x;
     if (jb >= njobs) return;
@@ -2390,7 +2392,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t i = min(lofs + e * 64u, jj.len - 1);  // len >= 2
-            kn[e] = src_keys[jj.start + i];
+            kn[e] = (uint64_t)src_keys[jj.start + i];
             vn[e] = src_vals[jj.start + i];
         }
     };
@@ -2504,7 +2506,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const bool ok = pp[e] != 0xFFFFFFFFu;
-            *(ok ? out_keys + start + pp[e] : sink_k) = k[e];
+            *(ok ? out_keys + start + pp[e] : sink_k) = (K)k[e];
             *(ok ? out_vals + start + pp[e] : sink_v) = v[e];
         }
         __syncthreads();  // the next job reuses the LDS
@@ -2512,12 +2514,12 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
 }
 
-template <int MODE, typename V, int W>
-__global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, uint32_t njobs, const uint64_t* src_keys,
-                                                 const V* src_vals, uint64_t* out_keys, V* out_vals,
+template <int MODE, typename V, int W, typename K = uint64_t>
+__global__ __launch_bounds__(W * 64) void k_base(const Job* __restrict__ jobs, uint32_t njobs, const K* src_keys,
+                                                 const V* src_vals, K* out_keys, V* out_vals,
                                                  uint64_t* sink, LevelInfo* info)
 {
-    base_run<MODE, V, W>(jobs, njobs, src_keys, src_vals, out_keys, out_vals, sink, info);
+    base_run<MODE, V, W, K>(jobs, njobs, src_keys, src_vals, out_keys, out_vals, sink, info);
 }
 
 // Device-counted: the class's job count is read from *count (bounded by cap).
@@ -2535,9 +2537,9 @@ __global__ __launch_bounds__(W * 64) void k_base_ds(const Job* __restrict__ jobs
 // blocks fit on a CU.  Values are gathered from the source by index after the
 // sort (the bucket was just read, so the gather hits in L2); all reads finish
 // before the first write, so the output may be the source.
-template <int MODE, typename V>
-__device__ __forceinline__ void base_2pass_item(const Job j, const uint64_t* src_keys, const V* src_vals,
-                                                uint64_t* out_keys, V* out_vals, LevelInfo* info)
+template <int MODE, typename V, typename K = uint64_t>
+__device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, const V* src_vals,
+                                                K* out_keys, V* out_vals, LevelInfo* info)
 {
     constexpr int W = 8, BS = 512, E = 8, CAP = 4096;
     __shared__ uint64_t kl[CAP];
@@ -2556,7 +2558,7 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const uint64_t* src
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t i = w * 64 * E + e * 64 + lane;
-        k[e] = i < m ? src_keys[start + i] : 0ull;
+        k[e] = i < m ? (uint64_t)src_keys[start + i] : 0ull;
         if (i < m) kl[i] = k[e];
     }
     for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
@@ -2661,18 +2663,18 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const uint64_t* src
     for (int e = 0; e < E; ++e) {
         const uint32_t q = tid + e * BS;
         if (q < m) {
-            out_keys[start + q] = ok[e];
+            out_keys[start + q] = (K)ok[e];
             out_vals[start + q] = ov[e];
         }
     }
     if (bad) atomicOr(&info->status, kStatusBaseIndex);
 }
 
-template <int MODE, typename V>
-__global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                                    uint64_t* out_keys, V* out_vals, LevelInfo* info)
+template <int MODE, typename V, typename K = uint64_t>
+__global__ __launch_bounds__(512) void k_base_2pass(const Job* jobs, const K* src_keys, const V* src_vals,
+                                                    K* out_keys, V* out_vals, LevelInfo* info)
 {
-    base_2pass_item<MODE, V>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals, info);
+    base_2pass_item<MODE, V, K>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals, info);
 }
 
 template <int MODE, typename V>
@@ -2720,9 +2722,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 // are sorted, 8 bits per pass, each pass a stable multisplit (ballot match
 // plus per-wave counters).  All loads precede all stores, so the output may
 // be the source.
-template <typename V, int W>
-__global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                                      uint64_t* out_keys, V* out_vals)
+template <typename V, int W, typename K = uint64_t>
+__global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const K* src_keys, const V* src_vals,
+                                                      K* out_keys, V* out_vals)
 {
     constexpr int BS = W * 64, E = 8, CAP = BS * E;
     __shared__ uint64_t sk[CAP];
@@ -2742,7 +2744,7 @@ __global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uin
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t q = w * 64 * E + e * 64 + lane;
-        k[e] = q < m ? src_keys[start + q] : 0ull;
+        k[e] = q < m ? (uint64_t)src_keys[start + q] : 0ull;
         v[e] = q < m ? src_vals[start + q] : (V)0;
         if (q < m) {
             mn = k[e] < mn ? k[e] : mn;
@@ -2838,16 +2840,16 @@ __global__ __launch_bounds__(W * 64) void k_base_less(const Job* jobs, const uin
     for (int e = 0; e < E; ++e) {
         const uint32_t q = w * 64 * E + e * 64 + lane;
         if (q < m) {
-            out_keys[start + q] = k[e];
+            out_keys[start + q] = (K)k[e];
             out_vals[start + q] = v[e];
         }
     }
 }
 
 // Copy jobs: buckets that are final but sit in T (Section 3.4).
-template <typename V>
-__device__ __forceinline__ void copy_item(const Job j, const uint64_t* src_keys, const V* src_vals,
-                                          uint64_t* out_keys, V* out_vals)
+template <typename V, typename K = uint64_t>
+__device__ __forceinline__ void copy_item(const Job j, const K* src_keys, const V* src_vals,
+                                          K* out_keys, V* out_vals)
 {
     const uint64_t st = j.start;
     for (uint32_t i = threadIdx.x; i < j.len; i += 256) {
@@ -2856,11 +2858,11 @@ __device__ __forceinline__ void copy_item(const Job j, const uint64_t* src_keys,
     }
 }
 
-template <typename V>
-__global__ __launch_bounds__(256) void k_copy(const Job* jobs, const uint64_t* src_keys, const V* src_vals,
-                                              uint64_t* out_keys, V* out_vals)
+template <typename V, typename K = uint64_t>
+__global__ __launch_bounds__(256) void k_copy(const Job* jobs, const K* src_keys, const V* src_vals,
+                                              K* out_keys, V* out_vals)
 {
-    copy_item<V>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals);
+    copy_item<V, K>(jobs[blockIdx.x], src_keys, src_vals, out_keys, out_vals);
 }
 
 template <typename V>
@@ -2873,24 +2875,31 @@ __global__ __launch_bounds__(256) void k_copy_ds(const Job* jobs, const uint32_t
 }
 
 // Key-fill jobs: the keys of a one-key bucket are one value repeated.
-// 16-byte stores after an odd first element, if any.
-__device__ __forceinline__ void fill_item(const FillJob j, uint64_t* out_keys)
+// 16-byte stores between a head and a tail of fewer than 16 bytes each
+// (keys are aligned to their size).
+template <typename K = uint64_t>
+__device__ __forceinline__ void fill_item(const FillJob j, K* out_keys)
 {
-    uint64_t* o = out_keys + j.start;
-    const uint32_t head = (((uintptr_t)o & 8u) && j.len) ? 1u : 0u;  // keys are 8-byte aligned
-    const uint32_t n2 = (j.len - head) / 2;
-    if (threadIdx.x == 0) {
-        if (head) o[0] = j.key;
-        if ((j.len - head) & 1u) o[j.len - 1] = j.key;
-    }
-    ulonglong2* o2 = (ulonglong2*)(o + head);
-    const ulonglong2 kk = make_ulonglong2(j.key, j.key);
-    for (uint32_t i = threadIdx.x; i < n2; i += 1024) o2[i] = kk;
+    constexpr uint32_t P = 16 / sizeof(K);  // keys per 16-byte store
+    K* o = out_keys + j.start;
+    const K key = (K)j.key;
+    const uint32_t mis = (uint32_t)(((uintptr_t)o & 15u) / sizeof(K));
+    const uint32_t head = mis ? (P - mis < j.len ? P - mis : j.len) : 0u;
+    const uint32_t n4 = (j.len - head) / P;
+    const uint32_t tail = head + n4 * P;
+    if (threadIdx.x < head) o[threadIdx.x] = key;
+    if (threadIdx.x < j.len - tail) o[tail + threadIdx.x] = key;
+    const uint32_t lo = (uint32_t)(uint64_t)key;
+    const uint32_t hi = sizeof(K) == 8 ? (uint32_t)((uint64_t)key >> 32) : lo;
+    const uint4 kk = make_uint4(lo, hi, lo, hi);
+    uint4* o4 = (uint4*)(o + head);
+    for (uint32_t i = threadIdx.x; i < n4; i += 1024) o4[i] = kk;
 }
 
-__global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, uint64_t* out_keys)
+template <typename K = uint64_t>
+__global__ __launch_bounds__(1024) void k_fill(const FillJob* jobs, K* out_keys)
 {
-    fill_item(jobs[blockIdx.x], out_keys);
+    fill_item<K>(jobs[blockIdx.x], out_keys);
 }
 
 // Device-counted: the level's fill-job count is read from *count (bounded by cap).

@@ -78,6 +78,8 @@ def lib():
         L.ss_semisort_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
         L.ss_semisort_equal_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_semisort_less.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
+        L.ss_semisort_equal_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
+        L.ss_semisort_less_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
         L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
         L.ss_collect_reduce.argtypes = [vp, vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
@@ -201,12 +203,14 @@ def sync(device=0):
     context(device).sync()
 
 
-def _check_kv(keys, vals):
+def _check_kv(keys, vals, allow_k32=False):
     import torch
     if not (keys.is_cuda and vals.is_cuda):
         raise ValueError("keys and vals must be device tensors")
-    if keys.dtype != torch.int64 or vals.dtype not in (torch.int64, torch.int32):
-        raise ValueError("keys must be int64 (uint64 bits), vals int64 or int32 (uint bits)")
+    kd = (torch.int64, torch.int32) if allow_k32 else (torch.int64,)
+    if keys.dtype not in kd or vals.dtype not in (torch.int64, torch.int32):
+        raise ValueError("keys must be int64 (uint64 bits)" + (" or int32 (uint32 bits)" if allow_k32 else "") +
+                         ", vals int64 or int32 (uint bits)")
     if keys.dim() != 1 or vals.shape != keys.shape or not keys.is_contiguous() or not vals.is_contiguous():
         raise ValueError("keys and vals must be contiguous 1-D tensors of equal length")
     return vals.element_size()
@@ -216,34 +220,36 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def semisort_equal(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
-    """ss_semisort_equal: equal keys contiguous, stable.  Returns (keys_out, vals_out)."""
+def _semisort(less, keys, vals, keys_out, vals_out, params, ctx):
     import torch
-    vb = _check_kv(keys, vals)
+    vb = _check_kv(keys, vals, allow_k32=True)
+    kb = keys.element_size()  # 4: ss_semisort_*_keys with 32-bit keys
     ctx = ctx or context(keys.device.index or 0)
     ctx._bind_stream()
     if keys_out is None:
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
-    ctx.check(lib().ss_semisort_equal(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out),
-                                      _ptr(vals_out), ctypes.byref(params) if params is not None else None))
+    pp = ctypes.byref(params) if params is not None else None
+    if kb == 4:
+        fn = lib().ss_semisort_less_keys if less else lib().ss_semisort_equal_keys
+        ctx.check(fn(ctx.h, _ptr(keys), 4, _ptr(vals), vb, keys.numel(), _ptr(keys_out), _ptr(vals_out), pp))
+    else:
+        fn = lib().ss_semisort_less if less else lib().ss_semisort_equal
+        ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out), _ptr(vals_out), pp))
     return keys_out, vals_out
+
+
+def semisort_equal(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
+    """ss_semisort_equal: equal keys contiguous, stable.  Returns (keys_out, vals_out).
+    keys: int64 (uint64 bits) or int32 (uint32 bits: ss_semisort_equal_keys)."""
+    return _semisort(False, keys, vals, keys_out, vals_out, params, ctx)
 
 
 def semisort_less(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
-    """ss_semisort_less: ascending keys, stable.  Returns (keys_out, vals_out)."""
-    import torch
-    vb = _check_kv(keys, vals)
-    ctx = ctx or context(keys.device.index or 0)
-    ctx._bind_stream()
-    if keys_out is None:
-        keys_out = torch.empty_like(keys)
-    if vals_out is None:
-        vals_out = torch.empty_like(vals)
-    ctx.check(lib().ss_semisort_less(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out),
-                                     _ptr(vals_out), ctypes.byref(params) if params is not None else None))
-    return keys_out, vals_out
+    """ss_semisort_less: ascending keys, stable.  Returns (keys_out, vals_out).
+    keys: int64 (uint64 bits) or int32 (uint32 bits: ss_semisort_less_keys)."""
+    return _semisort(True, keys, vals, keys_out, vals_out, params, ctx)
 
 
 def semisort_less_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, params=None, ctx=None):

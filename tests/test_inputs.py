@@ -141,3 +141,18 @@ def test_graph_generators_are_valid_csr_and_agree_across_back_ends():
     rows = np.repeat(np.arange(1000), np.diff(offs.astype(np.int64)))
     d = (cols.astype(np.int64) - rows) % 1000
     assert np.all((d <= I.KNN_WIDTH) | (d >= 1000 - I.KNN_WIDTH))
+
+
+def test_32bit_key_workloads():
+    # uint32 keys; the 32-bit mixer is a bijection (no two ranks collide), and
+    # the numpy and torch back ends give the same bits
+    import torch
+    for name in ("zipf1.2_hashed_k32", "uniform1e9_k32", "exp1e-5_k32_u32idx"):
+        k, v = I.np_workload(name, 100_000, 3)
+        assert k.dtype == np.uint32 and I.key_bytes(name) == 4
+        tk, tv = I.t_workload(name, 100_000, 3, "cpu")
+        assert np.array_equal(k, tk.numpy().view(np.uint32))
+    x = np.arange(1 << 20, dtype=np.uint32) * np.uint32(2654435761)
+    assert np.unique(I.np_fmix32(x)).size == x.size
+    z = I.np_zipf(200_000, 1.2, 10 ** 9, 3, 0)
+    assert np.unique(I.np_fmix32(z.astype(np.uint32))).size == np.unique(z).size

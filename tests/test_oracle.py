@@ -506,3 +506,28 @@ def test_transpose_csr_rejects_an_invalid_graph():
         O.transpose_csr(np.array([0, 2], dtype=np.uint64), np.array([0, 1], dtype=np.uint32))  # target >= nv
     with pytest.raises(ValueError):
         O.transpose_csr(np.array([0, 3, 2], dtype=np.uint64), np.array([0, 1], dtype=np.uint32))
+
+
+def test_oracle_on_32bit_extremes_exhaustive():
+    # 32-bit keys are zero-extended for the oracle: every sequence of length
+    # <= 6 over the uint32 extremes gives a stable grouping (semisort_=) and a
+    # stable sort (semisort_<, against numpy's stable argsort)
+    import itertools
+    ext = [0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFF]
+    for n in range(0, 7):
+        for seq in itertools.product(ext, repeat=n) if n <= 4 else [tuple(np.random.default_rng(n).choice(ext, n))]:
+            k = np.array(seq, dtype=np.uint32).astype(np.uint64)
+            v = np.arange(n, dtype=np.uint64)
+            ok, ov = O.semisort_equal(k, v)
+            assert sorted(ov.tolist()) == list(range(n))
+            assert np.array_equal(k[ov], ok)
+            seen = set()
+            for i in range(n):
+                if i == 0 or ok[i] != ok[i - 1]:
+                    assert int(ok[i]) not in seen
+                    seen.add(int(ok[i]))
+                else:
+                    assert ov[i] > ov[i - 1]
+            lk, lv = O.semisort_less(k, v)
+            o = np.argsort(k, kind="stable")
+            assert np.array_equal(lk, k[o]) and np.array_equal(lv, v[o])
