@@ -23,7 +23,7 @@ PAPER_GRECS = {"zipf1.2_hashed": 1.0 / 0.770}  # Table 3, Ours_= on Zipf-1.2, n 
 METRIC = "Grecords/s semisort_= 1e9 kv pairs, % HBM roofline; batched vs per-instance"
 # seeds of the 10^9-record workloads (the full-size tests check these inputs)
 CONFIG_SEEDS = {"uniform1e9": 2, "uniform1e3": 3, "zipf1.2_hashed": 4, "exp1e-5_u32idx": 5,
-                "zipf0.8_1e8_u32idx": 6}
+                "zipf0.8_1e8_u32idx": 6, "zipf1.2_hashed_k32": 7, "exp1e-5_k32_u32idx": 8}
 
 
 def log(*a):
@@ -88,7 +88,7 @@ def profile_op(args, S, I, torch):
     """--profile-op: only `warmup + steps` calls of one operation on one
     workload, then the calibration copy -- the program that rocprofv3 counter
     runs of the other configurations profile."""
-    keys, vals = I.t_workload(args.workload, args.n, args.seed, "cuda")
+    keys, vals = I.t_workload(args.workload, args.n, CONFIG_SEEDS.get(args.workload, args.seed), "cuda")
     torch.cuda.synchronize()
     out = None
     if args.profile_op in ("semisort_=", "semisort_<"):
@@ -138,8 +138,10 @@ def other_configs(args, S, I, torch):
     the full-size tests check): semisort_= and collect-reduce on uniform[0, 1e9), uniform[0, 1e3)
     and Zipf-1.2 (u64 keys and values; also the min monoid on uniform[0, 1e9)
     and the max and affine monoids on Zipf-1.2), semisort_< and histogram on
-    exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values).  Whole-job
-    HBM fraction from the algorithmic bytes per record: semisort K + 2R +
+    exponential(1e-5) and Zipf-0.8 over [1, 1e8] (u32 index values), and with
+    32-bit keys and 32-bit values semisort_= on Zipf-1.2 and semisort_< on
+    exponential(1e-5).  Whole-job HBM fraction from the algorithmic bytes per
+    record (K key bytes, R record bytes): semisort K + 2R +
     2R f_L; collect-reduce K + R + 2R f_L + 16 m/n; ordered histogram 2K +
     2K f_L + 16 m/n + 32 m/n (the m pairs read and written once more to order
     them), with f_H the records whose key occurs more than 500 ln n times."""
@@ -149,7 +151,9 @@ def other_configs(args, S, I, torch):
              ("uniform1e3", ("semisort_=", "collect_reduce")),
              ("zipf1.2_hashed", ("collect_reduce", "collect_reduce_max", "collect_reduce_affine")),
              ("exp1e-5_u32idx", ("semisort_<", "histogram_ordered")),
-             ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram_ordered"))]
+             ("zipf0.8_1e8_u32idx", ("semisort_<", "histogram_ordered")),
+             ("zipf1.2_hashed_k32", ("semisort_=",)),
+             ("exp1e-5_k32_u32idx", ("semisort_<",))]
     for wl, ops in cases:
         keys, vals = I.t_workload(wl, n, CONFIG_SEEDS[wl], "cuda")
         _, counts = torch.unique(keys, return_counts=True)
@@ -157,11 +161,12 @@ def other_configs(args, S, I, torch):
         m = int(counts.numel())
         del counts
         torch.cuda.empty_cache()
-        R = 8 + vals.element_size()
+        K = keys.element_size()
+        R = K + vals.element_size()
         for op in ops:
             fn = lambda op=op: run_op(S, op, keys, vals, torch)  # noqa: E731
             if op in ("semisort_=", "semisort_<"):
-                b = 8 + 2 * R + 2 * R * (1 - f_h)
+                b = K + 2 * R + 2 * R * (1 - f_h)
             elif op.startswith("collect_reduce"):
                 b = 8 + 16 + 32 * (1 - f_h) + 16.0 * m / n
                 if op.endswith("affine"):  # semisort_=, two reads of the grouped records, flags, results

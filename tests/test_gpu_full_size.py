@@ -58,9 +58,9 @@ def _check_grouping(keys, ko, vo, ordered, samples=24, seed=0):
     assert bool(torch.equal(ko, keys[vo64])), "a record lost its key"
     same = ko[1:] == ko[:-1]
     if ordered:
-        # ascending keys (as unsigned 64-bit words)
-        a = ko[:-1] ^ torch.iinfo(torch.int64).min
-        b = ko[1:] ^ torch.iinfo(torch.int64).min
+        # ascending keys (as unsigned words of the key's width)
+        a = ko[:-1] ^ torch.iinfo(ko.dtype).min
+        b = ko[1:] ^ torch.iinfo(ko.dtype).min
         assert bool((a <= b).all()), "keys are not in ascending order"
     # contiguity: the keys that start runs are all different
     starts = torch.ones(N, dtype=torch.bool, device="cuda")
@@ -208,6 +208,24 @@ def test_full_size_semisort_less_zipf08_u32_values():
     ko, vo = S.semisort_less(keys, vals)
     S.sync()
     _check_grouping(keys, ko, vo, ordered=True, seed=5)
+
+
+def test_full_size_semisort_equal_zipf12_32bit_keys():
+    keys, vals = _indexed("zipf1.2_hashed_k32", 7)
+    assert keys.dtype == torch.int32 and vals.dtype == torch.int32
+    _say("case: semisort_= zipf1.2_hashed n=1e9, 32-bit keys and values")
+    ko, vo = S.semisort_equal(keys, vals)
+    S.sync()
+    _check_grouping(keys, ko, vo, ordered=False, seed=7)
+
+
+def test_full_size_semisort_less_exponential_32bit_keys():
+    keys, vals = _indexed("exp1e-5_k32_u32idx", 8)
+    assert keys.dtype == torch.int32 and vals.dtype == torch.int32
+    _say("case: semisort_< exp(1e-5) n=1e9, 32-bit keys and values")
+    ko, vo = S.semisort_less(keys, vals)
+    S.sync()
+    _check_grouping(keys, ko, vo, ordered=True, seed=8)
 
 
 def test_full_size_histogram_exponential():
