@@ -40,6 +40,10 @@ def lib():
         L.orc_transpose_csr.argtypes = [u64, u64, vp, vp, vp, vp]
         L.orc_collect_reduce_monoid.restype = i64
         L.orc_collect_reduce_monoid.argtypes = [vp, vp, u64, ctypes.c_int, vp, vp]
+        L.orc_semisort_equal_wide.restype = i32
+        L.orc_semisort_equal_wide.argtypes = [vp, vp, u32, u64, vp, vp]
+        L.orc_canonicalize_equal_wide.restype = i64
+        L.orc_canonicalize_equal_wide.argtypes = [vp, vp, u32, u64, vp, vp]
         L.orc_canonicalize_equal.restype = i64
         L.orc_canonicalize_equal.argtypes = [vp, vp, u32, u64, i32, vp, vp]
         L.orc_stats.restype = i32
@@ -164,6 +168,38 @@ def canonicalize_equal(keys, vals, hash_mode=HASH_MIX64):
     bad = lib().orc_canonicalize_equal(_p(keys), _p(vals), vb, keys.size, hash_mode, _p(ck), _p(cv))
     if bad == -2:
         raise MemoryError("oracle canonicalize")
+    return int(bad), ck, cv
+
+
+def _wide(keys):
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    if k.ndim != 2 or k.shape[1] != 2:
+        raise ValueError("128-bit keys are an (n, 2) uint64 array of (low, high) words")
+    return k
+
+
+def semisort_equal_wide(keys, vals):
+    """Stable semisort of 128-bit keys ((n, 2) uint64: low, high words), groups
+    in ascending key order."""
+    keys = _wide(keys)
+    vals, vb = _vals(vals)
+    ko = np.empty_like(keys)
+    vo = np.empty_like(vals)
+    if lib().orc_semisort_equal_wide(_p(keys), _p(vals), vb, keys.shape[0], _p(ko), _p(vo)) != 0:
+        raise MemoryError("oracle semisort_equal_wide")
+    return ko, vo
+
+
+def canonicalize_equal_wide(keys, vals):
+    """Returns (bad, canon_keys, canon_vals) for 128-bit keys; bad == -1 when
+    equal keys are contiguous."""
+    keys = _wide(keys)
+    vals, vb = _vals(vals)
+    ck = np.empty_like(keys)
+    cv = np.empty_like(vals)
+    bad = lib().orc_canonicalize_equal_wide(_p(keys), _p(vals), vb, keys.shape[0], _p(ck), _p(cv))
+    if bad == -2:
+        raise MemoryError("oracle canonicalize_equal_wide")
     return int(bad), ck, cv
 
 

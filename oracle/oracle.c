@@ -371,6 +371,105 @@ int64_t orc_canonicalize_equal(const uint64_t* keys, const void* vals, uint32_t 
     return -1;
 }
 
+/* ---- 128-bit keys ------------------------------------------------------ */
+/* Section 2.1 takes keys of any type with an equality test.  A 128-bit key j
+ * is the pair (keys[2j], keys[2j + 1]) = (low word, high word); two keys are
+ * equal when both words are. */
+
+typedef struct { uint64_t hi, lo, i; } wki_t;
+
+static int cmp_wki(const void* a, const void* b)
+{
+    const wki_t* x = (const wki_t*)a;
+    const wki_t* y = (const wki_t*)b;
+    if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+    if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    return 0;
+}
+
+int orc_semisort_equal_wide(const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
+                            uint64_t* keys_out, void* vals_out)
+{
+    /* Sorting by (key as a 128-bit unsigned number, i) puts equal keys
+     * together, keeps their input order (stability) and orders the groups by
+     * key, so the result is unique. */
+    if (n == 0) return 0;
+    wki_t* t = (wki_t*)malloc(n * sizeof(wki_t));
+    if (!t) return -1;
+    for (uint64_t i = 0; i < n; i++) {
+        t[i].lo = keys[2 * i];
+        t[i].hi = keys[2 * i + 1];
+        t[i].i = i;
+    }
+    qsort(t, n, sizeof(wki_t), cmp_wki);
+    for (uint64_t p = 0; p < n; p++) {
+        keys_out[2 * p] = keys[2 * t[p].i];
+        keys_out[2 * p + 1] = keys[2 * t[p].i + 1];
+        store_val(vals_out, vb, p, load_val(vals, vb, t[p].i));
+    }
+    free(t);
+    return 0;
+}
+
+typedef struct { uint64_t hi, lo, start, len; } wrun_t;
+
+static int cmp_wrun(const void* a, const void* b)
+{
+    const wrun_t* x = (const wrun_t*)a;
+    const wrun_t* y = (const wrun_t*)b;
+    if (x->hi != y->hi) return x->hi < y->hi ? -1 : 1;
+    if (x->lo != y->lo) return x->lo < y->lo ? -1 : 1;
+    if (x->start != y->start) return x->start < y->start ? -1 : 1;
+    return 0;
+}
+
+int64_t orc_canonicalize_equal_wide(const uint64_t* keys, const void* vals, uint32_t vb, uint64_t n,
+                                    uint64_t* canon_keys, void* canon_vals)
+{
+    if (n == 0) return -1;
+    uint64_t nruns = 1;
+    for (uint64_t p = 1; p < n; p++)
+        if (keys[2 * p] != keys[2 * p - 2] || keys[2 * p + 1] != keys[2 * p - 1]) nruns++;
+    wrun_t* r = (wrun_t*)malloc(nruns * sizeof(wrun_t));
+    if (!r) return -2;
+    uint64_t j = 0, p = 0;
+    while (p < n) {
+        uint64_t q = p;
+        while (q < n && keys[2 * q] == keys[2 * p] && keys[2 * q + 1] == keys[2 * p + 1]) q++;
+        r[j].lo = keys[2 * p];
+        r[j].hi = keys[2 * p + 1];
+        r[j].start = p;
+        r[j].len = q - p;
+        j++;
+        p = q;
+    }
+    qsort(r, nruns, sizeof(wrun_t), cmp_wrun);
+    /* two runs of one key are neighbours after the sort; the later one is
+     * where contiguity broke */
+    int64_t bad = -1;
+    for (uint64_t x = 1; x < nruns; x++) {
+        if (r[x].lo == r[x - 1].lo && r[x].hi == r[x - 1].hi) {
+            if (bad < 0 || (int64_t)r[x].start < bad) bad = (int64_t)r[x].start;
+        }
+    }
+    if (bad >= 0) {
+        free(r);
+        return bad;
+    }
+    uint64_t o = 0;
+    for (uint64_t x = 0; x < nruns; x++) {
+        for (uint64_t y = 0; y < r[x].len; y++) {
+            canon_keys[2 * o] = keys[2 * (r[x].start + y)];
+            canon_keys[2 * o + 1] = keys[2 * (r[x].start + y) + 1];
+            store_val(canon_vals, vb, o, load_val(vals, vb, r[x].start + y));
+            o++;
+        }
+    }
+    free(r);
+    return -1;
+}
+
 int orc_stats(const uint64_t* keys, uint64_t n, double heavy_threshold,
               uint64_t* distinct, uint64_t* max_freq, uint64_t* heavy_records)
 {

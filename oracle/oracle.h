@@ -46,6 +46,19 @@ int orc_semisort_equal(const uint64_t* keys, const void* vals, uint32_t val_byte
 int orc_semisort_less(const uint64_t* keys, const void* vals, uint32_t val_bytes,
                       uint64_t n, uint64_t* keys_out, void* vals_out);
 
+/* semisort by equality of 128-bit keys (Section 2.1: any key type with an
+ * equality test).  keys holds 2n words, key j = (keys[2j] low, keys[2j + 1]
+ * high); keys_out likewise.  Canonical group order: ascending key as a 128-bit
+ * unsigned number.  Returns 0, or -1 when out of memory. */
+int orc_semisort_equal_wide(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                            uint64_t n, uint64_t* keys_out, void* vals_out);
+
+/* Canonical form of a candidate semisort of 128-bit keys: its runs reordered by
+ * ascending key.  Returns -1 when equal keys are contiguous, else the position
+ * of the first run whose key also occurs in another run; -2 when out of memory. */
+int64_t orc_canonicalize_equal_wide(const uint64_t* keys, const void* vals, uint32_t val_bytes,
+                                    uint64_t n, uint64_t* canon_keys, void* canon_vals);
+
 /* histogram: (unique key, occurrences), ascending keys.  Returns m or -1. */
 int64_t orc_histogram(const uint64_t* keys, uint64_t n, uint64_t* out_keys,
                       uint64_t* out_counts);

@@ -531,3 +531,96 @@ def test_oracle_on_32bit_extremes_exhaustive():
             lk, lv = O.semisort_less(k, v)
             o = np.argsort(k, kind="stable")
             assert np.array_equal(lk, k[o]) and np.array_equal(lv, v[o])
+
+
+# ---- 128-bit keys (Section 2.1: any key type with an equality test) ----------
+
+def _is_stable_grouping_wide(keys, vals, ok, ov):
+    """Brute-force definition for index values: a permutation of the input in
+    which every record kept its key, equal keys are contiguous, and records of
+    a key keep their input order."""
+    n = keys.shape[0]
+    if sorted(ov.tolist()) != list(range(n)):
+        return False
+    if not np.array_equal(keys[ov.astype(np.int64)], ok):
+        return False
+    seen = set()
+    for i in range(n):
+        k = (int(ok[i, 0]), int(ok[i, 1]))
+        if i == 0 or k != (int(ok[i - 1, 0]), int(ok[i - 1, 1])):
+            if k in seen:
+                return False
+            seen.add(k)
+        elif ov[i] <= ov[i - 1]:
+            return False
+    return True
+
+
+def test_wide_oracle_exhaustive_tiny():
+    # every sequence of up to 7 keys over four 128-bit keys that pairwise agree
+    # in one word (equal low or equal high word), so comparing one word only
+    # merges two keys and fails; the output is the unique stable grouping in
+    # ascending key order
+    alphabet = [(1, 0), (0, 1), (1, 1), (0, 0)]
+    for n in range(0, 8):
+        for seq in itertools.product(range(4), repeat=n):
+            k = np.array([alphabet[x] for x in seq], dtype=np.uint64).reshape(n, 2)
+            v = np.arange(n, dtype=np.uint64)
+            ok, ov = O.semisort_equal_wide(k, v)
+            assert _is_stable_grouping_wide(k, v, ok, ov), seq
+            as_int = [int(a) + (int(b) << 64) for a, b in ok.tolist()]
+            assert as_int == sorted(as_int), seq
+            bad, ck, cv = O.canonicalize_equal_wide(ok, ov)
+            assert bad == -1 and np.array_equal(ck, ok) and np.array_equal(cv, ov)
+
+
+def test_wide_oracle_reduces_to_a_stable_sort_of_either_word():
+    # with one word constant the result is a stable sort by the other word
+    # (numpy's stable argsort); u32 values move with their records
+    rng = np.random.default_rng(41)
+    n = 20_000
+    w = rng.integers(0, 300, n, dtype=np.uint64) * np.uint64(0x9E3779B97F4A7C15)
+    v = rng.integers(0, 2 ** 32, n, dtype=np.uint64).astype(np.uint32)
+    for lo_varies in (True, False):
+        k = np.zeros((n, 2), dtype=np.uint64)
+        k[:, 0 if lo_varies else 1] = w
+        k[:, 1 if lo_varies else 0] = 12345
+        ok, ov = O.semisort_equal_wide(k, v)
+        o = np.argsort(w, kind="stable")
+        assert np.array_equal(ok, k[o]) and np.array_equal(ov, v[o])
+
+
+def test_wide_oracle_groups_match_python_grouping():
+    # random keys drawn from few high and low words: the groups (as lists of
+    # input indices) equal those a Python dict builds in one pass
+    rng = np.random.default_rng(42)
+    n = 5_000
+    k = np.stack([rng.integers(0, 7, n, dtype=np.uint64), rng.integers(0, 5, n, dtype=np.uint64)], axis=1)
+    v = np.arange(n, dtype=np.uint64)
+    ok, ov = O.semisort_equal_wide(k, v)
+    groups = {}
+    for i, (a, b) in enumerate(k.tolist()):
+        groups.setdefault((b, a), []).append(i)
+    want = [i for key in sorted(groups) for i in groups[key]]
+    assert ov.tolist() == want
+
+
+def test_wide_canonicalizer_detects_split_runs_and_restores_order():
+    a, b, c = (5, 9), (5, 10), (6, 9)  # a and b differ in the high word only, a and c in the low word only
+    for seq, bad_at in (([a, b, a], 2), ([a, c, a], 2), ([b, b, a, c, b], 4), ([a, a, b, c], -1)):
+        k = np.array(seq, dtype=np.uint64)
+        v = np.arange(len(seq), dtype=np.uint64)
+        bad, _, _ = O.canonicalize_equal_wide(k, v)
+        assert bad == bad_at, seq
+    # any order of the groups of a valid result canonicalizes to the oracle's
+    rng = np.random.default_rng(43)
+    n = 3000
+    k = np.stack([rng.integers(0, 4, n, dtype=np.uint64), rng.integers(0, 4, n, dtype=np.uint64)], axis=1)
+    v = np.arange(n, dtype=np.uint64)
+    ok, ov = O.semisort_equal_wide(k, v)
+    starts = [0] + [i for i in range(1, n) if tuple(ok[i]) != tuple(ok[i - 1])] + [n]
+    runs = [list(range(starts[j], starts[j + 1])) for j in range(len(starts) - 1)]
+    rng.shuffle(runs)
+    perm = np.array([i for r in runs for i in r])
+    bad, ck, cv = O.canonicalize_equal_wide(ok[perm], ov[perm])
+    assert bad == -1 and np.array_equal(ck, ok) and np.array_equal(cv, ov)
