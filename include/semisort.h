@@ -181,15 +181,28 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
                             void* vals_out, const ss_params* params);
 
 /* semisort_= and semisort_< (as ss_semisort_equal / ss_semisort_less) with
- * keys of key_bytes = 4 or 8 bytes (Section 2.1 defines the problem for any
- * key type; Section 4.1 and the key-length study of Section 5 compare key
- * widths): keys[n] and keys_out[n] hold key_bytes-wide unsigned integers.
- * 32-bit records move 4 bytes less per key through every pass.  A 32-bit
- * key is hashed as its zero-extended 64-bit value, so SS_HASH_MIX64 stays a
- * bijection and the result equals the 64-bit call's on the zero-extended
- * keys.  SS_EINVAL for another key_bytes; otherwise the arguments,
- * conventions and errors of the 64-bit calls (in place: keys_out == keys
- * and vals_out == vals). */
+ * keys of key_bytes bytes (Section 2.1 defines the problem for any key type
+ * with an equality test; Section 4.1 and the key-length study of Section 5
+ * compare 32-, 64- and 128-bit keys): keys[n] and keys_out[n] hold
+ * key_bytes-wide keys.
+ *   4 or 8: unsigned integers.  A 32-bit key is hashed as its zero-extended
+ *     64-bit value, so SS_HASH_MIX64 stays a bijection and the result equals
+ *     the 64-bit call's on the zero-extended keys; its records move 4 bytes
+ *     less per key through every pass.
+ *   16 (semisort_= only): 128-bit keys, each two uint64 words, low word first,
+ *     compared for equality as whole keys; keys and keys_out 16-byte aligned.
+ *     SS_HASH_MIX64 hashes a key to 128 bits by a bijection (x = fmix64(low),
+ *     then fmix64(high ^ x)); SS_HASH_IDENTITY uses the words themselves, low
+ *     word first, which is slow when many keys share a low word (each level
+ *     then separates few of them until the high word is reached).  A heavy
+ *     bucket takes only records equal to one sampled key of its hash, so a
+ *     colliding 64-bit level hash sends other keys to the light buckets.
+ *     Workspace: beyond what ss_workspace_bytes reports for 8-byte keys, 8
+ *     bytes more per record (temporary keys of 16 bytes) and 8 KB per
+ *     subproblem of a level (the sampled key of every heavy id).
+ * SS_EINVAL for another key_bytes, 16 with semisort_<, or a misaligned
+ * 16-byte key array; otherwise the arguments, conventions and errors of the
+ * 64-bit calls (in place: keys_out == keys and vals_out == vals). */
 ss_status ss_semisort_equal_keys(ss_ctx* ctx, const void* keys, uint32_t key_bytes, const void* vals,
                                  uint32_t val_bytes, uint64_t n, void* keys_out, void* vals_out,
                                  const ss_params* params);

@@ -26,6 +26,9 @@ using namespace ssd;
 
 namespace {
 
+// Stores of lanes without a record go to a sink of 64 lanes of the widest key.
+constexpr size_t kSinkBytes = 64 * 16;
+
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
@@ -76,6 +79,7 @@ struct ss_ctx {
     DevBuf C, P, tot, bstart, heavy_list, tab_h, tab_id, bids, sink, bfin;
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
     DevBuf bkey;                     // keys of one-key buckets
+    DevBuf hrep;                     // 128-bit keys: one sampled key per heavy id
     DevBuf top;                      // two most sampled heavy buckets per subproblem
     DevBuf fills[2];                 // key-fill job lists (alternating levels)
     uint32_t fill_cap[2] = {0, 0};
@@ -416,8 +420,13 @@ void launch_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, 
                  uint64_t* ok, void* ov, uint64_t records)
 {
     ProfScope ps(c, SS_PROF_FINISH, records);
-    if (mode == 2) launch_jobs_m<2, V, K>(c, njobs, cap, sk, sv, ok, ov);
-    else if (mode == 1) launch_jobs_m<1, V, K>(c, njobs, cap, sk, sv, ok, ov);
+    if constexpr (!kWide<K>) {
+        if (mode == 2) {
+            launch_jobs_m<2, V, K>(c, njobs, cap, sk, sv, ok, ov);
+            return;
+        }
+    }
+    if (mode == 1) launch_jobs_m<1, V, K>(c, njobs, cap, sk, sv, ok, ov);
     else launch_jobs_m<0, V, K>(c, njobs, cap, sk, sv, ok, ov);
 }
 
@@ -445,24 +454,30 @@ void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks
     }
     {
         ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
-        switch (sizeof(K) == 8 ? c->dist_variant : std::min(c->dist_variant, 1)) {
-        case 1:
-            hipLaunchKernelGGL((k_distribute<V, 8, 8, 0, K>), dim3(tiles), dim3(512), 0, c->stream, a);
-            break;
-        case 2:
-            hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 4>), dim3(tiles), dim3(512), 0, c->stream, a);
-            break;
-        case 3:
-            hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 6>), dim3(tiles), dim3(512), 0, c->stream, a);
-            break;
-        case 4:
-            hipLaunchKernelGGL((k_distribute_direct<V, 16, 8, 4>), dim3(tiles), dim3(1024), 0, c->stream, a);
-            break;
-        case 5:
-            hipLaunchKernelGGL((k_distribute_direct<V, 4, 16, 6>), dim3(tiles), dim3(256), 0, c->stream, a);
-            break;
-        default:
-            hipLaunchKernelGGL((k_distribute<V, 16, 8, 0, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        if constexpr (kWide<K>) {
+            // two registers per key: four records per thread keep the staged
+            // sub-tile at the LDS size of the 64-bit form
+            hipLaunchKernelGGL((k_distribute<V, 16, 4, 0, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        } else {
+            switch (sizeof(K) == 8 ? c->dist_variant : std::min(c->dist_variant, 1)) {
+            case 1:
+                hipLaunchKernelGGL((k_distribute<V, 8, 8, 0, K>), dim3(tiles), dim3(512), 0, c->stream, a);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 4>), dim3(tiles), dim3(512), 0, c->stream, a);
+                break;
+            case 3:
+                hipLaunchKernelGGL((k_distribute_direct<V, 8, 8, 6>), dim3(tiles), dim3(512), 0, c->stream, a);
+                break;
+            case 4:
+                hipLaunchKernelGGL((k_distribute_direct<V, 16, 8, 4>), dim3(tiles), dim3(1024), 0, c->stream, a);
+                break;
+            case 5:
+                hipLaunchKernelGGL((k_distribute_direct<V, 4, 16, 6>), dim3(tiles), dim3(256), 0, c->stream, a);
+                break;
+            default:
+                hipLaunchKernelGGL((k_distribute<V, 16, 8, 0, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+            }
         }
     }
 }
@@ -471,15 +486,21 @@ template <typename V, typename K = uint64_t>
 void launch_level_v(ss_ctx* c, uint32_t mode, const LevelArgs& a, uint32_t tiles, uint32_t chunks,
                     uint64_t records, int part = 0)
 {
-    if (mode == 2) launch_level<2, V, K>(c, a, tiles, chunks, records, part);
-    else if (mode == 1) launch_level<1, V, K>(c, a, tiles, chunks, records, part);
+    if constexpr (!kWide<K>) {
+        if (mode == 2) {
+            launch_level<2, V, K>(c, a, tiles, chunks, records, part);
+            return;
+        }
+    }
+    if (mode == 1) launch_level<1, V, K>(c, a, tiles, chunks, records, part);
     else launch_level<0, V, K>(c, a, tiles, chunks, records, part);
 }
 
 // Sizes a level needs: per-subproblem tables, counting matrix rows, chunk rows.
-ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunks)
+ss_status ensure_level(ss_ctx* c, uint32_t nsegs, uint32_t tiles, uint32_t chunks, bool wide = false)
 {
     ss_status s;
+    if (wide && (s = ensure(c, c->hrep, (size_t)nsegs * kHeavyMax * 16)) != SS_OK) return s;
     if ((s = ensure(c, c->C, (size_t)tiles * kNbStride * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->P, (size_t)std::max(chunks, 1u) * kNbStride * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->tot, (size_t)nsegs * kNbStride * 4)) != SS_OK) return s;
@@ -530,6 +551,7 @@ LevelArgs make_args(ss_ctx* c, const Params& p, uint32_t level, Seg* segs, uint3
     a.ordered = p.mode == 2;
     a.bfin = (uint8_t*)c->bfin.p;
     a.bkey = (uint64_t*)c->bkey.p;
+    a.hrep = (uint64_t*)c->hrep.p;
     a.top = (uint32_t*)c->top.p;
     a.fill_heavy = 0;
     a.reduce = 0;
@@ -586,7 +608,7 @@ ss_status ensure_jobs(ss_ctx* c, uint32_t per_class)
 // segs[cur] -> segs[cur ^ 1], job lists) and reads the level's counters back
 // to the host; grows the lists and plans again when they overflow.
 ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs, int cur, uint32_t* seg_cap,
-                     bool finals_in_out, bool reduce, bool fill, LevelInfo* out)
+                     bool finals_in_out, bool reduce, bool fill, LevelInfo* out, uint32_t hash_bits = 64)
 {
     ss_status s;
     const int fb = level & 1;  // fill list of this level
@@ -619,6 +641,7 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         pa.bkey = (const uint64_t*)c->bkey.p;
         pa.fills = (FillJob*)c->fills[fb].p;
         pa.fill_cap = c->fill_cap[fb];
+        pa.hash_bits = hash_bits;
         {
             ProfScope ps(c, SS_PROF_PLAN, nsegs);
             hipLaunchKernelGGL(k_plan, dim3(nsegs), dim3(256), 0, c->stream, pa);
@@ -706,7 +729,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     }
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
-    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, kSinkBytes)) != SS_OK) return s;
     uint32_t seg_cap = std::max<uint32_t>(nsegs, 1024);
     if ((s = ensure(c, c->segs[0], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
     if ((s = ensure(c, c->segs[1], (size_t)seg_cap * sizeof(Seg))) != SS_OK) return s;
@@ -782,14 +805,15 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
             fin_k = keys_out;
             fin_v = vals_out;
         }
-        if ((s = ensure_level(c, nsegs, tiles, chunks)) != SS_OK) return s;
+        if ((s = ensure_level(c, nsegs, tiles, chunks, kWide<K>)) != SS_OK) return s;
         if ((s = reset_counters(c)) != SS_OK) return s;
         LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, fin_k,
                                 fin_v);
         // one-key buckets written to the output: only their values move,
         // their keys are filled as constant runs on the second stream while
-        // the next level runs (the two touch disjoint ranges)
-        const bool fill = fin_k == keys_out;
+        // the next level runs (the two touch disjoint ranges).  128-bit keys
+        // move with their values.
+        const bool fill = !kWide<K> && fin_k == keys_out;
         const int fb = level & 1;
         a.fill_heavy = fill;
         if (level == 0 && p.auto_tiles && nsegs == 1 && p.mode != 2) {
@@ -831,9 +855,10 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         LevelInfo li;
-        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, fill, &li)) != SS_OK)
+        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, fill, &li,
+                            KeyTraits<K>::hash_bits)) != SS_OK)
             return s;
-        if (li.nfills) {
+        if constexpr (!kWide<K>) if (li.nfills) {
             if ((s = ensure_aux(c)) != SS_OK) return s;
             {
                 ProfScope ps(c, SS_PROF_FILL, li.fill_records, c->aux);
@@ -1372,7 +1397,7 @@ ss_status run_reduce_multi(ss_ctx* c, const uint64_t* keys, const uint64_t* vals
     if ((s = ensure(c, c->bcnt, (nchunk + nblk) * 4)) != SS_OK) return s;
     if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
-    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, kSinkBytes)) != SS_OK) return s;
     // first level: instances of at least alpha records are subproblems, the
     // others base-case jobs (sum jobs for single records)
     std::vector<Seg> first;
@@ -1505,7 +1530,7 @@ ss_status check_common(ss_ctx* c, const void* keys, const void* vals, uint32_t v
 {
     if (!c) return SS_EINVAL;
     if (vb != 4 && vb != 8) return fail(c, SS_EINVAL, "val_bytes must be 4 or 8");
-    if (kb != 4 && kb != 8) return fail(c, SS_EINVAL, "key_bytes must be 4 or 8");
+    if (kb != 4 && kb != 8 && kb != 16) return fail(c, SS_EINVAL, "key_bytes must be 4, 8 or 16");
     if (n >= (1ull << 31)) return fail(c, SS_EINVAL, "n must be below 2^31");
     if (n == 0) return SS_OK;
     if (!keys || !vals || !ko || !vo) return fail(c, SS_EINVAL, "null array pointer");
@@ -1556,7 +1581,7 @@ size_t workspace_bound(int op, uint64_t n, uint32_t vb, const Params& p)
     auto add = [&](uint64_t x) { b += (x + 255) & ~(uint64_t)255; };
     auto grow = [&](uint64_t x) { add(x + x / 2); };
     add(sizeof(LevelInfo));  // status word, held from ss_create
-    add(512);                // sink
+    add(kSinkBytes);         // sink
     add(n * 8);              // T: keys
     add(n * (reduce ? 8 : vb));  // T: values
     add(n * 2);              // bucket ids
@@ -1655,7 +1680,7 @@ ss_status ss_destroy(ss_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
-                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->top, &c->fills[0], &c->fills[1],
+                      &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->hrep, &c->top, &c->fills[0], &c->fills[1],
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
                       &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos,
                       &c->pk_k, &c->pk_v, &c->po_k, &c->po_v, &c->pack_tab, &c->pack_rank};
@@ -1796,10 +1821,14 @@ ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, u
                    : run_semisort<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
 }
 
-// semisort_= / semisort_< with keys of key_bytes (4 or 8) bytes.
+// semisort_= / semisort_< with keys of key_bytes bytes: 4 or 8, or 16 for
+// semisort_= (the two words of a 128-bit key, low word first, 16-byte aligned).
 static ss_status semisort_keys(ss_ctx* c, bool less, const void* keys, uint32_t kb, const void* vals, uint32_t vb,
                                uint64_t n, void* keys_out, void* vals_out, const ss_params* params)
 {
+    if (c && less && kb == 16) return fail(c, SS_EINVAL, "semisort_< takes keys of 4 or 8 bytes");
+    if (c && kb == 16 && (((uintptr_t)keys | (uintptr_t)keys_out) & 15u))
+        return fail(c, SS_EINVAL, "16-byte keys must be 16-byte aligned");
     ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true, kb);
     if (s != SS_OK || n == 0) return s;
     Params p;
@@ -1817,6 +1846,9 @@ static ss_status semisort_keys(ss_ctx* c, bool less, const void* keys, uint32_t 
     if (kb == 4)
         return vb == 8 ? run_semisort<uint64_t, uint32_t>(c, k, vals, offs, 1, ko, vals_out, p)
                        : run_semisort<uint32_t, uint32_t>(c, k, vals, offs, 1, ko, vals_out, p);
+    if (kb == 16)
+        return vb == 8 ? run_semisort<uint64_t, Key128>(c, k, vals, offs, 1, ko, vals_out, p)
+                       : run_semisort<uint32_t, Key128>(c, k, vals, offs, 1, ko, vals_out, p);
     return vb == 8 ? run_semisort<uint64_t>(c, k, vals, offs, 1, ko, vals_out, p)
                    : run_semisort<uint32_t>(c, k, vals, offs, 1, ko, vals_out, p);
 }
@@ -2042,7 +2074,7 @@ ss_status ss_partition_equal(ss_ctx* c, const uint64_t* keys, const void* vals, 
     HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[0].p, c->seg_stage, sizeof(Seg), hipMemcpyHostToDevice, c->stream));
     if ((s = reset_counters(c)) != SS_OK) return s;
     if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
-    if ((s = ensure(c, c->sink, 512)) != SS_OK) return s;
+    if ((s = ensure(c, c->sink, kSinkBytes)) != SS_OK) return s;
     LevelArgs a = make_args(c, p, 0, (Seg*)c->segs[0].p, 1, tile, keys, vals, keys_out, vals_out, keys_out, vals_out);
     a.adaptive_nl = 0;  // the inspected level uses exactly n_light_log2 bits
     if (vb == 8) launch_level_v<uint64_t>(c, p.mode, a, tiles, chunks, n);

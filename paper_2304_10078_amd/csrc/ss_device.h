@@ -3,7 +3,9 @@
 // written for gfx950 (CDNA4, wave64, 160 KB LDS per CU).
 //
 // Layout conventions
-//   * keys[] (u64) and vals[] (u32 or u64) are separate arrays (SoA).
+//   * keys[] (u32, u64 or 128-bit) and vals[] (u32 or u64) are separate
+//     arrays (SoA).  In registers a key of up to 64 bits is held zero-extended
+//     to 64 bits; a 128-bit key as its two words.
 //   * A recursion level holds a list of subproblems (Seg).  Every kernel of
 //     the level runs over all of them at once: a block finds its subproblem
 //     by binary search over the subproblems' first tile / chunk.
@@ -165,6 +167,8 @@ struct LevelArgs {
     const LevelInfo* dims;
     uint32_t seg_cap;
     uint32_t* q;  // the level's work-queue counters, zero at the start: [0, 8) counting, [8, 16) distribution
+    // 128-bit keys: one sampled key per heavy id ([nsegs][kHeavyMax] pairs of words)
+    uint64_t* hrep;
 };
 
 // ---------------------------------------------------------------- hashing
@@ -206,6 +210,93 @@ __device__ __forceinline__ uint64_t key_of_hash(uint64_t h)
     else return h;
 }
 
+
+// ---------------------------------------------------------------- key types
+// Keys of 4 and 8 bytes are handled as 64-bit words (a 4-byte key
+// zero-extended); their hash is a bijection on 64 bits, so equal hashes mean
+// equal keys.  A 128-bit key (two words, low word first in memory) is held as
+// Key128; its hash is a bijection on 128 bits whose low word drives the first
+// 64 bits of bucketing and heavy detection, and the high word the rest.  Its
+// 64-bit level hash can collide, so heavy ids are confirmed against a sampled
+// key and the base cases compare whole keys.
+
+struct alignas(16) Key128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ bool operator==(const Key128& a, const Key128& b) { return a.lo == b.lo && a.hi == b.hi; }
+
+template <typename K> struct KeyTraits {
+    using R = uint64_t;  // register form
+    static constexpr uint32_t hash_bits = 64;
+    static constexpr bool wide = false;
+};
+template <> struct KeyTraits<Key128> {
+    using R = Key128;
+    static constexpr uint32_t hash_bits = 128;
+    static constexpr bool wide = true;
+};
+template <typename K> using KReg = typename KeyTraits<K>::R;
+template <typename K> constexpr bool kWide = KeyTraits<K>::wide;
+
+template <typename K>
+__device__ __forceinline__ KReg<K> kload(const K* p)
+{
+    if constexpr (kWide<K>) return *p;
+    else return (uint64_t)*p;
+}
+
+template <typename K>
+__device__ __forceinline__ K knarrow(const KReg<K>& r)
+{
+    return (K)r;
+}
+template <>
+__device__ __forceinline__ Key128 knarrow<Key128>(const Key128& r)
+{
+    return r;
+}
+
+// 64-bit fold of a key for LDS table slots (equal keys, equal folds).
+__device__ __forceinline__ uint64_t kfold(uint64_t k) { return k; }
+__device__ __forceinline__ uint64_t kfold(const Key128& k) { return k.lo ^ (k.hi * 0x9e3779b97f4a7c15ULL); }
+
+// The two hash words of a key (hi is 0 for keys of up to 64 bits).
+struct Hash2 {
+    uint64_t lo, hi;
+};
+
+template <int MODE>
+__device__ __forceinline__ Hash2 khash(uint64_t k)
+{
+    return Hash2{user_hash<MODE>(k), 0ull};
+}
+
+// 128-bit keys.  Identity (MODE 1): the key's own words.  Mixed: x = fmix64(lo)
+// then y = fmix64(hi ^ x), hash (y, x); each step is invertible given the
+// other word, so the map is a bijection on 128 bits, and y depends on every
+// bit of the key.
+template <int MODE>
+__device__ __forceinline__ Hash2 khash(const Key128& k)
+{
+    if constexpr (MODE == 1) return Hash2{k.lo, k.hi};
+    else {
+        const uint64_t x = fmix64(k.lo);
+        return Hash2{fmix64(k.hi ^ x), x};
+    }
+}
+
+// Hash that identifies heavy keys at a level starting at hash bit `shift`:
+// the word that holds the level's first bucket bit.
+__device__ __forceinline__ uint64_t level_hash(const Hash2& h, uint32_t shift) { return shift < 64 ? h.lo : h.hi; }
+
+// Hash bits from `shift` on, as a 64-bit window (shift < 128).
+__device__ __forceinline__ uint64_t hash_window(const Hash2& h, uint32_t shift)
+{
+    if (shift == 0) return h.lo;
+    if (shift < 64) return (h.lo >> shift) | (h.hi << (64 - shift));
+    return h.hi >> (shift - 64);
+}
 
 // SplitMix64's output function (Steele, Lea, Flood 2014).
 __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
@@ -255,11 +346,13 @@ __device__ __forceinline__ uint32_t heavy_slot(uint64_t h, uint32_t hfield, int 
 // heavy table has two choices per key (cuckoo hashing), so a lookup is four
 // independent LDS reads and no probe loop.  K: 0 = no heavy table, 1 = direct
 // slots, 2 = mixed slots (the caller branches once per subproblem).
+// `w` holds the hash bits from the level's first bucket bit on, `h` the level
+// hash the heavy table is keyed by.
 template <int K>
-__device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, const uint16_t* tid,
-                                              uint32_t hfield, uint32_t shift, uint32_t lmask)
+__device__ __forceinline__ uint32_t bucket_of_w(uint64_t h, uint64_t w, const uint64_t* th, const uint16_t* tid,
+                                                uint32_t hfield, uint32_t lmask)
 {
-    uint32_t b = (uint32_t)(h >> shift) & lmask;
+    uint32_t b = (uint32_t)w & lmask;
     if constexpr (K != 0) {
         const uint32_t s1 = heavy_slot(h, (hfield & 0x7FFFu) | (K == 1 ? kDirectSlots : 0u), 0);
         const uint32_t s2 = heavy_slot(h, (hfield & 0x7FFFu) | (K == 1 ? kDirectSlots : 0u), 1) + kHeavySlotsMax;
@@ -269,6 +362,13 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, co
         if (i1 != kEmpty16 && h1 == h) b = i1;
     }
     return b;
+}
+
+template <int K>
+__device__ __forceinline__ uint32_t bucket_of(uint64_t h, const uint64_t* th, const uint16_t* tid,
+                                              uint32_t hfield, uint32_t shift, uint32_t lmask)
+{
+    return bucket_of_w<K>(h, h >> shift, th, tid, hfield, lmask);
 }
 
 // ---------------------------------------------------------------- wave / block helpers
@@ -477,14 +577,14 @@ __host__ __device__ __forceinline__ uint32_t ceil_log2_u32(uint32_t x)
 // about alpha/4 records, leaving room below alpha for the spread of bucket
 // sizes (at least 1 bit, at most kLightBitsMax and the hash bits left).
 __host__ __device__ __forceinline__ uint32_t choose_nl(uint32_t len, uint32_t alpha, uint32_t cap,
-                                                       uint32_t shift)
+                                                       uint32_t shift, uint32_t hash_bits = 64)
 {
     uint32_t target = alpha / 4 ? alpha / 4 : 1;
     uint32_t q = (len + target - 1) / target;
     uint32_t nl = ceil_log2_u32(q);
     if (nl < 1) nl = 1;
     if (nl > cap) nl = cap;
-    if (nl > 64 - shift) nl = 64 - shift;
+    if (nl > hash_bits - shift) nl = hash_bits - shift;
     return nl;
 }
 
@@ -531,27 +631,50 @@ __device__ __forceinline__ void bitonic_regs(uint64_t (&e)[C], uint32_t base, ui
 // t*C .. t*C + C - 1 (h(key) when hashed, else the key); positions past s are
 // padded with ~0.  Positions are drawn with replacement from the
 // counter-based generator; all loads of a thread are issued before use.
+// Stream key of the sample positions of a subproblem at a level.
+__device__ __forceinline__ uint64_t sample_stream(const LevelArgs& a, const Seg& sg)
+{
+    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
+    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
+    return splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
+}
+
+// Position of sample i (drawn with replacement) in the subproblem's records.
+__device__ __forceinline__ uint64_t sample_pos(uint64_t k1, const Seg& sg, uint32_t i)
+{
+    const uint64_t x = splitmix_mix(k1 + 0x9e3779b97f4a7c15ULL * ((uint64_t)i + 1));
+    return (uint64_t)sg.start + __umul64hi(x, (uint64_t)sg.len);
+}
+
 template <int MODE, int C, typename K>
 __device__ __forceinline__ void gather_regs(const LevelArgs& a, const Seg& sg, uint32_t s, bool hashed,
                                             uint64_t (&e)[C])
 {
-    const uint64_t golden = 0x9e3779b97f4a7c15ULL;
-    const uint64_t k0 = splitmix_mix(a.seed + golden * ((uint64_t)a.level + 1));
-    const uint64_t k1 = splitmix_mix(k0 ^ (uint64_t)(sg.start - sg.ibase));
+    const uint64_t k1 = sample_stream(a, sg);
     const uint32_t base = threadIdx.x * C;
+    if constexpr (kWide<K>) {
+        // 128-bit keys: always hashed; the level hash of each sampled key
+        Key128 kv[C];
 #pragma unroll
-    for (int q = 0; q < C; ++q) {
-        const uint32_t i = base + q;
-        e[q] = ~0ull;
-        if (i < s) {
-            const uint64_t x = splitmix_mix(k1 + golden * ((uint64_t)i + 1));
-            e[q] = ((const K*)a.src_keys)[(uint64_t)sg.start + __umul64hi(x, (uint64_t)sg.len)];
+        for (int q = 0; q < C; ++q) {
+            const uint32_t i = base + q;
+            if (i < s) kv[q] = ((const K*)a.src_keys)[sample_pos(k1, sg, i)];
         }
-    }
-    if (hashed) {
 #pragma unroll
         for (int q = 0; q < C; ++q)
-            if (base + q < s) e[q] = user_hash<MODE>(e[q]);
+            e[q] = base + q < s ? level_hash(khash<MODE>(kv[q]), sg.shift) : ~0ull;
+    } else {
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+            const uint32_t i = base + q;
+            e[q] = ~0ull;
+            if (i < s) e[q] = (uint64_t)((const K*)a.src_keys)[sample_pos(k1, sg, i)];
+        }
+        if (hashed) {
+#pragma unroll
+            for (int q = 0; q < C; ++q)
+                if (base + q < s) e[q] = user_hash<MODE>(e[q]);
+        }
     }
 }
 
@@ -788,7 +911,7 @@ __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t s
         hlog2 = ceil_log2_u32(2 * nh);
         if (hlog2 < 4) hlog2 = 4;
     }
-    const uint32_t direct = (MODE == 0 && sg.shift < 32) ? kDirectSlots : 0u;
+    const uint32_t direct = (MODE == 0 && !kWide<K> && sg.shift < 32) ? kDirectSlots : 0u;
     const uint32_t slots = nh ? (1u << hlog2) : 0u;
     uint32_t salt = 0;
     bool built = nh == 0;
@@ -831,7 +954,37 @@ __device__ __forceinline__ void sample_heavy_item(const LevelArgs& a, uint32_t s
         a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + i] = o != kEmpty32 ? (uint16_t)(nL + o) : kEmpty16;
     }
     for (uint32_t b = tid; b < nL + nh; b += BS) a.bfin[(size_t)sid * kNbStride + b] = b >= nL ? 1 : 0;
-    for (uint32_t h = tid; h < nh; h += BS) a.bkey[(size_t)sid * kNbStride + nL + h] = key_of_hash<MODE>(hv[h]);
+    if constexpr (kWide<K>) {
+        // One sampled key per heavy id: the lowest-numbered sample whose level
+        // hash is the id's.  The counting pass sends a record to the heavy
+        // bucket only if its key equals this one, so the bucket holds one key
+        // whatever collides with its hash.  Every heavy hash came from the
+        // sample, so each id finds a key; were one missing, its records would
+        // all stay light, which is still correct.
+        uint32_t* repi = (uint32_t*)smp;  // the sample is no longer needed
+        for (uint32_t h = tid; h < nh; h += BS) repi[h] = kEmpty32;
+        __syncthreads();
+        const uint64_t k1 = sample_stream(a, sg);
+        const K* src = (const K*)a.src_keys;
+        if (nh && built) {
+            for (uint32_t i = tid; i < s; i += BS) {
+                const uint64_t h = level_hash(khash<MODE>(src[sample_pos(k1, sg, i)]), sg.shift);
+                const uint32_t o1 = owner[heavy_slot(h, hfield, 0)];
+                const uint32_t o2 = owner[kHeavySlotsMax + heavy_slot(h, hfield, 1)];
+                const uint32_t o = (o1 != kEmpty32 && hv[o1] == h) ? o1 : (o2 != kEmpty32 && hv[o2] == h) ? o2 : kEmpty32;
+                if (o != kEmpty32) atomicMin(&repi[o], i);
+            }
+        }
+        __syncthreads();
+        for (uint32_t h = tid; h < nh; h += BS) {
+            const uint32_t i = repi[h];
+            Key128 k{~0ull, ~0ull};
+            if (i != kEmpty32) k = src[sample_pos(k1, sg, i)];
+            ((Key128*)a.hrep)[(size_t)sid * kHeavyMax + h] = k;
+        }
+    } else {
+        for (uint32_t h = tid; h < nh; h += BS) a.bkey[(size_t)sid * kNbStride + nL + h] = key_of_hash<MODE>(hv[h]);
+    }
     if (a.reduce)
         for (uint32_t h = tid; h < nh; h += BS) a.hsum[(size_t)sid * kHeavyMax + h] = red_identity(a.rop);
     if (tid == 0) {
@@ -886,6 +1039,7 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
     __shared__ uint8_t finl[kNbStride];
     __shared__ uint64_t th[2 * kHeavySlotsMax];
     __shared__ uint16_t tidh[2 * kHeavySlotsMax];
+    __shared__ Key128 rep[kWide<K> ? kHeavyMax : 1];  // 128-bit keys: the sampled key of each heavy id
 
     const uint32_t tid = threadIdx.x;
     const uint32_t sid = find_by_tile(a.segs, nsegs, t);
@@ -907,6 +1061,10 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
         const uint32_t j = i < slots ? i : kHeavySlotsMax + (i - slots);
         th[j] = a.tab_h[(size_t)sid * 2 * kHeavySlotsMax + j];
         tidh[j] = a.tab_id[(size_t)sid * 2 * kHeavySlotsMax + j];
+    }
+    if constexpr (kWide<K>) {
+        const uint32_t nh = nb - nL < kHeavyMax ? nb - nL : kHeavyMax;
+        for (uint32_t h = tid; h < nh; h += BS) rep[h] = ((const Key128*)a.hrep)[(size_t)sid * kHeavyMax + h];
     }
     __syncthreads();
 
@@ -935,22 +1093,34 @@ __device__ __forceinline__ void count_item(const LevelArgs& a, uint32_t t, uint3
     const K* kt = keys + r0;
     uint16_t* bt = bids + r0;
     const uint32_t len = (uint32_t)(r1 - r0);
-    auto pass = [&](auto kind) {
+    // GetBucketId of one key.  128-bit keys: a heavy id holds only its
+    // sampled key; another key with the same level hash takes its light bucket.
+    auto bucket_key = [&](const KReg<K>& k, auto kind) -> uint32_t {
         constexpr int TK = decltype(kind)::value;  // heavy table kind
+        if constexpr (kWide<K>) {
+            const Hash2 hh = khash<MODE>(k);
+            const uint64_t w = hash_window(hh, shift);
+            const uint32_t b = bucket_of_w<TK>(level_hash(hh, shift), w, th, tidh, hlog2, lmask);
+            return (b >= nL && !(k == rep[b - nL])) ? ((uint32_t)w & lmask) : b;
+        } else {
+            return bucket_of<TK>(user_hash<MODE>(k), th, tidh, hlog2, shift, lmask);
+        }
+    };
+    auto pass = [&](auto kind) {
         uint32_t o = tid;
         for (; o + (U - 1) * BS < len; o += U * BS) {
-            uint64_t kk[U];
+            KReg<K> kk[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) kk[u] = kt[o + u * BS];
+            for (int u = 0; u < U; ++u) kk[u] = kload(kt + o + u * BS);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t b = bucket_of<TK>(user_hash<MODE>(kk[u]), th, tidh, hlog2, shift, lmask);
+                const uint32_t b = bucket_key(kk[u], kind);
                 bt[o + u * BS] = (uint16_t)b;
                 tally(b);
             }
         }
         for (; o < len; o += BS) {
-            const uint32_t b = bucket_of<TK>(user_hash<MODE>(kt[o]), th, tidh, hlog2, shift, lmask);
+            const uint32_t b = bucket_key(kload(kt + o), kind);
             bt[o] = (uint16_t)b;
             tally(b);
         }
@@ -1508,7 +1678,8 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     __shared__ uint32_t dl[kNbStride];
     __shared__ uint32_t sh_bad;
     __shared__ uint16_t wc[W * kNbStride];
-    __shared__ uint64_t stage[SUB];
+    constexpr int KW = sizeof(KReg<K>) / 8;  // words per key in registers
+    __shared__ uint64_t stage[SUB * KW];
     __shared__ uint16_t stage_b[SUB];
     __shared__ uint32_t tmp[20];
     __shared__ unsigned long long hs[RED ? kNbStride : 1];
@@ -1527,7 +1698,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     const uint32_t nb = sg.nbk;
     const uint32_t nbits = 32 - __clz(nb - 1);
     const bool split = a.fin_keys != a.dst_keys;
-    const bool all_bits = a.ordered == 0 && (uint32_t)sg.shift + sg.nl_bits >= 64;
+    const bool all_bits = a.ordered == 0 && (uint32_t)sg.shift + sg.nl_bits >= KeyTraits<K>::hash_bits;
     const uint32_t* bsz = a.bstart + (size_t)sid * (kNbStride + 1);
     const uint8_t* fin = a.bfin + (size_t)sid * kNbStride;
     const V* src_vals = (const V*)a.src_vals;
@@ -1550,7 +1721,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
     // keys and bucket ids are loaded one sub-tile ahead; values at the top of
     // their own iteration (needed only after the ranking)
     const uint32_t lofs = w * 64 * E + lane;  // this lane's first offset in a sub-tile
-    K* sink_k = (K*)(a.sink + lane);
+    K* sink_k = (K*)a.sink + lane;
     V* sink_v = (V*)(a.sink + lane);
     const uint64_t kdiff = (uint64_t)a.fin_keys - (uint64_t)a.dst_keys;
     const uint64_t vdiff = (uint64_t)fin_vals - (uint64_t)dst_vals;
@@ -1562,7 +1733,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
         if constexpr (RED != 0) return finl[b] != 0;
         else return fillk && finl[b] != 0;
     };
-    uint64_t kn[E];
+    KReg<K> kn[E];
     uint16_t bn[E];
     {
         const uint16_t* bs = a.bids + r0;
@@ -1576,12 +1747,12 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
         const K* ks = (const K*)a.src_keys + r0;
         const uint32_t lim = (uint32_t)(rlast - r0 < SUB ? rlast - r0 : SUB);
 #pragma unroll
-        for (int e = 0; e < E; ++e) kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + e * 64u, lim));
+        for (int e = 0; e < E; ++e) kn[e] = kload(skip_key(bn[e]) ? sink_k : ks + min(lofs + e * 64u, lim));
     }
 
     bool out_of_range = false;
     for (uint64_t sub = r0; sub < r1; sub += SUB) {
-        uint64_t k[E];
+        KReg<K> k[E];
         V v[E];
         uint32_t bk[E], pos[E];
         const uint32_t left = (uint32_t)(r1 - sub < 2 * SUB ? r1 - sub : 2 * SUB);  // records from sub on
@@ -1624,7 +1795,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
             const K* ks = (const K*)a.src_keys + sub;
 #pragma unroll
             for (int e = 0; e < E; ++e)
-                kn[e] = *(skip_key(bn[e]) ? sink_k : ks + min(lofs + SUB + e * 64u, left - 1));
+                kn[e] = kload(skip_key(bn[e]) ? sink_k : ks + min(lofs + SUB + e * 64u, left - 1));
         }
         __syncthreads();
 
@@ -1672,7 +1843,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
                 const uint32_t b = bk[e];
                 const uint32_t p = lst[b] + wc[w * nb + b] + pos[e];
                 pos[e] = p;
-                stage[p] = k[e];
+                ((KReg<K>*)stage)[p] = k[e];
                 // bit 15: the key is not stored (one-key bucket, filled later)
                 stage_b[p] = (uint16_t)(b | ((fillk && finl[b]) ? 0x8000u : 0u));
             }
@@ -1697,7 +1868,7 @@ __device__ __forceinline__ void distribute_item(const LevelArgs& a, uint32_t t, 
             const uint64_t sel = ((uint64_t)msk << 32) | msk;
             K* out = (K*)((char*)a.dst_keys + (kdiff & sel)) + d;
             // bit 15: the key is not stored (one-key bucket, filled later)
-            *(j < m && !(sb >> 15) ? out : sink_k) = (K)stage[jj];
+            *(j < m && !(sb >> 15) ? out : sink_k) = knarrow<K>(((const KReg<K>*)stage)[jj]);
         }
         for (uint32_t i = tid; i < W * nb; i += BS) wc[i] = 0;
         __syncthreads();
@@ -1907,6 +2078,7 @@ struct PlanArgs {
     const uint64_t* bkey;    // [nsegs][kNbStride] keys of one-key buckets
     FillJob* fills;
     uint32_t fill_cap;
+    uint32_t hash_bits = 64;  // hash bits the levels can consume (128 for 128-bit keys)
     // device-sized levels: the current level's subproblem count is read from
     // dims (bounded by cur_cap) instead of nsegs
     const LevelInfo* dims;
@@ -1932,7 +2104,7 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
     const uint32_t sz = bs[b + 1] - st;
     if (sz == 0) return;
     const uint32_t shift2 = p.ordered ? 0u : (uint32_t)sg.shift + sg.nl_bits;
-    const bool all_bits_used = shift2 >= 64;
+    const bool all_bits_used = shift2 >= p.hash_bits;
     if (p.reduce) {
         // heavy bucket: its result was written with the level; a bucket of one
         // record, or of one hash value (one key: the hash is a bijection),
@@ -1981,7 +2153,7 @@ __device__ __forceinline__ void plan_bucket(const PlanArgs& p, uint32_t sidx, co
                 ns.len = sz;
                 ns.ibase = sg.ibase;
                 ns.tile0 = ns.chunk0 = ns.ntiles = 0;
-                ns.nl_bits = (uint8_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2);
+                ns.nl_bits = (uint8_t)choose_nl(sz, p.alpha, kLightBitsMax, shift2, p.hash_bits);
                 ns.shift = (uint8_t)shift2;
                 ns.nbk = 0;
                 ns.nheavy = 0;
@@ -2374,25 +2546,25 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
     // stores (a sink for lanes without a record) are issued unconditionally,
     // so waiting for the prefetched records does not wait for the stores.
     constexpr int BS = W * 64, E = 8, CAP = BS * E;
-    __shared__ uint64_t kl[CAP];
+    __shared__ KReg<K> kl[CAP];
     __shared__ uint32_t tab[2 * CAP];  // slot owners; reused for digit starts
     __shared__ uint16_t wc[W * CAP];
     __shared__ uint32_t tmp[8 * 16 + 8];
 
     const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
     const uint32_t lofs = w * 64 * E + lane;
-    K* sink_k = (K*)(sink + lane);
+    K* sink_k = (K*)sink + lane;
     V* sink_v = (V*)(sink + lane);
     uint32_t jb = blockIdx.x;
     if (jb >= njobs) return;
     Job jn = jobs[jb];
-    uint64_t kn[E];
+    KReg<K> kn[E];
     V vn[E];
     auto fetch = [&](const Job& jj) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const uint32_t i = min(lofs + e * 64u, jj.len - 1);  // len >= 2
-            kn[e] = (uint64_t)src_keys[jj.start + i];
+            kn[e] = kload(src_keys + jj.start + i);
             vn[e] = src_vals[jj.start + i];
         }
     };
@@ -2400,7 +2572,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
     bool bad = false;
     for (; jb < njobs; jb += gridDim.x) {
         const Job j = jn;
-        uint64_t k[E];
+        KReg<K> k[E];
         V v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
@@ -2439,7 +2611,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
             const uint32_t i = lofs + e * 64u;
             sl[e] = 0;
             if (i < m) {
-                uint32_t s = fib_slot(k[e], lg);
+                uint32_t s = fib_slot(kfold(k[e]), lg);
                 while (true) {
                     const uint32_t o = atomicCAS(&tab[s], kEmpty32, i);
                     if (o == kEmpty32 || kl[o] == k[e]) break;
@@ -2506,7 +2678,7 @@ __device__ __forceinline__ void base_run(const Job* __restrict__ jobs, uint32_t 
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const bool ok = pp[e] != 0xFFFFFFFFu;
-            *(ok ? out_keys + start + pp[e] : sink_k) = (K)k[e];
+            *(ok ? out_keys + start + pp[e] : sink_k) = knarrow<K>(k[e]);
             *(ok ? out_vals + start + pp[e] : sink_v) = v[e];
         }
         __syncthreads();  // the next job reuses the LDS
@@ -2542,7 +2714,7 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, 
                                                 K* out_keys, V* out_vals, LevelInfo* info)
 {
     constexpr int W = 8, BS = 512, E = 8, CAP = 4096;
-    __shared__ uint64_t kl[CAP];
+    __shared__ KReg<K> kl[CAP];
     __shared__ uint32_t tab[2 * CAP];  // slot owners, then the two sort buffers
     __shared__ uint16_t wc[W * 64];
     __shared__ uint32_t dst_[64];
@@ -2554,12 +2726,15 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, 
     const uint32_t lg = ceil_log2_u32(2 * m) < 6 ? 6 : ceil_log2_u32(2 * m);
     const uint32_t slots = 1u << lg, smask = slots - 1;
 
-    uint64_t k[E];
+    KReg<K> k[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const uint32_t i = w * 64 * E + e * 64 + lane;
-        k[e] = i < m ? (uint64_t)src_keys[start + i] : 0ull;
-        if (i < m) kl[i] = k[e];
+        k[e] = KReg<K>{};
+        if (i < m) {
+            k[e] = kload(src_keys + start + i);
+            kl[i] = k[e];
+        }
     }
     for (uint32_t i = tid; i < slots; i += BS) tab[i] = kEmpty32;
     __syncthreads();
@@ -2571,7 +2746,7 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, 
         if (i < m) {
             // one compare-and-swap claims the slot or returns its owner;
             // Fibonacci hashing of the folded key (as in k_base)
-            uint32_t sx = fib_slot(k[e], lg);
+            uint32_t sx = fib_slot(kfold(k[e]), lg);
             while (true) {
                 const uint32_t o = atomicCAS(&tab[sx], kEmpty32, i);
                 if (o == kEmpty32 || kl[o] == k[e]) break;
@@ -2642,7 +2817,7 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, 
             }
         }
     }
-    uint64_t ok[E];
+    KReg<K> ok[E];
     V ov[E];
     bool bad = false;
 #pragma unroll
@@ -2663,7 +2838,7 @@ __device__ __forceinline__ void base_2pass_item(const Job j, const K* src_keys, 
     for (int e = 0; e < E; ++e) {
         const uint32_t q = tid + e * BS;
         if (q < m) {
-            out_keys[start + q] = (K)ok[e];
+            out_keys[start + q] = knarrow<K>(ok[e]);
             out_vals[start + q] = ov[e];
         }
     }

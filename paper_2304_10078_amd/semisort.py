@@ -204,16 +204,30 @@ def sync(device=0):
 
 
 def _check_kv(keys, vals, allow_k32=False):
+    """Value width of a (keys, vals) pair of device tensors.  Keys: int64
+    (uint64 bits), or with allow_k32 also int32 (uint32 bits) and an (n, 2)
+    int64 tensor of 128-bit keys as (low, high) words."""
     import torch
     if not (keys.is_cuda and vals.is_cuda):
         raise ValueError("keys and vals must be device tensors")
+    wide = allow_k32 and keys.dim() == 2 and keys.shape[-1] == 2 and keys.dtype == torch.int64
     kd = (torch.int64, torch.int32) if allow_k32 else (torch.int64,)
     if keys.dtype not in kd or vals.dtype not in (torch.int64, torch.int32):
-        raise ValueError("keys must be int64 (uint64 bits)" + (" or int32 (uint32 bits)" if allow_k32 else "") +
+        raise ValueError("keys must be int64 (uint64 bits)" +
+                         (", int32 (uint32 bits) or (n, 2) int64 (128-bit)" if allow_k32 else "") +
                          ", vals int64 or int32 (uint bits)")
-    if keys.dim() != 1 or vals.shape != keys.shape or not keys.is_contiguous() or not vals.is_contiguous():
-        raise ValueError("keys and vals must be contiguous 1-D tensors of equal length")
+    if (keys.dim() != (2 if wide else 1) or vals.dim() != 1 or vals.shape[0] != keys.shape[0]
+            or not keys.is_contiguous() or not vals.is_contiguous()):
+        raise ValueError("keys and vals must be contiguous tensors of equal length (1-D, or (n, 2) keys)")
     return vals.element_size()
+
+
+def _check_out(name, out, like):
+    """An output tensor must match the input it stands for (device, dtype,
+    shape, contiguity): the library writes as many bytes as the input holds."""
+    if (not out.is_cuda or out.device != like.device or out.dtype != like.dtype or out.shape != like.shape
+            or not out.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous device tensor like the input ({like.dtype}, {tuple(like.shape)})")
 
 
 def _ptr(t):
@@ -223,26 +237,30 @@ def _ptr(t):
 def _semisort(less, keys, vals, keys_out, vals_out, params, ctx):
     import torch
     vb = _check_kv(keys, vals, allow_k32=True)
-    kb = keys.element_size()  # 4: ss_semisort_*_keys with 32-bit keys
+    n = keys.shape[0]
+    kb = keys.element_size() * (2 if keys.dim() == 2 else 1)  # 4 or 16: ss_semisort_*_keys
     ctx = ctx or context(keys.device.index or 0)
     ctx._bind_stream()
     if keys_out is None:
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
     pp = ctypes.byref(params) if params is not None else None
-    if kb == 4:
+    if kb != 8:
         fn = lib().ss_semisort_less_keys if less else lib().ss_semisort_equal_keys
-        ctx.check(fn(ctx.h, _ptr(keys), 4, _ptr(vals), vb, keys.numel(), _ptr(keys_out), _ptr(vals_out), pp))
+        ctx.check(fn(ctx.h, _ptr(keys), kb, _ptr(vals), vb, n, _ptr(keys_out), _ptr(vals_out), pp))
     else:
         fn = lib().ss_semisort_less if less else lib().ss_semisort_equal
-        ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), vb, keys.numel(), _ptr(keys_out), _ptr(vals_out), pp))
+        ctx.check(fn(ctx.h, _ptr(keys), _ptr(vals), vb, n, _ptr(keys_out), _ptr(vals_out), pp))
     return keys_out, vals_out
 
 
 def semisort_equal(keys, vals, keys_out=None, vals_out=None, params=None, ctx=None):
     """ss_semisort_equal: equal keys contiguous, stable.  Returns (keys_out, vals_out).
-    keys: int64 (uint64 bits) or int32 (uint32 bits: ss_semisort_equal_keys)."""
+    keys: int64 (uint64 bits), int32 (uint32 bits) or (n, 2) int64 (128-bit keys
+    as low, high words): the last two through ss_semisort_equal_keys."""
     return _semisort(False, keys, vals, keys_out, vals_out, params, ctx)
 
 
@@ -264,6 +282,8 @@ def semisort_less_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, p
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
     ctx.check(lib().ss_semisort_less_batch(ctx.h, _ptr(keys), _ptr(vals), vb, ctypes.c_void_p(offs.ctypes.data),
                                            offs.size - 1, _ptr(keys_out), _ptr(vals_out),
                                            ctypes.byref(params) if params is not None else None))
@@ -283,6 +303,8 @@ def semisort_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, 
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
     ctx.check(lib().ss_semisort_equal_batch(ctx.h, _ptr(keys), _ptr(vals), vb,
                                             ctypes.c_void_p(offs.ctypes.data), offs.size - 1, _ptr(keys_out),
                                             _ptr(vals_out), ctypes.byref(params) if params is not None else None))
@@ -310,6 +332,8 @@ def semisort_equal_batch_capturable(keys, vals, seg_offsets, keys_out=None, vals
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
     ctx.check(lib().ss_semisort_equal_batch_capturable(
         ctx.h, _ptr(keys), _ptr(vals), vb, _ptr(seg_offsets), seg_offsets.numel() - 1, keys.numel(),
         _ptr(keys_out), _ptr(vals_out), max_levels, ctypes.byref(params) if params is not None else None))
@@ -509,6 +533,8 @@ def autotune_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, 
         keys_out = torch.empty_like(keys)
     if vals_out is None:
         vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
     best = ss_params()
     ms = ctypes.c_double()
     ctx.check(lib().ss_autotune_equal_batch(ctx.h, _ptr(keys), _ptr(vals), vb, offs.ctypes.data_as(ctypes.c_void_p),

@@ -228,6 +228,50 @@ def test_full_size_semisort_less_exponential_32bit_keys():
     _check_grouping(keys, ko, vo, ordered=True, seed=8)
 
 
+def test_full_size_semisort_equal_zipf12_128bit_keys():
+    # 128-bit keys (low, high words): permutation, every record kept its key,
+    # equal keys contiguous (the keys that start runs are distinct), stable,
+    # and sampled groups by brute force.  Every gather is 1-D, one word at a
+    # time: torch's row gather of an (n, 2) tensor returns zero rows once n
+    # passes about 2^26 here.
+    keys, vals = _indexed("zipf1.2_hashed_k128", 9)
+    assert keys.shape == (N, 2)
+    _say("case: semisort_= zipf1.2_hashed n=1e9, 128-bit keys, u64 values")
+    ko, vo = S.semisort_equal(keys, vals)
+    S.sync()
+    mark = torch.zeros(N, dtype=torch.bool, device="cuda")
+    mark[vo] = True
+    assert bool(mark.all()), "output is not a permutation of the input"
+    del mark
+    same = None
+    for w in (0, 1):
+        kin = keys[:, w].contiguous()
+        kout = ko[:, w].contiguous()
+        assert bool(torch.equal(kout, kin[vo])), f"a record lost word {w} of its key"
+        eq = kout[1:] == kout[:-1]
+        same = eq if same is None else same & eq
+        del kin, kout, eq
+    starts = torch.ones(N, dtype=torch.bool, device="cuda")
+    starts[1:] = ~same
+    lo, hi = ko[:, 0].contiguous()[starts], ko[:, 1].contiguous()[starts]
+    del starts
+    # a key in two runs: two equal rows after a lexicographic sort (two
+    # stable 1-D sorts, low word then high word)
+    o = torch.sort(lo, stable=True).indices
+    o = o[torch.sort(hi[o], stable=True).indices]
+    slo, shi = lo[o], hi[o]
+    assert not bool(((slo[1:] == slo[:-1]) & (shi[1:] == shi[:-1])).any()), "a key occurs in two runs"
+    del lo, hi, o, slo, shi
+    assert bool(((vo[1:] > vo[:-1]) | ~same).all()), "records of a key lost their input order"
+    del same
+    g = torch.Generator(device="cpu").manual_seed(9)
+    for p in torch.randint(0, N, (12,), generator=g).tolist():
+        k = ko[p]
+        want = torch.nonzero((keys == k).all(dim=1)).flatten()
+        got = vo[(ko == k).all(dim=1)]
+        assert torch.equal(got, want), f"group of key {k.tolist()} differs from the input positions"
+
+
 def test_full_size_histogram_exponential():
     keys, _ = I.t_workload("exp1e-5_u32idx", N, 5, "cuda")
     _say("case: ordered histogram exp(1e-5) n=1e9")

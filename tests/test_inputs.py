@@ -156,3 +156,14 @@ def test_32bit_key_workloads():
     assert np.unique(I.np_fmix32(x)).size == x.size
     z = I.np_zipf(200_000, 1.2, 10 ** 9, 3, 0)
     assert np.unique(I.np_fmix32(z.astype(np.uint32))).size == np.unique(z).size
+
+
+def test_128bit_key_workloads():
+    # (n, 2) words; the numpy and torch back ends give the same bits; the low
+    # word is the distribution's key, so distinct keys stay distinct
+    for name in ("zipf1.2_hashed_k128", "uniform1e9_k128"):
+        k, v = I.np_workload(name, 50_000, 5)
+        assert k.shape == (50_000, 2) and k.dtype == np.uint64 and I.key_bytes(name) == 16
+        tk, tv = I.t_workload(name, 50_000, 5, "cpu")
+        assert np.array_equal(k, tk.numpy().view(np.uint64)) and np.array_equal(v, tv.numpy().view(v.dtype))
+        assert np.unique(k[:, 0]).size == np.unique(k, axis=0).shape[0]
