@@ -125,7 +125,7 @@ def histogram(keys):
     return ok[:m].copy(), oc[:m].copy()
 
 
-MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5, "affine": 6}
+MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5, "affine": 6, "mat2": 7}
 
 
 def collect_reduce(keys, vals, op="sum"):

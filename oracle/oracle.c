@@ -225,9 +225,23 @@ static uint64_t affine_then(uint64_t x, uint64_t y)
     return ((uint64_t)a << 32) | b;
 }
 
+/* 7: products of 2 x 2 matrices over the integers mod 2^16.  A value holds
+ * the entries (a, b; c, d) as its 16-bit fields from the low end; x (+) y is
+ * the matrix product x y, identity (1, 0; 0, 1).  Associative (matrix
+ * multiplication is), not commutative. */
+static uint64_t mat2_mul(uint64_t x, uint64_t y)
+{
+    const uint32_t xa = (uint16_t)x, xb = (uint16_t)(x >> 16), xc = (uint16_t)(x >> 32), xd = (uint16_t)(x >> 48);
+    const uint32_t ya = (uint16_t)y, yb = (uint16_t)(y >> 16), yc = (uint16_t)(y >> 32), yd = (uint16_t)(y >> 48);
+    const uint64_t a = (uint16_t)(xa * ya + xb * yc), b = (uint16_t)(xa * yb + xb * yd);
+    const uint64_t c = (uint16_t)(xc * ya + xd * yc), d = (uint16_t)(xc * yb + xd * yd);
+    return a | (b << 16) | (c << 32) | (d << 48);
+}
+
 /* Non-commutative monoids (Section 3.5: a stable algorithm folds any
  * associative operation): 4 = first (x (+) y = x), 5 = last (x (+) y = y),
- * 6 = affine composition, folded over each key's records in input order. */
+ * 6 = affine composition, 7 = 2 x 2 matrix product, folded over each key's
+ * records in input order. */
 static int64_t collect_reduce_in_order(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                        uint64_t* out_keys, uint64_t* out_vals)
 {
@@ -244,7 +258,8 @@ static int64_t collect_reduce_in_order(const uint64_t* keys, const uint64_t* val
         uint64_t acc = vals[s[p].i];
         uint64_t q = p + 1;
         while (q < n && s[q].k == s[p].k) {
-            acc = op == 4 ? acc : op == 5 ? vals[s[q].i] : affine_then(acc, vals[s[q].i]);
+            acc = op == 4 ? acc : op == 5 ? vals[s[q].i] : op == 6 ? affine_then(acc, vals[s[q].i])
+                                                                   : mat2_mul(acc, vals[s[q].i]);
             q++;
         }
         out_keys[m] = s[p].k;
@@ -261,7 +276,7 @@ int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, ui
 {
     /* R = { (k, fold of the monoid over M(r), r in S_k) } with M(r) =
      * value(r); ascending keys. */
-    if (op < 0 || op > 6) return -2;
+    if (op < 0 || op > 7) return -2;
     if (op >= 4) return n ? collect_reduce_in_order(keys, vals, n, op, out_keys, out_vals) : 0;
     if (n == 0) return 0;
     kv_t* s = (kv_t*)malloc(n * sizeof(kv_t));

@@ -73,9 +73,11 @@ int64_t orc_collect_reduce(const uint64_t* keys, const uint64_t* vals, uint64_t 
  * key, fold of its values), ascending keys; 4 = first and 5 = last (the
  * value of the key's first / last record in input order) and 6 = affine
  * (a value (a, b) = (high, low 32 bits) is t -> a t + b mod 2^32; the fold
- * applies the maps in input order) are non-commutative, folded in input
- * order.  Returns m, -1 when out of memory, -2 for an
- * unknown op. */
+ * applies the maps in input order) and 7 = mat2 (a value's 16-bit fields
+ * from the low end are the entries (a, b; c, d) of a 2 x 2 matrix over the
+ * integers mod 2^16; the fold is the product in input order) are
+ * non-commutative, folded in input order.  Returns m, -1 when out of memory,
+ * -2 for an unknown op. */
 int64_t orc_collect_reduce_monoid(const uint64_t* keys, const uint64_t* vals, uint64_t n, int op,
                                   uint64_t* out_keys, uint64_t* out_vals);
 

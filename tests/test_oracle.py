@@ -624,3 +624,41 @@ def test_wide_canonicalizer_detects_split_runs_and_restores_order():
     perm = np.array([i for r in runs for i in r])
     bad, ck, cv = O.canonicalize_equal_wide(ok[perm], ov[perm])
     assert bad == -1 and np.array_equal(ck, ok) and np.array_equal(cv, ov)
+
+
+# ---- the 2 x 2 matrix product monoid (a non-commutative fold, Section 3.5) ----
+
+def _mat(a, b, c, d):
+    return np.uint64(a | (b << 16) | (c << 32) | (d << 48))
+
+
+def test_mat2_monoid_special_cases_and_order():
+    rng = np.random.default_rng(61)
+    n = 6000
+    keys = rng.integers(0, 40, n, dtype=np.uint64)
+    # diagonal matrices: the fold is the product of each diagonal entry mod 2^16
+    a = rng.integers(0, 1 << 16, n)
+    d = rng.integers(0, 1 << 16, n)
+    vals = np.array([_mat(int(x), 0, 0, int(y)) for x, y in zip(a, d)], dtype=np.uint64)
+    ok, ov = O.collect_reduce(keys, vals, op="mat2")
+    for k, v in zip(ok.tolist(), ov.tolist()):
+        sel = np.nonzero(keys == k)[0]
+        pa = pd = 1
+        for i in sel:
+            pa = pa * int(a[i]) % 65536
+            pd = pd * int(d[i]) % 65536
+        assert v == int(_mat(pa, 0, 0, pd)), k
+    # unipotent upper-triangular matrices (1, x; 0, 1): the fold adds the x
+    x = rng.integers(0, 1 << 16, n)
+    vals = np.array([_mat(1, int(t), 0, 1) for t in x], dtype=np.uint64)
+    ok, ov = O.collect_reduce(keys, vals, op="mat2")
+    for k, v in zip(ok.tolist(), ov.tolist()):
+        s = int(x[keys == k].sum()) % 65536
+        assert v == int(_mat(1, s, 0, 1)), k
+    # order: (1,1;0,1)(1,0;1,1) = (2,1;1,1), the other order gives (1,1;1,2)
+    A, B = _mat(1, 1, 0, 1), _mat(1, 0, 1, 1)
+    ok, ov = O.collect_reduce(np.array([5, 5, 9], dtype=np.uint64), np.array([A, B, B], dtype=np.uint64), op="mat2")
+    assert ok.tolist() == [5, 9]
+    assert ov.tolist() == [int(_mat(2, 1, 1, 1)), int(B)]
+    ok, ov = O.collect_reduce(np.array([5, 5], dtype=np.uint64), np.array([B, A], dtype=np.uint64), op="mat2")
+    assert ov.tolist() == [int(_mat(1, 1, 1, 2))]
