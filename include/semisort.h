@@ -371,6 +371,37 @@ ss_status ss_collect_reduce_monoid(ss_ctx* ctx, const uint64_t* keys, const uint
                                    uint64_t n, int op, int ordered, uint64_t* out_keys,
                                    uint64_t* out_vals, uint64_t* m_out, const ss_params* params);
 
+/* collect-reduce with a caller's monoid (Section 3.5 defines collect-reduce for
+ * any map and monoid; a stable semisort_= lets the fold run in input order, so
+ * the operation need not be commutative).  ss_monoid_compile compiles, with
+ * hipRTC for gfx950 and the context's device, a source text that defines
+ *   ss_t                              the element type: trivially copyable, at
+ *                                     most 8 bytes
+ *   __device__ ss_t ss_identity()     the identity element
+ *   __device__ ss_t ss_map(ss_u64 v)  the element of a record's value (its bits,
+ *                                     zero-extended from val_bytes)
+ *   __device__ ss_t ss_combine(ss_t a, ss_t b)   associative; a comes first in
+ *                                     input order
+ * (ss_u64 / ss_u32 / ss_u8 are defined before the source), into the kernels of
+ * an in-order segmented fold.  The handle belongs to the caller and serves
+ * calls on contexts of that device until ss_monoid_destroy.  A source that does
+ * not compile gives SS_EINVAL with the compiler's messages in ss_last_error
+ * (lines counted from 1 in the caller's text); compiling takes a fraction of a
+ * second.
+ * ss_collect_reduce_user: (unique key, fold of map(value) over its records in
+ * input order) for the n records (keys uint64, vals val_bytes = 4 or 8 bytes
+ * each); out_vals[i] holds the element's bytes zero-extended to 8.  Pairs in
+ * an unspecified order, or ascending keys with ordered != 0.  Workspace: the
+ * semisort's, plus 2n uint64 of fold results and n bytes of flags.  Other
+ * conventions as ss_collect_reduce; SS_EINVAL for a handle of another device. */
+typedef struct ss_user_monoid ss_user_monoid;
+ss_status ss_monoid_compile(ss_ctx* ctx, const char* source, ss_user_monoid** out);
+ss_status ss_monoid_destroy(ss_user_monoid* monoid);
+ss_status ss_collect_reduce_user(ss_ctx* ctx, const ss_user_monoid* monoid, const uint64_t* keys,
+                                 const void* vals, uint32_t val_bytes, uint64_t n, int ordered,
+                                 uint64_t* out_keys, uint64_t* out_vals, uint64_t* m_out,
+                                 const ss_params* params);
+
 /* histogram (Section 3.5): collect-reduce with every value 1, so no value
  * array is read or moved.  out_counts[i] is the number of records with key
  * out_keys[i].  Same conventions as ss_collect_reduce. */

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsemisort_hip.so")
 SOURCES = [os.path.join(HERE, "csrc", "engine.hip"), os.path.join(HERE, "csrc", "server.hip")]
-HEADERS = [os.path.join(HERE, "csrc", "ss_device.h"), os.path.join(ROOT, "include", "semisort.h")]
+HEADERS = [os.path.join(HERE, "csrc", "ss_device.h"), os.path.join(HERE, "csrc", "user_fold.inc"),
+           os.path.join(ROOT, "include", "semisort.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -22,6 +23,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
     "-I", os.path.join(HERE, "csrc"),
+    # run-time compilation of caller monoids
+    "-L/opt/rocm/lib", "-lhiprtc",
 ]
 
 

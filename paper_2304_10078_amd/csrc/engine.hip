@@ -9,6 +9,7 @@
 // Buffers alternate between the output and the temporary array T as in the
 // in-place optimization of Section 3.4.
 #include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <cstddef>
@@ -21,6 +22,7 @@
 
 #include "semisort.h"
 #include "ss_device.h"
+#include "user_fold.inc"
 
 using namespace ssd;
 
@@ -125,6 +127,14 @@ struct ss_ctx {
     double prof_ms[SS_PROF_KINDS] = {};
     uint64_t prof_launches[SS_PROF_KINDS] = {};
     uint64_t prof_units[SS_PROF_KINDS] = {};
+};
+
+// A caller's monoid compiled for one device: the module of the in-order fold
+// kernels instantiated for it.
+struct ss_user_monoid {
+    int device = -1;
+    hipModule_t mod = nullptr;
+    hipFunction_t aggr = nullptr, carry_blocks = nullptr, carry_top = nullptr, apply = nullptr;
 };
 
 namespace {
@@ -2512,6 +2522,142 @@ ss_status ss_histogram_ordered(ss_ctx* c, const uint64_t* keys, uint64_t n, uint
     ss_status s = ss_histogram(c, keys, n, out_keys, out_counts, m_out, params);
     if (s != SS_OK) return s;
     return order_results(c, out_keys, out_counts, *m_out, params);
+}
+
+// ---------------------------------------------------------------- caller monoids
+
+ss_status ss_monoid_compile(ss_ctx* c, const char* source, ss_user_monoid** out)
+{
+    if (!c) return SS_EINVAL;
+    if (!source || !out) return fail(c, SS_EINVAL, "null source or out");
+    *out = nullptr;
+    // the caller's definitions, then the fold kernels that use them; #line
+    // makes compiler messages count the caller's lines from 1
+    const std::string full = std::string(kUserFoldPrelude) + "#line 1 \"monoid\"\n" + source + "\n#line 1 \"ss_fold\"\n" +
+                             kUserFoldKernels;
+    hiprtcProgram prog = nullptr;
+    if (hiprtcCreateProgram(&prog, full.c_str(), "ss_monoid.hip", 0, nullptr, nullptr) != HIPRTC_SUCCESS)
+        return fail(c, SS_EHIP, "hiprtcCreateProgram");
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    if (hiprtcCompileProgram(prog, (int)(sizeof(opts) / sizeof(opts[0])), opts) != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        std::string log;
+        if (hiprtcGetProgramLogSize(prog, &ls) == HIPRTC_SUCCESS && ls) {
+            log.resize(ls);
+            if (hiprtcGetProgramLog(prog, &log[0]) != HIPRTC_SUCCESS) log.clear();
+        }
+        hiprtcDestroyProgram(&prog);
+        return fail(c, SS_EINVAL, "the monoid source does not compile: " + log);
+    }
+    size_t cs = 0;
+    std::vector<char> code;
+    if (hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs) {
+        code.resize(cs);
+        if (hiprtcGetCode(prog, code.data()) != HIPRTC_SUCCESS) code.clear();
+    }
+    hiprtcDestroyProgram(&prog);
+    if (code.empty()) return fail(c, SS_EHIP, "hiprtcGetCode");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    ss_user_monoid* m = new (std::nothrow) ss_user_monoid;
+    if (!m) return fail(c, SS_ENOMEM, "monoid");
+    m->device = c->device;
+    if (hipModuleLoadData(&m->mod, code.data()) != hipSuccess) {
+        delete m;
+        return fail(c, SS_EHIP, "hipModuleLoadData");
+    }
+    if (hipModuleGetFunction(&m->aggr, m->mod, "ss_fold_aggr") != hipSuccess ||
+        hipModuleGetFunction(&m->carry_blocks, m->mod, "ss_fold_carry_blocks") != hipSuccess ||
+        hipModuleGetFunction(&m->carry_top, m->mod, "ss_fold_carry_top") != hipSuccess ||
+        hipModuleGetFunction(&m->apply, m->mod, "ss_fold_apply") != hipSuccess) {
+        (void)hipModuleUnload(m->mod);
+        delete m;
+        return fail(c, SS_EHIP, "hipModuleGetFunction");
+    }
+    *out = m;
+    return SS_OK;
+}
+
+ss_status ss_monoid_destroy(ss_user_monoid* m)
+{
+    if (!m) return SS_EINVAL;
+    (void)hipSetDevice(m->device);
+    (void)hipModuleUnload(m->mod);
+    delete m;
+    return SS_OK;
+}
+
+ss_status ss_collect_reduce_user(ss_ctx* c, const ss_user_monoid* mo, const uint64_t* keys, const void* vals,
+                                 uint32_t vb, uint64_t n, int ordered, uint64_t* out_keys, uint64_t* out_vals,
+                                 uint64_t* m_out, const ss_params* params)
+{
+    if (!c) return SS_EINVAL;
+    if (!mo) return fail(c, SS_EINVAL, "null monoid");
+    if (mo->device != c->device) return fail(c, SS_EINVAL, "the monoid was compiled for another device");
+    if (vb != 4 && vb != 8) return fail(c, SS_EINVAL, "val_bytes must be 4 or 8");
+    Params p;
+    ss_status s = check_reduce(c, keys, nullptr, n, out_keys, out_vals, m_out, params, &p);
+    if (s != SS_OK) return s;
+    *m_out = 0;
+    if (n == 0) return SS_OK;
+    if (!vals) return fail(c, SS_EINVAL, "null vals");
+    if (overlaps(out_keys, n * 8, vals, n * vb) || overlaps(out_vals, n * 8, vals, n * vb))
+        return fail(c, SS_EINVAL, "outputs overlap inputs");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+    // a stable semisort_= makes every key's records contiguous and in input
+    // order; the fold then runs over positions
+    Params q = p;
+    default_tiles(c, params, &q, 32768u, 16384u);
+    if ((s = ensure(c, c->tr_keys, n * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->tr_sorted, n * vb)) != SS_OK) return s;
+    uint64_t* sk = (uint64_t*)c->tr_keys.p;
+    void* sv = c->tr_sorted.p;
+    const uint64_t so[2] = {0, n};
+    if ((s = vb == 8 ? run_semisort<uint64_t>(c, keys, vals, so, 1, sk, sv, q)
+                     : run_semisort<uint32_t>(c, keys, vals, so, 1, sk, sv, q)) != SS_OK)
+        return s;
+    const uint64_t nblk = (n + kFlagBlock - 1) / kFlagBlock;
+    const uint64_t nch = (n + kFoldChunk - 1) / kFoldChunk;
+    const uint64_t ncb = (nch + 255) / 256;
+    if ((s = ensure(c, c->t_keys, n * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->t_vals, n * 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->rflag, nblk * kFlagBlock)) != SS_OK) return s;
+    if ((s = ensure(c, c->bcnt, (nblk * (kFlagBlock / kFlagChunk) + nblk) * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->mdev, 8)) != SS_OK) return s;
+    if ((s = ensure(c, c->pos, (nch + ncb) * 12)) != SS_OK) return s;
+    // 8 bytes per element of the monoid (its type is at most 8 bytes)
+    void* aggv = c->pos.p;
+    void* totv = (char*)aggv + nch * 8;
+    uint32_t* aggf = (uint32_t*)((char*)totv + ncb * 8);
+    uint32_t* totf = aggf + nch;
+    uint8_t* rf = (uint8_t*)c->rflag.p;
+    HIP_OR_FAIL(c, hipMemsetAsync(rf, 0, nblk * kFlagBlock, c->stream));
+    const uint64_t* ck = sk;
+    const void* cv = sv;
+    uint32_t vbk = vb;
+    uint64_t nk = n;
+    uint32_t nchk = (uint32_t)nch, ncbk = (uint32_t)ncb, rb = c->fold_round;
+    uint64_t* rk = (uint64_t*)c->t_keys.p;
+    uint64_t* rv = (uint64_t*)c->t_vals.p;
+    {
+        void* a[] = {&ck, &cv, &vbk, &nk, &aggv, &aggf};
+        HIP_OR_FAIL(c, hipModuleLaunchKernel(mo->aggr, nchk, 1, 1, 256, 1, 1, 0, c->stream, a, nullptr));
+    }
+    {
+        void* a[] = {&aggv, &aggf, &nchk, &totv, &totf};
+        HIP_OR_FAIL(c, hipModuleLaunchKernel(mo->carry_blocks, ncbk, 1, 1, 256, 1, 1, 0, c->stream, a, nullptr));
+    }
+    {
+        void* a[] = {&totv, &totf, &ncbk, &rb};
+        HIP_OR_FAIL(c, hipModuleLaunchKernel(mo->carry_top, 1, 1, 1, 1024, 1, 1, 0, c->stream, a, nullptr));
+    }
+    {
+        void* a[] = {&ck, &cv, &vbk, &nk, &aggv, &aggf, &totv, &rk, &rv, &rf};
+        HIP_OR_FAIL(c, hipModuleLaunchKernel(mo->apply, nchk, 1, 1, 256, 1, 1, 0, c->stream, a, nullptr));
+    }
+    if ((s = compact_results(c, n, (const uint64_t*)rk, (const uint64_t*)rv, rf, out_keys, out_vals, m_out)) != SS_OK)
+        return s;
+    return ordered ? order_results(c, out_keys, out_vals, *m_out, params) : SS_OK;
 }
 
 }  // extern "C"

@@ -80,6 +80,9 @@ def lib():
         L.ss_semisort_less.argtypes = [vp, vp, vp, u32, u64, vp, vp, P]
         L.ss_semisort_equal_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
         L.ss_semisort_less_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
+        L.ss_monoid_compile.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.ss_monoid_destroy.argtypes = [vp]
+        L.ss_collect_reduce_user.argtypes = [vp, vp, vp, vp, u32, u64, ctypes.c_int, vp, vp, ctypes.POINTER(u64), P]
         L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
         L.ss_partition_equal.argtypes = [vp, vp, vp, u32, u64, vp, vp, vp, vp, ctypes.POINTER(u32), P]
         L.ss_collect_reduce.argtypes = [vp, vp, vp, u64, vp, vp, ctypes.POINTER(u64), P]
@@ -223,11 +226,13 @@ def _check_kv(keys, vals, allow_k32=False):
 
 
 def _check_out(name, out, like):
-    """An output tensor must match the input it stands for (device, dtype,
-    shape, contiguity): the library writes as many bytes as the input holds."""
-    if (not out.is_cuda or out.device != like.device or out.dtype != like.dtype or out.shape != like.shape
-            or not out.is_contiguous()):
-        raise ValueError(f"{name} must be a contiguous device tensor like the input ({like.dtype}, {tuple(like.shape)})")
+    """An output tensor must hold at least what the input it stands for holds
+    (device, dtype, row shape, at least as many rows, contiguous): the library
+    writes up to as many bytes as the input has."""
+    if (not out.is_cuda or out.device != like.device or out.dtype != like.dtype or out.dim() != like.dim()
+            or out.shape[1:] != like.shape[1:] or out.shape[0] < like.shape[0] or not out.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous device tensor of at least the input's size "
+                         f"({like.dtype}, {tuple(like.shape)})")
 
 
 def _ptr(t):
@@ -390,6 +395,55 @@ def _check_keys(keys, name="keys"):
 MONOIDS = {"sum": 0, "min": 1, "max": 2, "xor": 3, "first": 4, "last": 5, "affine": 6}
 
 
+class Monoid:
+    """A caller's monoid compiled for one device (ss_monoid_compile).  `source`
+    defines ss_t, ss_identity(), ss_map(ss_u64 value) and ss_combine(a, b)
+    (associative, a first in input order) as __device__ functions."""
+
+    def __init__(self, source, ctx=None, device=0):
+        ctx = ctx or context(device)
+        h = ctypes.c_void_p()
+        ctx.check(lib().ss_monoid_compile(ctx.h, source.encode(), ctypes.byref(h)))
+        self.h = h
+        self.device = ctx.device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ss_monoid_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def collect_reduce_user(keys, vals, monoid, ordered=False, params=None, ctx=None, out_keys=None, out_vals=None):
+    """ss_collect_reduce_user: (unique keys, fold of ss_map(value) over each
+    key's records in input order with the monoid's ss_combine); vals int64 or
+    int32 (uint bits).  Each result holds the element's bytes zero-extended to
+    8.  Returns views of length m of the two output tensors (capacity n each)."""
+    import torch
+    _check_keys(keys)
+    if not vals.is_cuda or vals.dtype not in (torch.int64, torch.int32) or vals.shape != keys.shape \
+            or not vals.is_contiguous():
+        raise ValueError("vals must be a contiguous int64 or int32 device tensor as long as keys")
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    if out_keys is None:
+        out_keys = torch.empty_like(keys)
+    if out_vals is None:
+        out_vals = torch.empty_like(keys)
+    _check_out("out_keys", out_keys, keys)
+    _check_out("out_vals", out_vals, keys)
+    m = ctypes.c_uint64()
+    ctx.check(lib().ss_collect_reduce_user(ctx.h, monoid.h, _ptr(keys), _ptr(vals), vals.element_size(),
+                                           keys.numel(), int(bool(ordered)), _ptr(out_keys), _ptr(out_vals),
+                                           ctypes.byref(m), ctypes.byref(params) if params is not None else None))
+    return out_keys[:m.value], out_vals[:m.value]
+
+
 def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=None, ordered=False, op="sum"):
     """ss_collect_reduce: (unique keys, wrapping uint64 sums of their values);
     ss_collect_reduce_ordered with ordered=True (keys ascending as uint64);
@@ -408,6 +462,8 @@ def collect_reduce(keys, vals, params=None, ctx=None, out_keys=None, out_sums=No
         out_keys = torch.empty_like(keys)
     if out_sums is None:
         out_sums = torch.empty_like(keys)
+    _check_out("out_keys", out_keys, keys)
+    _check_out("out_sums", out_sums, keys)
     m = ctypes.c_uint64()
     pp = ctypes.byref(params) if params is not None else None
     if op != "sum":
@@ -432,6 +488,8 @@ def histogram(keys, params=None, ctx=None, out_keys=None, out_counts=None, order
         out_keys = torch.empty_like(keys)
     if out_counts is None:
         out_counts = torch.empty_like(keys)
+    _check_out("out_keys", out_keys, keys)
+    _check_out("out_counts", out_counts, keys)
     m = ctypes.c_uint64()
     fn = lib().ss_histogram_ordered if ordered else lib().ss_histogram
     ctx.check(fn(ctx.h, _ptr(keys), keys.numel(), _ptr(out_keys), _ptr(out_counts),
@@ -446,6 +504,10 @@ def collect_reduce_async(keys, vals, d_m, out_keys, out_vals, op="sum", ordered=
     _check_keys(keys)
     _check_keys(vals, "vals")
     _check_keys(d_m, "d_m")
+    if vals.shape != keys.shape or d_m.numel() < 1:
+        raise ValueError("vals must be as long as keys, and d_m hold one entry")
+    _check_out("out_keys", out_keys, keys)
+    _check_out("out_vals", out_vals, keys)
     ctx = ctx or context(keys.device.index or 0)
     ctx._bind_stream()
     ctx.check(lib().ss_collect_reduce_async(ctx.h, _ptr(keys), _ptr(vals), keys.numel(), MONOIDS[op],
@@ -457,6 +519,10 @@ def histogram_async(keys, d_m, out_keys, out_counts, ordered=False, params=None,
     """ss_histogram_async: like histogram, with m to the device tensor d_m."""
     _check_keys(keys)
     _check_keys(d_m, "d_m")
+    if d_m.numel() < 1:
+        raise ValueError("d_m must hold one entry")
+    _check_out("out_keys", out_keys, keys)
+    _check_out("out_counts", out_counts, keys)
     ctx = ctx or context(keys.device.index or 0)
     ctx._bind_stream()
     ctx.check(lib().ss_histogram_async(ctx.h, _ptr(keys), keys.numel(), int(bool(ordered)), _ptr(out_keys),

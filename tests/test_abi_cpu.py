@@ -25,7 +25,8 @@ def test_header_declares_the_boundary():
                  "ss_server_drain", "ss_server_stats", "ss_server_destroy", "ss_server_now",
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync",
                  "ss_semisort_equal_batch_noalloc", "ss_batch", "ss_collect_reduce_async", "ss_histogram_async",
-                 "ss_workspace_bytes", "ss_workspace_held"]:
+                 "ss_workspace_bytes", "ss_workspace_held", "ss_semisort_equal_keys", "ss_semisort_less_keys",
+                 "ss_monoid_compile", "ss_monoid_destroy", "ss_collect_reduce_user"]:
         assert want in names
 
 
@@ -59,6 +60,12 @@ def test_null_context_is_rejected():
     assert L.ss_histogram_async(None, None, 10, 0, None, None, None, None) == S.SS_EINVAL
     assert L.ss_batch(None, None, 1, None) == S.SS_EINVAL
     assert L.ss_workspace_held(None, None) == S.SS_EINVAL
+    assert L.ss_semisort_equal_keys(None, None, 16, None, 8, 10, None, None, None) == S.SS_EINVAL
+    assert L.ss_semisort_less_keys(None, None, 4, None, 8, 10, None, None, None) == S.SS_EINVAL
+    h = ctypes.c_void_p()
+    assert L.ss_monoid_compile(None, b"typedef ss_u64 ss_t;", ctypes.byref(h)) == S.SS_EINVAL and not h.value
+    assert L.ss_monoid_destroy(None) == S.SS_EINVAL
+    assert L.ss_collect_reduce_user(None, None, None, None, 8, 10, 0, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_destroy(None) == S.SS_EINVAL
     assert L.ss_sync(None) == S.SS_EINVAL
     assert L.ss_last_error(None) == b"null context"

@@ -147,6 +147,6 @@ def test_rejects_what_128bit_keys_do_not_support():
     base = torch.zeros(129, dtype=torch.int64, device="cuda")
     with pytest.raises(S.SemisortError):
         S.semisort_equal(base[1:].view(64, 2), v)
-    # outputs must match the input's shape
+    # outputs must be at least as large as the input
     with pytest.raises(ValueError):
         S.semisort_equal(k, v, torch.empty(64, dtype=torch.int64, device="cuda"), torch.empty_like(v))
