@@ -204,6 +204,42 @@ def other_configs(args, S, I, torch):
     return res
 
 
+def pooled(args, S, I, torch):
+    """semisort_= at 10^9 records with the n-record temporary array T and with
+    the bounded pool in its place (temp_records = n / 16): the median of three
+    calls each, and the HBM the call needs besides input and output (the
+    workspace a fresh context holds afterwards)."""
+    n = 10 ** 9
+    res = {}
+    for wl in ("zipf1.2_hashed", "uniform1e9"):
+        keys, vals = I.t_workload(wl, n, CONFIG_SEEDS[wl], "cuda")
+        ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+        for pool in (0, n // 16):
+            ctx = S.Context(0)
+            try:
+                prm = S.default_params(temp_records=pool)
+                S.semisort_equal(keys, vals, ko, vo, params=prm, ctx=ctx)
+                ctx.sync()
+                times = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    S.semisort_equal(keys, vals, ko, vo, params=prm, ctx=ctx)
+                    ctx.sync()
+                    times.append((time.perf_counter() - t0) * 1e3)
+                held = ctx.workspace_held()
+            finally:
+                ctx.close()
+            ms = sorted(times)[1]
+            io = n * (keys.element_size() + vals.element_size()) * 2
+            key = f"semisort_= {wl} {'pool n/16' if pool else 'T'}"
+            res[key] = {"ms": round(ms, 3), "ms_runs": [round(t, 3) for t in times], "grecs": round(n / ms / 1e6, 2),
+                        "workspace_bytes": held, "footprint_bytes": io + held}
+            log(f"pooled: {key}: {res[key]}")
+        del keys, vals, ko, vo
+        torch.cuda.empty_cache()
+    return res
+
+
 def small_config(args, S, I, torch):
     """n = 10^6 records, keys uniform in [0, 10^5) (about ten records per
     key), values the record index: the launch chain of one semisort_= call,
@@ -605,6 +641,7 @@ def main():
             out["small"] = small_config(args, S, I, torch)
             out["configs"] = other_configs(args, S, I, torch)
             out["applications"] = transposes(args, S, I, torch)
+            out["pooled"] = pooled(args, S, I, torch)
         if not args.no_batch:
             out["batched"] = batched(args, S, I, torch)
         if not args.no_serve:

@@ -72,6 +72,12 @@ typedef struct {
     uint32_t heavy_min;    /* tau: a key sampled at least tau times is heavy (default 3; 0 = ceil(ln n'),
                               the paper's rule).  At most 512 keys per subproblem are heavy: if more
                               reach tau, tau rises to the least value that leaves at most 512. */
+    uint32_t temp_records; /* 0 (default): semisort holds an n-record temporary array T.  Otherwise,
+                              when the output is not the input (keys_out != keys), the first level
+                              writes every bucket to the output and the levels below refine their
+                              subproblems in groups through a pool of this many records (raised to
+                              the largest subproblem if that is longer), in place of T.  In-place
+                              calls, the reductions and the capturable batch keep T. */
     uint64_t seed;         /* sampling seed */
 } ss_params;
 

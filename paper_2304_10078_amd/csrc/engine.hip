@@ -313,6 +313,7 @@ struct Params {
     uint32_t nl0, alpha, c, tmin, tmax, mode, tau;
     uint32_t tmax0, tmaxd;  // tile limits of the first and of the deeper levels
     bool auto_tiles;        // defaults apply: the first level's sample may choose smaller tiles
+    uint32_t pool;          // records of the pool that replaces T below the first level (0: T)
     uint64_t seed;
 };
 
@@ -328,6 +329,7 @@ ss_status resolve_params(ss_ctx* c, const ss_params* in, Params* p)
     p->tmax = s.tile_max ? s.tile_max : 65536u;
     p->mode = s.hash_mode;
     p->tau = s.heavy_min;
+    p->pool = s.temp_records;
     p->seed = s.seed;
     if (p->nl0 < 1 || p->nl0 > kLightBitsMax) return fail(c, SS_EINVAL, "n_light_log2 must be in [1, 10]");
     if (p->alpha < 64 || p->alpha > kAlphaMax) return fail(c, SS_EINVAL, "base_case must be in [64, 4096]");
@@ -702,6 +704,9 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
 {
     const uint64_t n = offs[ninst];
     const bool inplace = keys_out == keys;
+    // bounded temporary: the first level writes every bucket to the output,
+    // the levels below refine groups of subproblems through a pool
+    const bool pooled = p.pool != 0 && !inplace;
     c->call_tmaxd = 0;
     ss_status s;
     if ((s = stage_wait(c)) != SS_OK) return s;
@@ -734,8 +739,10 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     for (const Seg& sg : c->host_segs) records += sg.len;
     if (nsegs) {
         host_prefix(c->host_segs, p, &tiles, &chunks, &tile);
-        if ((s = ensure(c, c->t_keys, n * sizeof(K))) != SS_OK) return s;
-        if ((s = ensure(c, c->t_vals, n * sizeof(V))) != SS_OK) return s;
+        if (!pooled) {
+            if ((s = ensure(c, c->t_keys, n * sizeof(K))) != SS_OK) return s;
+            if ((s = ensure(c, c->t_vals, n * sizeof(V))) != SS_OK) return s;
+        }
         if ((s = ensure(c, c->bids, n * 2)) != SS_OK) return s;
     }
     if ((s = ensure(c, c->info, sizeof(LevelInfo))) != SS_OK) return s;
@@ -781,10 +788,14 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     int cur = 0;
     HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, c->seg_stage, nsegs * sizeof(Seg), hipMemcpyHostToDevice, c->stream));
 
-    const uint64_t* loc_k = keys;
-    const void* loc_v = vals;
+    // Where the current level's records are; T is the temporary array, or
+    // the pool placed so that the current group's positions index it.
+    enum Where { kInput, kOut, kTemp };
+    Where loc = kInput;
     uint64_t* T_k = (uint64_t*)c->t_keys.p;
     void* T_v = c->t_vals.p;
+    auto kptr = [&](Where w) -> uint64_t* { return w == kInput ? (uint64_t*)keys : w == kOut ? keys_out : T_k; };
+    auto vptr = [&](Where w) -> void* { return w == kInput ? (void*)vals : w == kOut ? vals_out : T_v; };
     bool fill_used[2] = {false, false};
     // on an early error return, do not leave a fill running into the caller's buffers
     struct AuxGuard {
@@ -795,35 +806,32 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
             if (armed && c->aux) (void)hipStreamSynchronize(c->aux);
         }
     } guard{c};
-    for (uint32_t level = 0; nsegs; ++level) {
-        // Where this level writes: buckets that need more work go to the buffer
-        // that is not the source; final buckets go straight to the output
-        // unless the output is the source (other blocks still read it).
-        uint64_t* dst_k;
-        void* dst_v;
-        uint64_t* fin_k;
-        void* fin_v;
-        if (loc_k == keys_out) {
-            dst_k = fin_k = T_k;
-            dst_v = fin_v = T_v;
-        } else if (loc_k == T_k) {
-            dst_k = fin_k = keys_out;
-            dst_v = fin_v = vals_out;
-        } else {  // the caller's input, distinct from the output
-            dst_k = T_k;
-            dst_v = T_v;
-            fin_k = keys_out;
-            fin_v = vals_out;
+    // One level over the current subproblem list (segs[cur]); all_to_out:
+    // every bucket goes to the output (the first level of the pooled form).
+    auto step = [&](uint32_t level, bool all_to_out) -> ss_status {
+        ss_status s;
+        // Buckets that need more work go to the buffer that is not the
+        // source; final buckets go straight to the output unless the output
+        // is the source (other blocks still read it).
+        Where dst, fin;
+        if (all_to_out) dst = fin = kOut;
+        else if (loc == kOut) dst = fin = kTemp;
+        else if (loc == kTemp) dst = fin = kOut;
+        else {  // the caller's input, distinct from the output
+            dst = kTemp;
+            fin = kOut;
         }
+        uint64_t* dst_k = kptr(dst);
+        void* dst_v = vptr(dst);
         if ((s = ensure_level(c, nsegs, tiles, chunks, kWide<K>)) != SS_OK) return s;
         if ((s = reset_counters(c)) != SS_OK) return s;
-        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, loc_k, loc_v, dst_k, dst_v, fin_k,
-                                fin_v);
+        LevelArgs a = make_args(c, p, level, (Seg*)c->segs[cur].p, nsegs, tile, kptr(loc), vptr(loc), dst_k, dst_v,
+                                kptr(fin), vptr(fin));
         // one-key buckets written to the output: only their values move,
         // their keys are filled as constant runs on the second stream while
         // the next level runs (the two touch disjoint ranges).  128-bit keys
         // move with their values.
-        const bool fill = !kWide<K> && fin_k == keys_out;
+        const bool fill = !kWide<K> && fin == kOut;
         const int fb = level & 1;
         a.fill_heavy = fill;
         if (level == 0 && p.auto_tiles && nsegs == 1 && p.mode != 2) {
@@ -865,7 +873,7 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         LevelInfo li;
-        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin_k == keys_out, false, fill, &li,
+        if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin == kOut, false, fill, &li,
                             KeyTraits<K>::hash_bits)) != SS_OK)
             return s;
         if constexpr (!kWide<K>) if (li.nfills) {
@@ -886,9 +894,69 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         tiles = li.tiles;
         chunks = li.chunks;
         tile = li.tile;
-        loc_k = dst_k;
-        loc_v = dst_v;
+        loc = dst;
         cur ^= 1;
+        return SS_OK;
+    };
+    uint32_t level = 0;
+    if (!pooled) {
+        while (nsegs)
+            if ((s = step(level++, false)) != SS_OK) return s;
+    } else {
+        if ((s = step(level++, true)) != SS_OK) return s;
+        if (nsegs) {
+            // the subproblems below the first level, on the host, in ascending
+            // positions (the planning step lists each subproblem's buckets
+            // thread by thread)
+            const uint32_t nall = nsegs;
+            if ((s = ensure_pinned(c, (void**)&c->seg_stage, &c->seg_stage_cap, (size_t)nall * sizeof(Seg))) != SS_OK)
+                return s;
+            HIP_OR_FAIL(c, hipMemcpyAsync(c->seg_stage, c->segs[cur].p, (size_t)nall * sizeof(Seg),
+                                          hipMemcpyDeviceToHost, c->stream));
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+            std::vector<Seg> all(c->seg_stage, c->seg_stage + nall);
+            std::sort(all.begin(), all.end(), [](const Seg& x, const Seg& y) { return x.start < y.start; });
+            // groups of consecutive subproblems spanning at most `cap`
+            // positions, cap = the pool size, or the longest subproblem
+            uint64_t cap = p.pool;
+            for (const Seg& sg : all) cap = std::max<uint64_t>(cap, sg.len);
+            cap = std::min<uint64_t>(cap, n);
+            if ((s = ensure(c, c->t_keys, cap * sizeof(K))) != SS_OK) return s;
+            if ((s = ensure(c, c->t_vals, cap * sizeof(V))) != SS_OK) return s;
+            const uint32_t tile1 = tile;
+            for (uint32_t i0 = 0; i0 < nall;) {
+                const uint64_t g0 = all[i0].start;
+                uint32_t i1 = i0 + 1;
+                while (i1 < nall && (uint64_t)all[i1].start + all[i1].len - g0 <= cap) ++i1;
+                // the group's subarrays numbered from 0 (same subarray size)
+                uint32_t gt = 0, gc = 0;
+                uint64_t grec = 0;
+                for (uint32_t j = i0; j < i1; ++j) {
+                    Seg sg = all[j];
+                    sg.tile0 = gt;
+                    sg.chunk0 = gc;
+                    gt += sg.ntiles;
+                    gc += (sg.ntiles + kChunk - 1) / kChunk;
+                    grec += sg.len;
+                    c->seg_stage[j - i0] = sg;
+                }
+                nsegs = i1 - i0;
+                if ((s = ensure(c, c->segs[cur], (size_t)std::max(nsegs, seg_cap) * sizeof(Seg))) != SS_OK) return s;
+                HIP_OR_FAIL(c, hipMemcpyAsync(c->segs[cur].p, c->seg_stage, (size_t)nsegs * sizeof(Seg),
+                                              hipMemcpyHostToDevice, c->stream));
+                tiles = gt;
+                chunks = gc;
+                records = grec;
+                tile = tile1;
+                // the pool stands for positions [g0, g0 + cap)
+                T_k = (uint64_t*)((char*)c->t_keys.p - (size_t)g0 * sizeof(K));
+                T_v = (char*)c->t_vals.p - (size_t)g0 * sizeof(V);
+                loc = kOut;
+                for (uint32_t lv = level; nsegs; ++lv)
+                    if ((s = step(lv, false)) != SS_OK) return s;
+                i0 = i1;
+            }
+        }
     }
     // The last level's base cases and fills are left running: the call
     // returns once they are enqueued (the stream waits for the fills), and a
@@ -1644,6 +1712,7 @@ ss_status ss_default_params(ss_params* p)
     p->tile_max = 0;  // by operation (equal_tiles)
     p->hash_mode = SS_HASH_MIX64;
     p->heavy_min = 3;
+    p->temp_records = 0;
     p->seed = 0x5eed5eed2023ULL;
     return SS_OK;
 }

@@ -37,6 +37,7 @@ class ss_params(ctypes.Structure):
         ("tile_max", ctypes.c_uint32),
         ("hash_mode", ctypes.c_uint32),
         ("heavy_min", ctypes.c_uint32),
+        ("temp_records", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
     ]
 

@@ -272,6 +272,16 @@ def test_full_size_semisort_equal_zipf12_128bit_keys():
         assert torch.equal(got, want), f"group of key {k.tolist()} differs from the input positions"
 
 
+def test_full_size_semisort_equal_pooled_uniform_1e9():
+    # the bounded-temporary form: every level-1 subproblem refined through a
+    # pool of n/16 records (uniform keys: all records reach level 1)
+    keys, vals = _indexed("uniform1e9", 2)
+    _say("case: semisort_= uniform[0,1e9) n=1e9 with a pool of n/16 records")
+    ko, vo = S.semisort_equal(keys, vals, params=S.default_params(temp_records=N // 16))
+    S.sync()
+    _check_grouping(keys, ko, vo, ordered=False, seed=10)
+
+
 def test_full_size_histogram_exponential():
     keys, _ = I.t_workload("exp1e-5_u32idx", N, 5, "cuda")
     _say("case: ordered histogram exp(1e-5) n=1e9")
