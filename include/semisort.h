@@ -305,6 +305,21 @@ ss_status ss_autotune_equal_batch(ss_ctx* ctx, const uint64_t* keys, const void*
                                   uint64_t* keys_out, void* vals_out, uint32_t reps,
                                   ss_params* best, double* best_ms);
 
+/* Batched semisort_= with cached tuned parameters: the batch's class (key and
+ * value widths, and the binary orders of its total size and of its mean
+ * instance size) selects parameters the context tuned before; on the first
+ * batch of a class, ss_autotune_equal_batch (one timed run per candidate)
+ * picks them and the context keeps them.  Either way the outputs hold the
+ * batch's result; *used receives the parameters and *tuned_now 1 when this
+ * call tuned (both may be NULL).  Arguments as for ss_autotune_equal_batch.
+ * ss_autotune_cache: with clear != 0 forgets every class; *entries receives
+ * the number of classes kept (may be NULL). */
+ss_status ss_semisort_equal_batch_tuned(ss_ctx* ctx, const uint64_t* keys, const void* vals,
+                                        uint32_t val_bytes, const uint64_t* seg_offsets, uint64_t nseg,
+                                        uint64_t* keys_out, void* vals_out, ss_params* used,
+                                        int* tuned_now);
+ss_status ss_autotune_cache(ss_ctx* ctx, int clear, uint64_t* entries);
+
 /* semisort_< (Section 2.1 with the comparison base case of Section 3.3):
  * reorders the records into ascending key order, records with equal keys in
  * input order (stable).  The result is unique: a stable sort by key.

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -114,7 +115,8 @@ struct ss_ctx {
     uint32_t nl_target = 0;   // adaptive light-bucket target, percent of alpha; 0: per bucketing (ss_set_option)
     uint32_t tile0 = 0, tile_deep = 0;  // tile limits of the first / deeper levels, 0 = tile_max (ss_set_option)
     uint32_t call_tmaxd = 0;            // deeper-level tile limit chosen by the current call (0: Params)
-    uint32_t fold_round = 1024;         // block totals per round of the in-order fold's top carry (ss_set_option)
+    uint32_t fold_round = 1024;
+    std::map<uint64_t, ss_params> tuned;  // autotuned batch parameters by batch class         // block totals per round of the in-order fold's top carry (ss_set_option)
     // kernel timing with HIP events on the context's stream (ss_profile_*)
     bool prof_on = false;
     struct Pending {
@@ -2086,6 +2088,48 @@ ss_status ss_autotune_equal_batch(ss_ctx* c, const uint64_t* keys, const void* v
     if ((s = ss_sync(c)) != SS_OK) return s;
     *best = cand[bi];
     *best_ms = best_t;
+    return SS_OK;
+}
+
+// Class of a batch for the autotuned parameters: the operation, key and value
+// widths, and the binary orders of the total size and of the mean instance size.
+static uint64_t batch_class(int op, uint32_t kb, uint32_t vb, uint64_t n, uint64_t nseg)
+{
+    auto lg = [](uint64_t x) -> uint64_t { return x ? 63 - (uint64_t)__builtin_clzll(x) : 0; };
+    return ((uint64_t)op << 40) | ((uint64_t)kb << 32) | ((uint64_t)vb << 24) | (lg(n) << 8) |
+           lg(nseg ? n / nseg : 0);
+}
+
+ss_status ss_semisort_equal_batch_tuned(ss_ctx* c, const uint64_t* keys, const void* vals, uint32_t vb,
+                                        const uint64_t* offs, uint64_t nseg, uint64_t* keys_out, void* vals_out,
+                                        ss_params* used, int* tuned_now)
+{
+    if (!c) return SS_EINVAL;
+    if (!offs) return fail(c, SS_EINVAL, "null seg_offsets");
+    if (nseg == 0) return fail(c, SS_EINVAL, "empty batch");
+    const uint64_t cls = batch_class(SS_OP_SEMISORT_EQUAL, 8, vb, offs[nseg], nseg);
+    auto it = c->tuned.find(cls);
+    ss_status s;
+    if (it == c->tuned.end()) {
+        ss_params best;
+        double ms = 0;
+        if ((s = ss_autotune_equal_batch(c, keys, vals, vb, offs, nseg, keys_out, vals_out, 1, &best, &ms)) != SS_OK)
+            return s;
+        c->tuned[cls] = best;
+        if (used) *used = best;
+        if (tuned_now) *tuned_now = 1;
+        return SS_OK;
+    }
+    if (used) *used = it->second;
+    if (tuned_now) *tuned_now = 0;
+    return ss_semisort_equal_batch(c, keys, vals, vb, offs, nseg, keys_out, vals_out, &it->second);
+}
+
+ss_status ss_autotune_cache(ss_ctx* c, int clear, uint64_t* entries)
+{
+    if (!c) return SS_EINVAL;
+    if (clear) c->tuned.clear();
+    if (entries) *entries = c->tuned.size();
     return SS_OK;
 }
 

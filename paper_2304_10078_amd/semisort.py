@@ -82,6 +82,8 @@ def lib():
         L.ss_semisort_equal_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
         L.ss_semisort_less_keys.argtypes = [vp, vp, u32, vp, u32, u64, vp, vp, P]
         L.ss_monoid_compile.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.ss_semisort_equal_batch_tuned.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P, ctypes.POINTER(ctypes.c_int)]
+        L.ss_autotune_cache.argtypes = [vp, ctypes.c_int, ctypes.POINTER(u64)]
         L.ss_monoid_destroy.argtypes = [vp]
         L.ss_collect_reduce_user.argtypes = [vp, vp, vp, vp, u32, u64, ctypes.c_int, vp, vp, ctypes.POINTER(u64), P]
         L.ss_semisort_less_batch.argtypes = [vp, vp, vp, u32, vp, u64, vp, vp, P]
@@ -585,6 +587,40 @@ def transpose_csr(offsets, cols, params=None, ctx=None, out_offsets=None, out_co
                                      _ptr(out_offsets), _ptr(out_cols),
                                      ctypes.byref(params) if params is not None else None))
     return out_offsets, out_cols
+
+
+def semisort_equal_batch_tuned(keys, vals, seg_offsets, keys_out=None, vals_out=None, ctx=None):
+    """ss_semisort_equal_batch_tuned: the batch semisorted with the parameters
+    the context tuned for its class (tuning them on the first batch of a
+    class).  Returns (keys_out, vals_out, parameters used, tuned now)."""
+    import numpy as np
+    import torch
+    vb = _check_kv(keys, vals)
+    ctx = ctx or context(keys.device.index or 0)
+    ctx._bind_stream()
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.uint64))
+    if keys_out is None:
+        keys_out = torch.empty_like(keys)
+    if vals_out is None:
+        vals_out = torch.empty_like(vals)
+    _check_out("keys_out", keys_out, keys)
+    _check_out("vals_out", vals_out, vals)
+    used = ss_params()
+    now = ctypes.c_int()
+    ctx.check(lib().ss_semisort_equal_batch_tuned(ctx.h, _ptr(keys), _ptr(vals), vb,
+                                                  offs.ctypes.data_as(ctypes.c_void_p), offs.size - 1,
+                                                  _ptr(keys_out), _ptr(vals_out), ctypes.byref(used),
+                                                  ctypes.byref(now)))
+    return keys_out, vals_out, used, bool(now.value)
+
+
+def autotune_cache(clear=False, ctx=None, device=0):
+    """ss_autotune_cache: number of batch classes with tuned parameters (after
+    forgetting them all with clear=True)."""
+    ctx = ctx or context(device)
+    e = ctypes.c_uint64()
+    ctx.check(lib().ss_autotune_cache(ctx.h, int(bool(clear)), ctypes.byref(e)))
+    return e.value
 
 
 def autotune_equal_batch(keys, vals, seg_offsets, keys_out=None, vals_out=None, reps=2, ctx=None):

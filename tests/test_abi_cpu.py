@@ -26,7 +26,8 @@ def test_header_declares_the_boundary():
                  "ss_partition_equal", "ss_default_params", "ss_last_error", "ss_sync",
                  "ss_semisort_equal_batch_noalloc", "ss_batch", "ss_collect_reduce_async", "ss_histogram_async",
                  "ss_workspace_bytes", "ss_workspace_held", "ss_semisort_equal_keys", "ss_semisort_less_keys",
-                 "ss_monoid_compile", "ss_monoid_destroy", "ss_collect_reduce_user"]:
+                 "ss_monoid_compile", "ss_monoid_destroy", "ss_collect_reduce_user",
+                 "ss_semisort_equal_batch_tuned", "ss_autotune_cache"]:
         assert want in names
 
 
@@ -65,6 +66,8 @@ def test_null_context_is_rejected():
     h = ctypes.c_void_p()
     assert L.ss_monoid_compile(None, b"typedef ss_u64 ss_t;", ctypes.byref(h)) == S.SS_EINVAL and not h.value
     assert L.ss_monoid_destroy(None) == S.SS_EINVAL
+    assert L.ss_semisort_equal_batch_tuned(None, None, None, 8, None, 1, None, None, None, None) == S.SS_EINVAL
+    assert L.ss_autotune_cache(None, 1, None) == S.SS_EINVAL
     assert L.ss_collect_reduce_user(None, None, None, None, 8, 10, 0, None, None, ctypes.byref(m), None) == S.SS_EINVAL
     assert L.ss_destroy(None) == S.SS_EINVAL
     assert L.ss_sync(None) == S.SS_EINVAL

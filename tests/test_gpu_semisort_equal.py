@@ -218,6 +218,43 @@ def test_autotuner_returns_a_grid_point_and_a_correct_result():
         assert_semisort_equal(k[a:b], v[a:b], ko[a:b], vo[a:b], ctx=f"tuned instance {i}")
 
 
+def test_tuned_batches_reuse_the_parameters_of_their_class():
+    ctx = S.Context(0)
+    try:
+        assert S.autotune_cache(ctx=ctx) == 0
+        k, v, offs, d = I.np_batch_workload(48, 1e3, 3e4, 5e5, 12)
+        kd, vd = to_dev(k), to_dev(v)
+        _say(f"case: tuned batch (first of its class), n={k.size}")
+        ko, vo, used, now = S.semisort_equal_batch_tuned(kd, vd, offs, ctx=ctx)
+        ctx.sync()
+        assert now and S.autotune_cache(ctx=ctx) == 1
+        first = (used.sample_mult, used.heavy_min, used.n_light_log2, used.base_case, used.tile_max)
+        hk, hv = to_host(ko, np.uint64), to_host(vo, np.uint64)
+        for i in range(48):
+            a, b = int(offs[i]), int(offs[i + 1])
+            assert_semisort_equal(k[a:b], v[a:b], hk[a:b], hv[a:b], ctx=f"tuned instance {i}")
+        # another batch of the same class: no tuning, the same parameters,
+        # the result of the plain batch call with them
+        # (the same instance sizes, other keys)
+        k2, v2, offs2 = k[::-1].copy(), v, offs
+        _say("case: tuned batch (same class)")
+        ko2, vo2, used2, now2 = S.semisort_equal_batch_tuned(to_dev(k2), to_dev(v2), offs2, ctx=ctx)
+        rk, rv = S.semisort_equal_batch(to_dev(k2), to_dev(v2), offs2, params=used2, ctx=ctx)
+        ctx.sync()
+        assert not now2 and S.autotune_cache(ctx=ctx) == 1
+        assert (used2.sample_mult, used2.heavy_min, used2.n_light_log2, used2.base_case, used2.tile_max) == first
+        assert torch.equal(ko2, rk) and torch.equal(vo2, rv)
+        # a batch of another size class is tuned on its own
+        k3, v3, offs3, _ = I.np_batch_workload(8, 1e3, 3e3, 2e4, 14)
+        _say("case: tuned batch (another class)")
+        S.semisort_equal_batch_tuned(to_dev(k3), to_dev(v3), offs3, ctx=ctx)
+        ctx.sync()
+        assert S.autotune_cache(ctx=ctx) == 2
+        assert S.autotune_cache(clear=True, ctx=ctx) == 0
+    finally:
+        ctx.close()
+
+
 @pytest.mark.parametrize("t0,td", [(8192, 8192), (65536, 65536), (16384, 65536)])
 def test_subarray_limits_do_not_change_the_result(t0, td):
     """The output of semisort_= depends only on the buckets and the input
