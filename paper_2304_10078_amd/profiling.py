@@ -58,7 +58,7 @@ def _col(header, *want):
     raise KeyError(f"none of {want} in {header}")
 
 
-def kstats(path, out, cmd, top=25):
+def kstats(path, out, cmd, top=10):
     with open(path, newline="") as f:
         r = csv.reader(f)
         hdr = next(r)
@@ -66,11 +66,18 @@ def kstats(path, out, cmd, top=25):
     ni, ci, ti, ai = (_col(hdr, "Name"), _col(hdr, "Calls"), _col(hdr, "TotalDurationNs"), _col(hdr, "AverageNs"))
     mi, xi, pi = _col(hdr, "MinNs"), _col(hdr, "MaxNs"), _col(hdr, "Percentage")
     rows.sort(key=lambda x: -float(x[ti]))
-    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", cmd, "```", "",
-             "| kernel | calls | total ms | avg ms | min ms | max ms | % |", "|---|---|---|---|---|---|---|"]
-    for x in rows[:top]:
-        lines.append(f"| `{short_name(x[ni])}` | {int(x[ci])} | {float(x[ti]) / 1e6:.3f} | {float(x[ai]) / 1e6:.4f} "
-                     f"| {float(x[mi]) / 1e6:.4f} | {float(x[xi]) / 1e6:.4f} | {float(x[pi]):.2f} |")
+    # every kernel of the engine, then the largest others (the input's
+    # generation and statistics, outside the timed region)
+    ours = [x for x in rows if short_name(x[ni]).startswith("k_")]
+    others = [x for x in rows if not short_name(x[ni]).startswith("k_")]
+    lines = ["# rocprofv3 kernel statistics", "", "Command:", "", "```", cmd, "```", ""]
+    head = ["| kernel | calls | total ms | avg ms | min ms | max ms | % |", "|---|---|---|---|---|---|---|"]
+
+    def row(x):
+        return (f"| `{short_name(x[ni])}` | {int(x[ci])} | {float(x[ti]) / 1e6:.3f} | {float(x[ai]) / 1e6:.4f} "
+                f"| {float(x[mi]) / 1e6:.4f} | {float(x[xi]) / 1e6:.4f} | {float(x[pi]):.2f} |")
+    lines += ["Engine kernels:", ""] + head + [row(x) for x in ours]
+    lines += ["", f"Largest other kernels (of {len(others)}):", ""] + head + [row(x) for x in others[:top]]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
 
