@@ -950,9 +950,12 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
                 chunks = gc;
                 records = grec;
                 tile = tile1;
-                // the pool stands for positions [g0, g0 + cap)
-                T_k = (uint64_t*)((char*)c->t_keys.p - (size_t)g0 * sizeof(K));
-                T_v = (char*)c->t_vals.p - (size_t)g0 * sizeof(V);
+                // the pool stands for positions [g0, g0 + cap): its address
+                // less g0 records, so that the kernels' absolute positions
+                // land in it (formed as an integer: only positions of the
+                // group are ever added back)
+                T_k = (uint64_t*)((uintptr_t)c->t_keys.p - (uintptr_t)g0 * sizeof(K));
+                T_v = (void*)((uintptr_t)c->t_vals.p - (uintptr_t)g0 * sizeof(V));
                 loc = kOut;
                 for (uint32_t lv = level; nsegs; ++lv)
                     if ((s = step(lv, false)) != SS_OK) return s;
