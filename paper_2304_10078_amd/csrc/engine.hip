@@ -793,7 +793,9 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
     // Where the current level's records are; T is the temporary array, or
     // the pool placed so that the current group's positions index it.
     enum Where { kInput, kOut, kTemp };
-    Where loc = kInput;
+    // in place, the caller's input is the output: the first level must not
+    // write final buckets there while other blocks still read it
+    Where loc = inplace ? kOut : kInput;
     uint64_t* T_k = (uint64_t*)c->t_keys.p;
     void* T_v = c->t_vals.p;
     auto kptr = [&](Where w) -> uint64_t* { return w == kInput ? (uint64_t*)keys : w == kOut ? keys_out : T_k; };

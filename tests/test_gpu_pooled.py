@@ -130,3 +130,23 @@ def test_pooled_workspace_is_the_pool_not_T():
     # (or the longest subproblem) of those
     assert held[0] >= 16 * n
     assert held[n // 16] < held[0] - 12 * n
+
+
+@pytest.mark.parametrize("name", ["zipf1.2_hashed", "uniform1e9", "zipf1.2_hashed_k32", "zipf1.2_hashed_k128"])
+def test_in_place_equals_out_of_place(name):
+    # In place, the first level must send every bucket to T (the output is
+    # the array other blocks still read); the result is the out-of-place
+    # call's, bit for bit, for both semisorts and every key width.
+    n = 8_000_009
+    k, _ = I.np_workload(name, n, 87)
+    v = np.arange(n, dtype=np.uint64)
+    less_ops = (False,) if k.ndim == 2 else (False, True)
+    for less in less_ops:
+        fn = S.semisort_less if less else S.semisort_equal
+        kd, vd = _dev_keys(k), to_dev(v)
+        ok, ov = fn(kd, vd)
+        ik, iv = kd.clone(), vd.clone()
+        _say(f"case: in place {name} n={n} less={less}")
+        fn(ik, iv, ik, iv)
+        S.sync()
+        assert torch.equal(ik, ok) and torch.equal(iv, ov), f"{name} less={less}: in place differs"
