@@ -195,8 +195,9 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
  *     64-bit value, so SS_HASH_MIX64 stays a bijection and the result equals
  *     the 64-bit call's on the zero-extended keys; its records move 4 bytes
  *     less per key through every pass.
- *   16 (semisort_= only): 128-bit keys, each two uint64 words, low word first,
- *     compared for equality as whole keys; keys and keys_out 16-byte aligned.
+ *   16: 128-bit keys, each two uint64 words, low word first, compared as whole
+ *     keys (semisort_<: as 128-bit unsigned numbers); keys and keys_out
+ *     16-byte aligned.
  *     SS_HASH_MIX64 hashes a key to 128 bits by a bijection (x = fmix64(low),
  *     then fmix64(high ^ x)); SS_HASH_IDENTITY uses the words themselves, low
  *     word first, which is slow when many keys share a low word (each level
@@ -206,9 +207,16 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
  *     Workspace: beyond what ss_workspace_bytes reports for 8-byte keys, 8
  *     bytes more per record (temporary keys of 16 bytes) and 8 KB per
  *     subproblem of a level (the sampled key of every heavy id).
- * SS_EINVAL for another key_bytes, 16 with semisort_<, or a misaligned
- * 16-byte key array; otherwise the arguments, conventions and errors of the
- * 64-bit calls (in place: keys_out == keys and vals_out == vals). */
+ *     semisort_< of 128-bit keys runs the stable semisort_= (the hash mode as
+ *     given), numbers the runs of equal keys, sorts the m runs by key with two
+ *     stable semisort_< passes over (word, run) pairs (low word, then high
+ *     word) and scatters every record to its run's place; it holds the grouped
+ *     records (n * (16 + val_bytes) bytes), a run number per record (4 n) and
+ *     about 48 bytes per run besides the semisorts' own workspace, and waits
+ *     once for m.
+ * SS_EINVAL for another key_bytes or a misaligned 16-byte key array;
+ * otherwise the arguments, conventions and errors of the 64-bit calls (in
+ * place: keys_out == keys and vals_out == vals). */
 ss_status ss_semisort_equal_keys(ss_ctx* ctx, const void* keys, uint32_t key_bytes, const void* vals,
                                  uint32_t val_bytes, uint64_t n, void* keys_out, void* vals_out,
                                  const ss_params* params);

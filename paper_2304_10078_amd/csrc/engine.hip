@@ -83,6 +83,7 @@ struct ss_ctx {
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
     DevBuf bkey;                     // keys of one-key buckets
     DevBuf hrep;                     // 128-bit keys: one sampled key per heavy id
+    DevBuf wl_gk, wl_gv, wl_run, wl_chunk, wl_desc;  // semisort_< of 128-bit keys: grouped records, runs
     DevBuf top;                      // two most sampled heavy buckets per subproblem
     DevBuf fills[2];                 // key-fill job lists (alternating levels)
     uint32_t fill_cap[2] = {0, 0};
@@ -1767,6 +1768,7 @@ ss_status ss_destroy(ss_ctx* c)
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->hrep, &c->top, &c->fills[0], &c->fills[1],
+                      &c->wl_gk, &c->wl_gv, &c->wl_run, &c->wl_chunk, &c->wl_desc,
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
                       &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos,
                       &c->pk_k, &c->pk_v, &c->po_k, &c->po_v, &c->pack_tab, &c->pack_rank};
@@ -1907,18 +1909,114 @@ ss_status ss_semisort_equal(ss_ctx* c, const uint64_t* keys, const void* vals, u
                    : run_semisort<uint32_t>(c, keys, vals, offs, 1, keys_out, vals_out, p);
 }
 
+}  // extern "C"
+
+// semisort_< of 128-bit keys (Section 2.1: groups in ascending key order,
+// records of a key in input order): a stable semisort_= of the records puts
+// every key's records in one run; the runs are numbered and sorted by key with
+// two stable semisort_< passes over (word, run) pairs, low word first, so that
+// the high word decides and the low word breaks its ties; a scatter then moves
+// every record to its run's place in that order.  p holds the caller's hash
+// mode for the semisort_=.
+template <typename V>
+ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint64_t n, uint64_t* keys_out,
+                        void* vals_out, const ss_params* params, const Params& p)
+{
+    ss_status s;
+    if ((s = ensure(c, c->wl_gk, n * 16)) != SS_OK) return s;
+    if ((s = ensure(c, c->wl_gv, n * sizeof(V))) != SS_OK) return s;
+    Key128* gk = (Key128*)c->wl_gk.p;
+    V* gv = (V*)c->wl_gv.p;
+    {
+        Params q = p;
+        default_tiles(c, params, &q, 32768u, 16384u);
+        const uint64_t offs[2] = {0, n};
+        if ((s = run_semisort<V, Key128>(c, keys, vals, offs, 1, (uint64_t*)gk, gv, q)) != SS_OK) return s;
+    }
+    // runs of the grouped records
+    const uint64_t nch = (n + kRunChunk - 1) / kRunChunk;
+    if ((s = ensure(c, c->wl_chunk, (nch + 2) * 4)) != SS_OK) return s;
+    if ((s = ensure(c, c->wl_run, n * 4)) != SS_OK) return s;
+    uint32_t* chunk = (uint32_t*)c->wl_chunk.p;
+    uint32_t* dtotal = chunk + nch;
+    uint32_t* run = (uint32_t*)c->wl_run.p;
+    hipLaunchKernelGGL(k_runs_count, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n, chunk);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, chunk, (uint32_t)nch, dtotal);
+    HIP_OR_FAIL(c, hipGetLastError());
+    uint32_t m = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, dtotal, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    memcpy(&m, c->info_host, 4);
+    if (m == 0 || m > n) return fail(c, SS_EINVAL, "run count out of range");
+    // per run: start, words, and the arrays of the two sorts
+    const uint64_t mch = (m + kRunChunk - 1) / kRunChunk;
+    auto al = [](uint64_t b) { return (b + 255) & ~(uint64_t)255; };
+    const uint64_t o_gstart = 0, o_glo = o_gstart + al(m * 4ull), o_ghi = o_glo + al(m * 8ull),
+                   o_idx = o_ghi + al(m * 8ull), o_slo = o_idx + al(m * 4ull), o_sidx = o_slo + al(m * 8ull),
+                   o_len = o_sidx + al(m * 4ull), o_dest = o_len + al(m * 4ull), o_csum = o_dest + al(m * 4ull),
+                   o_end = o_csum + al((mch + 2) * 4);
+    if ((s = ensure(c, c->wl_desc, o_end)) != SS_OK) return s;
+    char* d = (char*)c->wl_desc.p;
+    uint32_t* gstart = (uint32_t*)(d + o_gstart);
+    uint64_t* glo = (uint64_t*)(d + o_glo);
+    uint64_t* ghi = (uint64_t*)(d + o_ghi);
+    uint32_t* idx = (uint32_t*)(d + o_idx);
+    uint64_t* slo = (uint64_t*)(d + o_slo);
+    uint32_t* sidx = (uint32_t*)(d + o_sidx);
+    uint32_t* len = (uint32_t*)(d + o_len);
+    uint32_t* dest = (uint32_t*)(d + o_dest);
+    uint32_t* csum = (uint32_t*)(d + o_csum);
+    const uint32_t gm = (uint32_t)std::min<uint64_t>((m + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_runs_emit, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n,
+                       (const uint32_t*)chunk, run, gstart, glo, ghi);
+    hipLaunchKernelGGL(k_iota_u32, dim3(gm), dim3(256), 0, c->stream, idx, m);
+    HIP_OR_FAIL(c, hipGetLastError());
+    // the runs in key order: by low word, then (stably) by high word
+    Params q = p;
+    q.mode = 2;
+    default_tiles(c, params, &q, 32768u, 65536u);
+    const uint64_t mo[2] = {0, m};
+    if ((s = run_semisort<uint32_t>(c, glo, idx, mo, 1, slo, sidx, q)) != SS_OK) return s;
+    hipLaunchKernelGGL(k_gather_u64_u32, dim3(gm), dim3(256), 0, c->stream, (const uint64_t*)ghi,
+                       (const uint32_t*)sidx, m, glo);
+    HIP_OR_FAIL(c, hipGetLastError());
+    uint32_t* order = idx;  // the second sort's values land where the run numbers were
+    if ((s = run_semisort<uint32_t>(c, glo, sidx, mo, 1, slo, order, q)) != SS_OK) return s;
+    // destinations of the runs, then every record to its place
+    hipLaunchKernelGGL(k_runs_lens, dim3(gm), dim3(256), 0, c->stream, (const uint32_t*)order,
+                       (const uint32_t*)gstart, m, n, len);
+    hipLaunchKernelGGL(k_sum_chunks_u32, dim3((uint32_t)mch), dim3(256), 0, c->stream, (const uint32_t*)len, m, csum);
+    hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, csum, (uint32_t)mch, csum + mch);
+    hipLaunchKernelGGL(k_runs_dest, dim3((uint32_t)mch), dim3(256), 0, c->stream, (const uint32_t*)len,
+                       (const uint32_t*)order, m, (const uint32_t*)csum, dest);
+    const uint32_t gn = (uint32_t)std::min<uint64_t>((n + 255) / 256, 1u << 20);
+    hipLaunchKernelGGL((k_runs_scatter<V>), dim3(gn), dim3(256), 0, c->stream, (const Key128*)gk, (const V*)gv, n,
+                       (const uint32_t*)run, (const uint32_t*)gstart, (const uint32_t*)dest, (Key128*)keys_out,
+                       (V*)vals_out);
+    HIP_OR_FAIL(c, hipGetLastError());
+    return SS_OK;
+}
+
+extern "C" {
+
 // semisort_= / semisort_< with keys of key_bytes bytes: 4 or 8, or 16 for
 // semisort_= (the two words of a 128-bit key, low word first, 16-byte aligned).
 static ss_status semisort_keys(ss_ctx* c, bool less, const void* keys, uint32_t kb, const void* vals, uint32_t vb,
                                uint64_t n, void* keys_out, void* vals_out, const ss_params* params)
 {
-    if (c && less && kb == 16) return fail(c, SS_EINVAL, "semisort_< takes keys of 4 or 8 bytes");
     if (c && kb == 16 && (((uintptr_t)keys | (uintptr_t)keys_out) & 15u))
         return fail(c, SS_EINVAL, "16-byte keys must be 16-byte aligned");
     ss_status s = check_common(c, keys, vals, vb, n, keys_out, vals_out, true, kb);
     if (s != SS_OK || n == 0) return s;
     Params p;
     if ((s = resolve_params(c, params, &p)) != SS_OK) return s;
+    if (less && kb == 16) {
+        if (hipSetDevice(c->device) != hipSuccess) return fail(c, SS_EHIP, "hipSetDevice");
+        return vb == 8 ? run_less_wide<uint64_t>(c, (const uint64_t*)keys, vals, n, (uint64_t*)keys_out, vals_out,
+                                                 params, p)
+                       : run_less_wide<uint32_t>(c, (const uint64_t*)keys, vals, n, (uint64_t*)keys_out, vals_out,
+                                                 params, p);
+    }
     if (less) {
         p.mode = 2;
         default_tiles(c, params, &p, 32768u, 65536u);

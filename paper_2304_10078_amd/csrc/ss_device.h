@@ -3760,4 +3760,169 @@ __global__ __launch_bounds__(256) void k_pack_scatter_red(const PackJob* jobs, u
 }
 
 
+// ================================================================ semisort_< of 128-bit keys
+// After a stable semisort_= the records of a key form one run, in input
+// order.  These kernels number the runs, list each run's start and key words,
+// and, once the runs are sorted by key, move every record to its run's place
+// in that order: groups in ascending key order, records of a key in input
+// order (Section 2.1's semisort_<, stable as in Section 2.2).
+
+constexpr uint32_t kRunChunk = 4096;              // positions per block
+constexpr uint32_t kRunPer = kRunChunk / 256;     // positions per thread
+constexpr uint32_t kRunWords = kRunChunk / 32;    // words of the chunk's run-start bitmap
+
+// Run starts of a chunk into an LDS bitmap (bit i: a run starts at the
+// chunk's position i) and the popcount prefix of its words; thread t looks at
+// positions t, t + 256, ... (coalesced loads) and keeps their keys.  Returns
+// the chunk's run count.
+__device__ __forceinline__ uint32_t run_bitmap(const Key128* k, uint64_t n, uint64_t base, uint32_t* bm,
+                                               uint32_t* wpre, uint32_t* tmp, Key128 (&kk)[kRunPer])
+{
+    const uint32_t t = threadIdx.x;
+    for (uint32_t w = t; w < kRunWords; w += 256) bm[w] = 0;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < kRunPer; ++j) {
+        const uint64_t i = base + j * 256 + t;
+        if (i < n) {
+            kk[j] = k[i];
+            if (i == 0 || !(kk[j] == k[i - 1])) atomicOr(&bm[(j * 256 + t) >> 5], 1u << (t & 31u));
+        }
+    }
+    __syncthreads();
+    const uint32_t c = t < kRunWords ? (uint32_t)__popc(bm[t]) : 0u;
+    uint32_t tot = 0;
+    const uint32_t ex = block_excl_scan<256>(c, tmp, &tot);
+    if (t < kRunWords) wpre[t] = ex;
+    __syncthreads();
+    return tot;
+}
+
+// Runs starting in each chunk of positions.
+__global__ __launch_bounds__(256) void k_runs_count(const Key128* k, uint64_t n, uint32_t* cnt)
+{
+    __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
+    Key128 kk[kRunPer];
+    const uint32_t tot = run_bitmap(k, n, (uint64_t)blockIdx.x * kRunChunk, bm, wpre, tmp, kk);
+    if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+}
+
+// In place: exclusive prefix of v[0, count) (one block, rounds of 1024 with
+// the earlier rounds' sum carried in); the total to *total.
+__global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t count, uint32_t* total)
+{
+    __shared__ uint32_t tmp[20];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint32_t b = 0; b < count; b += 1024) {
+        const uint32_t i = b + threadIdx.x;
+        const uint32_t x = i < count ? v[i] : 0u;
+        uint32_t tot = 0;
+        const uint32_t ex = block_excl_scan<1024>(x, tmp, &tot);
+        const uint32_t c0 = carry;
+        if (i < count) v[i] = c0 + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c0 + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+// Every record's run number (runs starting at or before it, minus one), and
+// per run its start and its key's words.  cbase: runs before each chunk.
+__global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, const uint32_t* cbase, uint32_t* run,
+                                                    uint32_t* gstart, uint64_t* glo, uint64_t* ghi)
+{
+    __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
+    Key128 kk[kRunPer];
+    const uint64_t base = (uint64_t)blockIdx.x * kRunChunk;
+    (void)run_bitmap(k, n, base, bm, wpre, tmp, kk);
+    const uint32_t t = threadIdx.x, c0 = cbase[blockIdx.x];
+#pragma unroll
+    for (uint32_t j = 0; j < kRunPer; ++j) {
+        const uint32_t q = j * 256 + t;
+        const uint64_t i = base + q;
+        if (i >= n) break;
+        const uint32_t word = bm[q >> 5], bit = q & 31u;
+        // starts at positions <= q of this chunk, plus the runs before it;
+        // position 0 starts run 0, so this is at least 1
+        const uint32_t r = c0 + wpre[q >> 5] + (uint32_t)__popc(word & (0xFFFFFFFFu >> (31u - bit)));
+        run[i] = r - 1;
+        if ((word >> bit) & 1u) {
+            gstart[r - 1] = (uint32_t)i;
+            glo[r - 1] = kk[j].lo;
+            ghi[r - 1] = kk[j].hi;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_iota_u32(uint32_t* p, uint32_t m)
+{
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) p[j] = j;
+}
+
+// out[j] = src[idx[j]] for j < m (a word of every run, in a run order).
+__global__ __launch_bounds__(256) void k_gather_u64_u32(const uint64_t* src, const uint32_t* idx, uint32_t m,
+                                                         uint64_t* out)
+{
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) out[j] = src[idx[j]];
+}
+
+// Lengths of the runs in key order: len[j] of run order[j].
+__global__ __launch_bounds__(256) void k_runs_lens(const uint32_t* order, const uint32_t* gstart, uint32_t m,
+                                                   uint64_t n, uint32_t* len)
+{
+    for (uint32_t j = blockIdx.x * 256 + threadIdx.x; j < m; j += gridDim.x * 256) {
+        const uint32_t g = order[j];
+        const uint64_t end = g + 1 < m ? gstart[g + 1] : n;
+        len[j] = (uint32_t)(end - gstart[g]);
+    }
+}
+
+// Per chunk of 4096 entries of len: its sum (for the scan over chunks).
+__global__ __launch_bounds__(256) void k_sum_chunks_u32(const uint32_t* len, uint32_t m, uint32_t* csum)
+{
+    __shared__ uint32_t tmp[20];
+    const uint64_t j0 = (uint64_t)blockIdx.x * kRunChunk + (uint64_t)threadIdx.x * kRunPer;
+    uint32_t c = 0;
+    for (uint32_t q = 0; q < kRunPer; ++q)
+        if (j0 + q < m) c += len[j0 + q];
+    uint32_t tot = 0;
+    (void)block_excl_scan<256>(c, tmp, &tot);
+    if (threadIdx.x == 0) csum[blockIdx.x] = tot;
+}
+
+// Destination of every run: dest[order[j]] = the lengths of the runs before
+// position j of the key order (csum: the chunks' exclusive prefix).
+__global__ __launch_bounds__(256) void k_runs_dest(const uint32_t* len, const uint32_t* order, uint32_t m,
+                                                   const uint32_t* csum, uint32_t* dest)
+{
+    __shared__ uint32_t tmp[20];
+    const uint64_t j0 = (uint64_t)blockIdx.x * kRunChunk + (uint64_t)threadIdx.x * kRunPer;
+    uint32_t c = 0;
+    for (uint32_t q = 0; q < kRunPer; ++q)
+        if (j0 + q < m) c += len[j0 + q];
+    uint32_t p = csum[blockIdx.x] + block_excl_scan<256>(c, tmp, nullptr);
+    for (uint32_t q = 0; q < kRunPer; ++q) {
+        const uint64_t j = j0 + q;
+        if (j >= m) break;
+        dest[order[j]] = p;
+        p += len[j];
+    }
+}
+
+// Every record to its run's place: position dest[r] + (i - gstart[r]).
+template <typename V>
+__global__ __launch_bounds__(256) void k_runs_scatter(const Key128* gk, const V* gv, uint64_t n, const uint32_t* run,
+                                                      const uint32_t* gstart, const uint32_t* dest, Key128* ok, V* ov)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
+        const uint32_t r = run[i];
+        const uint64_t p = (uint64_t)dest[r] + (i - gstart[r]);
+        ok[p] = gk[i];
+        ov[p] = gv[i];
+    }
+}
+
 }  // namespace ssd

@@ -272,6 +272,27 @@ def test_full_size_semisort_equal_zipf12_128bit_keys():
         assert torch.equal(got, want), f"group of key {k.tolist()} differs from the input positions"
 
 
+def test_full_size_semisort_less_zipf12_128bit_keys():
+    # semisort_< of 128-bit keys: permutation, every record kept its key,
+    # keys ascending as 128-bit unsigned numbers (high word, then low word),
+    # records of a key in input order; 1-D gathers only
+    keys, vals = _indexed("zipf1.2_hashed_k128", 9)
+    _say("case: semisort_< zipf1.2_hashed n=1e9, 128-bit keys, u64 values")
+    ko, vo = S.semisort_less(keys, vals)
+    S.sync()
+    mark = torch.zeros(N, dtype=torch.bool, device="cuda")
+    mark[vo] = True
+    assert bool(mark.all()), "output is not a permutation of the input"
+    del mark
+    for w in (0, 1):
+        assert bool(torch.equal(ko[:, w].contiguous(), keys[:, w].contiguous()[vo])), f"a record lost word {w}"
+    lo, hi = ko[:, 0].contiguous() ^ _SIGN, ko[:, 1].contiguous() ^ _SIGN  # unsigned order as signed
+    up = (hi[1:] > hi[:-1]) | ((hi[1:] == hi[:-1]) & (lo[1:] >= lo[:-1]))
+    assert bool(up.all()), "keys are not in ascending order"
+    same = (hi[1:] == hi[:-1]) & (lo[1:] == lo[:-1])
+    assert bool(((vo[1:] > vo[:-1]) | ~same).all()), "records of a key lost their input order"
+
+
 def test_full_size_semisort_equal_pooled_uniform_1e9():
     # the bounded-temporary form: every level-1 subproblem refined through a
     # pool of n/16 records (uniform keys: all records reach level 1)

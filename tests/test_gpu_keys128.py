@@ -1,6 +1,8 @@
-"""GPU parity of semisort_= with 128-bit keys (ss_semisort_equal_keys with
-key_bytes = 16, keys as (low, high) word pairs) against the oracle's stable
-grouping of 128-bit keys, compared in canonical form (runs ordered by key).
+"""GPU parity of semisort_= and semisort_< with 128-bit keys
+(ss_semisort_equal_keys / ss_semisort_less_keys with key_bytes = 16, keys as
+(low, high) word pairs) against the oracle's stable grouping of 128-bit keys:
+semisort_= compared in canonical form (runs ordered by key), semisort_<
+element by element (the oracle's grouping is the stable sort by key).
 Section 2.1 takes keys of any type with an equality test; here the 64-bit
 level hash of a key can collide, so the cases include keys that agree in one
 word (the identity hash then collides on purpose): heavy keys sharing a low
@@ -138,11 +140,68 @@ def test_edge_cases_128bit_keys():
     assert ko.shape == (0, 2)
 
 
+def _check_less(k, v, params=None, ctx="", inplace=False):
+    """semisort_< of 128-bit keys: exactly the oracle's stable sort by the key
+    as a 128-bit unsigned number, element by element."""
+    kd, vd = _k128_dev(k), to_dev(v)
+    if inplace:
+        S.semisort_less(kd, vd, kd, vd, params=params)
+        ko, vo = kd, vd
+    else:
+        ko, vo = S.semisort_less(kd, vd, params=params)
+    S.sync()
+    hk = ko.cpu().numpy().view(np.uint64)
+    hv = to_host(vo, v.dtype)
+    rk, rv = O.semisort_equal_wide(k, v)
+    if not np.array_equal(hk, rk):
+        i = int(np.nonzero((hk != rk).any(axis=1))[0][0])
+        raise AssertionError(f"{ctx}: key at position {i} differs from the oracle's sorted order")
+    if not np.array_equal(hv, rv):
+        i = int(np.nonzero(hv != rv)[0][0])
+        raise AssertionError(f"{ctx}: value at position {i} differs from the oracle (stability or moves)")
+
+
+@pytest.mark.parametrize("name,n", [("zipf1.2_hashed_k128", 3_000_001), ("uniform1e9_k128", 2_500_003),
+                                    ("zipf1.2_hashed_k128", 65_537)])
+def test_semisort_less_128bit_keys(name, n):
+    k, _ = I.np_workload(name, n, 58)
+    v = np.arange(n, dtype=np.uint64)
+    _say(f"case: semisort_< {name} n={n}")
+    _check_less(k, v, ctx=f"less {name} n={n}")
+
+
+def test_semisort_less_128bit_keys_sharing_words_and_edges():
+    k = _collision_keys(1_000_003, 59)
+    v = np.arange(k.shape[0], dtype=np.uint64)
+    for mode in ("mix64", "identity"):
+        _say(f"case: semisort_< shared low words, hash={mode}")
+        _check_less(k, v, params=S.default_params(hash_mode=mode), ctx=f"less shared {mode}")
+    _say("case: semisort_< u32 values, in place, deep recursion")
+    v32 = np.arange(k.shape[0], dtype=np.uint32)
+    _check_less(k, v32, ctx="less u32 values")
+    _check_less(k, v, ctx="less in place", inplace=True)
+    p = S.default_params(n_light_log2=3, base_case=256, sample_mult=30, tile_min=8192, tile_max=8192)
+    _check_less(k, v, params=p, ctx="less deep")
+    rng = np.random.default_rng(60)
+    ext = np.array([[0, 0], [~0, ~0], [0, ~0], [~0, 0], [1, 0], [0, 1]], dtype=np.int64).view(np.uint64)
+    cases = {
+        "one record": np.array([[7, 9]], dtype=np.uint64),
+        "two records": np.array([[0, 1], [1, 0]], dtype=np.uint64),
+        "below the base case": np.stack([rng.integers(0, 5, 3000, dtype=np.uint64),
+                                         rng.integers(0, 5, 3000, dtype=np.uint64)], axis=1),
+        "extreme words": ext[rng.integers(0, ext.shape[0], 200_003)],
+        "all equal": np.tile(np.array([[0xDEADBEEF, 0xFEEDFACE]], dtype=np.uint64), (150_001, 1)),
+        "all distinct": np.stack([rng.permutation(np.arange(600_001, dtype=np.uint64)),
+                                  rng.permutation(np.arange(600_001, dtype=np.uint64)) % np.uint64(7)], axis=1),
+    }
+    for name, kk in cases.items():
+        _say(f"case: semisort_< {name} n={kk.shape[0]}")
+        _check_less(kk, np.arange(kk.shape[0], dtype=np.uint64), ctx=f"less {name}")
+
+
 def test_rejects_what_128bit_keys_do_not_support():
     k = _k128_dev(np.zeros((64, 2), dtype=np.uint64))
     v = torch.zeros(64, dtype=torch.int64, device="cuda")
-    with pytest.raises(S.SemisortError):
-        S.semisort_less(k, v)  # semisort_< takes 4- and 8-byte keys
     # a key array at an 8-byte offset is not 16-byte aligned
     base = torch.zeros(129, dtype=torch.int64, device="cuda")
     with pytest.raises(S.SemisortError):
