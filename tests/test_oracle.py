@@ -292,30 +292,30 @@ def test_canonicalizer_rejects_each_mutation():
     rk, rv = O.semisort_equal(keys, v)
     flat = [(int(a), int(b)) for a, b in zip(rk, rv)]
 
-    def verdict(f):
+    def canonical_ok(f):
         k = np.array([x[0] for x in f], dtype=np.uint64)
         w = np.array([x[1] for x in f], dtype=np.uint64)
         bad, ck, cv = O.canonicalize_equal(k, w)
         return bad == -1 and np.array_equal(ck, rk) and np.array_equal(cv, rv)
 
-    assert verdict(flat)
+    assert canonical_ok(flat)
     # split a group: move the last record of the first multi-record group to the end
     p = next(i for i in range(1, len(flat)) if flat[i][0] == flat[i - 1][0])
     split = flat[:p] + flat[p + 1:] + [flat[p]]
-    assert not verdict(split)
+    assert not canonical_ok(split)
     # swap two records inside a group (breaks stability)
     sw = list(flat)
     sw[p - 1], sw[p] = sw[p], sw[p - 1]
-    assert not verdict(sw)
+    assert not canonical_ok(sw)
     # duplicate one record over another
     dup = list(flat)
     dup[0] = dup[1] if dup[1][0] == dup[0][0] else dup[0]
     dup[-1] = dup[0]
-    assert not verdict(dup)
+    assert not canonical_ok(dup)
     # change a value
     cv = list(flat)
     cv[3] = (cv[3][0], cv[3][1] + 100)
-    assert not verdict(cv)
+    assert not canonical_ok(cv)
 
 
 # ------------------------------------------------- Table 3 input statistics
