@@ -414,6 +414,7 @@ def serving(args, S, I, torch):
     # served: submit at the arrival times, keep at most ~48 GB of outputs in flight
     srv = S.Server(lanes=args.serve_lanes, hbm_budget=200 << 30)
     lat = np.zeros(R)
+    lag = np.zeros(R)  # how late the submitting thread handed each request over
     pending = {}
     out_bytes, cap = 0, 48 << 30
 
@@ -440,6 +441,7 @@ def serving(args, S, I, torch):
             reap(False)
         oa = torch.empty_like(k)
         ob = torch.empty_like(k)
+        lag[i] = srv.now() - base - arrival[i]
         t = srv.submit(op, k, v if op != S.OP_HISTOGRAM else None, oa, ob, arrival=base + arrival[i])
         pending[i] = (t, nb)
         out_bytes += nb
@@ -452,6 +454,8 @@ def serving(args, S, I, torch):
               "grecs": round(sizes.sum() / t_end / 1e9, 3), "req_per_s": round(R / t_end, 1),
               "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
               "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+              "submit_lag_p50_ms": round(float(np.percentile(lag, 50)) * 1e3, 3),
+              "submit_lag_max_ms": round(float(lag.max()) * 1e3, 3),
               "calls": st["calls"], "packed": st["packed"], "peak_reserved_gb": round(st["peak_reserved"] / 2 ** 30, 2)}
     log(f"serving: served {served}")
 
