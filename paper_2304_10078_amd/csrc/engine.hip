@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <functional>
 #include <map>
 #include <cmath>
 #include <cstdio>
@@ -90,6 +91,7 @@ struct ss_ctx {
     hipStream_t aux = nullptr;       // second stream: key fills overlap the next level
     hipEvent_t fill_done[2] = {nullptr, nullptr};
     hipEvent_t fill_fork[2] = {nullptr, nullptr};  // device-sized levels: fills start after the planning
+    hipEvent_t plan_ev = nullptr;    // the level's plan has been read back (planning ahead of the distribution)
     DevBuf info;
     LevelInfo* info_host = nullptr;  // pinned
     DevBuf ds_jobs, ds_info, ds_q;   // device-sized batches: job lists, per-level counts, queue counters
@@ -445,29 +447,33 @@ void launch_jobs(ss_ctx* c, uint32_t mode, const uint32_t* njobs, uint32_t cap, 
     else launch_jobs_m<0, V, K>(c, njobs, cap, sk, sv, ok, ov);
 }
 
-// part 0: the whole level; 1: sampling only; 2: everything after sampling.
+// part 0: the whole level; 1: sampling only; 2: everything after sampling;
+// 3: sampling, counting and the prefix (no distribution); 4: counting and the
+// prefix only; 5: the distribution only.
 template <int MODE, typename V, typename K = uint64_t>
 void launch_level(ss_ctx* c, const LevelArgs& a, uint32_t tiles, uint32_t chunks, uint64_t records, int part)
 {
-    if (part != 2) {
+    const bool do_sample = part == 0 || part == 1 || part == 3;
+    const bool do_count = part == 0 || part == 2 || part == 3 || part == 4;
+    const bool do_dist = part == 0 || part == 2 || part == 5;
+    if (do_sample) {
         ProfScope ps(c, SS_PROF_SAMPLE, a.nsegs);
         if constexpr (MODE == 2) hipLaunchKernelGGL((k_sample_less<K>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
         else hipLaunchKernelGGL((k_sample_heavy<MODE, K>), dim3(a.nsegs), dim3(1024), 0, c->stream, a);
     }
-    if (part == 1) return;
-    {
-        ProfScope ps(c, SS_PROF_COUNT, records);
-        if constexpr (MODE == 2) hipLaunchKernelGGL((k_count_less<K>), dim3(tiles), dim3(1024), 0, c->stream, a);
-        else hipLaunchKernelGGL((k_count<MODE, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
-    }
-    {
+    if (do_count) {
+        {
+            ProfScope ps(c, SS_PROF_COUNT, records);
+            if constexpr (MODE == 2) hipLaunchKernelGGL((k_count_less<K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+            else hipLaunchKernelGGL((k_count<MODE, K>), dim3(tiles), dim3(1024), 0, c->stream, a);
+        }
         ProfScope ps(c, SS_PROF_SCAN, tiles);
         hipLaunchKernelGGL(k_scan_chunks, dim3(chunks), dim3(256), 0, c->stream, a);
         hipLaunchKernelGGL(k_scan_buckets, dim3(a.nsegs * kBucketGroups), dim3(1024), 0, c->stream, a);
         hipLaunchKernelGGL(k_scan_offsets, dim3(a.nsegs), dim3(1024), 0, c->stream, a);
         hipLaunchKernelGGL(k_scan_fill, dim3(chunks), dim3(256), 0, c->stream, a);
     }
-    {
+    if (do_dist) {
         ProfScope ps(c, SS_PROF_DISTRIBUTE, records);
         if constexpr (kWide<K>) {
             // two registers per key: four records per thread keep the staged
@@ -622,8 +628,12 @@ ss_status ensure_jobs(ss_ctx* c, uint32_t per_class)
 // Plans the next level from the buckets of the current one (subproblem list
 // segs[cur] -> segs[cur ^ 1], job lists) and reads the level's counters back
 // to the host; grows the lists and plans again when they overflow.
+// With `between`, the plan is enqueued ahead of the level's distribution:
+// between() launches the distribution after the plan's read-back, and the
+// host waits for the read-back only (a retry waits for everything).
 ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs, int cur, uint32_t* seg_cap,
-                     bool finals_in_out, bool reduce, bool fill, LevelInfo* out, uint32_t hash_bits = 64)
+                     bool finals_in_out, bool reduce, bool fill, LevelInfo* out, uint32_t hash_bits = 64,
+                     const std::function<void()>* between = nullptr)
 {
     ss_status s;
     const int fb = level & 1;  // fill list of this level
@@ -665,7 +675,15 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
         }
         HIP_OR_FAIL(c, hipGetLastError());
         HIP_OR_FAIL(c, hipMemcpyAsync(c->info_host, c->info.p, sizeof(LevelInfo), hipMemcpyDeviceToHost, c->stream));
-        HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        if (between && attempt == 0) {
+            if (!c->plan_ev) HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->plan_ev, hipEventDisableTiming));
+            HIP_OR_FAIL(c, hipEventRecord(c->plan_ev, c->stream));
+            (*between)();
+            HIP_OR_FAIL(c, hipGetLastError());
+            HIP_OR_FAIL(c, hipEventSynchronize(c->plan_ev));
+        } else {
+            HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+        }
         const LevelInfo li = *c->info_host;
         if (li.status) return status_failure(c, li.status, "at level " + std::to_string(level));
         bool again = false;
@@ -839,6 +857,14 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         const bool fill = !kWide<K> && fin == kOut;
         const int fb = level & 1;
         a.fill_heavy = fill;
+        // semisort_<: the level is planned before its distribution, so that
+        // its key fills run beside the distribution instead of beside the
+        // next level's base cases (10^9 records: exponential keys 2.2-2.5%
+        // faster, Zipf-0.8 unchanged).  semisort_= keeps the fills after the
+        // distribution: beside it they slow the first level more than they
+        // save (Zipf-1.2 1.7% slower).  The fills write only the keys of
+        // one-key buckets, which the distribution does not write.
+        const bool early = fill && p.mode == 2;
         if (level == 0 && p.auto_tiles && nsegs == 1 && p.mode != 2) {
             // Light-dominated input (under half of the first level's sample on
             // heavy keys): subarrays of 8192 records on every level, so that
@@ -870,16 +896,17 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
                 a.P = (uint32_t*)c->P.p;
                 a.tile = tile;
             }
-            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, 2);
+            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, early ? 4 : 2);
         } else {
-            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records);
+            launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, early ? 3 : 0);
         }
         HIP_OR_FAIL(c, hipGetLastError());
         if (fill_used[fb]) HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->fill_done[fb], 0));  // list reuse
 
         LevelInfo li;
+        const std::function<void()> dist = [&] { launch_level_v<V, K>(c, p.mode, a, tiles, chunks, records, 5); };
         if ((s = plan_level(c, p, level, nsegs, cur, &seg_cap, fin == kOut, false, fill, &li,
-                            KeyTraits<K>::hash_bits)) != SS_OK)
+                            KeyTraits<K>::hash_bits, early ? &dist : nullptr)) != SS_OK)
             return s;
         if constexpr (!kWide<K>) if (li.nfills) {
             if ((s = ensure_aux(c)) != SS_OK) return s;
@@ -1784,6 +1811,7 @@ ss_status ss_destroy(ss_ctx* c)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : c->fill_fork)
         if (e) (void)hipEventDestroy(e);
+    if (c->plan_ev) (void)hipEventDestroy(c->plan_ev);
     if (c->aux) (void)hipStreamDestroy(c->aux);
     if (c->info_host) (void)hipHostFree(c->info_host);
     if (c->seg_stage) (void)hipHostFree(c->seg_stage);
