@@ -685,7 +685,12 @@ ss_status plan_level(ss_ctx* c, const Params& p, uint32_t level, uint32_t nsegs,
             HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
         }
         const LevelInfo li = *c->info_host;
-        if (li.status) return status_failure(c, li.status, "at level " + std::to_string(level));
+        if (li.status) {
+            // the distribution enqueued by between() still writes the caller's
+            // buffers: let it finish before reporting
+            if (between) HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+            return status_failure(c, li.status, "at level " + std::to_string(level));
+        }
         bool again = false;
         if (li.nsegs > *seg_cap) {
             // the current list must survive: copy it aside while both lists grow
@@ -865,7 +870,11 @@ ss_status run_semisort(ss_ctx* c, const uint64_t* keys, const void* vals, const 
         // save (Zipf-1.2 1.7% slower).  The fills write only the keys of
         // one-key buckets, which the distribution does not write.
         const bool early = fill && p.mode == 2;
-        if (level == 0 && p.auto_tiles && nsegs == 1 && p.mode != 2) {
+        // Below 2 * 2048 * tile_min records every level already takes
+        // tile_min-record subarrays (about 2048 subarrays per level), so the
+        // sample's count could change nothing: no synchronization for it.
+        const bool tiles_open = (uint64_t)records / 2048 >= 2ull * p.tmin;
+        if (level == 0 && p.auto_tiles && nsegs == 1 && p.mode != 2 && tiles_open) {
             // Light-dominated input (under half of the first level's sample on
             // heavy keys): subarrays of 8192 records on every level, so that
             // neighbouring ones complete each other's partial lines in L2
