@@ -680,7 +680,10 @@ __device__ __forceinline__ void gather_regs(const LevelArgs& a, const Seg& sg, u
 
 // Ascending bitonic sort of P = C * nt elements, thread t < nt holding the
 // logical elements t*C + q in e[q] (nt = BS for C >= 2; nt = P <= BS for
-// C = 1).  Stages of distance j < C run in registers.  Longer stages go
+// C = 1).  Stages of distance j < C run in registers.  Distances from C up to
+// 64*C pair element t*C + q with element (t ^ j/C)*C + q, held by another lane
+// of the same wave in the same register: those stages exchange registers
+// across lanes, with no LDS round trip and no block barrier.  Longer stages go
 // through LDS in a q-major layout (element t*C + q at smp[q*nt + t]) with
 // pairs handed out so that neighbouring lanes touch neighbouring words.  On
 // return e[] is sorted in the same layout and smp holds the sorted sequence
@@ -692,34 +695,50 @@ __device__ void bitonic_sort_block(uint64_t (&e)[C], uint64_t* smp, uint32_t P)
     const uint32_t nt = P / C;
     const bool own = t < nt;
     const uint32_t base = t * C;
+    constexpr uint32_t kWaveSpan = 64u * (uint32_t)C;  // elements of one wave
 #pragma unroll
     for (uint32_t k = 2; k <= (uint32_t)C; k <<= 1) bitonic_regs<C>(e, base, k, k >> 1);
     for (uint32_t k = 2 * C; k <= P; k <<= 1) {
-        if (own) {
+        uint32_t j = k >> 1;
+        if (j >= kWaveSpan) {
+            if (own) {
 #pragma unroll
-            for (int q = 0; q < C; ++q) smp[q * nt + t] = e[q];
-        }
-        __syncthreads();
-        for (uint32_t j = k >> 1; j >= (uint32_t)C; j >>= 1) {
-            const uint32_t jt = j / C;  // distance in threads
-            for (uint32_t pp = t; pp < (P >> 1); pp += BS) {
-                const uint32_t q = pp / (nt >> 1);
-                const uint32_t u = pp % (nt >> 1);
-                const uint32_t ta = ((u & ~(jt - 1)) << 1) | (u & (jt - 1));
-                uint64_t* pa = smp + q * nt + ta;
-                uint64_t x = pa[0], y = pa[jt];
-                bitonic_cx(x, y, ((ta * C + q) & k) == 0);
-                pa[0] = x;
-                pa[jt] = y;
+                for (int q = 0; q < C; ++q) smp[q * nt + t] = e[q];
+            }
+            __syncthreads();
+            for (; j >= kWaveSpan; j >>= 1) {
+                const uint32_t jt = j / C;  // distance in threads
+                for (uint32_t pp = t; pp < (P >> 1); pp += BS) {
+                    const uint32_t q = pp / (nt >> 1);
+                    const uint32_t u = pp % (nt >> 1);
+                    const uint32_t ta = ((u & ~(jt - 1)) << 1) | (u & (jt - 1));
+                    uint64_t* pa = smp + q * nt + ta;
+                    uint64_t x = pa[0], y = pa[jt];
+                    bitonic_cx(x, y, ((ta * C + q) & k) == 0);
+                    pa[0] = x;
+                    pa[jt] = y;
+                }
+                __syncthreads();
+            }
+            if (own) {
+#pragma unroll
+                for (int q = 0; q < C; ++q) e[q] = smp[q * nt + t];
             }
             __syncthreads();
         }
-        if (own) {
+        // the lower element of a pair keeps the minimum in an ascending run
+        const bool up = (base & k) == 0;
+        for (; j >= (uint32_t)C; j >>= 1) {
+            const uint32_t d = j / C;  // lane distance, below 64
+            const bool keep_min = ((t & d) == 0) == up;
 #pragma unroll
-            for (int q = 0; q < C; ++q) e[q] = smp[q * nt + t];
+            for (int q = 0; q < C; ++q) {
+                const uint64_t y = __shfl_xor(e[q], (int)d, 64);
+                const uint64_t x = e[q];
+                e[q] = keep_min ? (y < x ? y : x) : (y < x ? x : y);
+            }
         }
         bitonic_regs<C>(e, base, k, C / 2);
-        __syncthreads();
     }
     if (own) {
 #pragma unroll
