@@ -211,7 +211,7 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
  *     given), numbers the runs of equal keys, sorts the m runs by key with two
  *     stable semisort_< passes over (word, run) pairs (low word, then high
  *     word) and scatters every record to its run's place; it holds the grouped
- *     records (n * (16 + val_bytes) bytes), a run number per record (4 n) and
+ *     records (n * (16 + val_bytes) bytes), 4 bytes per 4096 records and
  *     about 48 bytes per run besides the semisorts' own workspace, and waits
  *     once for m.
  * SS_EINVAL for another key_bytes or a misaligned 16-byte key array;

@@ -84,7 +84,7 @@ struct ss_ctx {
     DevBuf hsum, rflag, bcnt, mdev;  // collect-reduce and histogram
     DevBuf bkey;                     // keys of one-key buckets
     DevBuf hrep;                     // 128-bit keys: one sampled key per heavy id
-    DevBuf wl_gk, wl_gv, wl_run, wl_chunk, wl_desc;  // semisort_< of 128-bit keys: grouped records, runs
+    DevBuf wl_gk, wl_gv, wl_chunk, wl_desc;  // semisort_< of 128-bit keys: grouped records, runs
     DevBuf top;                      // two most sampled heavy buckets per subproblem
     DevBuf fills[2];                 // key-fill job lists (alternating levels)
     uint32_t fill_cap[2] = {0, 0};
@@ -1804,7 +1804,7 @@ ss_status ss_destroy(ss_ctx* c)
     DevBuf* bufs[] = {&c->t_keys, &c->t_vals, &c->segs[0], &c->segs[1], &c->jobs, &c->C, &c->P,
                       &c->tot, &c->bstart, &c->heavy_list, &c->tab_h, &c->tab_id, &c->info, &c->bids, &c->sink, &c->bfin,
                       &c->hsum, &c->rflag, &c->bcnt, &c->mdev, &c->bkey, &c->hrep, &c->top, &c->fills[0], &c->fills[1],
-                      &c->wl_gk, &c->wl_gv, &c->wl_run, &c->wl_chunk, &c->wl_desc,
+                      &c->wl_gk, &c->wl_gv, &c->wl_chunk, &c->wl_desc,
                       &c->ds_jobs, &c->ds_info, &c->ds_q,
                       &c->tr_keys, &c->tr_vals, &c->tr_sorted, &c->tr_min, &c->pos,
                       &c->pk_k, &c->pk_v, &c->po_k, &c->po_v, &c->pack_tab, &c->pack_rank};
@@ -1973,10 +1973,8 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     // runs of the grouped records
     const uint64_t nch = (n + kRunChunk - 1) / kRunChunk;
     if ((s = ensure(c, c->wl_chunk, (nch + 2) * 4)) != SS_OK) return s;
-    if ((s = ensure(c, c->wl_run, n * 4)) != SS_OK) return s;
     uint32_t* chunk = (uint32_t*)c->wl_chunk.p;
     uint32_t* dtotal = chunk + nch;
-    uint32_t* run = (uint32_t*)c->wl_run.p;
     hipLaunchKernelGGL(k_runs_count, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n, chunk);
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, chunk, (uint32_t)nch, dtotal);
     HIP_OR_FAIL(c, hipGetLastError());
@@ -2005,7 +2003,7 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     uint32_t* csum = (uint32_t*)(d + o_csum);
     const uint32_t gm = (uint32_t)std::min<uint64_t>((m + 255) / 256, 65536);
     hipLaunchKernelGGL(k_runs_emit, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n,
-                       (const uint32_t*)chunk, run, gstart, glo, ghi);
+                       (const uint32_t*)chunk, gstart, glo, ghi);
     hipLaunchKernelGGL(k_iota_u32, dim3(gm), dim3(256), 0, c->stream, idx, m);
     HIP_OR_FAIL(c, hipGetLastError());
     // the runs in key order: by low word, then (stably) by high word
@@ -2026,10 +2024,9 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, csum, (uint32_t)mch, csum + mch);
     hipLaunchKernelGGL(k_runs_dest, dim3((uint32_t)mch), dim3(256), 0, c->stream, (const uint32_t*)len,
                        (const uint32_t*)order, m, (const uint32_t*)csum, dest);
-    const uint32_t gn = (uint32_t)std::min<uint64_t>((n + 255) / 256, 1u << 20);
-    hipLaunchKernelGGL((k_runs_scatter<V>), dim3(gn), dim3(256), 0, c->stream, (const Key128*)gk, (const V*)gv, n,
-                       (const uint32_t*)run, (const uint32_t*)gstart, (const uint32_t*)dest, (Key128*)keys_out,
-                       (V*)vals_out);
+    hipLaunchKernelGGL((k_runs_scatter<V>), dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk,
+                       (const V*)gv, n, (const uint32_t*)chunk, (const uint32_t*)gstart, (const uint32_t*)dest,
+                       (Key128*)keys_out, (V*)vals_out);
     HIP_OR_FAIL(c, hipGetLastError());
     return SS_OK;
 }

@@ -3848,9 +3848,16 @@ __global__ __launch_bounds__(1024) void k_scan_u32(uint32_t* v, uint32_t count, 
     if (threadIdx.x == 0) *total = carry;
 }
 
-// Every record's run number (runs starting at or before it, minus one), and
-// per run its start and its key's words.  cbase: runs before each chunk.
-__global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, const uint32_t* cbase, uint32_t* run,
+// Run number of chunk position q: the run starts at positions <= q of the
+// chunk plus the runs before it (cbase), minus one (position 0 starts run 0).
+__device__ __forceinline__ uint32_t run_of(const uint32_t* bm, const uint32_t* wpre, uint32_t c0, uint32_t q)
+{
+    const uint32_t word = bm[q >> 5], bit = q & 31u;
+    return c0 + wpre[q >> 5] + (uint32_t)__popc(word & (0xFFFFFFFFu >> (31u - bit))) - 1u;
+}
+
+// Per run: its start and its key's words.  cbase: runs before each chunk.
+__global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, const uint32_t* cbase,
                                                     uint32_t* gstart, uint64_t* glo, uint64_t* ghi)
 {
     __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
@@ -3863,15 +3870,11 @@ __global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, 
         const uint32_t q = j * 256 + t;
         const uint64_t i = base + q;
         if (i >= n) break;
-        const uint32_t word = bm[q >> 5], bit = q & 31u;
-        // starts at positions <= q of this chunk, plus the runs before it;
-        // position 0 starts run 0, so this is at least 1
-        const uint32_t r = c0 + wpre[q >> 5] + (uint32_t)__popc(word & (0xFFFFFFFFu >> (31u - bit)));
-        run[i] = r - 1;
-        if ((word >> bit) & 1u) {
-            gstart[r - 1] = (uint32_t)i;
-            glo[r - 1] = kk[j].lo;
-            ghi[r - 1] = kk[j].hi;
+        if ((bm[q >> 5] >> (q & 31u)) & 1u) {
+            const uint32_t r = run_of(bm, wpre, c0, q);
+            gstart[r] = (uint32_t)i;
+            glo[r] = kk[j].lo;
+            ghi[r] = kk[j].hi;
         }
     }
 }
@@ -3931,16 +3934,34 @@ __global__ __launch_bounds__(256) void k_runs_dest(const uint32_t* len, const ui
     }
 }
 
-// Every record to its run's place: position dest[r] + (i - gstart[r]).
+// Every record to its run's place, position dest[r] + (i - gstart[r]), one
+// chunk per block: the run number r comes from the chunk's run starts, found
+// again from the keys the block moves anyway (no per-record run array).
 template <typename V>
-__global__ __launch_bounds__(256) void k_runs_scatter(const Key128* gk, const V* gv, uint64_t n, const uint32_t* run,
+__global__ __launch_bounds__(256) void k_runs_scatter(const Key128* gk, const V* gv, uint64_t n, const uint32_t* cbase,
                                                       const uint32_t* gstart, const uint32_t* dest, Key128* ok, V* ov)
 {
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) {
-        const uint32_t r = run[i];
+    __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
+    Key128 kk[kRunPer];
+    V vv[kRunPer];
+    const uint64_t base = (uint64_t)blockIdx.x * kRunChunk;
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (uint32_t j = 0; j < kRunPer; ++j) {
+        const uint64_t i = base + j * 256 + t;
+        vv[j] = i < n ? gv[i] : (V)0;
+    }
+    (void)run_bitmap(gk, n, base, bm, wpre, tmp, kk);
+    const uint32_t c0 = cbase[blockIdx.x];
+#pragma unroll
+    for (uint32_t j = 0; j < kRunPer; ++j) {
+        const uint32_t q = j * 256 + t;
+        const uint64_t i = base + q;
+        if (i >= n) break;
+        const uint32_t r = run_of(bm, wpre, c0, q);
         const uint64_t p = (uint64_t)dest[r] + (i - gstart[r]);
-        ok[p] = gk[i];
-        ov[p] = gv[i];
+        ok[p] = kk[j];
+        ov[p] = vv[j];
     }
 }
 
