@@ -211,8 +211,8 @@ ss_status ss_semisort_equal(ss_ctx* ctx, const uint64_t* keys, const void* vals,
  *     given), numbers the runs of equal keys, sorts the m runs by key with two
  *     stable semisort_< passes over (word, run) pairs (low word, then high
  *     word) and scatters every record to its run's place; it holds the grouped
- *     records (n * (16 + val_bytes) bytes), 4 bytes per 4096 records and
- *     about 48 bytes per run besides the semisorts' own workspace, and waits
+ *     records (n * (16 + val_bytes) bytes), a run-start bitmap (n / 8 bytes)
+ *     and about 48 bytes per run besides the semisorts' own workspace, and waits
  *     once for m.
  * SS_EINVAL for another key_bytes or a misaligned 16-byte key array;
  * otherwise the arguments, conventions and errors of the 64-bit calls (in

@@ -1972,10 +1972,13 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     }
     // runs of the grouped records
     const uint64_t nch = (n + kRunChunk - 1) / kRunChunk;
-    if ((s = ensure(c, c->wl_chunk, (nch + 2) * 4)) != SS_OK) return s;
+    // per chunk: its run count (scanned in place, then the total), and its
+    // run-start bitmap of kRunWords words
+    if ((s = ensure(c, c->wl_chunk, (nch + 2 + nch * kRunWords) * 4)) != SS_OK) return s;
     uint32_t* chunk = (uint32_t*)c->wl_chunk.p;
     uint32_t* dtotal = chunk + nch;
-    hipLaunchKernelGGL(k_runs_count, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n, chunk);
+    uint32_t* bits = chunk + nch + 2;
+    hipLaunchKernelGGL(k_runs_count, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n, chunk, bits);
     hipLaunchKernelGGL(k_scan_u32, dim3(1), dim3(1024), 0, c->stream, chunk, (uint32_t)nch, dtotal);
     HIP_OR_FAIL(c, hipGetLastError());
     uint32_t m = 0;
@@ -2003,7 +2006,7 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     uint32_t* csum = (uint32_t*)(d + o_csum);
     const uint32_t gm = (uint32_t)std::min<uint64_t>((m + 255) / 256, 65536);
     hipLaunchKernelGGL(k_runs_emit, dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk, n,
-                       (const uint32_t*)chunk, gstart, glo, ghi);
+                       (const uint32_t*)chunk, (const uint32_t*)bits, gstart, glo, ghi);
     hipLaunchKernelGGL(k_iota_u32, dim3(gm), dim3(256), 0, c->stream, idx, m);
     HIP_OR_FAIL(c, hipGetLastError());
     // the runs in key order: by low word, then (stably) by high word
@@ -2025,8 +2028,8 @@ ss_status run_less_wide(ss_ctx* c, const uint64_t* keys, const void* vals, uint6
     hipLaunchKernelGGL(k_runs_dest, dim3((uint32_t)mch), dim3(256), 0, c->stream, (const uint32_t*)len,
                        (const uint32_t*)order, m, (const uint32_t*)csum, dest);
     hipLaunchKernelGGL((k_runs_scatter<V>), dim3((uint32_t)nch), dim3(256), 0, c->stream, (const Key128*)gk,
-                       (const V*)gv, n, (const uint32_t*)chunk, (const uint32_t*)gstart, (const uint32_t*)dest,
-                       (Key128*)keys_out, (V*)vals_out);
+                       (const V*)gv, n, (const uint32_t*)chunk, (const uint32_t*)bits, (const uint32_t*)gstart,
+                       (const uint32_t*)dest, (Key128*)keys_out, (V*)vals_out);
     HIP_OR_FAIL(c, hipGetLastError());
     return SS_OK;
 }

@@ -3817,13 +3817,27 @@ __device__ __forceinline__ uint32_t run_bitmap(const Key128* k, uint64_t n, uint
     return tot;
 }
 
-// Runs starting in each chunk of positions.
-__global__ __launch_bounds__(256) void k_runs_count(const Key128* k, uint64_t n, uint32_t* cnt)
+// Runs starting in each chunk of positions, and the chunk's run-start bitmap
+// (kRunWords words per chunk) for the passes after it.
+__global__ __launch_bounds__(256) void k_runs_count(const Key128* k, uint64_t n, uint32_t* cnt, uint32_t* bits)
 {
     __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
     Key128 kk[kRunPer];
     const uint32_t tot = run_bitmap(k, n, (uint64_t)blockIdx.x * kRunChunk, bm, wpre, tmp, kk);
     if (threadIdx.x == 0) cnt[blockIdx.x] = tot;
+    for (uint32_t w = threadIdx.x; w < kRunWords; w += 256) bits[(size_t)blockIdx.x * kRunWords + w] = bm[w];
+}
+
+// A chunk's stored run-start bitmap into LDS, with the popcount prefix of its
+// words (as run_bitmap leaves them).
+__device__ __forceinline__ void load_run_bitmap(const uint32_t* bits, uint32_t* bm, uint32_t* wpre, uint32_t* tmp)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t w = t < kRunWords ? bits[(size_t)blockIdx.x * kRunWords + t] : 0u;
+    if (t < kRunWords) bm[t] = w;
+    const uint32_t ex = block_excl_scan<256>((uint32_t)__popc(w), tmp, nullptr);
+    if (t < kRunWords) wpre[t] = ex;
+    __syncthreads();
 }
 
 // In place: exclusive prefix of v[0, count) (one block, rounds of 1024 with
@@ -3856,14 +3870,15 @@ __device__ __forceinline__ uint32_t run_of(const uint32_t* bm, const uint32_t* w
     return c0 + wpre[q >> 5] + (uint32_t)__popc(word & (0xFFFFFFFFu >> (31u - bit))) - 1u;
 }
 
-// Per run: its start and its key's words.  cbase: runs before each chunk.
+// Per run: its start and its key's words, from the stored run-start bitmap
+// (only the keys at run starts are read).  cbase: runs before each chunk.
 __global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, const uint32_t* cbase,
-                                                    uint32_t* gstart, uint64_t* glo, uint64_t* ghi)
+                                                    const uint32_t* bits, uint32_t* gstart, uint64_t* glo,
+                                                    uint64_t* ghi)
 {
     __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
-    Key128 kk[kRunPer];
+    load_run_bitmap(bits, bm, wpre, tmp);
     const uint64_t base = (uint64_t)blockIdx.x * kRunChunk;
-    (void)run_bitmap(k, n, base, bm, wpre, tmp, kk);
     const uint32_t t = threadIdx.x, c0 = cbase[blockIdx.x];
 #pragma unroll
     for (uint32_t j = 0; j < kRunPer; ++j) {
@@ -3872,9 +3887,10 @@ __global__ __launch_bounds__(256) void k_runs_emit(const Key128* k, uint64_t n, 
         if (i >= n) break;
         if ((bm[q >> 5] >> (q & 31u)) & 1u) {
             const uint32_t r = run_of(bm, wpre, c0, q);
+            const Key128 key = k[i];
             gstart[r] = (uint32_t)i;
-            glo[r] = kk[j].lo;
-            ghi[r] = kk[j].hi;
+            glo[r] = key.lo;
+            ghi[r] = key.hi;
         }
     }
 }
@@ -3935,11 +3951,12 @@ __global__ __launch_bounds__(256) void k_runs_dest(const uint32_t* len, const ui
 }
 
 // Every record to its run's place, position dest[r] + (i - gstart[r]), one
-// chunk per block: the run number r comes from the chunk's run starts, found
-// again from the keys the block moves anyway (no per-record run array).
+// chunk per block: the run number r comes from the chunk's stored run-start
+// bitmap (no per-record run array).
 template <typename V>
 __global__ __launch_bounds__(256) void k_runs_scatter(const Key128* gk, const V* gv, uint64_t n, const uint32_t* cbase,
-                                                      const uint32_t* gstart, const uint32_t* dest, Key128* ok, V* ov)
+                                                      const uint32_t* bits, const uint32_t* gstart,
+                                                      const uint32_t* dest, Key128* ok, V* ov)
 {
     __shared__ uint32_t bm[kRunWords], wpre[kRunWords], tmp[20];
     Key128 kk[kRunPer];
@@ -3949,9 +3966,10 @@ __global__ __launch_bounds__(256) void k_runs_scatter(const Key128* gk, const V*
 #pragma unroll
     for (uint32_t j = 0; j < kRunPer; ++j) {
         const uint64_t i = base + j * 256 + t;
+        kk[j] = i < n ? gk[i] : Key128{0ull, 0ull};
         vv[j] = i < n ? gv[i] : (V)0;
     }
-    (void)run_bitmap(gk, n, base, bm, wpre, tmp, kk);
+    load_run_bitmap(bits, bm, wpre, tmp);
     const uint32_t c0 = cbase[blockIdx.x];
 #pragma unroll
     for (uint32_t j = 0; j < kRunPer; ++j) {
