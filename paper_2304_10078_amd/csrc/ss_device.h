@@ -3242,11 +3242,21 @@ constexpr uint32_t kFoldSlots = 256 * (kFoldPer + 1);
 __device__ __forceinline__ void stage_chunk(const uint64_t* sk, const uint64_t* sv, uint64_t n, uint64_t base,
                                             uint64_t* lk, uint64_t* lv, uint64_t* prev_next)
 {
-    for (uint32_t j = threadIdx.x; j < kFoldChunk; j += 256) {
-        const uint64_t i = base + j;
+    // every load of the chunk in flight before the first LDS store (coalesced:
+    // thread t reads positions t, t + 256, ...)
+    uint64_t kr[kFoldPer], vr[kFoldPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kFoldPer; ++u) {
+        const uint64_t i = base + u * 256 + threadIdx.x;
+        kr[u] = i < n ? sk[i] : 0ull;
+        vr[u] = i < n ? sv[i] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kFoldPer; ++u) {
+        const uint32_t j = u * 256 + threadIdx.x;
         const uint32_t slot = (j / kFoldPer) * (kFoldPer + 1) + j % kFoldPer;
-        lk[slot] = i < n ? sk[i] : 0ull;
-        lv[slot] = i < n ? sv[i] : 0ull;
+        lk[slot] = kr[u];
+        lv[slot] = vr[u];
     }
     if (threadIdx.x == 0) prev_next[0] = base ? sk[base - 1] : 0ull;
     if (threadIdx.x == 1) prev_next[1] = base + kFoldChunk < n ? sk[base + kFoldChunk] : 0ull;
